@@ -1,0 +1,394 @@
+"""FP64 CPU oracle: 1-D azimuthal integration with bounding-box pixel splitting.
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+benchmark's CPU-baseline leg, never by the product path.  It is written from
+the paper (Kieffer & Ashiotis, "PyFAI: a Python library for high performance
+azimuthal integration on GPU", EuroSciPy 2014) and shares no code, table or
+helper with the HIP library.
+
+What is computed (each function cites the passage it follows):
+
+* per-pixel radial coordinate and its extent over the pixel area
+  (Section 3, coordinate list; Section 3.1 test case; Section 4.1),
+* the pixel-to-bin coefficients of bounding-box splitting (Section 4.1), or
+  of plain histogramming (Section 3.3),
+* the per-pixel correction map (Section 6.4, "Kernel timings"),
+* the weighted histogram W, the unweighted histogram U and their ratio
+  I = W / U (Section 3.3; Section 5.2 states the same sums as a sparse
+  matrix-vector product),
+* the adjoint of I (and W) with respect to the corrected image,
+* Kahan-compensated float32 summation (Section 5.2.2).
+
+The integration itself reaches exactly, up to the order of the additions,
+the plain definition W_b = sum_p A_bp x_p, U_b = sum_p A_bp: the
+scatter-to-gather rewrite and the CSR storage of Section 5.2 only reorder
+these sums.  So the oracle is that definition: a forward scatter over pixels
+with the sums carried in extended precision (numpy.longdouble, a 64-bit
+mantissa on x86-64), rounded once to float64.
+
+Readings of passages the paper leaves open (numbered as in the design notes):
+
+R1  pixel (i, j) covers [j, j+1] x [i, i+1] in pixel units; the beam centre
+    is given in the same units.
+R2  the bounding box of Section 4.1 spans the pixel's true radial extent:
+    ``hi`` is the largest corner distance, ``lo`` the distance to the nearest
+    point of the closed pixel square (0 when the centre lies inside it).
+R3  bins are uniform over an explicit [pmin, pmax]; by default
+    [min lo, max hi] (split) or [min centre, max centre] (no split); the
+    last bin is closed.
+R4  boxes partly outside the range are clipped; the weights stay normalised
+    by the full box width, so the part outside is dropped.
+R5  a box [fl, fh] in fractional-bin units covers bins floor(fl) ..
+    ceil(fh) - 1, so no zero coefficient is ever produced.
+R6  every inner bin receives 1 / (fh - fl): the overlap of a whole bin over
+    the box width, which is what "the remaining contribution, evenly
+    distributed" amounts to for uniform bins.
+R7  an empty bin (U = 0) yields the caller's ``empty`` value (default 0.0).
+R9  units: r in m or mm, 2theta in rad or deg, q in 1/nm.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+UNITS = ("r_m", "r_mm", "2th_rad", "2th_deg", "q_nm")
+SPLITS = ("none", "bbox")
+
+__all__ = [
+    "UNITS", "SPLITS", "unit_of_radius", "pixel_extents", "pixel_extents_loop",
+    "default_range", "bbox_entries", "bbox_entries_loop", "nosplit_entries",
+    "entries_to_csr", "build_matrix", "correct", "integrate", "integrate_loop",
+    "integrate_vjp", "kahan_sum_f32", "positions",
+]
+
+
+# ----------------------------------------------------------------------------
+# Geometry (Section 3 coordinate list; Section 3.1; Section 4.1)
+# ----------------------------------------------------------------------------
+
+def unit_of_radius(r, unit: str, dist: float, wavelength: float):
+    """Map a radius in metres to the output coordinate (Section 3 list).
+
+    2theta = atan(r / d); q = 4 pi sin(2theta / 2) / lambda, with lambda in
+    nm so that q is in 1/nm (reading R9).  Every map is monotone
+    non-decreasing in r, so a radial interval maps to an interval.
+    """
+    if unit == "r_m":
+        return r
+    if unit == "r_mm":
+        return r * 1e3
+    tth = np.arctan(r / dist)
+    if unit == "2th_rad":
+        return tth
+    if unit == "2th_deg":
+        return tth * (180.0 / math.pi)
+    if unit == "q_nm":
+        return (4.0 * math.pi) * np.sin(tth / 2.0) / (wavelength * 1e9)
+    raise ValueError(f"unknown unit {unit!r}")
+
+
+def pixel_extents(h, w, pixel_y, pixel_x, center_y, center_x, dist, wavelength,
+                  unit="r_m"):
+    """Per-pixel (lo, hi, centre) of the output coordinate, row-major (h*w,).
+
+    The radius of a point is r = sqrt(x^2 + y^2) measured from the beam
+    centre (Section 3.1).  ``hi`` is the largest of the four corner radii and
+    ``lo`` the radius of the nearest point of the pixel square (reading R2);
+    the centre value is the radius of the pixel midpoint.
+    """
+    i = np.arange(h, dtype=np.int64)[:, None]
+    j = np.arange(w, dtype=np.int64)[None, :]
+    x0 = (j - center_x) * pixel_x
+    x1 = ((j + 1) - center_x) * pixel_x
+    y0 = (i - center_y) * pixel_y
+    y1 = ((i + 1) - center_y) * pixel_y
+    s00 = x0 * x0 + y0 * y0
+    s01 = x1 * x1 + y0 * y0
+    s10 = x0 * x0 + y1 * y1
+    s11 = x1 * x1 + y1 * y1
+    hi = np.sqrt(np.maximum(np.maximum(s00, s01), np.maximum(s10, s11)))
+    # nearest point of [j, j+1] x [i, i+1] to the centre, per axis
+    ex = np.maximum(np.maximum(j - center_x, center_x - (j + 1)), 0.0) * pixel_x
+    ey = np.maximum(np.maximum(i - center_y, center_y - (i + 1)), 0.0) * pixel_y
+    lo = np.sqrt(ex * ex + ey * ey)
+    xc = ((j + 0.5) - center_x) * pixel_x
+    yc = ((i + 0.5) - center_y) * pixel_y
+    rc = np.sqrt(xc * xc + yc * yc)
+    lo, hi, rc = (np.broadcast_to(a, (h, w)).reshape(-1) for a in (lo, hi, rc))
+    f = lambda r: np.asarray(unit_of_radius(r, unit, dist, wavelength), dtype=np.float64)
+    return f(lo), f(hi), f(rc)
+
+
+def pixel_extents_loop(h, w, pixel_y, pixel_x, center_y, center_x, dist,
+                       wavelength, unit="r_m"):
+    """Pure-Python form of :func:`pixel_extents` for small images."""
+    n = h * w
+    lo, hi, rc = [0.0] * n, [0.0] * n, [0.0] * n
+    for i in range(h):
+        for j in range(w):
+            p = i * w + j
+            best = 0.0
+            for a in (0, 1):
+                for b in (0, 1):
+                    x = ((j + a) - center_x) * pixel_x
+                    y = ((i + b) - center_y) * pixel_y
+                    best = max(best, x * x + y * y)
+            hi[p] = math.sqrt(best)
+            ex = max(j - center_x, center_x - (j + 1), 0.0) * pixel_x
+            ey = max(i - center_y, center_y - (i + 1), 0.0) * pixel_y
+            lo[p] = math.sqrt(ex * ex + ey * ey)
+            xc = ((j + 0.5) - center_x) * pixel_x
+            yc = ((i + 0.5) - center_y) * pixel_y
+            rc[p] = math.sqrt(xc * xc + yc * yc)
+    f = lambda v: np.asarray(unit_of_radius(np.asarray(v, dtype=np.float64), unit,
+                                            dist, wavelength), dtype=np.float64)
+    return f(lo), f(hi), f(rc)
+
+
+def default_range(lo, hi, centre, split):
+    """Reading R3: [min lo, max hi] with splitting, [min c, max c] without."""
+    if split == "bbox":
+        return float(np.min(lo)), float(np.max(hi))
+    return float(np.min(centre)), float(np.max(centre))
+
+
+def positions(npt, pmin, pmax):
+    """Bin centres pmin + (b + 0.5) * delta, delta = (pmax - pmin) / npt."""
+    delta = (pmax - pmin) / npt
+    return pmin + (np.arange(npt) + 0.5) * delta
+
+
+# ----------------------------------------------------------------------------
+# Pixel-to-bin coefficients (Section 4.1 bounding box; Section 3.3 histogram)
+# ----------------------------------------------------------------------------
+
+def bbox_entries_loop(lo, hi, npt, pmin, pmax):
+    """Bounding-box splitting, one pixel at a time (Section 4.1).
+
+    The box [lo, hi] is mapped to fractional-bin units [fl, fh]; a box inside
+    one bin gives that bin its whole weight; otherwise the two outermost bins
+    get the part of the box they hold, and every inner bin an equal share
+    (readings R4-R6).  Returns (pixel, bin, coefficient) in scatter order.
+    """
+    delta = (pmax - pmin) / npt
+    pix, bins, coef = [], [], []
+    for p in range(len(lo)):
+        fl = (float(lo[p]) - pmin) / delta
+        fh = (float(hi[p]) - pmin) / delta
+        if fh == fl:
+            if 0.0 <= fl <= npt:
+                pix.append(p); bins.append(min(math.floor(fl), npt - 1)); coef.append(1.0)
+            continue
+        flc = max(fl, 0.0)
+        fhc = min(fh, float(npt))
+        if fhc <= flc:
+            continue
+        width = fh - fl
+        b0 = math.floor(flc)
+        b1 = math.ceil(fhc) - 1
+        if b0 == b1:
+            pix.append(p); bins.append(b0); coef.append((fhc - flc) / width)
+            continue
+        pix.append(p); bins.append(b0); coef.append(((b0 + 1) - flc) / width)
+        for b in range(b0 + 1, b1):
+            pix.append(p); bins.append(b); coef.append(1.0 / width)
+        pix.append(p); bins.append(b1); coef.append((fhc - b1) / width)
+    return (np.asarray(pix, dtype=np.int64), np.asarray(bins, dtype=np.int64),
+            np.asarray(coef, dtype=np.float64))
+
+
+def bbox_entries(lo, hi, npt, pmin, pmax):
+    """Vectorised form of :func:`bbox_entries_loop` (same arithmetic)."""
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    delta = (pmax - pmin) / npt
+    fl = (lo - pmin) / delta
+    fh = (hi - pmin) / delta
+    degen = fh == fl
+    flc = np.maximum(fl, 0.0)
+    fhc = np.minimum(fh, float(npt))
+    keep = (~degen) & (fhc > flc)
+    width = fh - fl
+    with np.errstate(invalid="ignore", divide="ignore"):
+        b0 = np.floor(flc)
+        b1 = np.ceil(fhc) - 1.0
+    pid = np.arange(lo.size, dtype=np.int64)
+    out_p, out_b, out_c = [], [], []
+    # degenerate boxes: a single full-weight entry
+    dmask = degen & (fl >= 0.0) & (fl <= npt)
+    if dmask.any():
+        out_p.append(pid[dmask])
+        out_b.append(np.minimum(np.floor(fl[dmask]), npt - 1).astype(np.int64))
+        out_c.append(np.ones(int(dmask.sum())))
+    if keep.any():
+        kp = pid[keep]
+        kfl, kfh, kw = flc[keep], fhc[keep], width[keep]
+        kb0 = b0[keep].astype(np.int64)
+        kb1 = b1[keep].astype(np.int64)
+        span = int((kb1 - kb0).max()) + 1
+        single = kb0 == kb1
+        for k in range(span):
+            b = kb0 + k
+            m = b <= kb1
+            if not m.any():
+                break
+            c = np.where(single, (kfh - kfl) / kw,
+                         np.where(k == 0, ((kb0 + 1) - kfl) / kw,
+                                  np.where(b == kb1, (kfh - kb1) / kw, 1.0 / kw)))
+            out_p.append(kp[m]); out_b.append(b[m]); out_c.append(c[m])
+    if not out_p:
+        z = np.zeros(0, dtype=np.int64)
+        return z, z.copy(), np.zeros(0)
+    return np.concatenate(out_p), np.concatenate(out_b), np.concatenate(out_c)
+
+
+def nosplit_entries(centre, npt, pmin, pmax):
+    """No splitting (Section 3.3): each pixel goes whole to the bin holding
+    its centre; the last bin is closed (reading R3)."""
+    c = np.asarray(centre, dtype=np.float64)
+    delta = (pmax - pmin) / npt
+    fc = (c - pmin) / delta
+    m = (fc >= 0.0) & (fc <= npt)
+    pid = np.arange(c.size, dtype=np.int64)[m]
+    b = np.minimum(np.floor(fc[m]), npt - 1).astype(np.int64)
+    return pid, b, np.ones(pid.size)
+
+
+def entries_to_csr(pix, bins, coef, npt):
+    """CSR of A (rows = bins, columns = pixels) with ascending pixel ids in a
+    row, the layout scipy.sparse.csr_matrix accepts (Section 5.2.1)."""
+    order = np.lexsort((pix, bins))
+    indptr = np.zeros(npt + 1, dtype=np.int64)
+    np.add.at(indptr, bins + 1, 1)
+    return np.cumsum(indptr), pix[order].astype(np.int64), coef[order]
+
+
+def build_matrix(h, w, pixel_y, pixel_x, center_y, center_x, dist, wavelength,
+                 npt, unit="r_m", split="bbox", range_=None, loop=False):
+    """Geometry -> coefficients -> CSR; returns a dict of plain arrays."""
+    ext = pixel_extents_loop if loop else pixel_extents
+    lo, hi, rc = ext(h, w, pixel_y, pixel_x, center_y, center_x, dist, wavelength, unit)
+    pmin, pmax = default_range(lo, hi, rc, split) if range_ is None else map(float, range_)
+    if not pmax > pmin:
+        raise ValueError("empty integration range")
+    if split == "bbox":
+        ent = (bbox_entries_loop if loop else bbox_entries)(lo, hi, npt, pmin, pmax)
+    elif split == "none":
+        ent = nosplit_entries(rc, npt, pmin, pmax)
+    else:
+        raise ValueError(f"unknown split {split!r}")
+    indptr, indices, data = entries_to_csr(*ent, npt)
+    return dict(npt=npt, npix=h * w, pmin=pmin, pmax=pmax, lo=lo, hi=hi, centre=rc,
+                pix=ent[0], bins=ent[1], coef=ent[2],
+                indptr=indptr, indices=indices, data=data,
+                positions=positions(npt, pmin, pmax))
+
+
+# ----------------------------------------------------------------------------
+# Per-frame computation
+# ----------------------------------------------------------------------------
+
+def correct(raw, dark=None, flat=None, solid=None, polar=None):
+    """Correction map of Section 6.4: x = (raw - dark) / ((flat*solid)*polar).
+
+    Missing arrays act as identity; the products are formed left to right.
+    """
+    x = np.asarray(raw).astype(np.float64).reshape(-1)
+    if dark is not None:
+        x = x - np.asarray(dark, dtype=np.float64).reshape(-1)
+    norm = None
+    for arr in (flat, solid, polar):
+        if arr is None:
+            continue
+        a = np.asarray(arr, dtype=np.float64).reshape(-1)
+        norm = a if norm is None else norm * a
+    if norm is not None:
+        x = x / norm
+    return x
+
+
+def correction_norm(flat=None, solid=None, polar=None):
+    norm = None
+    for arr in (flat, solid, polar):
+        if arr is None:
+            continue
+        a = np.asarray(arr, dtype=np.float64).reshape(-1)
+        norm = a if norm is None else norm * a
+    return norm
+
+
+def integrate(m, x, empty=0.0):
+    """W_b = sum_p A_bp x_p, U_b = sum_p A_bp, I_b = W_b / U_b (Section 3.3).
+
+    ``m`` is a dict holding the coefficient triplets ``pix``, ``bins``,
+    ``coef`` and ``npt``.  Products are float64; their sums are carried in
+    numpy.longdouble and rounded once.  An empty bin gives ``empty`` (R7).
+    """
+    x = np.asarray(x, dtype=np.float64).reshape(-1)
+    npt = int(m["npt"])
+    pix, bins, coef = m["pix"], m["bins"], np.asarray(m["coef"], dtype=np.float64)
+    prod = (coef * x[pix]).astype(np.longdouble)
+    W = np.zeros(npt, dtype=np.longdouble)
+    U = np.zeros(npt, dtype=np.longdouble)
+    np.add.at(W, bins, prod)
+    np.add.at(U, bins, coef.astype(np.longdouble))
+    W = W.astype(np.float64)
+    U = U.astype(np.float64)
+    I = np.full(npt, float(empty))
+    nz = U != 0.0
+    I[nz] = W[nz] / U[nz]
+    return I, W, U
+
+
+def integrate_loop(m, x, empty=0.0):
+    """Pure-Python form of :func:`integrate`, exact sums via math.fsum."""
+    npt = int(m["npt"])
+    wterms = [[] for _ in range(npt)]
+    uterms = [[] for _ in range(npt)]
+    for p, b, c in zip(m["pix"].tolist(), m["bins"].tolist(), m["coef"].tolist()):
+        wterms[b].append(c * float(x[p]))
+        uterms[b].append(c)
+    W = np.array([math.fsum(t) for t in wterms])
+    U = np.array([math.fsum(t) for t in uterms])
+    I = np.array([W[b] / U[b] if U[b] != 0.0 else float(empty) for b in range(npt)])
+    return I, W, U
+
+
+def integrate_vjp(m, U, grad_I=None, grad_W=None, norm=None):
+    """Adjoint of the forward map with respect to the corrected image.
+
+    dI_b/dx_p = A_bp / U_b and dW_b/dx_p = A_bp, so with upstream gradients
+    g_I and g_W:  gx_p = sum_b A_bp (g_I,b / U_b + g_W,b).  Empty bins give a
+    constant and contribute nothing.  With a correction map, the gradient
+    with respect to the raw counts is gx / norm (Section 6.4 map is affine in
+    raw).
+    """
+    npt, npix = int(m["npt"]), int(m["npix"])
+    U = np.asarray(U, dtype=np.float64)
+    v = np.zeros(npt, dtype=np.float64)
+    if grad_I is not None:
+        gI = np.asarray(grad_I, dtype=np.float64)
+        nz = U != 0.0
+        v[nz] = gI[nz] / U[nz]
+    if grad_W is not None:
+        v = v + np.asarray(grad_W, dtype=np.float64)
+    pix, bins, coef = m["pix"], m["bins"], np.asarray(m["coef"], dtype=np.float64)
+    gx = np.zeros(npix, dtype=np.longdouble)
+    np.add.at(gx, pix, (coef * v[bins]).astype(np.longdouble))
+    gx = gx.astype(np.float64)
+    if norm is not None:
+        gx = gx / np.asarray(norm, dtype=np.float64).reshape(-1)
+    return gx
+
+
+def kahan_sum_f32(values):
+    """Kahan compensated summation carried entirely in float32 (Section 5.2.2)."""
+    s = np.float32(0.0)
+    c = np.float32(0.0)
+    for v in np.asarray(values, dtype=np.float32):
+        y = np.float32(v - c)
+        t = np.float32(s + y)
+        c = np.float32(np.float32(t - s) - y)
+        s = t
+    return s

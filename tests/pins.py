@@ -1,0 +1,373 @@
+"""Checks that pin the oracle to facts other than itself.
+
+Each ``pin_*`` function takes an oracle-like namespace (the real ``oracle``
+package, or a copy with a planted mistake) and raises AssertionError when the
+fact it checks does not hold.  The facts come from the paper and from plain
+mathematics: exact rational brute force, numpy's histogram, the plain masked
+mean, conservation laws, symmetry, scipy's sparse product and the adjoint
+identity.
+"""
+from __future__ import annotations
+
+import math
+from fractions import Fraction as F
+
+import numpy as np
+
+TINY_CASES = [
+    # (h, w, center_y, center_x, npt, pixel_y, pixel_x)
+    (3, 3, 1.5, 1.5, 4, 1e-4, 1e-4),
+    (4, 5, 2.0, 2.5, 5, 1e-4, 1e-4),
+    (7, 6, 3.5, 3.0, 9, 1e-4, 1e-4),
+    (5, 4, 0.3, 3.7, 6, 1e-4, 1e-4),      # off-centre beam
+    (6, 7, -1.25, 2.2, 7, 1e-4, 1e-4),    # beam outside the detector
+    (4, 6, 1.1, 2.9, 13, 1.5e-4, 1e-4),   # rectangular pixels, fine bins
+]
+DIST, WL = 0.1, 1e-10
+
+
+def _geom_args(case):
+    h, w, cy, cx, npt, py, px = case
+    return dict(h=h, w=w, pixel_y=py, pixel_x=px, center_y=cy, center_x=cx,
+                dist=DIST, wavelength=WL)
+
+
+def exact_extent_sq(h, w, py, px, cy, cx):
+    """Exact squared radial extent of every pixel square, as Fractions.
+
+    hi^2 is the largest squared corner distance (the distance is convex);
+    lo^2 is the squared distance to the point of the square nearest to the
+    centre, found by clamping the centre into the square.
+    """
+    py, px, cy, cx = F(py), F(px), F(cy), F(cx)
+    lo2, hi2 = [], []
+    for i in range(h):
+        for j in range(w):
+            corners = [(((j + a) - cx) * px) ** 2 + (((i + b) - cy) * py) ** 2
+                       for a in (0, 1) for b in (0, 1)]
+            hi2.append(max(corners))
+            nx = min(max(cx, F(j)), F(j + 1))
+            ny = min(max(cy, F(i)), F(i + 1))
+            lo2.append(((nx - cx) * px) ** 2 + ((ny - cy) * py) ** 2)
+    return lo2, hi2
+
+
+def exact_bbox_matrix(lo, hi, npt, pmin, pmax):
+    """Exact overlap / width of every box with every bin (dense, Fractions)."""
+    pmin, pmax = F(pmin), F(pmax)
+    d = (pmax - pmin) / npt
+    A = {}
+    for p, (l, u) in enumerate(zip(lo, hi)):
+        l, u = F(float(l)), F(float(u))
+        if u == l:
+            continue
+        for b in range(npt):
+            a0, a1 = pmin + b * d, pmin + (b + 1) * d
+            ov = min(u, a1) - max(l, a0)
+            if ov > 0:
+                A[(b, p)] = ov / (u - l)
+    return A
+
+
+def pin_extents_exact(O):
+    """P1a: lo and hi are the correctly rounded true radial extent (R2)."""
+    for case in TINY_CASES:
+        h, w, cy, cx, npt, py, px = case
+        lo, hi, _ = O.pixel_extents(**_geom_args(case))
+        lo2, hi2 = exact_extent_sq(h, w, py, px, cy, cx)
+        for p in range(h * w):
+            for got, ex in ((lo[p], lo2[p]), (hi[p], hi2[p])):
+                ref = math.sqrt(float(ex))
+                assert abs(got - ref) <= 4 * math.ulp(max(ref, 1e-300)), (case, p, got, ref)
+
+
+def pin_bbox_bruteforce(O):
+    """P1b: bbox coefficients equal exact overlap/width (Section 4.1)."""
+    for case in TINY_CASES:
+        args = _geom_args(case)
+        npt = case[4]
+        m = O.build_matrix(npt=npt, split="bbox", **args)
+        exact = exact_bbox_matrix(m["lo"], m["hi"], npt, m["pmin"], m["pmax"])
+        got = {}
+        for b, p, c in zip(m["bins"].tolist(), m["pix"].tolist(), m["coef"].tolist()):
+            assert (b, p) not in got, "duplicate entry"
+            got[(b, p)] = c
+        for key, c in got.items():
+            ref = float(exact.get(key, 0))
+            assert abs(c - ref) <= 1e-12, (case, key, c, ref)
+        for key, ref in exact.items():
+            if key not in got:
+                assert float(ref) <= 1e-12, (case, key, float(ref))
+
+
+def pin_results_exact(O):
+    """P1c: W, U, I equal their exact rational values on integer images."""
+    rng = np.random.default_rng(11)
+    for case in TINY_CASES:
+        h, w = case[0], case[1]
+        npt = case[4]
+        m = O.build_matrix(npt=npt, split="bbox", **_geom_args(case))
+        x = rng.integers(0, 1 << 20, size=h * w)
+        I, W, U = O.integrate(m, x.astype(np.float64))
+        exact = exact_bbox_matrix(m["lo"], m["hi"], npt, m["pmin"], m["pmax"])
+        for b in range(npt):
+            We = sum((c * int(x[p]) for (bb, p), c in exact.items() if bb == b), F(0))
+            Ue = sum((c for (bb, p), c in exact.items() if bb == b), F(0))
+            assert abs(W[b] - float(We)) <= 1e-12 * max(1.0, abs(float(We))), (case, b)
+            assert abs(U[b] - float(Ue)) <= 1e-12 * max(1.0, float(Ue)), (case, b)
+            if Ue != 0:
+                Ie = float(We / Ue)
+                assert abs(I[b] - Ie) <= 1e-12 * max(1.0, abs(Ie)), (case, b, I[b], Ie)
+
+
+def pin_nosplit_histogram(O):
+    """P2: no splitting == ratio of numpy's weighted/unweighted histograms
+    (Section 3.3), except pixels within rounding of a bin edge."""
+    rng = np.random.default_rng(5)
+    for (h, w, npt) in [(37, 41, 23), (64, 48, 50), (100, 100, 100)]:
+        args = dict(h=h, w=w, pixel_y=1e-4, pixel_x=1e-4, center_y=h / 2 + 0.3,
+                    center_x=w / 2 - 0.2, dist=DIST, wavelength=WL)
+        m = O.build_matrix(npt=npt, split="none", **args)
+        x = rng.integers(0, 1 << 20, size=h * w).astype(np.float64)
+        I, W, U = O.integrate(m, x)
+        r = m["centre"]
+        hu, edges = np.histogram(r, npt, range=(m["pmin"], m["pmax"]))
+        hw, _ = np.histogram(r, npt, range=(m["pmin"], m["pmax"]), weights=x)
+        frac = (r - m["pmin"]) / ((m["pmax"] - m["pmin"]) / npt)
+        near_edge = np.abs(frac - np.round(frac)) < 1e-9
+        if not near_edge.any():
+            assert np.array_equal(U, hu.astype(np.float64))
+            assert np.allclose(W, hw, rtol=1e-15, atol=0)
+        else:
+            assert abs(U.sum() - hu.sum()) == 0
+            assert np.abs(U - hu).sum() <= 2 * near_edge.sum()
+
+
+def pin_naive_mean(O):
+    """P3: no splitting over [0, max r] == per-bin masked mean of the pixels
+    with r1 <= r < r2 (Section 3.2), the pixel at r == rmax aside."""
+    rng = np.random.default_rng(6)
+    h, w, npt = 30, 34, 40
+    args = dict(h=h, w=w, pixel_y=1e-4, pixel_x=1e-4, center_y=11.3, center_x=20.6,
+                dist=DIST, wavelength=WL)
+    probe = O.build_matrix(npt=npt, split="none", **args)
+    r = probe["centre"]
+    rmax = float(r.max())
+    m = O.build_matrix(npt=npt, split="none", range_=(0.0, rmax), **args)
+    x = rng.integers(0, 1 << 16, size=h * w).astype(np.float64)
+    I, W, U = O.integrate(m, x, empty=np.nan)
+    frac = r / (rmax / npt)
+    near = np.abs(frac - np.round(frac)) < 1e-9
+    near[np.argmax(r)] = False
+    assert not near.any(), "geometry chosen so that no centre sits on an edge"
+    compared = 0
+    for b in range(npt):
+        r1, r2 = rmax * b / npt, rmax * (b + 1) / npt
+        sel = x[(r >= r1) & (r < r2)]
+        if b == npt - 1:
+            sel = x[(r >= r1) & (r <= r2)]   # closed last bin (reading R3)
+        if sel.size == 0:
+            assert U[b] == 0 and np.isnan(I[b])
+        else:
+            assert U[b] == sel.size, (b, U[b], sel.size)
+            assert abs(I[b] - sel.mean()) <= 1e-12 * abs(sel.mean())
+            compared += 1
+    assert compared >= npt - 2
+
+
+def pin_conservation(O):
+    """P4: sum U = number of pixels and sum W = sum of the image over the
+    default range (Section 4: splitting conserves signal and pixel count)."""
+    rng = np.random.default_rng(7)
+    for (h, w, npt, cy, cx) in [(50, 60, 37, 25.0, 30.0), (41, 33, 80, 3.3, 29.1),
+                                (64, 64, 7, 32.0, 32.0)]:
+        for split in ("bbox", "none"):
+            m = O.build_matrix(h=h, w=w, pixel_y=1e-4, pixel_x=1e-4, center_y=cy,
+                               center_x=cx, dist=DIST, wavelength=WL, npt=npt,
+                               split=split)
+            x = rng.uniform(-1.0, 3.0, size=h * w)
+            I, W, U = O.integrate(m, x)
+            n = h * w
+            assert abs(U.sum() - n) <= 1e-12 * n, (split, U.sum(), n)
+            assert abs(W.sum() - x.sum()) <= 1e-12 * np.abs(x).sum(), split
+
+
+def pin_unit_weights(O):
+    """P5: every pixel's coefficients add up to one (box fully in range)."""
+    m = O.build_matrix(h=40, w=45, pixel_y=1e-4, pixel_x=1e-4, center_y=20.0,
+                       center_x=22.5, dist=DIST, wavelength=WL, npt=60, split="bbox")
+    s = np.zeros(m["npix"])
+    np.add.at(s, m["pix"], m["coef"])
+    assert np.all(np.abs(s - 1.0) <= 1e-13), np.abs(s - 1.0).max()
+    # every coefficient lies in (0, 1]
+    assert np.all(m["coef"] > 0) and np.all(m["coef"] <= 1.0 + 1e-15)
+
+
+def pin_constant_image(O):
+    """P6: a constant image integrates to that constant in every bin."""
+    for split in ("bbox", "none"):
+        m = O.build_matrix(h=33, w=29, pixel_y=1e-4, pixel_x=1e-4, center_y=5.5,
+                           center_x=14.0, dist=DIST, wavelength=WL, npt=45, split=split)
+        I, W, U = O.integrate(m, np.full(m["npix"], 3.25))
+        nz = U > 0
+        assert np.all(np.abs(I[nz] - 3.25) <= 4e-15 * 3.25)
+
+
+def pin_symmetry(O):
+    """P7: on a centred square detector the radial profile of an image equals
+    that of its transpose and of its mirror images."""
+    rng = np.random.default_rng(8)
+    n = 24
+    m = O.build_matrix(h=n, w=n, pixel_y=1e-4, pixel_x=1e-4, center_y=n / 2,
+                       center_x=n / 2, dist=DIST, wavelength=WL, npt=31, split="bbox")
+    img = rng.uniform(0, 10, size=(n, n))
+    I0, W0, U0 = O.integrate(m, img.reshape(-1))
+    for t in (img.T, img[::-1, :], img[:, ::-1], img[::-1, ::-1]):
+        I1, W1, U1 = O.integrate(m, np.ascontiguousarray(t).reshape(-1))
+        assert np.allclose(I1, I0, rtol=1e-13, atol=0)
+        assert np.allclose(W1, W0, rtol=1e-13, atol=0)
+
+
+def pin_scipy_csr(O):
+    """P8: the CSR arrays feed scipy.sparse.csr_matrix directly (Section 5.2.1):
+    A @ x gives W, the row sums give U, A.T @ v gives the adjoint."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(9)
+    m = O.build_matrix(h=45, w=52, pixel_y=1e-4, pixel_x=1e-4, center_y=10.0,
+                       center_x=40.5, dist=DIST, wavelength=WL, npt=70, split="bbox")
+    A = sp.csr_matrix((m["data"], m["indices"], m["indptr"]), shape=(m["npt"], m["npix"]))
+    x = rng.uniform(0, 100, size=m["npix"])
+    I, W, U = O.integrate(m, x)
+    assert np.allclose(A @ x, W, rtol=1e-13, atol=0)
+    assert np.allclose(np.asarray(A.sum(axis=1)).ravel(), U, rtol=1e-13, atol=0)
+    g = rng.standard_normal(m["npt"])
+    gx = O.integrate_vjp(m, U, grad_I=g)
+    v = np.where(U > 0, g / np.where(U > 0, U, 1.0), 0.0)
+    assert np.allclose(A.T @ v, gx, rtol=1e-12, atol=1e-300)
+    # rows hold strictly ascending pixel ids
+    for b in range(m["npt"]):
+        row = m["indices"][m["indptr"][b]:m["indptr"][b + 1]]
+        assert np.all(np.diff(row) > 0)
+
+
+def pin_adjoint(O):
+    """P9: <g, I(x)> is linear in x, so <g, I(x)> = <gx, x> exactly in real
+    arithmetic, and central differences carry no truncation error."""
+    rng = np.random.default_rng(10)
+    m = O.build_matrix(h=30, w=26, pixel_y=1e-4, pixel_x=1e-4, center_y=14.2,
+                       center_x=13.0, dist=DIST, wavelength=WL, npt=35, split="bbox")
+    x = rng.uniform(0, 1, size=m["npix"])
+    g = rng.standard_normal(m["npt"])
+    gw = rng.standard_normal(m["npt"])
+    I, W, U = O.integrate(m, x)
+    gx = O.integrate_vjp(m, U, grad_I=g, grad_W=gw)
+    lhs = float(np.dot(g, I) + np.dot(gw, W))
+    rhs = float(np.dot(gx, x))
+    assert abs(lhs - rhs) <= 1e-13 * (np.abs(g) @ np.abs(I) + np.abs(gw) @ np.abs(W))
+    h = 1e-6
+    for p in rng.choice(m["npix"], size=12, replace=False):
+        xp, xm = x.copy(), x.copy()
+        xp[p] += h
+        xm[p] -= h
+        Ip, Wp, _ = O.integrate(m, xp)
+        Im, Wm, _ = O.integrate(m, xm)
+        fd = (np.dot(g, Ip - Im) + np.dot(gw, Wp - Wm)) / (2 * h)
+        scale = (np.abs(g) @ np.abs(I) + np.abs(gw) @ np.abs(W)) * 2.3e-16 / h
+        assert abs(fd - gx[p]) <= 4 * scale + 1e-9 * abs(gx[p]), (p, fd, gx[p])
+
+
+def pin_kahan(O):
+    """P10: float32 Kahan summation stays within 2u * sum|x| (+O(n u^2)) of the
+    exact sum (Kahan 1965; Higham, Accuracy and Stability, Section 4.3),
+    where plain float32 summation does not."""
+    rng = np.random.default_rng(12)
+    u = 2.0 ** -24
+    for n in (1000, 20000):
+        vals = np.concatenate([rng.uniform(0, 1, n).astype(np.float32),
+                               np.float32([1e4]), rng.uniform(0, 1, n).astype(np.float32)])
+        exact = math.fsum(float(v) for v in vals)
+        got = float(O.kahan_sum_f32(vals))
+        bound = (2 * u + 4 * len(vals) * u * u) * float(np.abs(vals.astype(np.float64)).sum())
+        assert abs(got - exact) <= bound, (n, got - exact, bound)
+        naive = np.float32(0)
+        for v in vals:
+            naive = np.float32(naive + v)
+        assert abs(float(naive) - exact) > abs(got - exact)
+
+
+def pin_closed_forms(O):
+    """Hand-derived closed forms.
+
+    * 3x3 detector, beam at its middle: the middle pixel spans [0, sqrt(1/2)],
+      an edge pixel [1/2, sqrt(5/2)], a corner pixel [sqrt(1/2), sqrt(9/2)]
+      (pixel units; R2: an edge pixel's nearest point is an edge midpoint).
+    * 2x2 detector, beam at the shared corner, 2 bins over [0, sqrt 2]: every
+      pixel spans both bins with weight 1/2, so U = (2, 2), W = (S/2, S/2).
+    * a radius equal to the distance is 2theta = 45 deg exactly (pi/4 rad),
+      and q = 4 pi sin(pi/8) / lambda.
+    """
+    p = 1e-4
+    lo, hi, rc = O.pixel_extents(3, 3, p, p, 1.5, 1.5, DIST, WL, "r_m")
+    s = lambda v: math.sqrt(v) * p
+    assert lo[4] == 0.0 and abs(hi[4] - s(0.5)) <= 2 * math.ulp(s(0.5))
+    for e in (1, 3, 5, 7):
+        assert abs(lo[e] - 0.5 * p) <= 2 * math.ulp(p) and abs(hi[e] - s(2.5)) <= 2 * math.ulp(s(2.5))
+    for c in (0, 2, 6, 8):
+        assert abs(lo[c] - s(0.5)) <= 2 * math.ulp(s(0.5)) and abs(hi[c] - s(4.5)) <= 2 * math.ulp(s(4.5))
+    assert rc[4] == 0.0
+    m = O.build_matrix(h=2, w=2, pixel_y=p, pixel_x=p, center_y=1.0, center_x=1.0,
+                       dist=DIST, wavelength=WL, npt=2, split="bbox")
+    assert np.array_equal(m["indptr"], [0, 4, 8])
+    assert np.allclose(m["data"], 0.5, rtol=0, atol=2e-16)
+    x = np.array([1.0, 2.0, 4.0, 8.0])
+    I, W, U = O.integrate(m, x)
+    assert np.allclose(U, [2.0, 2.0], rtol=1e-15) and np.allclose(W, [7.5, 7.5], rtol=1e-15)
+    assert np.allclose(I, [3.75, 3.75], rtol=1e-15)
+    r = np.array([DIST])
+    assert abs(O.unit_of_radius(r, "2th_deg", DIST, WL)[0] - 45.0) <= 1e-13
+    assert abs(O.unit_of_radius(r, "2th_rad", DIST, WL)[0] - math.pi / 4) <= 1e-15
+    q = O.unit_of_radius(r, "q_nm", DIST, WL)[0]
+    assert abs(q - 4 * math.pi * math.sin(math.pi / 8) / (WL * 1e9)) <= 1e-13 * q
+    assert O.unit_of_radius(r, "r_mm", DIST, WL)[0] == 100.0
+
+
+def pin_bbox_clipped(O):
+    """P1d: with a range narrower than the data, each coefficient is the
+    exact overlap with the bin over the FULL box width (reading R4)."""
+    for case in TINY_CASES[:4]:
+        args = _geom_args(case)
+        npt = case[4]
+        full = O.build_matrix(npt=npt, split="bbox", **args)
+        span = full["pmax"] - full["pmin"]
+        rng_ = (full["pmin"] + 0.31 * span, full["pmin"] + 0.77 * span)
+        m = O.build_matrix(npt=npt, split="bbox", range_=rng_, **args)
+        exact = exact_bbox_matrix(m["lo"], m["hi"], npt, rng_[0], rng_[1])
+        got = {(b, p): c for b, p, c in zip(m["bins"].tolist(), m["pix"].tolist(),
+                                              m["coef"].tolist())}
+        assert len(got) > 0
+        for key in set(got) | set(exact):
+            assert abs(got.get(key, 0.0) - float(exact.get(key, 0))) <= 1e-12, (case, key)
+        s = np.zeros(m["npix"])
+        np.add.at(s, m["pix"], m["coef"])
+        assert s.max() <= 1.0 + 1e-13 and s.min() < 1.0 - 1e-3
+
+
+def pin_correction(O):
+    """Correction map of Section 6.4 on hand-computed values."""
+    raw = np.array([10, 7, 3, 1000], dtype=np.int32)
+    dark = np.array([2.0, 7.0, 4.0, 0.0])
+    flat = np.array([2.0, 1.0, 0.5, 1.0])
+    solid = np.array([0.5, 1.0, 1.0, 0.25])
+    polar = np.array([4.0, 1.0, 2.0, 1.0])
+    x = O.correct(raw, dark, flat, solid, polar)
+    assert np.array_equal(x, [2.0, 0.0, -1.0, 4000.0])
+    assert np.array_equal(O.correct(raw), raw.astype(np.float64))
+    assert np.array_equal(O.correct(raw, dark=dark), [8.0, 0.0, -1.0, 1000.0])
+    assert np.array_equal(O.correct(raw, flat=flat), [5.0, 7.0, 6.0, 1000.0])
+    assert np.array_equal(O.correct(raw, solid=solid, polar=polar), [5.0, 7.0, 1.5, 4000.0])
+
+
+ALL_PINS = [pin_extents_exact, pin_bbox_bruteforce, pin_results_exact,
+            pin_nosplit_histogram, pin_naive_mean, pin_conservation, pin_unit_weights,
+            pin_constant_image, pin_symmetry, pin_scipy_csr, pin_adjoint, pin_kahan,
+            pin_closed_forms, pin_bbox_clipped, pin_correction]
