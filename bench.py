@@ -1,0 +1,342 @@
+#!/usr/bin/env python3
+"""Benchmark of the azimuthal-integration hot path on one MI355X.
+
+Step = one frame through the per-frame pipeline of Section 6.4 (cast +
+dark/flat/solid-angle/polarisation correction, then the CSR gather
+integration that yields I, W, U; the output memset of the paper is not
+needed), on the ~1e7-pixel workload (3162 x 3163 int32 frame, bounding-box
+splitting, 3162 bins, float64).  Frames rotate over 4 distinct synthetic
+images already resident in HBM.  Prints ONE JSON line on stdout; progress
+goes to stderr.
+
+Extra lines in the same JSON object (``lines``): the float32-storage copy,
+a cold-cache timing of the integration kernel, the 4096-instance batch (one
+persistent graph launch vs a per-instance loop), the 1e6-pixel adjoint, and
+the 1024-instance float32 forward+adjoint batch with autotuned tiles.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--main-only", action="store_true", help="skip the extra lines")
+    ap.add_argument("--only", default="", help="comma list of extra lines to run")
+    return ap.parse_args()
+
+
+def mean_event_ms(pairs):
+    return sum(a.elapsed_time(b) for a, b in pairs) / len(pairs)
+
+
+def spmv_bytes(nnz, npix, npt, es):
+    """Algorithmic bytes of one integration: CSR coefficients and pixel ids,
+    the image, row pointers, three outputs."""
+    return nnz * (es + 4) + npix * es + (npt + 1) * 4 + 3 * npt * es
+
+
+def bwd_bytes(nnz, npix, npt, es):
+    """Adjoint: CSC coefficients and bin ids, column pointers, the gradient
+    written, U and the upstream gradient read."""
+    return nnz * (es + 4) + (npix + 1) * 4 + npix * es + 2 * npt * es
+
+
+def build_plans(insts, dtype, az, threads=16):
+    def mk(inst):
+        g = inst.geom
+        return az.Plan(g.h, g.w, inst.npt, center=(g.center_y, g.center_x), dtype=dtype)
+    with ThreadPoolExecutor(threads) as ex:
+        return list(ex.map(mk, insts))
+
+
+def pipeline_line(az, torch, np, synth, dev, dtype, steps, warmup, frames_n=4):
+    c = synth.C2
+    inst = synth.instance(c["n"], c["seed"], corrections=True)
+    g = inst.geom
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    npd = np.float64 if dtype == "f64" else np.float32
+    t0 = time.perf_counter()
+    plan = az.Plan(g.h, g.w, inst.npt, center=(g.center_y, g.center_x), dtype=tdt, device=dev)
+    log(f"[{dtype}] plan {g.h}x{g.w} npt={inst.npt} nnz={plan.nnz} built+uploaded in "
+        f"{time.perf_counter() - t0:.1f}s")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a).reshape(-1).astype(npd)).to(dev)
+    plan.set_corrections(t(inst.dark), t(inst.flat), t(inst.solid), t(inst.polar))
+    frames = [torch.from_numpy(inst.raw.reshape(-1)).to(dev)]
+    rng = np.random.default_rng(c["seed"] + 1000)
+    for _ in range(frames_n - 1):
+        frames.append(torch.from_numpy(
+            rng.integers(0, 1 << synth.RAW_BITS, size=g.npix, dtype=np.int32)).to(dev))
+    x = torch.empty(g.npix, dtype=tdt, device=dev)
+    outs = tuple(torch.empty(inst.npt, dtype=tdt, device=dev) for _ in range(3))
+    for k in range(warmup):
+        plan.correct(frames[k % frames_n], out=x)
+        plan.integrate(x, out=outs)
+    ev = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        e = ev[k]
+        e[0].record()
+        plan.correct(frames[k % frames_n], out=x)
+        e[1].record()
+        plan.integrate(x, out=outs)
+        e[2].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall * 1e3 / steps
+    corr_ms = mean_event_ms([(e[0], e[1]) for e in ev])
+    spmv_ms = mean_event_ms([(e[1], e[2]) for e in ev])
+    es = 8 if dtype == "f64" else 4
+    nnz = plan.nnz
+    b = spmv_bytes(nnz, g.npix, inst.npt, es)
+    corr_b = g.npix * (4 + 3 * es)
+    line = dict(npix=g.npix, npt=inst.npt, nnz=nnz, ms_per_step=ms_step,
+                elements_per_s=g.npix / (ms_step * 1e-3),
+                correct_ms=corr_ms, correct_gbs=corr_b / (corr_ms * 1e6),
+                integrate_ms=spmv_ms, integrate_bytes=b,
+                integrate_gbs=b / (spmv_ms * 1e6),
+                integrate_frac=b / (spmv_ms * 1e6) / HBM_PEAK_GBS)
+    return line, plan, x, outs
+
+
+def cold_line(torch, plan, x, outs, npix, npt, nnz, es, reps=20):
+    """Integration kernel alone after streaming 1 GiB (flushes L2 and MALL)."""
+    flush = torch.empty(1 << 28, dtype=torch.float32, device=x.device)
+    pairs = []
+    for _ in range(reps):
+        flush.fill_(1.0)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        plan.integrate(x, out=outs)
+        b.record()
+        pairs.append((a, b))
+    torch.cuda.synchronize()
+    ms = mean_event_ms(pairs)
+    by = spmv_bytes(nnz, npix, npt, es)
+    return dict(integrate_ms=ms, integrate_gbs=by / (ms * 1e6),
+                integrate_frac=by / (ms * 1e6) / HBM_PEAK_GBS)
+
+
+def batch_line(az, torch, np, synth, dev, cfg, dtype, with_bwd, tune, reps=20):
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    npd = np.float64 if dtype == "f64" else np.float32
+    t0 = time.perf_counter()
+    insts = synth.batch(cfg["count"], cfg["lo"], cfg["hi"], cfg["seed"], grad=with_bwd)
+    plans = build_plans(insts, tdt, az)
+    batch = az.Batch(plans, device=dev)
+    del plans
+    log(f"[{cfg['name']}] {batch.n} instances, npix={batch.npix} npt={batch.npt} "
+        f"nnz={batch.nnz}, built in {time.perf_counter() - t0:.1f}s")
+    x = torch.from_numpy(np.concatenate([i.raw.reshape(-1) for i in insts]).astype(npd)).to(dev)
+    gI = None
+    if with_bwd:
+        gI = torch.from_numpy(np.concatenate([i.grad for i in insts]).astype(npd)).to(dev)
+    del insts
+    report = None
+    if tune:
+        report = az.autotune(batch, x)
+        log(f"[{cfg['name']}] autotuned: {report['best']}")
+    tiling = batch.tiling()
+    I, W, U = (torch.empty(batch.npt, dtype=tdt, device=dev) for _ in range(3))
+    gx = torch.empty(batch.npix, dtype=tdt, device=dev) if with_bwd else None
+    es = 8 if dtype == "f64" else 4
+
+    def timed(fn):
+        fn()
+        pairs = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            pairs.append((a, b))
+        torch.cuda.synchronize()
+        return mean_event_ms(pairs)
+
+    fwd_ms = timed(lambda: batch.forward(x, out=(I, W, U)))
+    loop_ms = timed(lambda: batch.forward(x, out=(I, W, U), loop=True))
+    graph = batch.graph(x, I, W, U, grad_I=gI, grad_x=gx)
+    graph_ms = timed(graph.launch)
+    fb = spmv_bytes(batch.nnz, batch.npix, batch.npt, es)
+    line = dict(instances=batch.n, npix=batch.npix, npt=batch.npt, nnz=batch.nnz,
+                tiling=tiling, forward_ms=fwd_ms, forward_gbs=fb / (fwd_ms * 1e6),
+                forward_frac=fb / (fwd_ms * 1e6) / HBM_PEAK_GBS,
+                loop_forward_ms=loop_ms, loop_elements_per_s=batch.npix / (loop_ms * 1e-3),
+                batched_vs_loop=loop_ms / fwd_ms)
+    if with_bwd:
+        _, _, _ = batch.forward(x, out=(I, W, U))
+        bwd_ms = timed(lambda: batch.backward(U, gI, out=gx))
+        bb = bwd_bytes(batch.nnz, batch.npix, batch.npt, es)
+        line.update(backward_ms=bwd_ms, backward_gbs=bb / (bwd_ms * 1e6),
+                    backward_frac=bb / (bwd_ms * 1e6) / HBM_PEAK_GBS,
+                    graph_fwd_bwd_ms=graph_ms,
+                    graph_elements_per_s=batch.npix / (graph_ms * 1e-3))
+    else:
+        line.update(graph_forward_ms=graph_ms,
+                    graph_elements_per_s=batch.npix / (graph_ms * 1e-3),
+                    graph_frac=fb / (graph_ms * 1e6) / HBM_PEAK_GBS)
+    if report:
+        line["autotune_candidates"] = len(report["candidates"])
+    del graph, batch
+    torch.cuda.empty_cache()
+    return line
+
+
+def adjoint_line(az, torch, np, synth, dev, reps=50):
+    inst = synth.c4_instance()
+    g = inst.geom
+    plan = az.Plan(g.h, g.w, inst.npt, center=(g.center_y, g.center_x), device=dev)
+    x = torch.from_numpy(inst.extra["x"]).to(dev)
+    gI = torch.from_numpy(inst.grad).to(dev)
+    I, W, U = plan.integrate(x)
+    gx = torch.empty_like(x)
+    fw, bw = [], []
+    for _ in range(reps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record()
+        plan.integrate(x, out=(I, W, U))
+        ev[1].record()
+        plan.backward(U, gI, out=gx)
+        ev[2].record()
+        fw.append((ev[0], ev[1]))
+        bw.append((ev[1], ev[2]))
+    torch.cuda.synchronize()
+    f, b = mean_event_ms(fw), mean_event_ms(bw)
+    nnz = plan.nnz
+    return dict(npix=g.npix, npt=inst.npt, nnz=nnz, forward_ms=f, backward_ms=b,
+                forward_gbs=spmv_bytes(nnz, g.npix, inst.npt, 8) / (f * 1e6),
+                backward_gbs=bwd_bytes(nnz, g.npix, inst.npt, 8) / (b * 1e6))
+
+
+def cpu_baseline(np, synth):
+    """The FP64 oracle on the host: one full ~1e7-pixel frame per repetition
+    (correction + integration; the matrix is built beforehand, untimed, as
+    the GPU plan is)."""
+    import oracle
+    c = synth.C2
+    inst = synth.instance(c["n"], c["seed"], corrections=True)
+    g = inst.geom
+    t0 = time.perf_counter()
+    m = oracle.build_matrix(h=g.h, w=g.w, pixel_y=g.pixel_y, pixel_x=g.pixel_x,
+                            center_y=g.center_y, center_x=g.center_x, dist=g.dist,
+                            wavelength=g.wavelength, npt=inst.npt)
+    log(f"[cpu] oracle matrix built in {time.perf_counter() - t0:.1f}s")
+    best = None
+    total = 0.0
+    reps = 0
+    while reps < 3 and total < 20.0:
+        t0 = time.perf_counter()
+        x = oracle.correct(inst.raw, inst.dark, inst.flat, inst.solid, inst.polar)
+        oracle.integrate(m, x)
+        dt = time.perf_counter() - t0
+        total += dt
+        reps += 1
+        best = dt if best is None else min(best, dt)
+    return dict(value=g.npix / best, unit="elements/s", cores=1, kind="oracle",
+                sample=f"full 3162x3163 frame, correction + integration, best of {reps} "
+                       f"({best:.2f} s each; matrix built beforehand, untimed); "
+                       f"single-threaded NumPy")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path "
+              "shards by instance or by image band, see the design notes", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1412_6367_amd as az
+    import synth
+
+    dev = torch.device("cuda:0")
+    az.lib()
+    line64, plan, x, outs = pipeline_line(az, torch, np, synth, dev, "f64", args.steps,
+                                          args.warmup)
+    log(f"[f64] {json.dumps(line64)}")
+    result = {
+        "metric": "elements/s and fraction of HBM roofline, plain vs batched+adjoint",
+        "value": line64["elements_per_s"],
+        "unit": "elements/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": line64["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "c2: one 3162x3163 int32 frame (~1e7 px), raw values uniform in "
+                        "[0, 2^20), dark/flat/solid/polar corrections, bounding-box split, "
+                        "3162 radial bins, float64 storage and accumulation; step = cast + "
+                        "correction + CSR gather integration (I, W, U)",
+            "npix": line64["npix"], "npt": line64["npt"], "nnz": line64["nnz"],
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_spmv (+k_fixup), CSR gather integration",
+            "achieved": line64["integrate_gbs"],
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": line64["integrate_frac"],
+            "traffic": None,
+            "bytes_per_launch": line64["integrate_bytes"],
+            "avg_launch_ms": line64["integrate_ms"],
+        },
+        "lines": {"c2_f64": line64},
+    }
+    es64 = 8
+    want = set(args.only.split(",")) if args.only else None
+    run = lambda name: (not args.main_only) and (want is None or name in want)
+    if run("c2_f64_cold"):
+        result["lines"]["c2_f64_cold"] = cold_line(torch, plan, x, outs, line64["npix"],
+                                                   line64["npt"], line64["nnz"], es64)
+        log(f"[cold] {json.dumps(result['lines']['c2_f64_cold'])}")
+    del plan, x, outs
+    torch.cuda.empty_cache()
+    if run("c2_f32"):
+        l32, p32, x32, o32 = pipeline_line(az, torch, np, synth, dev, "f32", args.steps,
+                                           args.warmup)
+        result["lines"]["c2_f32"] = l32
+        log(f"[f32] {json.dumps(l32)}")
+        del p32, x32, o32
+        torch.cuda.empty_cache()
+    if run("c3"):
+        result["lines"]["c3"] = batch_line(az, torch, np, synth, dev, synth.C3, "f64",
+                                           False, False)
+        log(f"[c3] {json.dumps(result['lines']['c3'])}")
+    if run("c4"):
+        result["lines"]["c4"] = adjoint_line(az, torch, np, synth, dev)
+        log(f"[c4] {json.dumps(result['lines']['c4'])}")
+    if run("c5"):
+        result["lines"]["c5"] = batch_line(az, torch, np, synth, dev, synth.C5, "f32",
+                                           True, True)
+        log(f"[c5] {json.dumps(result['lines']['c5'])}")
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(np, synth)
+        log(f"[cpu] {json.dumps(result['cpu_baseline'])}")
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

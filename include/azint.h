@@ -1,0 +1,290 @@
+/*
+ * azint.h -- C ABI of the MI355X (gfx950) azimuthal-integration library.
+ *
+ * The library reduces a 2-D detector image to a 1-D profile by bounding-box
+ * pixel splitting (Kieffer & Ashiotis, "PyFAI: a Python library for high
+ * performance azimuthal integration on GPU", EuroSciPy 2014).  The image is
+ * corrected pixel by pixel (Section 6.4), then each output bin b receives
+ *
+ *     W_b = sum_p A_bp x_p      (weighted histogram)
+ *     U_b = sum_p A_bp          (unweighted histogram)
+ *     I_b = W_b / U_b           (their ratio, the profile)
+ *
+ * where A is the pixel-to-bin coefficient matrix of Section 4.1, built once
+ * per geometry and applied per frame as a CSR sparse-matrix / dense-vector
+ * product in "gather" form (Section 5.2, 5.2.1).
+ *
+ * Conventions shared by every call:
+ *   - Return value: AZI_OK (0) on success, a negative AZI_E* code otherwise;
+ *     azi_last_error() then returns a message for the calling thread.  A
+ *     failed call leaves its outputs unspecified and its objects unchanged.
+ *   - "device" pointers are HIP device addresses on the plan's device;
+ *     "host" pointers are ordinary CPU memory.  The caller owns every data
+ *     buffer it passes; the library owns plans, batches and graphs (their
+ *     device matrices, tile schedules and work buffers) and frees them in
+ *     the matching *_destroy call.
+ *   - Images are row-major h x w (pixel id p = i*w + j).  Arrays of a plan's
+ *     storage type hold float (AZI_F32) or double (AZI_F64) values.
+ *   - Per-frame calls (azi_correct, azi_integrate1d*, azi_batch_forward,
+ *     azi_batch_backward, azi_graph_launch) enqueue work on the given HIP
+ *     stream (NULL = the null stream) and return without synchronising; they
+ *     allocate nothing, so they may be captured into a HIP graph.  They use
+ *     work buffers owned by the plan or batch: two calls on one plan or batch
+ *     that overlap in time (different streams) race on those buffers.
+ *   - Integer and index work is exact; floating-point sums are deterministic
+ *     run to run for a fixed tiling (no floating-point atomics).
+ */
+#ifndef AZINT_H
+#define AZINT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AZI_ABI_VERSION 1
+
+/* Error codes. */
+#define AZI_OK          0
+#define AZI_EINVAL     -1  /* bad argument: null pointer, size, enum, range  */
+#define AZI_ENOMEM     -2  /* host or device allocation failed              */
+#define AZI_EOVERFLOW  -3  /* a count does not fit int32 (nnz, pixels, bins) */
+#define AZI_EDEVICE    -4  /* HIP runtime error or no usable device          */
+#define AZI_ESTATE     -5  /* object not in the state the call needs         */
+
+/* Output coordinate (Section 3, coordinate list). */
+#define AZI_UNIT_R_M     0  /* radius in metres                     */
+#define AZI_UNIT_R_MM    1  /* radius in millimetres                */
+#define AZI_UNIT_2TH_RAD 2  /* scattering angle 2theta = atan(r/d)  */
+#define AZI_UNIT_2TH_DEG 3  /* the same in degrees                  */
+#define AZI_UNIT_Q_NM    4  /* q = 4 pi sin(2theta/2) / lambda, 1/nm */
+
+/* Pixel splitting (Section 3.3 histogram, Section 4.1 bounding box). */
+#define AZI_SPLIT_NONE 0
+#define AZI_SPLIT_BBOX 1
+
+/* Element types. */
+#define AZI_I16 0
+#define AZI_U16 1
+#define AZI_I32 2
+#define AZI_U32 3
+#define AZI_F32 4
+#define AZI_F64 5
+
+/* Accumulation of the per-bin sums (Section 5.2.2). */
+#define AZI_ACC_F64     0  /* double accumulators (any storage type)            */
+#define AZI_ACC_KAHAN32 1  /* float with Kahan compensation (AZI_F32 storage only) */
+
+/*
+ * Detector geometry: a planar detector orthogonal to the beam (Section 3).
+ * Pixel (i, j) covers [j, j+1] x [i, i+1] in pixel units; the beam centre
+ * is given in those units (column center_x_px, row center_y_px).  Pixel
+ * sizes, distance and wavelength are in metres.
+ */
+typedef struct azi_geom {
+    int32_t h, w;
+    double pixel_y_m, pixel_x_m;
+    double center_y_px, center_x_px;
+    double dist_m;
+    double wavelength_m;
+} azi_geom;
+
+typedef struct azi_plan azi_plan;
+typedef struct azi_batch azi_batch;
+typedef struct azi_graph azi_graph;
+
+/* Library ABI version (AZI_ABI_VERSION of the build). */
+int32_t azi_version(void);
+
+/* Message of the last failed call on this thread ("" if none).  The string
+ * stays valid until the next call on this thread. */
+const char* azi_last_error(void);
+
+/*
+ * Build the coefficient matrix of one geometry on the host (Section 4.1 for
+ * AZI_SPLIT_BBOX, Section 3.3 for AZI_SPLIT_NONE; Section 5.2 turns the
+ * per-pixel contributions into a per-bin gather).  For every pixel the
+ * radial extent [lo, hi] of the pixel square is mapped to the output unit;
+ * bins are npt uniform intervals over range2 = {min, max} (host, may be NULL
+ * for the data's own range: [min lo, max hi] with splitting, the range of
+ * pixel-centre values without); a box partly outside the range keeps only
+ * its inside share, normalised by its full width; the last bin is closed.
+ * dtype (AZI_F32 / AZI_F64) is the storage type of coefficients, images and
+ * outputs; accum one of AZI_ACC_*.  Nothing is placed on a device yet (see
+ * azi_plan_upload).  Errors: AZI_EINVAL (null geom/out, h or w < 1, npt < 1,
+ * non-positive pixel size/distance/wavelength, min >= max, bad enum,
+ * Kahan accumulation with AZI_F64), AZI_EOVERFLOW (pixels or nnz >= 2^31).
+ */
+int azi_plan_create(const azi_geom* geom, int32_t npt, int32_t unit, int32_t split,
+                    const double* range2, int32_t dtype, int32_t accum, azi_plan** out);
+
+/* Free a plan and its device memory.  NULL is accepted (no-op). */
+int azi_plan_destroy(azi_plan* plan);
+
+/* Sizes of a plan (host outputs, each may be NULL).  range2 receives the
+ * {min, max} actually used. */
+int azi_plan_info(const azi_plan* plan, int32_t* npt, int64_t* npix, int64_t* nnz,
+                  double* range2);
+
+/* Bin centres min + (b + 0.5) * (max - min) / npt, npt doubles (host). */
+int azi_plan_positions(const azi_plan* plan, double* positions);
+
+/* Copy the matrix out in CSR form (host buffers): data[nnz] of the storage
+ * type, indices[nnz] pixel ids ascending within a row, indptr[npt + 1]; the
+ * triple is accepted as-is by scipy.sparse.csr_matrix (Section 5.2.1). */
+int azi_plan_export_csr(const azi_plan* plan, void* data, int32_t* indices,
+                        int32_t* indptr);
+
+/* Copy the matrix out in pixel-major (CSC) form (host buffers): data[nnz],
+ * bins[nnz] ascending within a pixel, colptr[npix + 1]. */
+int azi_plan_export_csc(const azi_plan* plan, void* data, int32_t* bins, int32_t* colptr);
+
+/* Forward tile schedule (tuning; no effect on results beyond summation order):
+ * tile_nnz = most nonzeros one workgroup sums per tile (64..16384, multiple
+ * of 64), block = threads per workgroup (64, 128, 256, 512).  Takes effect
+ * at the next azi_plan_upload (or immediately if already uploaded; that call
+ * then synchronises the device). */
+int azi_plan_set_tiling(azi_plan* plan, int32_t tile_nnz, int32_t block);
+
+/* Host-side view of the forward tile schedule for a given tile_nnz (no
+ * device needed; for inspection and tests).  Each tile is 8 int32:
+ * {row_begin, row_end, nnz_begin, nnz_end, partial_slot (-1 = whole rows),
+ * rowptr_pos, 0, 0}; each split row 4 int32: {row, slot_begin, slot_end, 0}.
+ * Pass NULL arrays to query the counts first. */
+int azi_plan_tile_schedule(const azi_plan* plan, int32_t tile_nnz, int32_t* ntiles,
+                           int32_t* tiles, int32_t* nsplits, int32_t* splits);
+
+/* Place the plan on HIP device `device`: copies the CSR and CSC matrices,
+ * the tile schedule and allocates the plan's work buffers.  Synchronous.
+ * Errors: AZI_EDEVICE (no such device / HIP failure), AZI_ENOMEM. */
+int azi_plan_upload(azi_plan* plan, int32_t device);
+
+/* Device memory held by the plan, in bytes (0 before upload). */
+int64_t azi_plan_device_bytes(const azi_plan* plan);
+
+/*
+ * Per-pixel correction arrays of Section 6.4 (device pointers of the storage
+ * type, npix values each, or NULL for "absent").  The plan keeps a copy of
+ * dark and of norm = (flat * solid) * polar, formed once here, so the
+ * per-frame map is x = (raw - dark) / norm.  Passing all NULL removes the
+ * corrections.  Runs on `stream` and synchronises it.  Needs an uploaded plan.
+ */
+int azi_plan_set_corrections(azi_plan* plan, const void* dark, const void* flat,
+                             const void* solid, const void* polar, void* stream);
+
+/*
+ * Cast and correction map (Section 6.4): x[p] = (T(raw[p]) - dark[p]) / norm[p]
+ * for the npix pixels, in the storage type T, absent corrections acting as
+ * identity.  raw (device, raw_dtype one of AZI_I16..AZI_F64), x (device).
+ */
+int azi_correct(const azi_plan* plan, const void* raw, int32_t raw_dtype, void* x,
+                void* stream);
+
+/*
+ * Integrate one corrected image (Section 5.2.1): out_I, out_W, out_U (device,
+ * npt values of the storage type; out_W / out_U may be NULL) receive I, W, U;
+ * a bin with U == 0 gets I = empty.  x (device, npix values of the storage
+ * type) is the corrected image (azi_correct), or the raw image itself when no
+ * corrections apply.
+ */
+int azi_integrate1d(const azi_plan* plan, const void* x, void* out_I, void* out_W,
+                    void* out_U, double empty, void* stream);
+
+/*
+ * The whole per-frame pipeline of Section 6.4 on a raw image: cast and
+ * correction into the plan's work image, then azi_integrate1d.  raw is a
+ * device image of raw_dtype.  The work image stays valid until the next
+ * call on this plan (it is the x the backward pass needs).
+ */
+int azi_integrate1d_raw(const azi_plan* plan, const void* raw, int32_t raw_dtype,
+                        void* out_I, void* out_W, void* out_U, double empty,
+                        void* stream);
+
+/*
+ * Adjoint of azi_integrate1d.  Since dI_b/dx_p = A_bp / U_b and
+ * dW_b/dx_p = A_bp, the gradient with respect to the corrected image is
+ *     gx_p = sum_b A_bp (grad_I[b] / U[b] + grad_W[b])
+ * (an empty bin contributes nothing).  U (device, npt) is the forward's U
+ * output; grad_I, grad_W (device, npt) may each be NULL (zero).  If wrt_raw
+ * is nonzero and corrections are set, gx is further divided by norm, giving
+ * the gradient with respect to the raw counts.  grad_x (device, npix).
+ */
+int azi_integrate1d_backward(const azi_plan* plan, const void* U, const void* grad_I,
+                             const void* grad_W, void* grad_x, int32_t wrt_raw,
+                             void* stream);
+
+/*
+ * Batches: n uploaded plans of one storage type and accumulation mode are
+ * stacked into one block-diagonal matrix on `device` (Section 5.2.2 notes
+ * several detectors handled together).  Images, outputs and gradients of a
+ * batch are flat concatenations in plan order; azi_batch_info gives the
+ * offsets.  The batch copies the matrices; the plans may be destroyed after.
+ */
+int azi_batch_create(azi_plan* const* plans, int32_t n, int32_t device, azi_batch** out);
+int azi_batch_destroy(azi_batch* batch);
+
+/* Sizes and offsets (host outputs, each may be NULL): pix_off[n + 1] and
+ * bin_off[n + 1] are the start of every instance in the flat image and
+ * output arrays. */
+int azi_batch_info(const azi_batch* batch, int32_t* n, int64_t* npix, int64_t* npt,
+                   int64_t* nnz, int64_t* pix_off, int64_t* bin_off);
+
+/* Tile schedule of the batch (as azi_plan_set_tiling) and launch shape:
+ * grid = 0 launches one workgroup per tile; grid > 0 launches that many
+ * persistent workgroups that walk the tiles.  Synchronises the device. */
+int azi_batch_set_tiling(azi_batch* batch, int32_t tile_nnz, int32_t block, int32_t grid);
+
+/* Current tiling: tile_nnz, block, grid, number of tiles (each may be NULL). */
+int azi_batch_get_tiling(const azi_batch* batch, int32_t* tile_nnz, int32_t* block,
+                         int32_t* grid, int32_t* ntiles);
+
+/* Forward of every instance in one launch (plus one small fix-up launch for
+ * bins split across tiles): x, out_I, out_W, out_U as in azi_integrate1d,
+ * concatenated. */
+int azi_batch_forward(azi_batch* batch, const void* x, void* out_I, void* out_W,
+                      void* out_U, double empty, void* stream);
+
+/* The same result computed instance by instance with the single-plan kernels
+ * (one launch sequence per instance): the baseline the batch replaces. */
+int azi_batch_forward_loop(azi_batch* batch, const void* x, void* out_I, void* out_W,
+                           void* out_U, double empty, void* stream);
+
+/* Adjoint of azi_batch_forward (as azi_integrate1d_backward, wrt the
+ * corrected images), all instances in one launch sequence. */
+int azi_batch_backward(azi_batch* batch, const void* U, const void* grad_I,
+                       const void* grad_W, void* grad_x, void* stream);
+
+/*
+ * Autotuner: times every candidate (tile_nnz, block, grid) on the batch's own
+ * data with HIP events on `stream`, keeps the fastest (azi_batch_set_tiling)
+ * and writes a JSON report of all candidates into report (host, report_len
+ * bytes, may be NULL).  x, out_* are device buffers as for azi_batch_forward
+ * (their contents are overwritten).  Synchronous.
+ */
+int azi_batch_autotune(azi_batch* batch, const void* x, void* out_I, void* out_W,
+                       void* out_U, void* stream, char* report, int32_t report_len);
+
+/*
+ * Capture a batch's forward (and, when grad_I or grad_W is non-NULL, its
+ * backward right after, reading the U written by the forward) into a HIP
+ * graph bound to these device buffers.  Replays with azi_graph_launch.
+ */
+int azi_graph_create_batch(azi_batch* batch, const void* x, void* out_I, void* out_W,
+                           void* out_U, double empty, const void* grad_I,
+                           const void* grad_W, void* grad_x, void* stream,
+                           azi_graph** out);
+
+/* Capture one plan's raw-image pipeline (azi_integrate1d_raw) into a graph. */
+int azi_graph_create_plan(const azi_plan* plan, const void* raw, int32_t raw_dtype,
+                          void* out_I, void* out_W, void* out_U, double empty,
+                          void* stream, azi_graph** out);
+
+int azi_graph_launch(azi_graph* graph, void* stream);
+int azi_graph_destroy(azi_graph* graph);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AZINT_H */

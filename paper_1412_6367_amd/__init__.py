@@ -1,0 +1,463 @@
+"""azint: azimuthal integration on MI355X (gfx950) through a C-ABI HIP library.
+
+Python binding of ``include/azint.h``: argument marshalling only.  Every step
+of the per-frame path runs in the library's HIP kernels; PyTorch provides
+device memory and streams.  Importing the package does not need a GPU; the
+library itself must have been built (``__graft_entry__.build()`` or
+``python paper_1412_6367_amd/build.py``), otherwise the first call raises.
+
+Method: Kieffer & Ashiotis, "PyFAI: a Python library for high performance
+azimuthal integration on GPU" (EuroSciPy 2014) -- bounding-box pixel
+splitting (Section 4.1) applied as a CSR gather product (Section 5.2).
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+
+import numpy as np
+import torch
+
+__all__ = ["lib", "AzintError", "Plan", "Batch", "Graph", "Integrate1d", "integrate1d",
+           "autotune", "UNITS", "SPLITS"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libazint.so")
+
+UNITS = {"r_m": 0, "r_mm": 1, "2th_rad": 2, "2th_deg": 3, "q_nm": 4}
+SPLITS = {"none": 0, "bbox": 1}
+_DT = {torch.int16: 0, torch.int32: 2, torch.float32: 4, torch.float64: 5}
+for _name, _code in (("uint16", 1), ("uint32", 3)):
+    if hasattr(torch, _name):
+        _DT[getattr(torch, _name)] = _code
+_DT_NP = {np.dtype(np.int16): 0, np.dtype(np.uint16): 1, np.dtype(np.int32): 2,
+          np.dtype(np.uint32): 3, np.dtype(np.float32): 4, np.dtype(np.float64): 5}
+_STORAGE = {torch.float32: 4, torch.float64: 5}
+_ACCUM = {"f64": 0, "kahan32": 1}
+
+
+class AzintError(RuntimeError):
+    pass
+
+
+class _Geom(ctypes.Structure):
+    _fields_ = [("h", ctypes.c_int32), ("w", ctypes.c_int32),
+                ("pixel_y_m", ctypes.c_double), ("pixel_x_m", ctypes.c_double),
+                ("center_y_px", ctypes.c_double), ("center_x_px", ctypes.c_double),
+                ("dist_m", ctypes.c_double), ("wavelength_m", ctypes.c_double)]
+
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_D = ctypes.c_double
+_SIGS = {
+    "azi_version": (_I32, []),
+    "azi_last_error": (ctypes.c_char_p, []),
+    "azi_plan_create": (ctypes.c_int, [ctypes.POINTER(_Geom), _I32, _I32, _I32, _P, _I32, _I32,
+                                       ctypes.POINTER(_P)]),
+    "azi_plan_destroy": (ctypes.c_int, [_P]),
+    "azi_plan_info": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "azi_plan_positions": (ctypes.c_int, [_P, _P]),
+    "azi_plan_export_csr": (ctypes.c_int, [_P, _P, _P, _P]),
+    "azi_plan_export_csc": (ctypes.c_int, [_P, _P, _P, _P]),
+    "azi_plan_set_tiling": (ctypes.c_int, [_P, _I32, _I32]),
+    "azi_plan_tile_schedule": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P]),
+    "azi_plan_upload": (ctypes.c_int, [_P, _I32]),
+    "azi_plan_device_bytes": (_I64, [_P]),
+    "azi_plan_set_corrections": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "azi_correct": (ctypes.c_int, [_P, _P, _I32, _P, _P]),
+    "azi_integrate1d": (ctypes.c_int, [_P, _P, _P, _P, _P, _D, _P]),
+    "azi_integrate1d_raw": (ctypes.c_int, [_P, _P, _I32, _P, _P, _P, _D, _P]),
+    "azi_integrate1d_backward": (ctypes.c_int, [_P, _P, _P, _P, _P, _I32, _P]),
+    "azi_batch_create": (ctypes.c_int, [_P, _I32, _I32, ctypes.POINTER(_P)]),
+    "azi_batch_destroy": (ctypes.c_int, [_P]),
+    "azi_batch_info": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    "azi_batch_set_tiling": (ctypes.c_int, [_P, _I32, _I32, _I32]),
+    "azi_batch_get_tiling": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "azi_batch_forward": (ctypes.c_int, [_P, _P, _P, _P, _P, _D, _P]),
+    "azi_batch_forward_loop": (ctypes.c_int, [_P, _P, _P, _P, _P, _D, _P]),
+    "azi_batch_backward": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "azi_batch_autotune": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, ctypes.c_char_p, _I32]),
+    "azi_graph_create_batch": (ctypes.c_int, [_P, _P, _P, _P, _P, _D, _P, _P, _P, _P,
+                                              ctypes.POINTER(_P)]),
+    "azi_graph_create_plan": (ctypes.c_int, [_P, _P, _I32, _P, _P, _P, _D, _P,
+                                             ctypes.POINTER(_P)]),
+    "azi_graph_launch": (ctypes.c_int, [_P, _P]),
+    "azi_graph_destroy": (ctypes.c_int, [_P]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded C-ABI library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise AzintError(f"{LIB_PATH} is missing: build it first "
+                             "(python -c 'import __graft_entry__ as g; g.build()')")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        msg = lib().azi_last_error().decode(errors="replace")
+        raise AzintError(f"azint error {rc}: {msg}")
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _need(t, dtype, n, device, name):
+    if t is None:
+        return
+    if not isinstance(t, torch.Tensor) or t.device != device:
+        raise AzintError(f"{name} must be a tensor on {device}")
+    if dtype is not None and t.dtype != dtype:
+        raise AzintError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous() or t.numel() != n:
+        raise AzintError(f"{name} must be contiguous with {n} elements, got {tuple(t.shape)}")
+
+
+class Plan:
+    """Coefficient matrix of one detector geometry (Sections 3, 4.1, 5.2.1).
+
+    ``pixel`` is a size in metres or a (y, x) pair; ``center`` the beam centre
+    (row, column) in pixel units (default: the middle of the detector).
+    """
+
+    def __init__(self, h, w, npt, *, pixel=1e-4, center=None, dist=0.1, wavelength=1e-10,
+                 unit="r_m", split="bbox", range=None, dtype=torch.float64, accum="f64",
+                 device=None, tile_nnz=None, block=None):
+        py, px = (pixel, pixel) if np.isscalar(pixel) else pixel
+        cy, cx = (h / 2.0, w / 2.0) if center is None else center
+        self.h, self.w, self.npt = int(h), int(w), int(npt)
+        self.dtype = dtype
+        self.accum = accum
+        self._h = None
+        g = _Geom(int(h), int(w), float(py), float(px), float(cy), float(cx), float(dist),
+                  float(wavelength))
+        rng = None if range is None else (ctypes.c_double * 2)(float(range[0]), float(range[1]))
+        out = ctypes.c_void_p()
+        _check(lib().azi_plan_create(ctypes.byref(g), int(npt), UNITS[unit], SPLITS[split],
+                                     ctypes.cast(rng, ctypes.c_void_p) if rng else None,
+                                     _STORAGE[dtype], _ACCUM[accum], ctypes.byref(out)))
+        self._h = out
+        self.device = None
+        if tile_nnz is not None or block is not None:
+            self.set_tiling(tile_nnz or 2048, block or 256)
+        if device is not None:
+            self.upload(device)
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.azi_plan_destroy(self._h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        npt, npix, nnz = _I32(), _I64(), _I64()
+        rng = (ctypes.c_double * 2)()
+        _check(lib().azi_plan_info(self._h, ctypes.byref(npt), ctypes.byref(npix),
+                                   ctypes.byref(nnz), ctypes.cast(rng, ctypes.c_void_p)))
+        return dict(npt=npt.value, npix=npix.value, nnz=nnz.value, range=(rng[0], rng[1]))
+
+    @property
+    def npix(self):
+        return self.h * self.w
+
+    @property
+    def nnz(self):
+        return self.info()["nnz"]
+
+    def positions(self):
+        out = np.empty(self.npt, dtype=np.float64)
+        _check(lib().azi_plan_positions(self._h, out.ctypes.data))
+        return out
+
+    def _np_dtype(self):
+        return np.float64 if self.dtype == torch.float64 else np.float32
+
+    def export_csr(self):
+        nnz = self.nnz
+        data = np.empty(nnz, dtype=self._np_dtype())
+        indices = np.empty(nnz, dtype=np.int32)
+        indptr = np.empty(self.npt + 1, dtype=np.int32)
+        _check(lib().azi_plan_export_csr(self._h, data.ctypes.data, indices.ctypes.data,
+                                         indptr.ctypes.data))
+        return data, indices, indptr
+
+    def export_csc(self):
+        nnz = self.nnz
+        data = np.empty(nnz, dtype=self._np_dtype())
+        bins = np.empty(nnz, dtype=np.int32)
+        colptr = np.empty(self.npix + 1, dtype=np.int32)
+        _check(lib().azi_plan_export_csc(self._h, data.ctypes.data, bins.ctypes.data,
+                                         colptr.ctypes.data))
+        return data, bins, colptr
+
+    def set_tiling(self, tile_nnz, block=256):
+        _check(lib().azi_plan_set_tiling(self._h, int(tile_nnz), int(block)))
+
+    def tile_schedule(self, tile_nnz=2048):
+        nt, ns = _I32(), _I32()
+        _check(lib().azi_plan_tile_schedule(self._h, int(tile_nnz), ctypes.byref(nt), None,
+                                            ctypes.byref(ns), None))
+        tiles = np.zeros((nt.value, 8), dtype=np.int32)
+        splits = np.zeros((ns.value, 4), dtype=np.int32)
+        _check(lib().azi_plan_tile_schedule(self._h, int(tile_nnz), ctypes.byref(nt),
+                                            tiles.ctypes.data, ctypes.byref(ns),
+                                            splits.ctypes.data))
+        return tiles, splits
+
+    def upload(self, device=None):
+        device = torch.device("cuda", torch.cuda.current_device()) if device is None \
+            else torch.device(device)
+        if device.type != "cuda":
+            raise AzintError("plans live on a GPU")
+        idx = device.index if device.index is not None else torch.cuda.current_device()
+        _check(lib().azi_plan_upload(self._h, idx))
+        self.device = torch.device("cuda", idx)
+        return self
+
+    def device_bytes(self):
+        return int(lib().azi_plan_device_bytes(self._h))
+
+    def set_corrections(self, dark=None, flat=None, solid=None, polar=None, stream=None):
+        for name, t in (("dark", dark), ("flat", flat), ("solid", solid), ("polar", polar)):
+            _need(t, self.dtype, self.npix, self.device, name)
+        _check(lib().azi_plan_set_corrections(self._h, _ptr(dark), _ptr(flat), _ptr(solid),
+                                              _ptr(polar), _stream(stream)))
+
+    def _raw_code(self, raw):
+        code = _DT.get(raw.dtype)
+        if code is None:
+            raise AzintError(f"unsupported raw dtype {raw.dtype}")
+        return code
+
+    def correct(self, raw, out=None, stream=None):
+        _need(raw, None, self.npix, self.device, "raw")
+        out = torch.empty(self.npix, dtype=self.dtype, device=self.device) if out is None else out
+        _need(out, self.dtype, self.npix, self.device, "x")
+        _check(lib().azi_correct(self._h, _ptr(raw), self._raw_code(raw), _ptr(out),
+                                 _stream(stream)))
+        return out
+
+    def _outs(self, out):
+        if out is None:
+            return tuple(torch.empty(self.npt, dtype=self.dtype, device=self.device)
+                         for _ in range(3))
+        for t in out:
+            _need(t, self.dtype, self.npt, self.device, "output")
+        return out
+
+    def integrate(self, x, *, empty=0.0, out=None, stream=None):
+        """(I, W, U) of a corrected image x (storage dtype, npix values)."""
+        _need(x, self.dtype, self.npix, self.device, "x")
+        I, W, U = self._outs(out)
+        _check(lib().azi_integrate1d(self._h, _ptr(x), _ptr(I), _ptr(W), _ptr(U),
+                                     float(empty), _stream(stream)))
+        return I, W, U
+
+    def integrate_raw(self, raw, *, empty=0.0, out=None, stream=None):
+        """Cast + correction + integration of a raw image (Section 6.4)."""
+        _need(raw, None, self.npix, self.device, "raw")
+        I, W, U = self._outs(out)
+        _check(lib().azi_integrate1d_raw(self._h, _ptr(raw), self._raw_code(raw), _ptr(I),
+                                         _ptr(W), _ptr(U), float(empty), _stream(stream)))
+        return I, W, U
+
+    def backward(self, U, grad_I=None, grad_W=None, *, wrt_raw=False, out=None, stream=None):
+        for name, t in (("U", U), ("grad_I", grad_I), ("grad_W", grad_W)):
+            _need(t, self.dtype, self.npt, self.device, name)
+        gx = torch.empty(self.npix, dtype=self.dtype, device=self.device) if out is None else out
+        _need(gx, self.dtype, self.npix, self.device, "grad_x")
+        _check(lib().azi_integrate1d_backward(self._h, _ptr(U), _ptr(grad_I), _ptr(grad_W),
+                                              _ptr(gx), int(bool(wrt_raw)), _stream(stream)))
+        return gx
+
+    def graph(self, raw, I, W=None, U=None, *, empty=0.0, stream=None):
+        out = ctypes.c_void_p()
+        _check(lib().azi_graph_create_plan(self._h, _ptr(raw), self._raw_code(raw), _ptr(I),
+                                           _ptr(W), _ptr(U), float(empty), _stream(stream),
+                                           ctypes.byref(out)))
+        return Graph(out, keep=(raw, I, W, U))
+
+
+class Integrate1d(torch.autograd.Function):
+    """I = W / U of a corrected image, differentiable with respect to it.
+
+    forward(x, plan, empty) -> (I, W); backward uses the library's adjoint
+    kernel: gx = A^T (gI / U + gW).
+    """
+
+    @staticmethod
+    def forward(ctx, x, plan, empty=0.0):
+        I, W, U = plan.integrate(x.contiguous(), empty=empty)
+        ctx.plan = plan
+        ctx.save_for_backward(U)
+        ctx.mark_non_differentiable(U)
+        return I, W, U
+
+    @staticmethod
+    def backward(ctx, gI, gW, gU):
+        (U,) = ctx.saved_tensors
+        gI = None if gI is None else gI.contiguous()
+        gW = None if gW is None else gW.contiguous()
+        gx = ctx.plan.backward(U, gI, gW)
+        return gx, None, None
+
+
+def integrate1d(image, plan, *, empty=0.0):
+    """(positions, I) as the paper's ``integrate1d`` returns (Section 3)."""
+    x = image.reshape(-1)
+    if x.dtype == plan.dtype:
+        I, _, _ = plan.integrate(x.contiguous(), empty=empty)
+    else:
+        I, _, _ = plan.integrate_raw(x.contiguous(), empty=empty)
+    return plan.positions(), I
+
+
+class Graph:
+    """A captured HIP graph bound to fixed device buffers."""
+
+    def __init__(self, handle, keep=()):
+        self._h = handle
+        self._keep = keep
+
+    def launch(self, stream=None):
+        _check(lib().azi_graph_launch(self._h, _stream(stream)))
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.azi_graph_destroy(self._h)
+            self._h = None
+
+
+class Batch:
+    """Many plans stacked into one block-diagonal matrix (one launch per pass)."""
+
+    def __init__(self, plans, device=None):
+        if not plans:
+            raise AzintError("empty batch")
+        self.dtype = plans[0].dtype
+        device = torch.device("cuda", torch.cuda.current_device()) if device is None \
+            else torch.device(device)
+        idx = device.index if device.index is not None else torch.cuda.current_device()
+        arr = (ctypes.c_void_p * len(plans))(*[p.handle for p in plans])
+        out = ctypes.c_void_p()
+        self._h = None
+        _check(lib().azi_batch_create(arr, len(plans), idx, ctypes.byref(out)))
+        self._h = out
+        self.device = torch.device("cuda", idx)
+        n = len(plans)
+        self.n = n
+        npix, npt, nnz = _I64(), _I64(), _I64()
+        self.pix_off = np.zeros(n + 1, dtype=np.int64)
+        self.bin_off = np.zeros(n + 1, dtype=np.int64)
+        _check(lib().azi_batch_info(self._h, None, ctypes.byref(npix), ctypes.byref(npt),
+                                    ctypes.byref(nnz), self.pix_off.ctypes.data,
+                                    self.bin_off.ctypes.data))
+        self.npix, self.npt, self.nnz = npix.value, npt.value, nnz.value
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.azi_batch_destroy(self._h)
+            self._h = None
+
+    def set_tiling(self, tile_nnz, block=256, grid=0):
+        _check(lib().azi_batch_set_tiling(self._h, int(tile_nnz), int(block), int(grid)))
+
+    def tiling(self):
+        t, b, g, n = _I32(), _I32(), _I32(), _I32()
+        _check(lib().azi_batch_get_tiling(self._h, ctypes.byref(t), ctypes.byref(b),
+                                          ctypes.byref(g), ctypes.byref(n)))
+        return dict(tile_nnz=t.value, block=b.value, grid=g.value, ntiles=n.value)
+
+    def _outs(self, out):
+        if out is None:
+            return tuple(torch.empty(self.npt, dtype=self.dtype, device=self.device)
+                         for _ in range(3))
+        for t in out:
+            _need(t, self.dtype, self.npt, self.device, "output")
+        return out
+
+    def forward(self, x, *, empty=0.0, out=None, stream=None, loop=False):
+        _need(x, self.dtype, self.npix, self.device, "x")
+        I, W, U = self._outs(out)
+        f = lib().azi_batch_forward_loop if loop else lib().azi_batch_forward
+        _check(f(self._h, _ptr(x), _ptr(I), _ptr(W), _ptr(U), float(empty), _stream(stream)))
+        return I, W, U
+
+    def backward(self, U, grad_I=None, grad_W=None, *, out=None, stream=None):
+        for name, t in (("U", U), ("grad_I", grad_I), ("grad_W", grad_W)):
+            _need(t, self.dtype, self.npt, self.device, name)
+        gx = torch.empty(self.npix, dtype=self.dtype, device=self.device) if out is None else out
+        _need(gx, self.dtype, self.npix, self.device, "grad_x")
+        _check(lib().azi_batch_backward(self._h, _ptr(U), _ptr(grad_I), _ptr(grad_W),
+                                        _ptr(gx), _stream(stream)))
+        return gx
+
+    def graph(self, x, I, W=None, U=None, *, empty=0.0, grad_I=None, grad_W=None,
+              grad_x=None, stream=None):
+        out = ctypes.c_void_p()
+        _check(lib().azi_graph_create_batch(self._h, _ptr(x), _ptr(I), _ptr(W), _ptr(U),
+                                            float(empty), _ptr(grad_I), _ptr(grad_W),
+                                            _ptr(grad_x), _stream(stream), ctypes.byref(out)))
+        return Graph(out, keep=(x, I, W, U, grad_I, grad_W, grad_x))
+
+    def autotune(self, x, *, stream=None):
+        I, W, U = self._outs(None)
+        buf = ctypes.create_string_buffer(1 << 16)
+        _check(lib().azi_batch_autotune(self._h, _ptr(x), _ptr(I), _ptr(W), _ptr(U),
+                                        _stream(stream), buf, len(buf)))
+        return json.loads(buf.value.decode())
+
+
+def _signature(batch):
+    """Cache key of a batch: device, storage type, sizes."""
+    name = torch.cuda.get_device_properties(batch.device).gcnArchName \
+        if torch.cuda.is_available() else "cpu"
+    return f"{name}|{batch.dtype}|n={batch.n}|npix={batch.npix}|nnz={batch.nnz}"
+
+
+def autotune(batch, x, cache_path=None):
+    """Choose the batch's tiling: reuse a cached choice for the same signature,
+    else sweep on the batch's own data and record the result in the cache."""
+    key = _signature(batch)
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as f:
+            cache = json.load(f)
+    if key in cache:
+        best = cache[key]["best"]
+        batch.set_tiling(best["tile_nnz"], best["block"], best["grid"])
+        return cache[key]
+    report = batch.autotune(x)
+    if cache_path:
+        cache[key] = report
+        with open(cache_path, "w") as f:
+            json.dump(cache, f, indent=1)
+    return report

@@ -1,0 +1,198 @@
+"""C-ABI library on the CPU: exports, host plan builder vs the oracle, tile
+schedule, argument errors.  No kernel runs here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from tests.helpers import ROOT, azint, oracle_matrix
+
+HEADER = os.path.join(ROOT, "include", "azint.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(azi_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    az = azint()
+    L = ctypes.CDLL(az.LIB_PATH)
+    names = declared_symbols()
+    assert len(names) >= 30
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    # the Python binding declares a signature for every one of them
+    assert set(names) == set(az._SIGS), set(names) ^ set(az._SIGS)
+    assert az.lib().azi_version() == 1
+
+
+GEOMS = [
+    # h, w, center_y, center_x, npt, pixel(y, x), unit, split, range
+    (100, 100, 50.0, 50.0, 100, (1e-4, 1e-4), "r_m", "bbox", None),
+    (37, 53, 10.25, 40.5, 61, (1e-4, 1e-4), "r_m", "bbox", None),
+    (64, 48, -5.0, 70.0, 40, (1.5e-4, 1e-4), "r_m", "bbox", None),
+    (31, 29, 15.5, 14.5, 300, (1e-4, 1e-4), "r_m", "bbox", None),    # bins finer than pixels
+    (45, 45, 22.5, 22.5, 7, (1e-4, 1e-4), "r_m", "bbox", None),      # wide bins
+    (50, 60, 25.0, 30.0, 37, (1e-4, 1e-4), "r_m", "bbox", (5e-4, 2.5e-3)),  # clipped range
+    (50, 60, 25.3, 30.7, 37, (1e-4, 1e-4), "r_m", "none", None),
+    (33, 20, 3.0, 2.0, 25, (1e-4, 1e-4), "r_mm", "bbox", None),
+    (1, 1, 0.5, 0.5, 4, (1e-4, 1e-4), "r_m", "bbox", None),          # one pixel
+    (1, 17, 0.5, 8.5, 5, (1e-4, 1e-4), "r_m", "bbox", None),         # one row
+]
+
+
+@pytest.mark.parametrize("g", GEOMS, ids=lambda g: f"{g[0]}x{g[1]}-{g[6]}-{g[7]}-{g[4]}")
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_plan_matrix_bit_exact_vs_oracle(g, dtype):
+    h, w, cy, cx, npt, (py, px), unit, split, rng = g
+    az = azint()
+    plan = az.Plan(h, w, npt, pixel=(py, px), center=(cy, cx), unit=unit, split=split,
+                   range=rng, dtype=dtype)
+    m = oracle_matrix(h, w, cy, cx, npt, py, px, unit, split, rng)
+    info = plan.info()
+    assert info["npt"] == npt and info["npix"] == h * w and info["nnz"] == m["data"].size
+    assert info["range"] == (m["pmin"], m["pmax"])
+    data, indices, indptr = plan.export_csr()
+    assert np.array_equal(indptr, m["indptr"])
+    assert np.array_equal(indices, m["indices"])
+    ref = m["data"] if dtype == torch.float64 else m["data"].astype(np.float32)
+    assert np.array_equal(data, ref)
+    cdata, bins, colptr = plan.export_csc()
+    order = np.lexsort((m["bins"], m["pix"]))
+    assert np.array_equal(bins, m["bins"][order])
+    assert np.array_equal(cdata, m["coef"][order].astype(data.dtype))
+    assert np.array_equal(colptr, np.r_[0, np.cumsum(np.bincount(m["pix"], minlength=h * w))])
+    assert np.array_equal(plan.positions(), oracle.positions(npt, m["pmin"], m["pmax"]))
+
+
+@pytest.mark.parametrize("unit", ["2th_deg", "2th_rad", "q_nm"])
+def test_transcendental_units_match_up_to_edges(unit):
+    """With atan/sin the host libm and numpy may round a value 1 ulp apart;
+    then a pixel edge lying on a bin edge may move by one bin.  Everything
+    else matches exactly."""
+    az = azint()
+    h, w, npt = 80, 70, 90
+    plan = az.Plan(h, w, npt, center=(40.0, 35.0), unit=unit)
+    m = oracle_matrix(h, w, 40.0, 35.0, npt, 1e-4, 1e-4, unit, "bbox", None)
+    lo_r, hi_r = plan.info()["range"]
+    assert abs(lo_r - m["pmin"]) <= 2 * np.spacing(abs(m["pmin"]) + 1e-300)
+    assert abs(hi_r - m["pmax"]) <= 2 * np.spacing(m["pmax"])
+    data, indices, indptr = plan.export_csr()
+    import scipy.sparse as sp
+    A = sp.csr_matrix((data, indices, indptr), shape=(npt, h * w)).toarray()
+    B = sp.csr_matrix((m["data"], m["indices"], m["indptr"]), shape=(npt, h * w)).toarray()
+    assert np.abs(A - B).max() <= 1e-9
+
+
+def test_tile_schedule_covers_every_nonzero_once():
+    az = azint()
+    plan = az.Plan(300, 280, 250, center=(150.2, 139.7))
+    _, _, indptr = plan.export_csr()
+    nnz = int(indptr[-1])
+    for tile_nnz in (64, 256, 1024, 2048, 8192):
+        tiles, splits = plan.tile_schedule(tile_nnz)
+        covered = np.zeros(nnz, dtype=np.int64)
+        rows = np.zeros(plan.npt, dtype=np.int64)
+        parts = set()
+        for r0, r1, z0, z1, part, ip0, _, _ in tiles:
+            assert r1 > r0 and z1 >= z0
+            # whole rows fit; a piece of a long row may gain up to 3 from the
+            # alignment of its cut to a multiple of 4
+            assert z1 - z0 <= tile_nnz + (3 if part >= 0 else 0)
+            covered[z0:z1] += 1
+            if part < 0:
+                rows[r0:r1] += 1
+                assert z0 == indptr[r0] and z1 == indptr[r1] and ip0 == r0
+            else:
+                assert r1 == r0 + 1 and part not in parts
+                parts.add(part)
+        for row, p0, p1, _ in splits:
+            rows[row] += 1
+            assert p1 - p0 >= 2
+            pieces = tiles[(tiles[:, 4] >= p0) & (tiles[:, 4] < p1)]
+            assert np.array_equal(pieces[:, 4], np.arange(p0, p1))
+            assert pieces[0, 2] == indptr[row] and pieces[-1, 3] == indptr[row + 1]
+            assert np.all(pieces[1:, 2] == pieces[:-1, 3])
+            assert np.all(pieces[1:, 2] % 4 == 0)
+        assert np.all(covered == 1)
+        assert np.all(rows == 1)
+        assert parts == set(range(len(parts)))
+
+
+def _err(rc):
+    return rc, azint().lib().azi_last_error().decode()
+
+
+def test_argument_errors():
+    az = azint()
+    L = az.lib()
+    g = az._Geom(10, 10, 1e-4, 1e-4, 5.0, 5.0, 0.1, 1e-10)
+    out = ctypes.c_void_p()
+    cases = [
+        (dict(npt=0), -1, "npt"),
+        (dict(unit=9), -1, "unit"),
+        (dict(split=7), -1, "split"),
+        (dict(dtype=2), -1, "dtype"),
+        (dict(accum=1, dtype=5), -1, "Kahan"),
+    ]
+    for kw, code, word in cases:
+        a = dict(npt=10, unit=0, split=1, dtype=5, accum=0)
+        a.update(kw)
+        rc, msg = _err(L.azi_plan_create(ctypes.byref(g), a["npt"], a["unit"], a["split"], None,
+                                         a["dtype"], a["accum"], ctypes.byref(out)))
+        assert rc == code and word in msg, (kw, rc, msg)
+    rc, msg = _err(L.azi_plan_create(None, 10, 0, 1, None, 5, 0, ctypes.byref(out)))
+    assert rc == -1
+    bad = az._Geom(10, 0, 1e-4, 1e-4, 5.0, 5.0, 0.1, 1e-10)
+    assert _err(L.azi_plan_create(ctypes.byref(bad), 10, 0, 1, None, 5, 0, ctypes.byref(out)))[0] == -1
+    neg = az._Geom(10, 10, -1e-4, 1e-4, 5.0, 5.0, 0.1, 1e-10)
+    assert _err(L.azi_plan_create(ctypes.byref(neg), 10, 0, 1, None, 5, 0, ctypes.byref(out)))[0] == -1
+    rng = (ctypes.c_double * 2)(2.0, 1.0)
+    assert _err(L.azi_plan_create(ctypes.byref(g), 10, 0, 1, ctypes.cast(rng, ctypes.c_void_p),
+                                  5, 0, ctypes.byref(out)))[0] == -1
+    # a range that holds no pixel is valid and gives an empty matrix
+    far = (ctypes.c_double * 2)(1.0, 2.0)
+    assert L.azi_plan_create(ctypes.byref(g), 10, 0, 1, ctypes.cast(far, ctypes.c_void_p), 5, 0,
+                             ctypes.byref(out)) == 0
+    nnz = ctypes.c_int64()
+    assert L.azi_plan_info(out, None, None, ctypes.byref(nnz), None) == 0 and nnz.value == 0
+    assert L.azi_plan_destroy(out) == 0
+    assert L.azi_plan_destroy(None) == 0
+    # per-frame calls on a plan that is not on a device
+    plan = az.Plan(10, 10, 10)
+    rc, msg = _err(L.azi_integrate1d(plan.handle, ctypes.c_void_p(16), ctypes.c_void_p(16),
+                                     None, None, 0.0, None))
+    assert rc == -5 and "azi_plan_upload" in msg
+    assert _err(L.azi_plan_set_tiling(plan.handle, 100, 256))[0] == -1
+    assert _err(L.azi_plan_set_tiling(plan.handle, 1024, 96))[0] == -1
+    assert L.azi_plan_set_tiling(plan.handle, 1024, 128) == 0
+    assert _err(L.azi_batch_create(None, 1, 0, ctypes.byref(out)))[0] == -1
+
+
+@pytest.mark.skipif(torch.cuda.is_available(), reason="checks the no-GPU error path")
+def test_upload_without_gpu_fails_cleanly():
+    az = azint()
+    plan = az.Plan(10, 10, 10)
+    rc, msg = _err(az.lib().azi_plan_upload(plan.handle, 0))
+    assert rc == -4 and "device" in msg
+
+
+def test_integration_on_cpu_via_exported_matrix_matches_oracle():
+    """The exported CSR is what the kernels stream: scipy's product with it
+    reproduces the oracle's W and U (Section 5.2.1 compatibility)."""
+    import scipy.sparse as sp
+    az = azint()
+    plan = az.Plan(120, 90, 110, center=(60.1, 44.8))
+    data, indices, indptr = plan.export_csr()
+    A = sp.csr_matrix((data, indices, indptr), shape=(110, 120 * 90))
+    x = np.random.default_rng(0).uniform(0, 100, size=120 * 90)
+    m = oracle_matrix(120, 90, 60.1, 44.8, 110, 1e-4, 1e-4, "r_m", "bbox", None)
+    I, W, U = oracle.integrate(m, x)
+    assert np.allclose(A @ x, W, rtol=1e-13, atol=0)
+    assert np.allclose(np.asarray(A.sum(1)).ravel(), U, rtol=1e-13, atol=0)

@@ -1,0 +1,214 @@
+"""Batched (block-diagonal, one launch) forward and adjoint on the GPU."""
+import json
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.helpers import azint, norm_err, oracle_matrix
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def make_batch(insts, dtype, dev, tile=None):
+    az = azint()
+    plans = []
+    for inst in insts:
+        g = inst.geom
+        p = az.Plan(g.h, g.w, inst.npt, center=(g.center_y, g.center_x), dtype=dtype)
+        if tile:
+            p.set_tiling(*tile)
+        plans.append(p)
+    return plans, az.Batch(plans, device=dev)
+
+
+def flat_images(insts, dtype):
+    return np.concatenate([i.raw.reshape(-1) for i in insts]).astype(dtype)
+
+
+def small_batch(n=40, seed=21):
+    return synth.batch(n, 1.0, 2e4, seed, grad=True)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_batch_equals_per_instance_and_oracle(dtype, dev):
+    say("batch vs per instance", dtype)
+    az = azint()
+    insts = small_batch()
+    plans, batch = make_batch(insts, dtype, dev)
+    npd = np.float64 if dtype == torch.float64 else np.float32
+    x = torch.from_numpy(flat_images(insts, npd)).to(dev)
+    I, W, U = batch.forward(x, empty=-3.0)
+    Il, Wl, Ul = batch.forward(x, empty=-3.0, loop=True)
+    torch.cuda.synchronize()
+    # identical tiles per instance -> identical bits
+    assert torch.equal(I, Il) and torch.equal(W, Wl) and torch.equal(U, Ul)
+    po, bo = batch.pix_off, batch.bin_off
+    for k, (inst, plan) in enumerate(zip(insts, plans)):
+        plan.upload(dev)
+        xs = x[po[k]:po[k + 1]].contiguous()
+        Ik, Wk, Uk = plan.integrate(xs, empty=-3.0)
+        assert torch.equal(Ik, I[bo[k]:bo[k + 1]]), k
+        assert torch.equal(Uk, U[bo[k]:bo[k + 1]]), k
+        g = inst.geom
+        m = oracle_matrix(g.h, g.w, g.center_y, g.center_x, inst.npt)
+        xv = inst.raw.reshape(-1).astype(np.float64)
+        if dtype == torch.float32:
+            m["coef"] = m["coef"].astype(np.float32).astype(np.float64)
+        Io, Wo, Uo = oracle.integrate(m, xv, empty=-3.0)
+        _, Wa, _ = oracle.integrate(m, np.abs(xv))
+        tol = 1e-12 if dtype == torch.float64 else 2.0 ** -22
+        Ig = I[bo[k]:bo[k + 1]].double().cpu().numpy()
+        Wg = W[bo[k]:bo[k + 1]].double().cpu().numpy()
+        assert norm_err(Wg, Wo, Wa) <= tol, k
+        sI = np.where(Uo > 0, Wa / np.where(Uo > 0, Uo, 1.0), 0.0)
+        assert norm_err(Ig, Io, sI) <= tol, k
+
+
+@pytest.mark.parametrize("grid", [8, 64, 1024, 0])
+@pytest.mark.parametrize("tiling", [(2048, 256), (256, 64), (8192, 512)])
+def test_persistent_grid_same_bits(grid, tiling, dev):
+    """The tile sums do not depend on which workgroup computes a tile."""
+    say("persistent", grid, tiling)
+    insts = small_batch(30, 5)
+    _, batch = make_batch(insts, torch.float64, dev)
+    x = torch.from_numpy(flat_images(insts, np.float64)).to(dev)
+    batch.set_tiling(tiling[0], tiling[1], 0)
+    ref = batch.forward(x)
+    batch.set_tiling(tiling[0], tiling[1], grid)
+    got = batch.forward(x)
+    torch.cuda.synchronize()
+    for a, b in zip(ref, got):
+        assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_batch_backward(dtype, dev):
+    say("batch backward", dtype)
+    insts = small_batch(25, 9)
+    plans, batch = make_batch(insts, dtype, dev)
+    npd = np.float64 if dtype == torch.float64 else np.float32
+    x = torch.from_numpy(flat_images(insts, npd)).to(dev)
+    gI = torch.from_numpy(np.concatenate([i.grad for i in insts]).astype(npd)).to(dev)
+    I, W, U = batch.forward(x)
+    gx = batch.backward(U, gI)
+    torch.cuda.synchronize()
+    po, bo = batch.pix_off, batch.bin_off
+    for k, plan in enumerate(plans):
+        plan.upload(dev)
+        gk = plan.backward(U[bo[k]:bo[k + 1]].contiguous(), gI[bo[k]:bo[k + 1]].contiguous())
+        assert torch.equal(gk, gx[po[k]:po[k + 1]]), k
+        inst = insts[k]
+        g = inst.geom
+        m = oracle_matrix(g.h, g.w, g.center_y, g.center_x, inst.npt)
+        if dtype == torch.float32:
+            m["coef"] = m["coef"].astype(np.float32).astype(np.float64)
+        Uk = U[bo[k]:bo[k + 1]].double().cpu().numpy()
+        gik = inst.grad.astype(npd).astype(np.float64)
+        ref = oracle.integrate_vjp(m, Uk, gik)
+        scale = oracle.integrate_vjp(m, Uk, np.abs(gik))
+        tol = 1e-12 if dtype == torch.float64 else 2.0 ** -22
+        assert norm_err(gx[po[k]:po[k + 1]].double().cpu().numpy(), ref, scale) <= tol, k
+
+
+def test_graph_replays_match_eager(dev):
+    """A captured forward+backward replays the same bits every time, with
+    eager work and synchronisations in between."""
+    say("graph replay")
+    insts = small_batch(20, 13)
+    _, batch = make_batch(insts, torch.float64, dev)
+    batch.set_tiling(1024, 256, 512)
+    x = torch.from_numpy(flat_images(insts, np.float64)).to(dev)
+    gI = torch.from_numpy(np.concatenate([i.grad for i in insts])).to(dev)
+    I0, W0, U0 = batch.forward(x)
+    gx0 = batch.backward(U0, gI)
+    I, W, U = (torch.full_like(I0, np.nan) for _ in range(3))
+    gx = torch.full_like(gx0, np.nan)
+    graph = batch.graph(x, I, W, U, grad_I=gI, grad_x=gx)
+    for rep in range(4):
+        for t in (I, W, U, gx):
+            t.fill_(np.nan)
+        graph.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(I, I0) and torch.equal(W, W0) and torch.equal(U, U0), rep
+        assert torch.equal(gx, gx0), rep
+        _ = (x * 2).sum().item()   # unrelated eager work between replays
+
+
+def test_plan_graph(dev):
+    say("plan graph")
+    az = azint()
+    inst = synth.instance(20000, 3)
+    g = inst.geom
+    plan = az.Plan(g.h, g.w, inst.npt, device=dev)
+    raw = torch.from_numpy(inst.raw.reshape(-1)).to(dev)
+    I0, W0, U0 = plan.integrate_raw(raw)
+    I, W, U = (torch.empty_like(I0) for _ in range(3))
+    graph = plan.graph(raw, I, W, U)
+    for _ in range(3):
+        I.zero_()
+        graph.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(I, I0) and torch.equal(W, W0) and torch.equal(U, U0)
+
+
+def test_autotune_picks_valid_config(dev, tmp_path):
+    say("autotune")
+    az = azint()
+    insts = small_batch(60, 17)
+    _, batch = make_batch(insts, torch.float64, dev)
+    x = torch.from_numpy(flat_images(insts, np.float64)).to(dev)
+    ref = [t.clone() for t in batch.forward(x)]
+    cache = tmp_path / "tune.json"
+    rep = az.autotune(batch, x, cache_path=str(cache))
+    best = rep["best"]
+    assert batch.tiling()["tile_nnz"] == best["tile_nnz"]
+    assert len(rep["candidates"]) >= 10
+    got = batch.forward(x)
+    torch.cuda.synchronize()
+    for a, b in zip(ref, got):
+        assert torch.allclose(a, b, rtol=1e-12, atol=0)
+    # a second call is served from the cache
+    batch.set_tiling(64, 64, 0)
+    rep2 = az.autotune(batch, x, cache_path=str(cache))
+    assert rep2["best"] == best and batch.tiling()["tile_nnz"] == best["tile_nnz"]
+    assert json.loads(cache.read_text())
+
+
+def test_c3_full_batch_sampled(dev):
+    """The 4096-instance workload at full size, in the benchmark's launch
+    configuration: batched forward == per-instance loop bit for bit, 12
+    sampled instances against the oracle, conservation over all."""
+    say("c3 full")
+    c = synth.C3
+    insts = synth.batch(c["count"], c["lo"], c["hi"], c["seed"])
+    plans, batch = make_batch(insts, torch.float64, dev)
+    batch.set_tiling(2048, 256, 0)
+    x = torch.from_numpy(flat_images(insts, np.float64)).to(dev)
+    I, W, U = batch.forward(x)
+    Il, Wl, Ul = batch.forward(x, loop=True)
+    torch.cuda.synchronize()
+    assert torch.equal(I, Il) and torch.equal(W, Wl) and torch.equal(U, Ul)
+    Uh = U.cpu().numpy()
+    Wh = W.cpu().numpy()
+    po, bo = batch.pix_off, batch.bin_off
+    xh = x.cpu().numpy()
+    for k in range(len(insts)):
+        assert abs(Uh[bo[k]:bo[k + 1]].sum() - (po[k + 1] - po[k])) <= 1e-9 * (po[k + 1] - po[k])
+        assert abs(Wh[bo[k]:bo[k + 1]].sum() - xh[po[k]:po[k + 1]].sum()) <= 1e-12 * xh[po[k]:po[k + 1]].sum()
+    for k in np.random.default_rng(0).choice(len(insts), 12, replace=False):
+        inst = insts[k]
+        g = inst.geom
+        m = oracle_matrix(g.h, g.w, g.center_y, g.center_x, inst.npt)
+        xv = inst.raw.reshape(-1).astype(np.float64)
+        Io, Wo, Uo = oracle.integrate(m, xv)
+        _, Wa, _ = oracle.integrate(m, xv)
+        assert norm_err(Wh[bo[k]:bo[k + 1]], Wo, Wa) <= 1e-12, k

@@ -1,0 +1,240 @@
+"""GPU forward path vs the FP64 oracle, element by element (C-ABI calls)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.helpers import azint, norm_err, oracle_matrix
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12          # FP64: normalised by sum_p A_bp |x_p| per bin
+TOL32_SAME = 2.0 ** -22  # FP32 storage, FP64 accumulation, vs oracle on the same FP32 inputs
+TOL32_F64 = 1e-6       # FP32 storage vs the FP64 oracle on FP64 inputs
+TOLK32 = 4e-7          # FP32 storage, Kahan float sums, vs oracle on the same FP32 inputs
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def scales(m, x):
+    """Per-bin scales: sum A|x| for W and I (the latter / U), U for U."""
+    _, Wabs, U = oracle.integrate(m, np.abs(x))
+    sI = np.where(U > 0, Wabs / np.where(U > 0, U, 1.0), 0.0)
+    return sI, Wabs, U
+
+
+def check(out, m, x, tol, empty=0.0, what=""):
+    I, W, U = (t.double().cpu().numpy() for t in out)
+    Io, Wo, Uo = oracle.integrate(m, x, empty=empty)
+    sI, sW, sU = scales(m, x)
+    eI, eW, eU = norm_err(I, Io, sI), norm_err(W, Wo, sW), norm_err(U, Uo, sU)
+    empty_bins = Uo == 0
+    if np.isnan(empty):
+        assert np.all(np.isnan(I[empty_bins])), what
+    else:
+        assert np.all(I[empty_bins] == empty), what
+    assert np.all(W[empty_bins] == 0) and np.all(U[empty_bins] == 0), what
+    assert eI <= tol and eW <= tol and eU <= tol, (what, eI, eW, eU)
+    return eI, eW, eU
+
+
+GEOMS = [
+    # h, w, center_y, center_x, npt, unit, split, range
+    (100, 100, 50.0, 50.0, 100, "r_m", "bbox", None),
+    (37, 53, 10.25, 40.5, 61, "r_m", "bbox", None),
+    (64, 48, -5.0, 70.0, 40, "r_m", "bbox", None),
+    (31, 29, 15.5, 14.5, 300, "r_m", "bbox", None),
+    (45, 45, 22.5, 22.5, 7, "r_m", "bbox", None),
+    (50, 60, 25.0, 30.0, 37, "r_m", "bbox", (5e-4, 2.5e-3)),
+    (50, 60, 25.3, 30.7, 37, "r_m", "none", None),
+    (1, 1, 0.5, 0.5, 4, "r_m", "bbox", None),
+    (1, 17, 0.5, 8.5, 5, "r_m", "bbox", None),
+    (257, 263, 128.5, 131.5, 256, "r_m", "bbox", None),
+    (300, 200, 10.0, 190.0, 150, "2th_deg", "bbox", None),
+]
+TILINGS = [(2048, 256), (64, 64), (256, 128), (1024, 512), (16384, 256)]
+
+
+@pytest.mark.parametrize("tiling", TILINGS, ids=lambda t: f"t{t[0]}b{t[1]}")
+@pytest.mark.parametrize("g", GEOMS, ids=lambda g: f"{g[0]}x{g[1]}-{g[5]}-{g[6]}-{g[4]}")
+def test_forward_f64(g, tiling, dev):
+    h, w, cy, cx, npt, unit, split, rng = g
+    say("forward f64", g, tiling)
+    az = azint()
+    plan = az.Plan(h, w, npt, center=(cy, cx), unit=unit, split=split, range=rng,
+                   tile_nnz=tiling[0], block=tiling[1], device=dev)
+    m = oracle_matrix(h, w, cy, cx, npt, 1e-4, 1e-4, unit, split, rng)
+    x = np.random.default_rng(h * w + npt).uniform(-2.0, 1000.0, size=h * w)
+    out = plan.integrate(torch.from_numpy(x).to(dev), empty=-1.5)
+    torch.cuda.synchronize()
+    check(out, m, x, TOL64, empty=-1.5, what=str(g))
+
+
+def test_c1_workload(dev):
+    """The smallest workload: 100x100 float64, seed 0, npt 100."""
+    say("c1")
+    az = azint()
+    inst = synth.instance(synth.C1["n"], synth.C1["seed"])
+    g = inst.geom
+    plan = az.Plan(g.h, g.w, inst.npt, center=(g.center_y, g.center_x), device=dev)
+    m = oracle_matrix(g.h, g.w, g.center_y, g.center_x, inst.npt)
+    x = inst.raw.reshape(-1).astype(np.float64)
+    raw = torch.from_numpy(inst.raw.reshape(-1)).to(dev)
+    out = plan.integrate_raw(raw)
+    torch.cuda.synchronize()
+    check(out, m, x, TOL64, what="c1")
+    # identical bits through the corrected-image entry point and on a rerun
+    out2 = plan.integrate(torch.from_numpy(x).to(dev))
+    out3 = plan.integrate(torch.from_numpy(x).to(dev))
+    torch.cuda.synchronize()
+    for a, b, c in zip(out, out2, out3):
+        assert torch.equal(a, b) and torch.equal(b, c)
+
+
+@pytest.mark.parametrize("raw_dtype", [np.int32, np.uint16, np.int16, np.uint32, np.float32,
+                                       np.float64])
+def test_correction_map_bit_exact(raw_dtype, dev):
+    """(raw - dark) / ((flat*solid)*polar) in FP64 is correctly rounded on both
+    sides, so the GPU map equals the oracle bit for bit."""
+    say("correction", raw_dtype)
+    az = azint()
+    inst = synth.instance_hw(61, 67, 5, npt=40, corrections=True)
+    g = inst.geom
+    plan = az.Plan(g.h, g.w, 40, device=dev)
+    hi = np.iinfo(raw_dtype).max if np.issubdtype(raw_dtype, np.integer) else 1 << 20
+    raw_np = np.random.default_rng(2).integers(0, min(hi, 1 << 20), size=g.npix).astype(raw_dtype)
+    raw = torch.from_numpy(raw_np).to(dev)
+    t = lambda a: torch.from_numpy(a.reshape(-1)).to(dev)
+    for combo in [(1, 1, 1, 1), (1, 0, 0, 0), (0, 1, 1, 0), (0, 0, 0, 1), (0, 0, 0, 0)]:
+        arrs = [a if on else None for a, on in zip((inst.dark, inst.flat, inst.solid, inst.polar), combo)]
+        plan.set_corrections(*(None if a is None else t(a) for a in arrs))
+        x = plan.correct(raw).cpu().numpy()
+        ref = oracle.correct(raw_np, *arrs)
+        assert np.array_equal(x, ref), combo
+
+
+def test_raw_pipeline_with_corrections(dev):
+    say("raw pipeline with corrections")
+    az = azint()
+    inst = synth.instance_hw(211, 190, 7, npt=160, corrections=True)
+    g = inst.geom
+    plan = az.Plan(g.h, g.w, inst.npt, center=(g.center_y, g.center_x), device=dev)
+    t = lambda a: torch.from_numpy(a.reshape(-1)).to(dev)
+    plan.set_corrections(t(inst.dark), t(inst.flat), t(inst.solid), t(inst.polar))
+    out = plan.integrate_raw(t(inst.raw))
+    torch.cuda.synchronize()
+    m = oracle_matrix(g.h, g.w, g.center_y, g.center_x, inst.npt)
+    x = oracle.correct(inst.raw, inst.dark, inst.flat, inst.solid, inst.polar)
+    check(out, m, x, TOL64, what="corrected")
+
+
+@pytest.mark.parametrize("accum", ["f64", "kahan32"])
+@pytest.mark.parametrize("tiling", [(2048, 256), (64, 64), (512, 512)])
+def test_forward_f32(accum, tiling, dev):
+    say("forward f32", accum, tiling)
+    az = azint()
+    h, w, npt = 240, 250, 230
+    plan = az.Plan(h, w, npt, center=(119.3, 125.8), dtype=torch.float32, accum=accum,
+                   tile_nnz=tiling[0], block=tiling[1], device=dev)
+    m = oracle_matrix(h, w, 119.3, 125.8, npt)
+    x64 = np.random.default_rng(3).integers(0, 1 << 20, size=h * w).astype(np.float64)
+    out = plan.integrate(torch.from_numpy(x64.astype(np.float32)).to(dev))
+    torch.cuda.synchronize()
+    m32 = dict(m)
+    m32["coef"] = m["coef"].astype(np.float32).astype(np.float64)
+    tol = TOL32_SAME if accum == "f64" else TOLK32
+    check(out, m32, x64, tol, what=f"f32 {accum} same inputs")
+    check(out, m, x64, TOL32_F64, what=f"f32 {accum} vs f64 oracle")
+
+
+def test_kahan_beats_plain_float_on_long_rows(dev):
+    """Few wide bins: rows of ~10^5 terms, where uncompensated float sums
+    would drift; the Kahan result stays within its bound of the FP64 sums."""
+    say("kahan long rows")
+    az = azint()
+    h, w, npt = 400, 400, 6
+    plan = az.Plan(h, w, npt, dtype=torch.float32, accum="kahan32", tile_nnz=16384, device=dev)
+    m = oracle_matrix(h, w, 200.0, 200.0, npt)
+    x = np.random.default_rng(4).integers(0, 1 << 20, size=h * w).astype(np.float64)
+    out = plan.integrate(torch.from_numpy(x.astype(np.float32)).to(dev))
+    m32 = dict(m)
+    m32["coef"] = m["coef"].astype(np.float32).astype(np.float64)
+    check(out, m32, x, TOLK32, what="kahan")
+
+
+def test_empty_and_degenerate(dev):
+    say("empty and degenerate")
+    az = azint()
+    # a range that holds no pixel: every bin is empty
+    plan = az.Plan(20, 20, 16, range=(1.0, 2.0), device=dev)
+    assert plan.nnz == 0
+    x = torch.rand(400, dtype=torch.float64, device=dev)
+    I, W, U = plan.integrate(x, empty=np.nan)
+    assert torch.isnan(I).all() and (W == 0).all() and (U == 0).all()
+    # many more bins than pixels: most bins empty, the rest exact
+    plan = az.Plan(6, 5, 500, center=(3.0, 2.5), device=dev)
+    m = oracle_matrix(6, 5, 3.0, 2.5, 500)
+    xv = np.arange(30, dtype=np.float64) + 1.0
+    out = plan.integrate(torch.from_numpy(xv).to(dev), empty=np.nan)
+    check(out, m, xv, TOL64, empty=np.nan, what="sparse bins")
+    # outputs W / U may be omitted
+    I_only = torch.empty(500, dtype=torch.float64, device=dev)
+    az.lib().azi_integrate1d(plan.handle, torch.from_numpy(xv).to(dev).data_ptr(),
+                             I_only.data_ptr(), None, None, 0.0, None)
+    torch.cuda.synchronize()
+    Io, _, Uo = oracle.integrate(m, xv)
+    nz = Uo > 0
+    assert np.allclose(I_only.cpu().numpy()[nz], Io[nz], rtol=1e-12, atol=0)
+
+
+def _sampled_bins_oracle(g, npt, x, bins):
+    """Oracle values of a few bins of a large image, computed from only the
+    pixels whose radial box overlaps them."""
+    lo, hi, _ = oracle.pixel_extents(g.h, g.w, g.pixel_y, g.pixel_x, g.center_y, g.center_x,
+                                     g.dist, g.wavelength, "r_m")
+    pmin, pmax = float(lo.min()), float(hi.max())
+    delta = (pmax - pmin) / npt
+    out = {}
+    for b in bins:
+        e0, e1 = pmin + (b - 1) * delta, pmin + (b + 2) * delta
+        sel = np.nonzero((hi >= e0) & (lo <= e1))[0]
+        pix, bb, coef = oracle.bbox_entries(lo[sel], hi[sel], npt, pmin, pmax)
+        keep = bb == b
+        m = dict(npt=npt, pix=sel[pix[keep]], bins=np.zeros(keep.sum(), dtype=np.int64),
+                 coef=coef[keep])
+        out[b] = (oracle.integrate(dict(m, npt=1), x), oracle.integrate(dict(m, npt=1), np.abs(x)))
+    return out
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_c2_full_size_sampled(dtype, dev):
+    """The ~1e7-pixel workload at full size, in the launch configuration the
+    benchmark times: 24 sampled bins against the oracle, plus conservation
+    over all bins."""
+    say("c2 full size", dtype)
+    az = azint()
+    inst = synth.instance(synth.C2["n"], synth.C2["seed"])
+    g = inst.geom
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    plan = az.Plan(g.h, g.w, inst.npt, center=(g.center_y, g.center_x), dtype=tdt, device=dev)
+    raw = torch.from_numpy(inst.raw.reshape(-1)).to(dev)
+    I, W, U = plan.integrate_raw(raw)
+    torch.cuda.synchronize()
+    I, W, U = (t.double().cpu().numpy() for t in (I, W, U))
+    x = inst.raw.reshape(-1).astype(np.float64)
+    bins = np.unique(np.r_[0, 1, 2, inst.npt - 1, inst.npt - 2,
+                           np.random.default_rng(0).choice(inst.npt, 19, replace=False)])
+    ref = _sampled_bins_oracle(g, inst.npt, x, bins)
+    tol = TOL64 if dtype == "f64" else TOL32_F64
+    for b, ((Io, Wo, Uo), (_, Wa, _)) in ref.items():
+        assert abs(W[b] - Wo[0]) <= tol * Wa[0], (b, W[b], Wo[0])
+        assert abs(U[b] - Uo[0]) <= tol * Uo[0], (b, U[b], Uo[0])
+        assert abs(I[b] - Io[0]) <= tol * Wa[0] / Uo[0], (b, I[b], Io[0])
+    assert abs(U.sum() - g.npix) <= (1e-12 if dtype == "f64" else 1e-6) * g.npix
+    assert abs(W.sum() - x.sum()) <= (1e-12 if dtype == "f64" else 1e-6) * x.sum()
