@@ -27,8 +27,32 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 
 
+KERNEL_OF_LAYOUT = {
+    "band": "k_band (+k_band_reduce): band-ordered gather integration",
+    "pixel": "k_spmv (+k_fixup): CSR gather integration",
+    "ring": "k_spmv (+k_fixup): CSR gather integration, ring-ordered image",
+    "tile": "k_block (+k_block_reduce): image-tile blocked integration",
+}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch of the integration kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE record (scaled by a plain copy's
+    reading), or None when the record is missing or was taken on other
+    kernel source than the one built now."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[workload]
+        src = os.path.join(ROOT, "paper_1412_6367_amd", "csrc", "kernels.hip")
+        if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["kernels_sha256"]:
+            return None
+        return rec["fetch_bytes"] + rec["write_bytes"]
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -83,20 +107,19 @@ def pipeline_line(az, torch, np, synth, dev, dtype, steps, warmup, frames_n=4):
     for _ in range(frames_n - 1):
         frames.append(torch.from_numpy(
             rng.integers(0, 1 << synth.RAW_BITS, size=g.npix, dtype=np.int32)).to(dev))
-    x = torch.empty(g.npix, dtype=tdt, device=dev)
     outs = tuple(torch.empty(inst.npt, dtype=tdt, device=dev) for _ in range(3))
     for k in range(warmup):
-        plan.correct(frames[k % frames_n], out=x)
-        plan.integrate(x, out=outs)
+        plan.stage(frames[k % frames_n])
+        plan.integrate_staged(out=outs)
     ev = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
         e = ev[k]
         e[0].record()
-        plan.correct(frames[k % frames_n], out=x)
+        plan.stage(frames[k % frames_n])
         e[1].record()
-        plan.integrate(x, out=outs)
+        plan.integrate_staged(out=outs)
         e[2].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -106,25 +129,27 @@ def pipeline_line(az, torch, np, synth, dev, dtype, steps, warmup, frames_n=4):
     es = 8 if dtype == "f64" else 4
     nnz = plan.nnz
     b = spmv_bytes(nnz, g.npix, inst.npt, es)
-    corr_b = g.npix * (4 + 3 * es)
-    line = dict(npix=g.npix, npt=inst.npt, nnz=nnz, ms_per_step=ms_step,
+    # raw + dark + norm read, corrected image written (+ the ring order read)
+    corr_b = g.npix * (4 + 3 * es + (4 if plan.layout() == "ring" else 0))
+    line = dict(npix=g.npix, npt=inst.npt, nnz=nnz, layout=plan.layout(),
+                tiling=plan.tiling(), ms_per_step=ms_step,
                 elements_per_s=g.npix / (ms_step * 1e-3),
                 correct_ms=corr_ms, correct_gbs=corr_b / (corr_ms * 1e6),
                 integrate_ms=spmv_ms, integrate_bytes=b,
                 integrate_gbs=b / (spmv_ms * 1e6),
                 integrate_frac=b / (spmv_ms * 1e6) / HBM_PEAK_GBS)
-    return line, plan, x, outs
+    return line, plan, outs
 
 
-def cold_line(torch, plan, x, outs, npix, npt, nnz, es, reps=20):
+def cold_line(torch, plan, outs, npix, npt, nnz, es, reps=20):
     """Integration kernel alone after streaming 1 GiB (flushes L2 and MALL)."""
-    flush = torch.empty(1 << 28, dtype=torch.float32, device=x.device)
+    flush = torch.empty(1 << 28, dtype=torch.float32, device=plan.device)
     pairs = []
     for _ in range(reps):
         flush.fill_(1.0)
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()
-        plan.integrate(x, out=outs)
+        plan.integrate_staged(out=outs)
         b.record()
         pairs.append((a, b))
     torch.cuda.synchronize()
@@ -241,7 +266,7 @@ def cpu_baseline(np, synth):
     best = None
     total = 0.0
     reps = 0
-    while reps < 3 and total < 20.0:
+    while reps < 40 and total < 10.0:
         t0 = time.perf_counter()
         x = oracle.correct(inst.raw, inst.dark, inst.flat, inst.solid, inst.polar)
         oracle.integrate(m, x)
@@ -269,8 +294,8 @@ def main():
 
     dev = torch.device("cuda:0")
     az.lib()
-    line64, plan, x, outs = pipeline_line(az, torch, np, synth, dev, "f64", args.steps,
-                                          args.warmup)
+    line64, plan, outs = pipeline_line(az, torch, np, synth, dev, "f64", args.steps,
+                                       args.warmup)
     log(f"[f64] {json.dumps(line64)}")
     result = {
         "metric": "elements/s and fraction of HBM roofline, plain vs batched+adjoint",
@@ -289,17 +314,17 @@ def main():
             "workload": "c2: one 3162x3163 int32 frame (~1e7 px), raw values uniform in "
                         "[0, 2^20), dark/flat/solid/polar corrections, bounding-box split, "
                         "3162 radial bins, float64 storage and accumulation; step = cast + "
-                        "correction + CSR gather integration (I, W, U)",
+                        "correction + sparse gather integration (I, W, U)",
             "npix": line64["npix"], "npt": line64["npt"], "nnz": line64["nnz"],
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_spmv (+k_fixup), CSR gather integration",
+            "kernel": KERNEL_OF_LAYOUT[line64["layout"]],
             "achieved": line64["integrate_gbs"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": line64["integrate_frac"],
-            "traffic": None,
+            "traffic": measured_traffic("c2_f64"),
             "bytes_per_launch": line64["integrate_bytes"],
             "avg_launch_ms": line64["integrate_ms"],
         },
@@ -309,17 +334,17 @@ def main():
     want = set(args.only.split(",")) if args.only else None
     run = lambda name: (not args.main_only) and (want is None or name in want)
     if run("c2_f64_cold"):
-        result["lines"]["c2_f64_cold"] = cold_line(torch, plan, x, outs, line64["npix"],
+        result["lines"]["c2_f64_cold"] = cold_line(torch, plan, outs, line64["npix"],
                                                    line64["npt"], line64["nnz"], es64)
         log(f"[cold] {json.dumps(result['lines']['c2_f64_cold'])}")
-    del plan, x, outs
+    del plan, outs
     torch.cuda.empty_cache()
     if run("c2_f32"):
-        l32, p32, x32, o32 = pipeline_line(az, torch, np, synth, dev, "f32", args.steps,
-                                           args.warmup)
+        l32, p32, o32 = pipeline_line(az, torch, np, synth, dev, "f32", args.steps,
+                                      args.warmup)
         result["lines"]["c2_f32"] = l32
         log(f"[f32] {json.dumps(l32)}")
-        del p32, x32, o32
+        del p32, o32
         torch.cuda.empty_cache()
     if run("c3"):
         result["lines"]["c3"] = batch_line(az, torch, np, synth, dev, synth.C3, "f64",

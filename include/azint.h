@@ -140,20 +140,82 @@ int azi_plan_export_csr(const azi_plan* plan, void* data, int32_t* indices,
  * bins[nnz] ascending within a pixel, colptr[npix + 1]. */
 int azi_plan_export_csc(const azi_plan* plan, void* data, int32_t* bins, int32_t* colptr);
 
-/* Forward tile schedule (tuning; no effect on results beyond summation order):
- * tile_nnz = most nonzeros one workgroup sums per tile (64..16384, multiple
- * of 64), block = threads per workgroup (64, 128, 256, 512).  Takes effect
- * at the next azi_plan_upload (or immediately if already uploaded; that call
- * then synchronises the device). */
-int azi_plan_set_tiling(azi_plan* plan, int32_t tile_nnz, int32_t block);
+/*
+ * Launch and tile schedule of the forward kernel (tuning only: results
+ * change at most in the order of the floating-point additions).
+ *   tile_nnz  most nonzeros one workgroup sums per tile (64..16384, a
+ *             multiple of 64); rows longer than that are cut into pieces
+ *             whose sums are added in order by a small fix-up kernel.
+ *   block     threads per workgroup: 64, 128, 256 or 512.
+ *   variant   load scheme, 0..AZI_NUM_VARIANTS-1: 0 four consecutive
+ *             nonzeros per lane, 2 loads in flight; 4 the same with 4 in
+ *             flight; 1, 2, 6 lane-strided (one gather instruction reads
+ *             consecutive nonzeros of a row) with 4, 8, 16 in flight;
+ *             3 and 5 as 2 and 6 with non-temporal loads of the matrix.
+ *   grid      0: one workgroup per tile; > 0: that many persistent
+ *             workgroups walk the tiles.
+ *   band      > 1: pieces of up to `band` consecutive long rows are
+ *             interleaved, so tiles that run together read the same part of
+ *             neighbouring rings; 0 or 1: rows one after the other.
+ *   stage     how an image is brought into ring positions (ring layout only):
+ *             AZI_STAGE_GATHER reads each ring position's pixel; _SCATTER
+ *             reads row-major and writes each pixel's ring position;
+ *             _TILE reads 32x128-pixel tiles row-major and writes them out in
+ *             ring order through LDS.
+ */
+#define AZI_NUM_VARIANTS 7
+#define AZI_STAGE_GATHER 0
+#define AZI_STAGE_SCATTER 1
+#define AZI_STAGE_TILE 2
+typedef struct azi_tiling {
+    int32_t tile_nnz, block, variant, grid, band, stage;
+} azi_tiling;
 
-/* Host-side view of the forward tile schedule for a given tile_nnz (no
- * device needed; for inspection and tests).  Each tile is 8 int32:
- * {row_begin, row_end, nnz_begin, nnz_end, partial_slot (-1 = whole rows),
- * rowptr_pos, 0, 0}; each split row 4 int32: {row, slot_begin, slot_end, 0}.
- * Pass NULL arrays to query the counts first. */
-int azi_plan_tile_schedule(const azi_plan* plan, int32_t tile_nnz, int32_t* ntiles,
+/* Set a plan's tiling (host struct).  Takes effect at the next
+ * azi_plan_upload, or immediately if already uploaded (the call then
+ * synchronises the device).  AZI_EINVAL for values outside the ranges above. */
+int azi_plan_set_tiling(azi_plan* plan, const azi_tiling* tiling);
+
+/* A plan's tiling and, if on a device, its number of tiles (may be NULL). */
+int azi_plan_get_tiling(const azi_plan* plan, azi_tiling* tiling, int32_t* ntiles);
+
+/* Host-side view of the tile schedule a tiling gives (no device needed;
+ * for inspection and tests).  Each tile is 8 int32: {row_begin, row_end,
+ * nnz_begin, nnz_end, partial_slot (-1 = whole rows), rowptr_pos, 0, 0};
+ * each split row 4 int32: {row, slot_begin, slot_end, 0}.  Pass NULL arrays
+ * to query the counts first. */
+int azi_plan_tile_schedule(const azi_plan* plan, const azi_tiling* tiling, int32_t* ntiles,
                            int32_t* tiles, int32_t* nsplits, int32_t* splits);
+
+/*
+ * Device layout of the matrix (default AZI_LAYOUT_BAND).  AZI_LAYOUT_PIXEL: the gather kernels
+ * read the image in its row-major pixel order.  AZI_LAYOUT_RING:
+ * the matrix columns are renumbered so that pixels are sorted by the first
+ * bin they feed (ties in pixel order); every bin then reads its pixels from
+ * a few short contiguous runs.  The renumbering is applied to the image by
+ * the per-frame correction pass (or a plain permutation pass for an image
+ * that is already corrected), so callers always pass row-major images and
+ * the results are the same sums (Section 5.2 gather) in another order.
+ * AZI_LAYOUT_TILE: the matrix is blocked by image tiles of 32 x 128 pixels.
+ * One workgroup per tile reads the tile's pixels once, coalesced, applying
+ * the cast and correction on the way, keeps them in LDS, and gathers every
+ * bin the tile feeds from there into a per-(tile, bin) partial sum; a second
+ * kernel adds each bin's partial sums in tile order.  Only block and grid of
+ * the tiling apply to this layout.
+ * AZI_LAYOUT_BAND: bins are grouped into bands of R consecutive bins (R =
+ * the tiling's band: 4, 8 or 16; other values mean 8) and each band's
+ * entries are ordered by pixel id, so the image is read in its own row-major
+ * order, a few nearly full cache lines per image row; pieces of tile_nnz
+ * entries add into per-bin partial sums that a second kernel adds in order.
+ * Images up to 2^27 pixels.
+ * Set before azi_plan_upload (a later call re-uploads).
+ */
+#define AZI_LAYOUT_PIXEL 0
+#define AZI_LAYOUT_RING 1
+#define AZI_LAYOUT_TILE 2
+#define AZI_LAYOUT_BAND 3
+int azi_plan_set_layout(azi_plan* plan, int32_t layout);
+int azi_plan_get_layout(const azi_plan* plan, int32_t* layout);
 
 /* Place the plan on HIP device `device`: copies the CSR and CSC matrices,
  * the tile schedule and allocates the plan's work buffers.  Synchronous.
@@ -193,13 +255,22 @@ int azi_integrate1d(const azi_plan* plan, const void* x, void* out_I, void* out_
 
 /*
  * The whole per-frame pipeline of Section 6.4 on a raw image: cast and
- * correction into the plan's work image, then azi_integrate1d.  raw is a
- * device image of raw_dtype.  The work image stays valid until the next
- * call on this plan (it is the x the backward pass needs).
+ * correction (into the plan's layout) in the plan's work image, then the
+ * integration.  raw is a device image of raw_dtype.
  */
 int azi_integrate1d_raw(const azi_plan* plan, const void* raw, int32_t raw_dtype,
                         void* out_I, void* out_W, void* out_U, double empty,
                         void* stream);
+
+/*
+ * The two stages of azi_integrate1d_raw as separate calls (for callers that
+ * time or overlap them): azi_plan_stage runs the cast and correction of a
+ * raw image into the plan's work image, in the plan's layout;
+ * azi_integrate1d_staged integrates the work image as it stands.
+ */
+int azi_plan_stage(const azi_plan* plan, const void* raw, int32_t raw_dtype, void* stream);
+int azi_integrate1d_staged(const azi_plan* plan, void* out_I, void* out_W, void* out_U,
+                           double empty, void* stream);
 
 /*
  * Adjoint of azi_integrate1d.  Since dI_b/dx_p = A_bp / U_b and
@@ -215,7 +286,7 @@ int azi_integrate1d_backward(const azi_plan* plan, const void* U, const void* gr
                              void* stream);
 
 /*
- * Batches: n uploaded plans of one storage type and accumulation mode are
+ * Batches: n plans of one storage type, accumulation mode and layout are
  * stacked into one block-diagonal matrix on `device` (Section 5.2.2 notes
  * several detectors handled together).  Images, outputs and gradients of a
  * batch are flat concatenations in plan order; azi_batch_info gives the
@@ -230,20 +301,24 @@ int azi_batch_destroy(azi_batch* batch);
 int azi_batch_info(const azi_batch* batch, int32_t* n, int64_t* npix, int64_t* npt,
                    int64_t* nnz, int64_t* pix_off, int64_t* bin_off);
 
-/* Tile schedule of the batch (as azi_plan_set_tiling) and launch shape:
- * grid = 0 launches one workgroup per tile; grid > 0 launches that many
- * persistent workgroups that walk the tiles.  Synchronises the device. */
-int azi_batch_set_tiling(azi_batch* batch, int32_t tile_nnz, int32_t block, int32_t grid);
+/* Tiling of a batch (as for plans; a batch starts with its first plan's).
+ * Synchronises the device. */
+int azi_batch_set_tiling(azi_batch* batch, const azi_tiling* tiling);
 
-/* Current tiling: tile_nnz, block, grid, number of tiles (each may be NULL). */
-int azi_batch_get_tiling(const azi_batch* batch, int32_t* tile_nnz, int32_t* block,
-                         int32_t* grid, int32_t* ntiles);
+/* A batch's tiling and number of tiles (each may be NULL). */
+int azi_batch_get_tiling(const azi_batch* batch, azi_tiling* tiling, int32_t* ntiles);
 
 /* Forward of every instance in one launch (plus one small fix-up launch for
  * bins split across tiles): x, out_I, out_W, out_U as in azi_integrate1d,
  * concatenated. */
 int azi_batch_forward(azi_batch* batch, const void* x, void* out_I, void* out_W,
                       void* out_U, double empty, void* stream);
+
+/* Forward of raw images (raw_dtype, concatenated): cast into the batch's
+ * work image (in its layout), then as azi_batch_forward.  Batches carry no
+ * correction arrays. */
+int azi_batch_forward_raw(azi_batch* batch, const void* raw, int32_t raw_dtype, void* out_I,
+                          void* out_W, void* out_U, double empty, void* stream);
 
 /* The same result computed instance by instance with the single-plan kernels
  * (one launch sequence per instance): the baseline the batch replaces. */
@@ -256,7 +331,7 @@ int azi_batch_backward(azi_batch* batch, const void* U, const void* grad_I,
                        const void* grad_W, void* grad_x, void* stream);
 
 /*
- * Autotuner: times every candidate (tile_nnz, block, grid) on the batch's own
+ * Autotuner: times candidate tilings (tile_nnz, block, variant, grid, band) on the batch's own
  * data with HIP events on `stream`, keeps the fastest (azi_batch_set_tiling)
  * and writes a JSON report of all candidates into report (host, report_len
  * bytes, may be NULL).  x, out_* are device buffers as for azi_batch_forward

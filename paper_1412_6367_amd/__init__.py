@@ -26,6 +26,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libazint.so")
 
 UNITS = {"r_m": 0, "r_mm": 1, "2th_rad": 2, "2th_deg": 3, "q_nm": 4}
+LAYOUTS = {"pixel": 0, "ring": 1, "tile": 2, "band": 3}
 SPLITS = {"none": 0, "bbox": 1}
 _DT = {torch.int16: 0, torch.int32: 2, torch.float32: 4, torch.float64: 5}
 for _name, _code in (("uint16", 1), ("uint32", 3)):
@@ -35,10 +36,33 @@ _DT_NP = {np.dtype(np.int16): 0, np.dtype(np.uint16): 1, np.dtype(np.int32): 2,
           np.dtype(np.uint32): 3, np.dtype(np.float32): 4, np.dtype(np.float64): 5}
 _STORAGE = {torch.float32: 4, torch.float64: 5}
 _ACCUM = {"f64": 0, "kahan32": 1}
+NUM_VARIANTS = 7
 
 
 class AzintError(RuntimeError):
     pass
+
+
+class Tiling(ctypes.Structure):
+    """Launch and tile schedule of the forward kernel (see include/azint.h)."""
+    _fields_ = [("tile_nnz", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("variant", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("band", ctypes.c_int32), ("stage", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+STAGES = {"gather": 0, "scatter": 1, "tile": 2}
+DEFAULT_TILING = dict(tile_nnz=2048, block=256, variant=5, grid=0, band=4, stage=0)
+
+
+def _tiling(cur=None, **kw):
+    if isinstance(kw.get("stage"), str):
+        kw["stage"] = STAGES[kw["stage"]]
+    d = dict(DEFAULT_TILING if cur is None else cur)
+    d.update({k: v for k, v in kw.items() if v is not None})
+    return Tiling(**{k: int(v) for k, v in d.items()})
 
 
 class _Geom(ctypes.Structure):
@@ -62,8 +86,11 @@ _SIGS = {
     "azi_plan_positions": (ctypes.c_int, [_P, _P]),
     "azi_plan_export_csr": (ctypes.c_int, [_P, _P, _P, _P]),
     "azi_plan_export_csc": (ctypes.c_int, [_P, _P, _P, _P]),
-    "azi_plan_set_tiling": (ctypes.c_int, [_P, _I32, _I32]),
-    "azi_plan_tile_schedule": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P]),
+    "azi_plan_set_tiling": (ctypes.c_int, [_P, _P]),
+    "azi_plan_get_tiling": (ctypes.c_int, [_P, _P, _P]),
+    "azi_plan_tile_schedule": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "azi_plan_set_layout": (ctypes.c_int, [_P, _I32]),
+    "azi_plan_get_layout": (ctypes.c_int, [_P, _P]),
     "azi_plan_upload": (ctypes.c_int, [_P, _I32]),
     "azi_plan_device_bytes": (_I64, [_P]),
     "azi_plan_set_corrections": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
@@ -71,13 +98,16 @@ _SIGS = {
     "azi_integrate1d": (ctypes.c_int, [_P, _P, _P, _P, _P, _D, _P]),
     "azi_integrate1d_raw": (ctypes.c_int, [_P, _P, _I32, _P, _P, _P, _D, _P]),
     "azi_integrate1d_backward": (ctypes.c_int, [_P, _P, _P, _P, _P, _I32, _P]),
+    "azi_plan_stage": (ctypes.c_int, [_P, _P, _I32, _P]),
+    "azi_integrate1d_staged": (ctypes.c_int, [_P, _P, _P, _P, _D, _P]),
     "azi_batch_create": (ctypes.c_int, [_P, _I32, _I32, ctypes.POINTER(_P)]),
     "azi_batch_destroy": (ctypes.c_int, [_P]),
     "azi_batch_info": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
-    "azi_batch_set_tiling": (ctypes.c_int, [_P, _I32, _I32, _I32]),
-    "azi_batch_get_tiling": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "azi_batch_set_tiling": (ctypes.c_int, [_P, _P]),
+    "azi_batch_get_tiling": (ctypes.c_int, [_P, _P, _P]),
     "azi_batch_forward": (ctypes.c_int, [_P, _P, _P, _P, _P, _D, _P]),
     "azi_batch_forward_loop": (ctypes.c_int, [_P, _P, _P, _P, _P, _D, _P]),
+    "azi_batch_forward_raw": (ctypes.c_int, [_P, _P, _I32, _P, _P, _P, _D, _P]),
     "azi_batch_backward": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "azi_batch_autotune": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, ctypes.c_char_p, _I32]),
     "azi_graph_create_batch": (ctypes.c_int, [_P, _P, _P, _P, _P, _D, _P, _P, _P, _P,
@@ -147,7 +177,7 @@ class Plan:
 
     def __init__(self, h, w, npt, *, pixel=1e-4, center=None, dist=0.1, wavelength=1e-10,
                  unit="r_m", split="bbox", range=None, dtype=torch.float64, accum="f64",
-                 device=None, tile_nnz=None, block=None):
+                 layout="band", device=None, **tiling):
         py, px = (pixel, pixel) if np.isscalar(pixel) else pixel
         cy, cx = (h / 2.0, w / 2.0) if center is None else center
         self.h, self.w, self.npt = int(h), int(w), int(npt)
@@ -163,8 +193,10 @@ class Plan:
                                      _STORAGE[dtype], _ACCUM[accum], ctypes.byref(out)))
         self._h = out
         self.device = None
-        if tile_nnz is not None or block is not None:
-            self.set_tiling(tile_nnz or 2048, block or 256)
+        if layout != "band":
+            self.set_layout(layout)
+        if tiling:
+            self.set_tiling(**tiling)
         if device is not None:
             self.upload(device)
 
@@ -218,19 +250,36 @@ class Plan:
                                          colptr.ctypes.data))
         return data, bins, colptr
 
-    def set_tiling(self, tile_nnz, block=256):
-        _check(lib().azi_plan_set_tiling(self._h, int(tile_nnz), int(block)))
+    def set_tiling(self, **kw):
+        """Change any of tile_nnz, block, variant, grid, band, stage."""
+        t = _tiling(self.tiling(), **kw)
+        _check(lib().azi_plan_set_tiling(self._h, ctypes.byref(t)))
 
-    def tile_schedule(self, tile_nnz=2048):
+    def tiling(self):
+        t = Tiling()
+        _check(lib().azi_plan_get_tiling(self._h, ctypes.byref(t), None))
+        return t.as_dict()
+
+    def tile_schedule(self, **tiling):
+        t = _tiling(self.tiling(), **tiling)
         nt, ns = _I32(), _I32()
-        _check(lib().azi_plan_tile_schedule(self._h, int(tile_nnz), ctypes.byref(nt), None,
+        _check(lib().azi_plan_tile_schedule(self._h, ctypes.byref(t), ctypes.byref(nt), None,
                                             ctypes.byref(ns), None))
         tiles = np.zeros((nt.value, 8), dtype=np.int32)
         splits = np.zeros((ns.value, 4), dtype=np.int32)
-        _check(lib().azi_plan_tile_schedule(self._h, int(tile_nnz), ctypes.byref(nt),
+        _check(lib().azi_plan_tile_schedule(self._h, ctypes.byref(t), ctypes.byref(nt),
                                             tiles.ctypes.data, ctypes.byref(ns),
                                             splits.ctypes.data))
         return tiles, splits
+
+    def set_layout(self, layout):
+        """"pixel", "ring", "tile" or "band" layout of the device matrix."""
+        _check(lib().azi_plan_set_layout(self._h, LAYOUTS[layout]))
+
+    def layout(self):
+        v = _I32()
+        _check(lib().azi_plan_get_layout(self._h, ctypes.byref(v)))
+        return {c: n for n, c in LAYOUTS.items()}[v.value]
 
     def upload(self, device=None):
         device = torch.device("cuda", torch.cuda.current_device()) if device is None \
@@ -287,6 +336,18 @@ class Plan:
         I, W, U = self._outs(out)
         _check(lib().azi_integrate1d_raw(self._h, _ptr(raw), self._raw_code(raw), _ptr(I),
                                          _ptr(W), _ptr(U), float(empty), _stream(stream)))
+        return I, W, U
+
+    def stage(self, raw, *, stream=None):
+        """Cast + correction of a raw image into the plan's work image."""
+        _need(raw, None, self.npix, self.device, "raw")
+        _check(lib().azi_plan_stage(self._h, _ptr(raw), self._raw_code(raw), _stream(stream)))
+
+    def integrate_staged(self, *, empty=0.0, out=None, stream=None):
+        """Integration of the work image left by :meth:`stage`."""
+        I, W, U = self._outs(out)
+        _check(lib().azi_integrate1d_staged(self._h, _ptr(I), _ptr(W), _ptr(U), float(empty),
+                                            _stream(stream)))
         return I, W, U
 
     def backward(self, U, grad_I=None, grad_W=None, *, wrt_raw=False, out=None, stream=None):
@@ -387,14 +448,19 @@ class Batch:
             _lib.azi_batch_destroy(self._h)
             self._h = None
 
-    def set_tiling(self, tile_nnz, block=256, grid=0):
-        _check(lib().azi_batch_set_tiling(self._h, int(tile_nnz), int(block), int(grid)))
+    def set_tiling(self, **kw):
+        """Change any of tile_nnz, block, variant, grid, band, stage."""
+        cur = self.tiling()
+        cur.pop("ntiles")
+        t = _tiling(cur, **kw)
+        _check(lib().azi_batch_set_tiling(self._h, ctypes.byref(t)))
 
     def tiling(self):
-        t, b, g, n = _I32(), _I32(), _I32(), _I32()
-        _check(lib().azi_batch_get_tiling(self._h, ctypes.byref(t), ctypes.byref(b),
-                                          ctypes.byref(g), ctypes.byref(n)))
-        return dict(tile_nnz=t.value, block=b.value, grid=g.value, ntiles=n.value)
+        t, n = Tiling(), _I32()
+        _check(lib().azi_batch_get_tiling(self._h, ctypes.byref(t), ctypes.byref(n)))
+        d = t.as_dict()
+        d["ntiles"] = n.value
+        return d
 
     def _outs(self, out):
         if out is None:
@@ -409,6 +475,17 @@ class Batch:
         I, W, U = self._outs(out)
         f = lib().azi_batch_forward_loop if loop else lib().azi_batch_forward
         _check(f(self._h, _ptr(x), _ptr(I), _ptr(W), _ptr(U), float(empty), _stream(stream)))
+        return I, W, U
+
+    def forward_raw(self, raw, *, empty=0.0, out=None, stream=None):
+        """Cast raw images (any supported dtype, concatenated) and integrate."""
+        _need(raw, None, self.npix, self.device, "raw")
+        code = _DT.get(raw.dtype)
+        if code is None:
+            raise AzintError(f"unsupported raw dtype {raw.dtype}")
+        I, W, U = self._outs(out)
+        _check(lib().azi_batch_forward_raw(self._h, _ptr(raw), code, _ptr(I), _ptr(W), _ptr(U),
+                                           float(empty), _stream(stream)))
         return I, W, U
 
     def backward(self, U, grad_I=None, grad_W=None, *, out=None, stream=None):
@@ -453,7 +530,8 @@ def autotune(batch, x, cache_path=None):
             cache = json.load(f)
     if key in cache:
         best = cache[key]["best"]
-        batch.set_tiling(best["tile_nnz"], best["block"], best["grid"])
+        batch.set_tiling(**{k: best[k] for k in ("tile_nnz", "block", "variant", "grid",
+                                                  "band", "stage") if k in best})
         return cache[key]
     report = batch.autotune(x)
     if cache_path:

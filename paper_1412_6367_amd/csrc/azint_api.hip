@@ -99,10 +99,27 @@ int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
 size_t elem_size(int32_t dtype) { return dtype == AZI_F64 ? 8 : 4; }
 
-bool valid_tiling(int32_t tile_nnz, int32_t block) {
-    return tile_nnz >= 64 && tile_nnz <= 16384 && tile_nnz % 64 == 0 &&
-           (block == 64 || block == 128 || block == 256 || block == 512);
+size_t elem_size_any(int32_t dtype) {
+    switch (dtype) {
+        case AZI_I16: case AZI_U16: return 2;
+        case AZI_F64: return 8;
+        default: return 4;
+    }
 }
+
+const char* kTilingRule =
+    "tiling: tile_nnz a multiple of 64 in [64, 16384], block one of 64/128/256/512, variant in "
+    "[0, AZI_NUM_VARIANTS), grid >= 0, band >= 0, stage one of AZI_STAGE_*";
+
+bool valid_tiling(const azi_tiling& t) {
+    return t.tile_nnz >= 64 && t.tile_nnz <= 16384 && t.tile_nnz % 64 == 0 &&
+           (t.block == 64 || t.block == 128 || t.block == 256 || t.block == 512) &&
+           t.variant >= 0 && t.variant < azi::kNumVariants && t.grid >= 0 && t.band >= 0 &&
+           t.stage >= AZI_STAGE_GATHER && t.stage <= AZI_STAGE_TILE;
+}
+
+// Fastest measured on the ~1e7-pixel, 3162-bin workload (float64 and float32).
+constexpr azi_tiling kDefaultTiling = {2048, 256, 5, 0, 4, AZI_STAGE_GATHER};
 
 // Converts double coefficients to the storage type into a padded buffer.
 std::vector<char> to_storage(const double* src, int64_t n, int64_t n_alloc, int32_t dtype) {
@@ -120,11 +137,16 @@ std::vector<char> to_storage(const double* src, int64_t n, int64_t n_alloc, int3
 
 struct azi_plan {
     azi::HostMatrix m;
+    azi_geom geom{};
     int32_t dtype = AZI_F64, accum = AZI_ACC_F64, unit = 0, split = AZI_SPLIT_BBOX;
-    int32_t tile_nnz = 2048, block = 256;
+    azi_tiling tiling = kDefaultTiling;
+    int32_t layout = AZI_LAYOUT_BAND;
     int device = -1;
+    int64_t used = 0;  // ring layout: pixels feeding at least one bin
     DevBuf rowptr, indices, data, colptr, rowidx, cdata, tiles, splits, parts, dark, norm, xwork,
-        vwork;
+        vwork, order, dark_r, norm_r, pos, stiles, lidx, dest, btiles, brows, blp, bcoef, bin_ptr,
+        bparts, npieces_buf, npacked, ncoef, bin_slot, bin_count, nparts_buf;
+    int32_t nstiles = 0, nbtiles = 0, npieces = 0, band_rows = 8;
     int32_t ntiles = 0, nsplits = 0, nparts = 0;
     bool has_dark = false, has_norm = false;
 };
@@ -135,9 +157,17 @@ struct azi_batch {
     int64_t npix = 0, npt = 0, nnz = 0, nnz_alloc = 0;
     std::vector<int64_t> pix_off, bin_off, nz_off, ip_off, tile_off, split_off;
     std::vector<int32_t> rp_host;  // concatenated row pointers, global nnz positions
-    int32_t tile_nnz = 2048, block = 256, grid = 0;
+    azi_tiling tiling = kDefaultTiling;
+    int32_t layout = AZI_LAYOUT_BAND;
     int32_t ntiles = 0, nsplits = 0, nparts = 0;
-    DevBuf rp, indices, data, colptr, rowidx, cdata, tiles, splits, parts, vwork;
+    DevBuf rp, indices, data, colptr, rowidx, cdata, tiles, splits, parts, vwork, order, xwork, pos,
+        stiles, lidx, dest, btiles, brows, blp, bcoef, bin_ptr, bparts, npieces_buf, npacked, ncoef,
+        bin_slot, bin_count, nparts_buf;
+    int32_t nbtiles = 0, npieces = 0, band_rows = 8;
+    std::vector<int64_t> cz_off;     // CSC entries of instance k
+    std::vector<int64_t> piece_off;  // band pieces of instance k
+    std::vector<int64_t> btile_off;  // blocked tiles of instance k
+    std::vector<int64_t> stile_off;  // stage tiles of instance k: [stile_off[k], stile_off[k+1])
 };
 
 struct azi_graph {
@@ -147,13 +177,19 @@ struct azi_graph {
 };
 
 namespace {
+int batch_build_bands(azi_batch* b, const std::vector<const azi::HostMatrix*>& ms);
+int batch_rebuild_bands(azi_batch* b);
+}  // namespace
+
+namespace {
 
 // (Re)builds and uploads the tile schedule of a plan.
 int plan_upload_tiles(azi_plan* p) {
     std::vector<azi::Tile> tiles;
     std::vector<azi::Split> splits;
     int32_t nparts = 0;
-    azi::build_tiles(p->m.indptr.data(), p->m.npt, 0, 0, 0, p->tile_nnz, tiles, splits, nparts);
+    azi::build_tiles(p->m.indptr.data(), p->m.npt, 0, 0, 0, p->tiling.tile_nnz, p->tiling.band,
+                     tiles, splits, nparts);
     AZI_HIP(p->tiles.upload(tiles.data(), tiles.size() * sizeof(azi::Tile), p->device), "tiles");
     AZI_HIP(p->splits.upload(splits.data(), splits.size() * sizeof(azi::Split), p->device),
             "splits");
@@ -175,7 +211,7 @@ int batch_upload_tiles(azi_batch* b, const std::vector<const int32_t*>& indptrs,
         b->tile_off[k] = (int64_t)tiles.size();
         b->split_off[k] = (int64_t)splits.size();
         azi::build_tiles(indptrs[k], npts[k], b->nz_off[k], b->bin_off[k], b->ip_off[k],
-                         b->tile_nnz, tiles, splits, nparts);
+                         b->tiling.tile_nnz, b->tiling.band, tiles, splits, nparts);
     }
     b->tile_off[b->n] = (int64_t)tiles.size();
     b->split_off[b->n] = (int64_t)splits.size();
@@ -212,6 +248,139 @@ int check_plan_ready(const azi_plan* p) {
     return AZI_OK;
 }
 
+int upload_blocks(const azi::BlockMatrix& bm, int32_t dtype, int device, DevBuf& tiles,
+                  DevBuf& rows, DevBuf& lp, DevBuf& coef, DevBuf& bin_ptr, DevBuf& parts) {
+    if (bm.lp.size() >= (size_t)INT32_MAX || bm.rows.size() >= (size_t)INT32_MAX ||
+        bm.tiles.size() >= (size_t)INT32_MAX)
+        return fail(AZI_EOVERFLOW, "blocked matrix exceeds 2^31 entries, rows or tiles");
+    AZI_HIP(tiles.upload(bm.tiles.data(), bm.tiles.size() * sizeof(azi::BlockTile), device),
+            "block tiles");
+    AZI_HIP(rows.upload(bm.rows.data(), bm.rows.size() * sizeof(azi::BlockRow), device),
+            "block rows");
+    AZI_HIP(lp.upload(bm.lp.data(), bm.lp.size() * 2, device), "block pixel ids");
+    std::vector<char> c = to_storage(bm.coef.data(), (int64_t)bm.coef.size(),
+                                     (int64_t)bm.coef.size(), dtype);
+    AZI_HIP(coef.upload(c.data(), c.size(), device), "block coefficients");
+    AZI_HIP(bin_ptr.upload(bm.bin_ptr.data(), bm.bin_ptr.size() * 4, device), "bin slots");
+    AZI_HIP(parts.alloc(std::max<size_t>(bm.rows.size(), 1) * 16, device), "block partials");
+    return AZI_OK;
+}
+
+int32_t band_rows_of(const azi_tiling& t) {
+    return (t.band == 4 || t.band == 8 || t.band == 16) ? t.band : 8;
+}
+
+int upload_bands(const azi::BandMatrix& bm, int32_t dtype, int device, DevBuf& pieces,
+                 DevBuf& packed, DevBuf& coef, DevBuf& bin_slot, DevBuf& bin_count,
+                 DevBuf& parts) {
+    if (bm.packed.size() + kPad >= (size_t)INT32_MAX || bm.pieces.size() >= (size_t)INT32_MAX)
+        return fail(AZI_EOVERFLOW, "band matrix exceeds 2^31 entries or pieces");
+    AZI_HIP(pieces.upload(bm.pieces.data(), bm.pieces.size() * sizeof(azi::BandPiece), device),
+            "band pieces");
+    std::vector<int32_t> pk(bm.packed);
+    pk.resize(pk.size() + kPad, 0);
+    AZI_HIP(packed.upload(pk.data(), pk.size() * 4, device), "band entries");
+    std::vector<char> c = to_storage(bm.coef.data(), (int64_t)bm.coef.size(),
+                                     (int64_t)bm.coef.size() + kPad, dtype);
+    AZI_HIP(coef.upload(c.data(), c.size(), device), "band coefficients");
+    AZI_HIP(bin_slot.upload(bm.bin_slot.data(), bm.bin_slot.size() * 4, device), "bin slots");
+    AZI_HIP(bin_count.upload(bm.bin_count.data(), bm.bin_count.size() * 4, device), "bin counts");
+    AZI_HIP(parts.alloc((size_t)std::max(bm.nslots, 1) * 16, device), "band partials");
+    return AZI_OK;
+}
+
+int plan_upload_bands(azi_plan* p) {
+    try {
+        azi::BandMatrix bm;
+        p->band_rows = band_rows_of(p->tiling);
+        if (!azi::build_bands(p->m, p->band_rows, p->tiling.tile_nnz, 0, 0, bm))
+            return fail(AZI_EOVERFLOW, "the band layout takes images below 2^27 pixels");
+        int rc = upload_bands(bm, p->dtype, p->device, p->npieces_buf, p->npacked, p->ncoef,
+                              p->bin_slot, p->bin_count, p->nparts_buf);
+        if (rc != AZI_OK) return rc;
+        p->npieces = (int32_t)bm.pieces.size();
+    } catch (const std::bad_alloc&) {
+        return fail(AZI_ENOMEM, "out of host memory building the band matrix");
+    }
+    return AZI_OK;
+}
+
+azi::BandLaunch plan_band_args(const azi_plan* p, const void* x, void* I, void* W, void* U,
+                               double empty) {
+    azi::BandLaunch a;
+    a.pieces = p->npieces_buf.as<azi::BandPiece>();
+    a.npieces = p->npieces;
+    a.packed = p->npacked.as<int32_t>();
+    a.coef = p->ncoef.p;
+    a.bin_slot = p->bin_slot.as<int32_t>();
+    a.bin_count = p->bin_count.as<int32_t>();
+    a.R = p->band_rows;
+    a.b0 = 0;
+    a.b1 = p->m.npt;
+    a.x = x;
+    a.parts = p->nparts_buf.p;
+    a.I = I;
+    a.W = W;
+    a.U = U;
+    a.empty = empty;
+    a.block = p->tiling.block;
+    a.grid = p->tiling.grid;
+    a.dtype = p->dtype;
+    a.accum = p->accum;
+    return a;
+}
+
+azi::BlockLaunch plan_block_args(const azi_plan* p, const void* img, int32_t img_dtype,
+                                 bool correct, void* I, void* W, void* U, double empty) {
+    azi::BlockLaunch a;
+    a.tiles = p->btiles.as<azi::BlockTile>();
+    a.ntiles = p->nbtiles;
+    a.rows = p->brows.as<azi::BlockRow>();
+    a.lp = p->blp.as<uint16_t>();
+    a.coef = p->bcoef.p;
+    a.bin_ptr = p->bin_ptr.as<int32_t>();
+    a.b0 = 0;
+    a.b1 = p->m.npt;
+    a.img = img;
+    a.img_dtype = img_dtype;
+    if (correct && p->has_dark) a.dark = p->dark.p;
+    if (correct && p->has_norm) a.norm = p->norm.p;
+    a.parts = p->bparts.p;
+    a.I = I;
+    a.W = W;
+    a.U = U;
+    a.empty = empty;
+    a.block = p->tiling.block;
+    a.grid = p->tiling.grid;
+    a.dtype = p->dtype;
+    a.accum = p->accum;
+    return a;
+}
+
+// Staging of a (raw or corrected) row-major image into the plan's ring work
+// image, with the plan's corrections when `correct` is set.
+azi::StageLaunch plan_stage_args(const azi_plan* p, const void* img, int32_t img_dtype,
+                                 bool correct) {
+    azi::StageLaunch a;
+    a.mode = p->tiling.stage;
+    a.raw = img;
+    a.raw_dtype = img_dtype;
+    a.order = p->order.as<int32_t>();
+    a.pos = p->pos.as<int32_t>();
+    a.tiles = p->stiles.as<azi::StageTile>();
+    a.ntiles = p->nstiles;
+    a.lidx = p->lidx.as<uint16_t>();
+    a.dest = p->dest.as<int32_t>();
+    const bool gather = a.mode == AZI_STAGE_GATHER;
+    if (correct && p->has_dark) a.dark = gather ? p->dark_r.p : p->dark.p;
+    if (correct && p->has_norm) a.norm = gather ? p->norm_r.p : p->norm.p;
+    a.x = p->xwork.p;
+    a.dtype = p->dtype;
+    a.p0 = 0;
+    a.p1 = gather ? p->used : p->m.npix;
+    return a;
+}
+
 azi::ForwardLaunch plan_forward_args(const azi_plan* p, const void* x, void* I, void* W, void* U,
                                      double empty) {
     azi::ForwardLaunch a;
@@ -228,8 +397,9 @@ azi::ForwardLaunch plan_forward_args(const azi_plan* p, const void* x, void* I, 
     a.U = U;
     a.parts = p->parts.p;
     a.empty = empty;
-    a.block = p->block;
-    a.grid = 0;
+    a.block = p->tiling.block;
+    a.variant = p->tiling.variant;
+    a.grid = p->tiling.grid;
     a.dtype = p->dtype;
     a.accum = p->accum;
     return a;
@@ -251,8 +421,9 @@ azi::ForwardLaunch batch_forward_args(const azi_batch* b, const void* x, void* I
     a.U = U;
     a.parts = b->parts.p;
     a.empty = empty;
-    a.block = b->block;
-    a.grid = b->grid;
+    a.block = b->tiling.block;
+    a.variant = b->tiling.variant;
+    a.grid = b->tiling.grid;
     a.dtype = b->dtype;
     a.accum = b->accum;
     return a;
@@ -288,6 +459,7 @@ int azi_plan_create(const azi_geom* geom, int32_t npt, int32_t unit, int32_t spl
     if (range2 && !(range2[1] > range2[0])) return fail(AZI_EINVAL, "range max must exceed min");
     std::unique_ptr<azi_plan> p(new (std::nothrow) azi_plan);
     if (!p) return fail(AZI_ENOMEM, "out of host memory");
+    p->geom = *geom;
     p->dtype = dtype;
     p->accum = accum;
     p->unit = unit;
@@ -352,33 +524,68 @@ int azi_plan_export_csc(const azi_plan* p, void* data, int32_t* bins, int32_t* c
     return AZI_OK;
 }
 
-int azi_plan_set_tiling(azi_plan* p, int32_t tile_nnz, int32_t block) {
-    if (!p) return fail(AZI_EINVAL, "plan is NULL");
-    if (!valid_tiling(tile_nnz, block))
-        return fail(AZI_EINVAL, "tile_nnz must be a multiple of 64 in [64, 16384] and block one of 64/128/256/512");
-    p->tile_nnz = tile_nnz;
-    p->block = block;
-    if (p->device >= 0) {
+int azi_plan_set_tiling(azi_plan* p, const azi_tiling* t) {
+    if (!p || !t) return fail(AZI_EINVAL, "plan and tiling must not be NULL");
+    if (!valid_tiling(*t)) return fail(AZI_EINVAL, kTilingRule);
+    const bool retile = t->tile_nnz != p->tiling.tile_nnz || t->band != p->tiling.band;
+    p->tiling = *t;
+    if (p->device >= 0 && retile) {
         DeviceGuard g(p->device);
         if (g.err != hipSuccess) return hip_fail(g.err, "set device");
         AZI_HIP(hipDeviceSynchronize(), "synchronise before retiling");
+        if (p->layout == AZI_LAYOUT_BAND) {
+            int rc = plan_upload_bands(p);
+            if (rc != AZI_OK) return rc;
+        }
         return plan_upload_tiles(p);
     }
     return AZI_OK;
 }
 
-int azi_plan_tile_schedule(const azi_plan* p, int32_t tile_nnz, int32_t* ntiles, int32_t* tiles,
-                           int32_t* nsplits, int32_t* splits) {
+int azi_plan_get_tiling(const azi_plan* p, azi_tiling* t, int32_t* ntiles) {
     if (!p) return fail(AZI_EINVAL, "plan is NULL");
-    if (!valid_tiling(tile_nnz, 256)) return fail(AZI_EINVAL, "bad tile_nnz");
+    if (t) *t = p->tiling;
+    if (ntiles) *ntiles = p->ntiles;
+    return AZI_OK;
+}
+
+int azi_plan_tile_schedule(const azi_plan* p, const azi_tiling* tl, int32_t* ntiles,
+                           int32_t* tiles, int32_t* nsplits, int32_t* splits) {
+    if (!p || !tl) return fail(AZI_EINVAL, "plan and tiling must not be NULL");
+    if (!valid_tiling(*tl)) return fail(AZI_EINVAL, kTilingRule);
     std::vector<azi::Tile> t;
     std::vector<azi::Split> sp;
     int32_t nparts = 0;
-    azi::build_tiles(p->m.indptr.data(), p->m.npt, 0, 0, 0, tile_nnz, t, sp, nparts);
+    azi::build_tiles(p->m.indptr.data(), p->m.npt, 0, 0, 0, tl->tile_nnz, tl->band, t, sp, nparts);
     if (ntiles) *ntiles = (int32_t)t.size();
     if (nsplits) *nsplits = (int32_t)sp.size();
     if (tiles) std::memcpy(tiles, t.data(), t.size() * sizeof(azi::Tile));
     if (splits) std::memcpy(splits, sp.data(), sp.size() * sizeof(azi::Split));
+    return AZI_OK;
+}
+
+int azi_plan_set_layout(azi_plan* p, int32_t layout) {
+    if (!p) return fail(AZI_EINVAL, "plan is NULL");
+    if (layout < AZI_LAYOUT_PIXEL || layout > AZI_LAYOUT_BAND)
+        return fail(AZI_EINVAL, "layout must be one of AZI_LAYOUT_PIXEL/RING/TILE/BAND");
+    if (layout == p->layout) return AZI_OK;
+    p->layout = layout;
+    if (p->device >= 0) {
+        if (p->has_dark || p->has_norm)
+            return fail(AZI_ESTATE, "set the layout before the corrections");
+        {
+            DeviceGuard g(p->device);
+            if (g.err != hipSuccess) return hip_fail(g.err, "set device");
+            AZI_HIP(hipDeviceSynchronize(), "synchronise before re-upload");
+        }
+        return azi_plan_upload(p, p->device);
+    }
+    return AZI_OK;
+}
+
+int azi_plan_get_layout(const azi_plan* p, int32_t* layout) {
+    if (!p || !layout) return fail(AZI_EINVAL, "plan and layout must not be NULL");
+    *layout = p->layout;
     return AZI_OK;
 }
 
@@ -397,9 +604,32 @@ int azi_plan_upload(azi_plan* p, int32_t device) {
         const size_t es = elem_size(p->dtype);
         try {
             std::vector<int32_t> idx((size_t)nnz_alloc, 0);
-            std::copy(p->m.indices.begin(), p->m.indices.end(), idx.begin());
+            const double* coef = p->m.data.data();
+            azi::RingLayout ring;
+            if (p->layout == AZI_LAYOUT_RING) {
+                azi::build_ring(p->m, ring);
+                std::copy(ring.indices.begin(), ring.indices.end(), idx.begin());
+                coef = ring.data.data();
+                AZI_HIP(p->order.upload(ring.order.data(), ring.order.size() * 4, device), "order");
+                AZI_HIP(p->pos.upload(ring.pos.data(), ring.pos.size() * 4, device), "pos");
+                std::vector<azi::StageTile> st;
+                std::vector<uint16_t> lidx;
+                std::vector<int32_t> dest;
+                azi::build_stage_tiles(p->geom.h, p->geom.w, ring.pos.data(), 0, 0, 0, st, lidx,
+                                       dest);
+                AZI_HIP(p->stiles.upload(st.data(), st.size() * sizeof(azi::StageTile), device),
+                        "stage tiles");
+                AZI_HIP(p->lidx.upload(lidx.data(), lidx.size() * 2, device), "stage ranks");
+                AZI_HIP(p->dest.upload(dest.data(), dest.size() * 4, device), "stage targets");
+                p->nstiles = (int32_t)st.size();
+                p->used = ring.used;
+            } else {
+                std::copy(p->m.indices.begin(), p->m.indices.end(), idx.begin());
+                p->order.release();
+                p->used = p->m.npix;
+            }
             AZI_HIP(p->indices.upload(idx.data(), idx.size() * 4, device), "indices");
-            std::vector<char> d = to_storage(p->m.data.data(), nnz, nnz_alloc, p->dtype);
+            std::vector<char> d = to_storage(coef, nnz, nnz_alloc, p->dtype);
             AZI_HIP(p->data.upload(d.data(), d.size(), device), "data");
             AZI_HIP(p->rowptr.upload(p->m.indptr.data(), p->m.indptr.size() * 4, device), "indptr");
             AZI_HIP(p->colptr.upload(p->m.colptr.data(), p->m.colptr.size() * 4, device), "colptr");
@@ -411,6 +641,23 @@ int azi_plan_upload(azi_plan* p, int32_t device) {
         }
         AZI_HIP(p->xwork.alloc((size_t)p->m.npix * es, device), "work image");
         AZI_HIP(p->vwork.alloc((size_t)p->m.npt * 8, device), "work vector");
+        if (p->layout == AZI_LAYOUT_BAND) {
+            int rc2 = plan_upload_bands(p);
+            if (rc2 != AZI_OK) return rc2;
+        }
+        if (p->layout == AZI_LAYOUT_TILE) {
+            try {
+                azi::BlockMatrix bm;
+                azi::build_blocks(p->m, p->geom.h, p->geom.w, 0, 0, bm);
+                azi::finish_blocks(p->m.npt, bm);
+                int rc2 = upload_blocks(bm, p->dtype, device, p->btiles, p->brows, p->blp,
+                                        p->bcoef, p->bin_ptr, p->bparts);
+                if (rc2 != AZI_OK) return rc2;
+                p->nbtiles = (int32_t)bm.tiles.size();
+            } catch (const std::bad_alloc&) {
+                return fail(AZI_ENOMEM, "out of host memory building the blocked matrix");
+            }
+        }
         return plan_upload_tiles(p);
     };
     const int rc = body();
@@ -422,7 +669,11 @@ int64_t azi_plan_device_bytes(const azi_plan* p) {
     if (!p) return 0;
     const DevBuf* bufs[] = {&p->rowptr, &p->indices, &p->data, &p->colptr, &p->rowidx,
                             &p->cdata, &p->tiles, &p->splits, &p->parts, &p->dark,
-                            &p->norm, &p->xwork, &p->vwork};
+                            &p->norm, &p->xwork, &p->vwork, &p->order, &p->dark_r,
+                            &p->norm_r, &p->pos, &p->stiles, &p->lidx, &p->dest,
+                            &p->btiles, &p->brows, &p->blp, &p->bcoef, &p->bin_ptr,
+                            &p->bparts, &p->npieces_buf, &p->npacked, &p->ncoef, &p->bin_slot,
+                            &p->bin_count, &p->nparts_buf};
     int64_t s = 0;
     for (const DevBuf* b : bufs) s += (int64_t)b->bytes;
     return s;
@@ -453,6 +704,22 @@ int azi_plan_set_corrections(azi_plan* p, const void* dark, const void* flat, co
     } else {
         p->norm.release();
     }
+    // ring-ordered copies for the ring layout's correction pass
+    p->dark_r.release();
+    p->norm_r.release();
+    if (p->layout == AZI_LAYOUT_RING) {
+        const int32_t st = p->dtype;
+        if (p->has_dark) {
+            AZI_HIP(p->dark_r.alloc(bytes, p->device), "dark (ring order)");
+            AZI_HIP(azi::launch_correct(p->dark.p, st, p->order.as<int32_t>(), nullptr, nullptr,
+                                        p->dark_r.p, st, p->used, s), "permute dark");
+        }
+        if (p->has_norm) {
+            AZI_HIP(p->norm_r.alloc(bytes, p->device), "norm (ring order)");
+            AZI_HIP(azi::launch_correct(p->norm.p, st, p->order.as<int32_t>(), nullptr, nullptr,
+                                        p->norm_r.p, st, p->used, s), "permute norm");
+        }
+    }
     AZI_HIP(hipStreamSynchronize(s), "corrections");
     return AZI_OK;
 }
@@ -464,7 +731,7 @@ int azi_correct(const azi_plan* p, const void* raw, int32_t raw_dtype, void* x, 
     if (!valid_raw_dtype(raw_dtype)) return fail(AZI_EINVAL, "unknown raw dtype");
     DeviceGuard g(p->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "set device");
-    AZI_HIP(azi::launch_correct(raw, raw_dtype, p->has_dark ? p->dark.p : nullptr,
+    AZI_HIP(azi::launch_correct(raw, raw_dtype, nullptr, p->has_dark ? p->dark.p : nullptr,
                                 p->has_norm ? p->norm.p : nullptr, x, p->dtype, p->m.npix,
                                 static_cast<hipStream_t>(stream)),
             "correction kernel");
@@ -478,7 +745,64 @@ int azi_integrate1d(const azi_plan* p, const void* x, void* I, void* W, void* U,
     if (!x || !I) return fail(AZI_EINVAL, "x and out_I must not be NULL");
     DeviceGuard g(p->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "set device");
-    AZI_HIP(azi::launch_forward(plan_forward_args(p, x, I, W, U, empty),
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (p->layout == AZI_LAYOUT_TILE) {
+        AZI_HIP(azi::launch_block(plan_block_args(p, x, p->dtype, false, I, W, U, empty), s),
+                "blocked forward kernels");
+        return AZI_OK;
+    }
+    if (p->layout == AZI_LAYOUT_BAND) {
+        AZI_HIP(azi::launch_band(plan_band_args(p, x, I, W, U, empty), s), "band forward kernels");
+        return AZI_OK;
+    }
+    const void* xin = x;
+    if (p->layout == AZI_LAYOUT_RING) {
+        AZI_HIP(azi::launch_stage(plan_stage_args(p, x, p->dtype, false), s), "permutation kernel");
+        xin = p->xwork.p;
+    }
+    AZI_HIP(azi::launch_forward(plan_forward_args(p, xin, I, W, U, empty), s), "forward kernel");
+    return AZI_OK;
+}
+
+int azi_plan_stage(const azi_plan* p, const void* raw, int32_t raw_dtype, void* stream) {
+    int rc = check_plan_ready(p);
+    if (rc != AZI_OK) return rc;
+    if (!raw) return fail(AZI_EINVAL, "raw must not be NULL");
+    if (!valid_raw_dtype(raw_dtype)) return fail(AZI_EINVAL, "unknown raw dtype");
+    DeviceGuard g(p->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "set device");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (p->layout == AZI_LAYOUT_RING) {
+        AZI_HIP(azi::launch_stage(plan_stage_args(p, raw, raw_dtype, true), s), "staging kernel");
+    } else {
+        AZI_HIP(azi::launch_correct(raw, raw_dtype, nullptr, p->has_dark ? p->dark.p : nullptr,
+                                    p->has_norm ? p->norm.p : nullptr, p->xwork.p, p->dtype,
+                                    p->m.npix, s),
+                "correction kernel");
+    }
+    return AZI_OK;
+}
+
+int azi_integrate1d_staged(const azi_plan* p, void* I, void* W, void* U, double empty,
+                           void* stream) {
+    int rc = check_plan_ready(p);
+    if (rc != AZI_OK) return rc;
+    if (!I) return fail(AZI_EINVAL, "out_I must not be NULL");
+    DeviceGuard g(p->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "set device");
+    if (p->layout == AZI_LAYOUT_TILE) {
+        AZI_HIP(azi::launch_block(plan_block_args(p, p->xwork.p, p->dtype, false, I, W, U, empty),
+                                  static_cast<hipStream_t>(stream)),
+                "blocked forward kernels");
+        return AZI_OK;
+    }
+    if (p->layout == AZI_LAYOUT_BAND) {
+        AZI_HIP(azi::launch_band(plan_band_args(p, p->xwork.p, I, W, U, empty),
+                                 static_cast<hipStream_t>(stream)),
+                "band forward kernels");
+        return AZI_OK;
+    }
+    AZI_HIP(azi::launch_forward(plan_forward_args(p, p->xwork.p, I, W, U, empty),
                                 static_cast<hipStream_t>(stream)),
             "forward kernel");
     return AZI_OK;
@@ -486,20 +810,21 @@ int azi_integrate1d(const azi_plan* p, const void* x, void* I, void* W, void* U,
 
 int azi_integrate1d_raw(const azi_plan* p, const void* raw, int32_t raw_dtype, void* I, void* W,
                         void* U, double empty, void* stream) {
-    int rc = check_plan_ready(p);
+    if (!I) return fail(AZI_EINVAL, "out_I must not be NULL");
+    if (p && p->layout == AZI_LAYOUT_TILE && p->device >= 0) {
+        // cast and correction fused into the blocked kernel
+        if (!raw) return fail(AZI_EINVAL, "raw must not be NULL");
+        if (!valid_raw_dtype(raw_dtype)) return fail(AZI_EINVAL, "unknown raw dtype");
+        DeviceGuard g(p->device);
+        if (g.err != hipSuccess) return hip_fail(g.err, "set device");
+        AZI_HIP(azi::launch_block(plan_block_args(p, raw, raw_dtype, true, I, W, U, empty),
+                                  static_cast<hipStream_t>(stream)),
+                "blocked forward kernels");
+        return AZI_OK;
+    }
+    int rc = azi_plan_stage(p, raw, raw_dtype, stream);
     if (rc != AZI_OK) return rc;
-    if (!raw || !I) return fail(AZI_EINVAL, "raw and out_I must not be NULL");
-    if (!valid_raw_dtype(raw_dtype)) return fail(AZI_EINVAL, "unknown raw dtype");
-    DeviceGuard g(p->device);
-    if (g.err != hipSuccess) return hip_fail(g.err, "set device");
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    AZI_HIP(azi::launch_correct(raw, raw_dtype, p->has_dark ? p->dark.p : nullptr,
-                                p->has_norm ? p->norm.p : nullptr, p->xwork.p, p->dtype,
-                                p->m.npix, s),
-            "correction kernel");
-    AZI_HIP(azi::launch_forward(plan_forward_args(p, p->xwork.p, I, W, U, empty), s),
-            "forward kernel");
-    return AZI_OK;
+    return azi_integrate1d_staged(p, I, W, U, empty, stream);
 }
 
 int azi_integrate1d_backward(const azi_plan* p, const void* U, const void* gI, const void* gW,
@@ -532,8 +857,9 @@ int azi_batch_create(azi_plan* const* plans, int32_t n, int32_t device, azi_batc
     *out = nullptr;
     for (int32_t k = 0; k < n; ++k) {
         if (!plans[k]) return fail(AZI_EINVAL, "plan is NULL");
-        if (plans[k]->dtype != plans[0]->dtype || plans[k]->accum != plans[0]->accum)
-            return fail(AZI_EINVAL, "plans of a batch must share dtype and accumulation");
+        if (plans[k]->dtype != plans[0]->dtype || plans[k]->accum != plans[0]->accum ||
+            plans[k]->layout != plans[0]->layout)
+            return fail(AZI_EINVAL, "plans of a batch must share dtype, accumulation and layout");
     }
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || count < 1)
@@ -545,8 +871,8 @@ int azi_batch_create(azi_plan* const* plans, int32_t n, int32_t device, azi_batc
     b->dtype = plans[0]->dtype;
     b->accum = plans[0]->accum;
     b->device = device;
-    b->tile_nnz = plans[0]->tile_nnz;
-    b->block = plans[0]->block;
+    b->tiling = plans[0]->tiling;
+    b->layout = plans[0]->layout;
     b->pix_off.assign(n + 1, 0);
     b->bin_off.assign(n + 1, 0);
     b->nz_off.assign(n + 1, 0);
@@ -574,17 +900,69 @@ int azi_batch_create(azi_plan* const* plans, int32_t n, int32_t device, azi_batc
         std::vector<int32_t> idx((size_t)b->nnz_alloc, 0);
         std::vector<char> dat((size_t)b->nnz_alloc * es, 0);
         b->rp_host.assign((size_t)b->ip_off[n], 0);
+        const bool ring = b->layout == AZI_LAYOUT_RING;
+        std::vector<int32_t> order(ring ? (size_t)b->npix : 0), pos(ring ? (size_t)b->npix : 0);
+        std::vector<azi::StageTile> st;
+        std::vector<uint16_t> lidx;
+        std::vector<int32_t> dest;
+        b->stile_off.assign(n + 1, 0);
         for (int32_t k = 0; k < n; ++k) {
             const azi::HostMatrix& m = plans[k]->m;
             const int64_t z0 = b->nz_off[k];
+            const int32_t po = (int32_t)b->pix_off[k];
+            azi::RingLayout rl;
+            if (ring) {
+                azi::build_ring(m, rl);
+                for (int64_t q = 0; q < m.npix; ++q) {
+                    order[po + q] = rl.order[q] + po;
+                    pos[po + q] = rl.pos[q] + po;
+                }
+                b->stile_off[k] = (int64_t)st.size();
+                azi::build_stage_tiles(plans[k]->geom.h, plans[k]->geom.w, rl.pos.data(), po, po, 0,
+                                       st, lidx, dest);
+                b->stile_off[k + 1] = (int64_t)st.size();
+            }
+            const int32_t* cols = ring ? rl.indices.data() : m.indices.data();
+            const double* coef = ring ? rl.data.data() : m.data.data();
             for (int64_t e = 0; e < m.nnz(); ++e) {
-                idx[z0 + e] = m.indices[e] + (int32_t)b->pix_off[k];
-                if (b->dtype == AZI_F64) reinterpret_cast<double*>(dat.data())[z0 + e] = m.data[e];
-                else reinterpret_cast<float*>(dat.data())[z0 + e] = (float)m.data[e];
+                idx[z0 + e] = cols[e] + po;
+                if (b->dtype == AZI_F64) reinterpret_cast<double*>(dat.data())[z0 + e] = coef[e];
+                else reinterpret_cast<float*>(dat.data())[z0 + e] = (float)coef[e];
             }
             for (int32_t r = 0; r <= m.npt; ++r)
                 b->rp_host[b->ip_off[k] + r] = m.indptr[r] + (int32_t)z0;
         }
+        b->cz_off = cz_off;
+        if (b->layout == AZI_LAYOUT_BAND) {
+            std::vector<const azi::HostMatrix*> ms(n);
+            for (int32_t k = 0; k < n; ++k) ms[k] = &plans[k]->m;
+            int rc2 = batch_build_bands(b.get(), ms);
+            if (rc2 != AZI_OK) return rc2;
+        }
+        if (b->layout == AZI_LAYOUT_TILE) {
+            azi::BlockMatrix bm;
+            b->btile_off.assign(n + 1, 0);
+            for (int32_t k = 0; k < n; ++k) {
+                b->btile_off[k] = (int64_t)bm.tiles.size();
+                azi::build_blocks(plans[k]->m, plans[k]->geom.h, plans[k]->geom.w, b->pix_off[k],
+                                  b->bin_off[k], bm);
+            }
+            b->btile_off[n] = (int64_t)bm.tiles.size();
+            azi::finish_blocks(b->npt, bm);
+            int rc2 = upload_blocks(bm, b->dtype, device, b->btiles, b->brows, b->blp, b->bcoef,
+                                    b->bin_ptr, b->bparts);
+            if (rc2 != AZI_OK) return rc2;
+            b->nbtiles = (int32_t)bm.tiles.size();
+        }
+        if (ring) {
+            AZI_HIP(b->order.upload(order.data(), order.size() * 4, device), "order");
+            AZI_HIP(b->pos.upload(pos.data(), pos.size() * 4, device), "pos");
+            AZI_HIP(b->stiles.upload(st.data(), st.size() * sizeof(azi::StageTile), device),
+                    "stage tiles");
+            AZI_HIP(b->lidx.upload(lidx.data(), lidx.size() * 2, device), "stage ranks");
+            AZI_HIP(b->dest.upload(dest.data(), dest.size() * 4, device), "stage targets");
+        }
+        AZI_HIP(b->xwork.alloc((size_t)b->npix * es, device), "work image");
         AZI_HIP(b->indices.upload(idx.data(), idx.size() * 4, device), "indices");
         AZI_HIP(b->data.upload(dat.data(), dat.size(), device), "data");
         AZI_HIP(b->rp.upload(b->rp_host.data(), b->rp_host.size() * 4, device), "row pointers");
@@ -637,17 +1015,20 @@ int azi_batch_info(const azi_batch* b, int32_t* n, int64_t* npix, int64_t* npt, 
     return AZI_OK;
 }
 
-int azi_batch_set_tiling(azi_batch* b, int32_t tile_nnz, int32_t block, int32_t grid) {
-    if (!b) return fail(AZI_EINVAL, "batch is NULL");
-    if (!valid_tiling(tile_nnz, block) || grid < 0)
-        return fail(AZI_EINVAL, "tile_nnz must be a multiple of 64 in [64, 16384], block one of 64/128/256/512, grid >= 0");
+int azi_batch_set_tiling(azi_batch* b, const azi_tiling* t) {
+    if (!b || !t) return fail(AZI_EINVAL, "batch and tiling must not be NULL");
+    if (!valid_tiling(*t)) return fail(AZI_EINVAL, kTilingRule);
     DeviceGuard g(b->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "set device");
-    AZI_HIP(hipDeviceSynchronize(), "synchronise before retiling");
-    b->grid = grid;
-    b->block = block;
-    if (tile_nnz != b->tile_nnz || b->ntiles == 0) {
-        b->tile_nnz = tile_nnz;
+    const bool retile =
+        t->tile_nnz != b->tiling.tile_nnz || t->band != b->tiling.band || b->ntiles == 0;
+    b->tiling = *t;
+    if (retile) {
+        AZI_HIP(hipDeviceSynchronize(), "synchronise before retiling");
+        if (b->layout == AZI_LAYOUT_BAND && b->npieces_buf.p) {
+            int rc = batch_rebuild_bands(b);
+            if (rc != AZI_OK) return rc;
+        }
         std::vector<std::vector<int32_t>> store;
         std::vector<const int32_t*> ptrs;
         std::vector<int32_t> npts;
@@ -657,15 +1038,165 @@ int azi_batch_set_tiling(azi_batch* b, int32_t tile_nnz, int32_t block, int32_t 
     return AZI_OK;
 }
 
-int azi_batch_get_tiling(const azi_batch* b, int32_t* tile_nnz, int32_t* block, int32_t* grid,
-                         int32_t* ntiles) {
+int azi_batch_get_tiling(const azi_batch* b, azi_tiling* t, int32_t* ntiles) {
     if (!b) return fail(AZI_EINVAL, "batch is NULL");
-    if (tile_nnz) *tile_nnz = b->tile_nnz;
-    if (block) *block = b->block;
-    if (grid) *grid = b->grid;
+    if (t) *t = b->tiling;
     if (ntiles) *ntiles = b->ntiles;
     return AZI_OK;
 }
+
+}  // extern "C"
+
+namespace {
+
+// Brings a batch's images into its work image (ring positions, or a cast
+// copy), instance range [k0, k1) only.
+int batch_build_bands(azi_batch* b, const std::vector<const azi::HostMatrix*>& ms) {
+    azi::BandMatrix bm;
+    b->band_rows = band_rows_of(b->tiling);
+    b->piece_off.assign(b->n + 1, 0);
+    for (int32_t k = 0; k < b->n; ++k) {
+        b->piece_off[k] = (int64_t)bm.pieces.size();
+        if (!azi::build_bands(*ms[k], b->band_rows, b->tiling.tile_nnz, b->pix_off[k],
+                              b->bin_off[k], bm))
+            return fail(AZI_EOVERFLOW, "the band layout takes images below 2^27 pixels");
+    }
+    b->piece_off[b->n] = (int64_t)bm.pieces.size();
+    int rc = upload_bands(bm, b->dtype, b->device, b->npieces_buf, b->npacked, b->ncoef,
+                          b->bin_slot, b->bin_count, b->nparts_buf);
+    if (rc != AZI_OK) return rc;
+    b->npieces = (int32_t)bm.pieces.size();
+    return AZI_OK;
+}
+
+// Rebuilds a batch's bands (new band rows or piece size) from its device CSC.
+int batch_rebuild_bands(azi_batch* b) {
+    const size_t es = elem_size(b->dtype);
+    std::vector<int32_t> colptr((size_t)b->npix + 1), rowidx((size_t)b->nnz);
+    std::vector<char> cd((size_t)b->nnz * es);
+    AZI_HIP(hipMemcpy(colptr.data(), b->colptr.p, colptr.size() * 4, hipMemcpyDeviceToHost),
+            "download colptr");
+    if (b->nnz > 0) {
+        AZI_HIP(hipMemcpy(rowidx.data(), b->rowidx.p, rowidx.size() * 4, hipMemcpyDeviceToHost),
+                "download rowidx");
+        AZI_HIP(hipMemcpy(cd.data(), b->cdata.p, cd.size(), hipMemcpyDeviceToHost),
+                "download cdata");
+    }
+    std::vector<azi::HostMatrix> ms(b->n);
+    std::vector<const azi::HostMatrix*> ptrs(b->n);
+    for (int32_t k = 0; k < b->n; ++k) {
+        azi::HostMatrix& m = ms[k];
+        m.npix = b->pix_off[k + 1] - b->pix_off[k];
+        m.npt = (int32_t)(b->bin_off[k + 1] - b->bin_off[k]);
+        const int64_t c0 = b->cz_off[k], c1 = b->cz_off[k + 1];
+        m.colptr.resize(m.npix + 1);
+        for (int64_t p = 0; p <= m.npix; ++p)
+            m.colptr[p] = colptr[b->pix_off[k] + p] - (int32_t)c0;
+        m.rowidx.resize(c1 - c0);
+        m.cdata.resize(c1 - c0);
+        m.indices.resize(c1 - c0);  // nnz() counts these
+        for (int64_t e = c0; e < c1; ++e) {
+            m.rowidx[e - c0] = rowidx[e] - (int32_t)b->bin_off[k];
+            m.cdata[e - c0] = b->dtype == AZI_F64 ? reinterpret_cast<const double*>(cd.data())[e]
+                                                  : (double)reinterpret_cast<const float*>(cd.data())[e];
+        }
+        ptrs[k] = &m;
+    }
+    return batch_build_bands(b, ptrs);
+}
+
+azi::BandLaunch batch_band_args(const azi_batch* b, const void* x, int32_t k0, int32_t k1,
+                                void* I, void* W, void* U, double empty) {
+    azi::BandLaunch a;
+    a.pieces = b->npieces_buf.as<azi::BandPiece>() + b->piece_off[k0];
+    a.npieces = (int32_t)(b->piece_off[k1] - b->piece_off[k0]);
+    a.packed = b->npacked.as<int32_t>();
+    a.coef = b->ncoef.p;
+    a.bin_slot = b->bin_slot.as<int32_t>();
+    a.bin_count = b->bin_count.as<int32_t>();
+    a.R = b->band_rows;
+    a.b0 = b->bin_off[k0];
+    a.b1 = b->bin_off[k1];
+    a.x = x;
+    a.parts = b->nparts_buf.p;
+    a.I = I;
+    a.W = W;
+    a.U = U;
+    a.empty = empty;
+    a.block = b->tiling.block;
+    a.grid = (k0 == 0 && k1 == b->n) ? b->tiling.grid : 0;
+    a.dtype = b->dtype;
+    a.accum = b->accum;
+    return a;
+}
+
+azi::BlockLaunch batch_block_args(const azi_batch* b, const void* img, int32_t img_dtype,
+                                  int32_t k0, int32_t k1, void* I, void* W, void* U,
+                                  double empty) {
+    azi::BlockLaunch a;
+    a.tiles = b->btiles.as<azi::BlockTile>() + b->btile_off[k0];
+    a.ntiles = (int32_t)(b->btile_off[k1] - b->btile_off[k0]);
+    a.rows = b->brows.as<azi::BlockRow>();
+    a.lp = b->blp.as<uint16_t>();
+    a.coef = b->bcoef.p;
+    a.bin_ptr = b->bin_ptr.as<int32_t>();
+    a.b0 = b->bin_off[k0];
+    a.b1 = b->bin_off[k1];
+    a.img = img;
+    a.img_dtype = img_dtype;
+    a.parts = b->bparts.p;
+    a.I = I;
+    a.W = W;
+    a.U = U;
+    a.empty = empty;
+    a.block = b->tiling.block;
+    a.grid = (k0 == 0 && k1 == b->n) ? b->tiling.grid : 0;
+    a.dtype = b->dtype;
+    a.accum = b->accum;
+    return a;
+}
+
+int batch_stage(azi_batch* b, const void* img, int32_t img_dtype, int32_t k0, int32_t k1,
+                hipStream_t s) {
+    const size_t es = elem_size(b->dtype);
+    const int64_t p0 = b->pix_off[k0], p1 = b->pix_off[k1];
+    if (b->layout != AZI_LAYOUT_RING) {
+        // plain cast into the work image, same positions
+        AZI_HIP(azi::launch_correct(static_cast<const char*>(img) + (size_t)p0 * elem_size_any(img_dtype),
+                                    img_dtype, nullptr, nullptr, nullptr,
+                                    static_cast<char*>(b->xwork.p) + (size_t)p0 * es, b->dtype,
+                                    p1 - p0, s),
+                "batch cast kernel");
+        return AZI_OK;
+    }
+    azi::StageLaunch a;
+    a.mode = b->tiling.stage;
+    a.raw = img;
+    a.raw_dtype = img_dtype;
+    a.dtype = b->dtype;
+    if (a.mode == AZI_STAGE_GATHER) {
+        // order holds global pixel ids, so the source stays at the base
+        a.order = b->order.as<int32_t>() + p0;
+        a.x = static_cast<char*>(b->xwork.p) + (size_t)p0 * es;
+        a.p0 = 0;
+        a.p1 = p1 - p0;
+    } else {
+        a.pos = b->pos.as<int32_t>();
+        a.tiles = b->stiles.as<azi::StageTile>() + b->stile_off[k0];
+        a.ntiles = (int32_t)(b->stile_off[k1] - b->stile_off[k0]);
+        a.lidx = b->lidx.as<uint16_t>();
+        a.dest = b->dest.as<int32_t>();
+        a.x = b->xwork.p;
+        a.p0 = p0;
+        a.p1 = p1;
+    }
+    AZI_HIP(azi::launch_stage(a, s), "batch staging kernel");
+    return AZI_OK;
+}
+
+}  // namespace
+
+extern "C" {
 
 int azi_batch_forward(azi_batch* b, const void* x, void* I, void* W, void* U, double empty,
                       void* stream) {
@@ -673,8 +1204,49 @@ int azi_batch_forward(azi_batch* b, const void* x, void* I, void* W, void* U, do
     if (!x || !I) return fail(AZI_EINVAL, "x and out_I must not be NULL");
     DeviceGuard g(b->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "set device");
-    AZI_HIP(azi::launch_forward(batch_forward_args(b, x, I, W, U, empty),
-                                static_cast<hipStream_t>(stream)),
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (b->layout == AZI_LAYOUT_TILE) {
+        AZI_HIP(azi::launch_block(batch_block_args(b, x, b->dtype, 0, b->n, I, W, U, empty), s),
+                "batched blocked kernels");
+        return AZI_OK;
+    }
+    if (b->layout == AZI_LAYOUT_BAND) {
+        AZI_HIP(azi::launch_band(batch_band_args(b, x, 0, b->n, I, W, U, empty), s),
+                "batched band kernels");
+        return AZI_OK;
+    }
+    const void* xin = x;
+    if (b->layout == AZI_LAYOUT_RING) {
+        int rc = batch_stage(b, x, b->dtype, 0, b->n, s);
+        if (rc != AZI_OK) return rc;
+        xin = b->xwork.p;
+    }
+    AZI_HIP(azi::launch_forward(batch_forward_args(b, xin, I, W, U, empty), s),
+            "batched forward kernel");
+    return AZI_OK;
+}
+
+int azi_batch_forward_raw(azi_batch* b, const void* raw, int32_t raw_dtype, void* I, void* W,
+                          void* U, double empty, void* stream) {
+    if (!b) return fail(AZI_EINVAL, "batch is NULL");
+    if (!raw || !I) return fail(AZI_EINVAL, "raw and out_I must not be NULL");
+    if (!valid_raw_dtype(raw_dtype)) return fail(AZI_EINVAL, "unknown raw dtype");
+    DeviceGuard g(b->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "set device");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (b->layout == AZI_LAYOUT_TILE) {
+        AZI_HIP(azi::launch_block(batch_block_args(b, raw, raw_dtype, 0, b->n, I, W, U, empty), s),
+                "batched blocked kernels");
+        return AZI_OK;
+    }
+    int rc = batch_stage(b, raw, raw_dtype, 0, b->n, s);
+    if (rc != AZI_OK) return rc;
+    if (b->layout == AZI_LAYOUT_BAND) {
+        AZI_HIP(azi::launch_band(batch_band_args(b, b->xwork.p, 0, b->n, I, W, U, empty), s),
+                "batched band kernels");
+        return AZI_OK;
+    }
+    AZI_HIP(azi::launch_forward(batch_forward_args(b, b->xwork.p, I, W, U, empty), s),
             "batched forward kernel");
     return AZI_OK;
 }
@@ -685,14 +1257,32 @@ int azi_batch_forward_loop(azi_batch* b, const void* x, void* I, void* W, void* 
     if (!x || !I) return fail(AZI_EINVAL, "x and out_I must not be NULL");
     DeviceGuard g(b->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "set device");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (b->layout == AZI_LAYOUT_TILE) {
+        for (int32_t k = 0; k < b->n; ++k)
+            AZI_HIP(azi::launch_block(batch_block_args(b, x, b->dtype, k, k + 1, I, W, U, empty), s),
+                    "per-instance blocked kernels");
+        return AZI_OK;
+    }
+    if (b->layout == AZI_LAYOUT_BAND) {
+        for (int32_t k = 0; k < b->n; ++k)
+            AZI_HIP(azi::launch_band(batch_band_args(b, x, k, k + 1, I, W, U, empty), s),
+                    "per-instance band kernels");
+        return AZI_OK;
+    }
     azi::ForwardLaunch a = batch_forward_args(b, x, I, W, U, empty);
     a.grid = 0;
+    if (b->layout == AZI_LAYOUT_RING) a.x = b->xwork.p;
     for (int32_t k = 0; k < b->n; ++k) {
+        if (b->layout == AZI_LAYOUT_RING) {
+            int rc = batch_stage(b, x, b->dtype, k, k + 1, s);
+            if (rc != AZI_OK) return rc;
+        }
         a.tiles = b->tiles.as<azi::Tile>() + b->tile_off[k];
         a.ntiles = (int32_t)(b->tile_off[k + 1] - b->tile_off[k]);
         a.splits = b->splits.as<azi::Split>() + b->split_off[k];
         a.nsplits = (int32_t)(b->split_off[k + 1] - b->split_off[k]);
-        AZI_HIP(azi::launch_forward(a, static_cast<hipStream_t>(stream)), "per-instance forward");
+        AZI_HIP(azi::launch_forward(a, s), "per-instance forward");
     }
     return AZI_OK;
 }
@@ -733,63 +1323,82 @@ int azi_batch_autotune(azi_batch* b, const void* x, void* I, void* W, void* U, v
     hipEvent_t e0, e1;
     AZI_HIP(hipEventCreate(&e0), "event");
     AZI_HIP(hipEventCreate(&e1), "event");
-    const int32_t tiles_c[] = {512, 1024, 2048, 4096, 8192};
-    const int32_t blocks_c[] = {128, 256, 512};
-    const int32_t grids_m[] = {0, 4, 8, 16};
+    // candidate tilings: the knobs that matter for the batch's layout
+    std::vector<azi_tiling> cands;
+    const int32_t st = b->tiling.stage;
+    if (b->layout == AZI_LAYOUT_BAND) {
+        for (int32_t tn : {1024, 2048, 4096, 8192})
+            for (int32_t band : {4, 8})
+                for (int32_t bl : {128, 256, 512})
+                    for (int32_t gm : {0, 8}) cands.push_back(azi_tiling{tn, bl, 5, gm * ncu, band, st});
+    } else if (b->layout == AZI_LAYOUT_TILE) {
+        for (int32_t bl : {128, 256, 512})
+            for (int32_t gm : {0, 4, 8})
+                cands.push_back(azi_tiling{b->tiling.tile_nnz, bl, 5, gm * ncu, b->tiling.band, st});
+    } else {
+        for (int32_t tn : {512, 1024, 2048, 4096, 8192})
+            for (int32_t band : {1, 4, 8, 16})
+                for (int32_t bl : {128, 256, 512})
+                    for (int32_t var : {2, 3, 5})
+                        for (int32_t gm : {0, 8})
+                            cands.push_back(azi_tiling{tn, bl, var, gm * ncu, band, st});
+    }
     std::string rep = "{\"cus\": " + std::to_string(ncu) + ", \"candidates\": [";
     float best_ms = 1e30f;
-    int32_t bt = b->tile_nnz, bb = b->block, bg = b->grid;
+    azi_tiling best_t = b->tiling;
     bool first = true;
     int rc = AZI_OK;
-    for (int32_t tn : tiles_c) {
-        for (int32_t bl : blocks_c) {
-            for (int32_t gm : grids_m) {
-                const int32_t grid = gm == 0 ? 0 : gm * ncu;
-                rc = azi_batch_set_tiling(b, tn, bl, grid);
-                if (rc != AZI_OK) break;
-                if (grid > 0 && grid >= b->ntiles) continue;  // no different from one per tile
-                azi::ForwardLaunch a = batch_forward_args(b, x, I, W, U, 0.0);
-                hipError_t e = azi::launch_forward(a, s);  // warm-up
-                float best = 1e30f;
-                for (int rep_i = 0; rep_i < 5 && e == hipSuccess; ++rep_i) {
-                    e = hipEventRecord(e0, s);
-                    if (e == hipSuccess) e = azi::launch_forward(a, s);
-                    if (e == hipSuccess) e = hipEventRecord(e1, s);
-                    if (e == hipSuccess) e = hipEventSynchronize(e1);
-                    float ms = 0.f;
-                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-                    best = std::min(best, ms);
-                }
-                if (e != hipSuccess) {
-                    rc = hip_fail(e, "autotune launch");
-                    break;
-                }
-                char buf[160];
-                std::snprintf(buf, sizeof buf,
-                              "%s{\"tile_nnz\": %d, \"block\": %d, \"grid\": %d, \"tiles\": %d, \"ms\": %.5f}",
-                              first ? "" : ", ", tn, bl, grid, b->ntiles, best);
-                rep += buf;
-                first = false;
-                if (best < best_ms) {
-                    best_ms = best;
-                    bt = tn;
-                    bb = bl;
-                    bg = grid;
-                }
-            }
-            if (rc != AZI_OK) break;
-        }
+    for (const azi_tiling& cand : cands) {
         if (rc != AZI_OK) break;
+        const int32_t tn = cand.tile_nnz, bl = cand.block, var = cand.variant, band = cand.band;
+
+        rc = azi_batch_set_tiling(b, &cand);
+        if (rc != AZI_OK) break;
+        const int32_t units = b->layout == AZI_LAYOUT_BAND   ? b->npieces
+                              : b->layout == AZI_LAYOUT_TILE ? b->nbtiles
+                                                             : b->ntiles;
+        if (cand.grid > 0 && cand.grid >= units) continue;  // same as one per unit
+        hipError_t e = hipSuccess;
+        // warm-up, then the best of 5 timed runs of the batch's own forward
+        if (azi_batch_forward(b, x, I, W, U, 0.0, s) != AZI_OK) e = hipErrorLaunchFailure;
+        float best = 1e30f;
+        for (int rep_i = 0; rep_i < 5 && e == hipSuccess; ++rep_i) {
+            e = hipEventRecord(e0, s);
+            if (e == hipSuccess && azi_batch_forward(b, x, I, W, U, 0.0, s) != AZI_OK)
+                e = hipErrorLaunchFailure;
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            best = std::min(best, ms);
+        }
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "autotune launch");
+            break;
+        }
+        char buf[224];
+        std::snprintf(buf, sizeof buf,
+                      "%s{\"tile_nnz\": %d, \"block\": %d, \"variant\": %d, \"grid\": %d, "
+                      "\"band\": %d, \"tiles\": %d, \"ms\": %.5f}",
+                      first ? "" : ", ", tn, bl, var, cand.grid, band, units, best);
+        rep += buf;
+        first = false;
+        if (best < best_ms) {
+            best_ms = best;
+            best_t = cand;
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != AZI_OK) return rc;
-    rc = azi_batch_set_tiling(b, bt, bb, bg);
+    rc = azi_batch_set_tiling(b, &best_t);
     if (rc != AZI_OK) return rc;
-    char buf[160];
+    char buf[224];
     std::snprintf(buf, sizeof buf,
-                  "], \"best\": {\"tile_nnz\": %d, \"block\": %d, \"grid\": %d, \"ms\": %.5f}}",
-                  bt, bb, bg, best_ms);
+                  "], \"best\": {\"tile_nnz\": %d, \"block\": %d, \"variant\": %d, "
+                  "\"grid\": %d, \"band\": %d, \"ms\": %.5f}}",
+                  best_t.tile_nnz, best_t.block, best_t.variant, best_t.grid, best_t.band,
+                  best_ms);
     rep += buf;
     if (report && report_len > 0) {
         const size_t n = std::min((size_t)report_len - 1, rep.size());

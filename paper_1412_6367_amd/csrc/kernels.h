@@ -22,10 +22,13 @@ struct ForwardLaunch {
     void* parts = nullptr;             // partial sums of split rows (16 bytes each)
     double empty = 0.0;
     int32_t block = 256;
+    int32_t variant = 2;               // load layout / unroll / streaming, see kVariants
     int32_t grid = 0;                  // 0: one workgroup per tile
     int32_t dtype = AZI_F64;
     int32_t accum = AZI_ACC_F64;
 };
+
+constexpr int32_t kNumVariants = AZI_NUM_VARIANTS;
 
 hipError_t launch_forward(const ForwardLaunch& a, hipStream_t s);
 
@@ -46,10 +49,91 @@ struct BackwardLaunch {
 
 hipError_t launch_backward(const BackwardLaunch& a, hipStream_t s);
 
-// x = (T(raw) - dark) / norm over n pixels (dark / norm may be null).
-hipError_t launch_correct(const void* raw, int32_t raw_dtype, const void* dark,
-                          const void* norm, void* x, int32_t dtype, int64_t n,
-                          hipStream_t s);
+// x[i] = (T(raw[order ? order[i] : i]) - dark[i]) / norm[i] for i < n (order,
+// dark, norm may be null).  With `order`, this is also the plain permutation
+// (cast) of an image into ring positions.
+hipError_t launch_correct(const void* raw, int32_t raw_dtype, const int32_t* order,
+                          const void* dark, const void* norm, void* x, int32_t dtype,
+                          int64_t n, hipStream_t s);
+
+// Band integration: k_band over pieces [0, npieces) fills the partial slots,
+// then k_band_reduce finishes bins [b0, b1).  x is the corrected image.
+struct BandLaunch {
+    const BandPiece* pieces = nullptr;
+    int32_t npieces = 0;
+    const int32_t* packed = nullptr;
+    const void* coef = nullptr;
+    const int32_t* bin_slot = nullptr;
+    const int32_t* bin_count = nullptr;
+    int32_t R = 8;
+    int64_t b0 = 0, b1 = 0;
+    const void* x = nullptr;
+    void* parts = nullptr;
+    void* I = nullptr;
+    void* W = nullptr;
+    void* U = nullptr;
+    double empty = 0.0;
+    int32_t block = 256;
+    int32_t grid = 0;
+    int32_t dtype = AZI_F64;
+    int32_t accum = AZI_ACC_F64;
+};
+
+hipError_t launch_band(const BandLaunch& a, hipStream_t s);
+
+// Blocked (image-tile) integration: k_block over tiles [0, ntiles) fills the
+// partial slots, then k_block_reduce finishes bins [b0, b1).  `img` is the
+// raw (img_dtype) or corrected image; dark / norm (storage type, row-major,
+// nullable) are applied on the fly.
+struct BlockLaunch {
+    const BlockTile* tiles = nullptr;
+    int32_t ntiles = 0;
+    const BlockRow* rows = nullptr;
+    const uint16_t* lp = nullptr;
+    const void* coef = nullptr;
+    const int32_t* bin_ptr = nullptr;
+    int64_t b0 = 0, b1 = 0;
+    const void* img = nullptr;
+    int32_t img_dtype = AZI_F64;
+    const void* dark = nullptr;
+    const void* norm = nullptr;
+    void* parts = nullptr;
+    void* I = nullptr;
+    void* W = nullptr;
+    void* U = nullptr;
+    double empty = 0.0;
+    int32_t block = 256;
+    int32_t grid = 0;
+    int32_t dtype = AZI_F64;
+    int32_t accum = AZI_ACC_F64;
+};
+
+hipError_t launch_block(const BlockLaunch& a, hipStream_t s);
+
+// Moving a raw image into ring positions (with cast and correction):
+//   gather   x[q] = f(raw[order[q]]), q in [p0, p1); dark / norm in ring order,
+//            `raw` and `order` already offset to the range's start
+//   scatter  x[pos[p]] = f(raw[p]), p in [p0, p1); dark / norm row-major
+//   tile     the stage tiles [0, ntiles) through LDS; dark / norm row-major
+constexpr int32_t kStageGather = 0, kStageScatter = 1, kStageTile = 2;
+struct StageLaunch {
+    int32_t mode = kStageTile;
+    const void* raw = nullptr;
+    int32_t raw_dtype = AZI_I32;
+    const int32_t* order = nullptr;
+    const int32_t* pos = nullptr;
+    const StageTile* tiles = nullptr;
+    int32_t ntiles = 0;
+    const uint16_t* lidx = nullptr;
+    const int32_t* dest = nullptr;
+    const void* dark = nullptr;
+    const void* norm = nullptr;
+    void* x = nullptr;
+    int32_t dtype = AZI_F64;
+    int64_t p0 = 0, p1 = 0;
+};
+
+hipError_t launch_stage(const StageLaunch& a, hipStream_t s);
 
 // norm = (flat * solid) * polar over the present arrays; returns false in
 // *any when all three are null (norm untouched).

@@ -157,6 +157,61 @@ __device__ inline void accumulate(Acc& a, int32_t zlo, int32_t zhi, int lane, in
     }
 }
 
+template <bool NT, class T>
+__device__ inline T ld(const T* p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+// Lane-strided form: lane j of the group takes nonzeros zlo + j, + lanes, ...
+// so one gather instruction reads `lanes` consecutive nonzeros of a row --
+// pixels that sit next to each other on the detector -- and touches few
+// cache lines.  NT streams the matrix with non-temporal loads, leaving the
+// caches to the image being gathered.
+template <int UNROLL, bool NT, class T, class Acc>
+__device__ inline void accumulate_strided(Acc& a, int32_t zlo, int32_t zhi, int lane, int lanes,
+                                          const int32_t* __restrict__ idx,
+                                          const T* __restrict__ dat, const T* __restrict__ x) {
+    for (int32_t z = zlo + lane; z < zhi; z += lanes * UNROLL) {
+        int32_t iv[UNROLL];
+        T dv[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            const int32_t e = z + u * lanes;
+            if (e < zhi) {
+                iv[u] = ld<NT>(idx + e);
+                dv[u] = ld<NT>(dat + e);
+            }
+        }
+        T xv[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) xv[u] = (z + u * lanes < zhi) ? x[iv[u]] : T(0);
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u)
+            if (z + u * lanes < zhi) a.add(dv[u], xv[u]);
+    }
+}
+
+// Kernel variants (load layout, unroll depth, non-temporal matrix stream).
+template <int VAR> struct Variant;
+template <> struct Variant<0> { static constexpr bool x4 = true;  static constexpr int unroll = 2; static constexpr bool nt = false; };
+template <> struct Variant<1> { static constexpr bool x4 = false; static constexpr int unroll = 4; static constexpr bool nt = false; };
+template <> struct Variant<2> { static constexpr bool x4 = false; static constexpr int unroll = 8; static constexpr bool nt = false; };
+template <> struct Variant<3> { static constexpr bool x4 = false; static constexpr int unroll = 8; static constexpr bool nt = true; };
+template <> struct Variant<4> { static constexpr bool x4 = true;  static constexpr int unroll = 4; static constexpr bool nt = false; };
+template <> struct Variant<5> { static constexpr bool x4 = false; static constexpr int unroll = 16; static constexpr bool nt = true; };
+template <> struct Variant<6> { static constexpr bool x4 = false; static constexpr int unroll = 16; static constexpr bool nt = false; };
+constexpr int kVariants = 7;
+
+template <int VAR, class T, class Acc>
+__device__ inline void accumulate_var(Acc& a, int32_t zlo, int32_t zhi, int lane, int lanes,
+                                      const int32_t* __restrict__ idx, const T* __restrict__ dat,
+                                      const T* __restrict__ x) {
+    using V = Variant<VAR>;
+    if constexpr (V::x4) accumulate<V::unroll>(a, zlo, zhi, lane, lanes, idx, dat, x);
+    else accumulate_strided<V::unroll, V::nt>(a, zlo, zhi, lane, lanes, idx, dat, x);
+}
+
 template <class Acc>
 __device__ inline void group_reduce(Acc& a, int lanes) {
     for (int m = lanes >> 1; m > 0; m >>= 1) a.merge(a.shfl_xor(m));
@@ -172,7 +227,7 @@ __device__ inline void write_row(int32_t r, const Acc& a, T* __restrict__ I, T* 
     I[r] = (u != 0) ? (T)(w / u) : (T)empty;
 }
 
-template <class T, class Acc, int BLOCK, int UNROLL>
+template <class T, class Acc, int BLOCK, int VAR>
 __device__ inline void process_tile(const Tile& t, Acc* red, const int32_t* __restrict__ rp,
                                     const int32_t* __restrict__ idx, const T* __restrict__ dat,
                                     const T* __restrict__ x, T* __restrict__ I,
@@ -180,11 +235,11 @@ __device__ inline void process_tile(const Tile& t, Acc* red, const int32_t* __re
                                     Acc* __restrict__ parts, double empty) {
     const int tid = threadIdx.x;
     const int32_t nr = t.r1 - t.r0;
-    if (nr == 1) {
+    if (t.mode == kTileRow) {
         // One row, or one piece of a long row: the whole workgroup sums it.
         Acc a;
         a.zero();
-        accumulate<UNROLL>(a, t.z0, t.z1, tid, BLOCK, idx, dat, x);
+        accumulate_var<VAR>(a, t.z0, t.z1, tid, BLOCK, idx, dat, x);
         group_reduce(a, kWave);
         if ((tid & (kWave - 1)) == 0) red[tid / kWave] = a;
         __syncthreads();
@@ -197,23 +252,36 @@ __device__ inline void process_tile(const Tile& t, Acc* red, const int32_t* __re
         __syncthreads();
         return;
     }
-    // Several whole rows: a group of G lanes per row, G a power of two that
-    // gives each lane about one 4-wide load per row, widened while the rows
-    // cannot keep the workgroup busy.
-    const int32_t avg = (t.z1 - t.z0 + nr - 1) / nr;
     int G = 1;
-    while (G < kWave && 4 * G < avg) G <<= 1;
-    while (G < kWave && nr * G < BLOCK) G <<= 1;
+    if (t.mode == kTileInterleave) {
+        // every row gets BLOCK / nr lanes (a power of two, at most a wave)
+        while (G < kWave && 2 * G * nr <= BLOCK) G <<= 1;
+    } else {
+        // whole rows: about one 4-wide load per lane and row, widened while
+        // the rows cannot keep the workgroup busy
+        const int32_t avg = (t.z1 - t.z0 + nr - 1) / nr;
+        while (G < kWave && 4 * G < avg) G <<= 1;
+        while (G < kWave && nr * G < BLOCK) G <<= 1;
+    }
     const int ngroups = BLOCK / G;
     const int grp = tid / G;
     const int lane = tid & (G - 1);
-    for (int32_t r = t.r0 + grp; r < t.r1; r += ngroups) {
-        const int32_t q = t.ip0 + (r - t.r0);
+    for (int32_t i = grp; i < nr; i += ngroups) {
+        const int32_t q = t.ip0 + i;
+        int32_t zlo = rp[q], zhi = rp[q + 1];
+        if (t.mode == kTileInterleave) {
+            const int32_t a0 = zlo, b0 = zhi;
+            zlo = piece_cut(a0, b0, t.k, t.z1);
+            zhi = piece_cut(a0, b0, t.k + 1, t.z1);
+        }
         Acc a;
         a.zero();
-        accumulate<UNROLL>(a, rp[q], rp[q + 1], lane, G, idx, dat, x);
+        accumulate_var<VAR>(a, zlo, zhi, lane, G, idx, dat, x);
         group_reduce(a, G);
-        if (lane == 0) write_row(r, a, I, W, U, empty);
+        if (lane == 0) {
+            if (t.mode == kTileInterleave && t.part >= 0) parts[t.part + i * t.z1 + t.k] = a;
+            else write_row(t.r0 + i, a, I, W, U, empty);
+        }
     }
 }
 
@@ -221,7 +289,7 @@ __device__ inline void process_tile(const Tile& t, Acc* red, const int32_t* __re
 // to the 8 XCDs in turn, so workgroup g runs on XCD g % 8; giving that XCD a
 // contiguous run of tiles keeps neighbouring bins -- which share most of
 // their pixels -- in the same L2.
-template <class T, class Acc, int BLOCK, int UNROLL>
+template <class T, class Acc, int BLOCK, int VAR>
 __global__ __launch_bounds__(BLOCK) void k_spmv(const Tile* __restrict__ tiles, int32_t ntiles,
                                                 const int32_t* __restrict__ rp,
                                                 const int32_t* __restrict__ idx,
@@ -233,7 +301,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmv(const Tile* __restrict__ tiles, 
     const int32_t g = blockIdx.x, G = gridDim.x;
     if (G < 8) {
         for (int32_t t = g; t < ntiles; t += G)
-            process_tile<T, Acc, BLOCK, UNROLL>(tiles[t], red, rp, idx, dat, x, I, W, U, parts, empty);
+            process_tile<T, Acc, BLOCK, VAR>(tiles[t], red, rp, idx, dat, x, I, W, U, parts, empty);
         return;
     }
     const int32_t xcd = g & 7, q = g >> 3;
@@ -242,7 +310,7 @@ __global__ __launch_bounds__(BLOCK) void k_spmv(const Tile* __restrict__ tiles, 
     const int32_t t0 = xcd * per + min(xcd, rem);
     const int32_t t1 = t0 + per + (xcd < rem ? 1 : 0);
     for (int32_t t = t0 + q; t < t1; t += nq)
-        process_tile<T, Acc, BLOCK, UNROLL>(tiles[t], red, rp, idx, dat, x, I, W, U, parts, empty);
+        process_tile<T, Acc, BLOCK, VAR>(tiles[t], red, rp, idx, dat, x, I, W, U, parts, empty);
 }
 
 template <class T, class Acc>
@@ -258,19 +326,277 @@ __global__ void k_fixup(const Split* __restrict__ splits, int32_t nsplits,
 }
 
 // ---------------------------------------------------------------------------
+// Band form: entries of R consecutive bins ordered by pixel id
+// ---------------------------------------------------------------------------
+
+// One workgroup per piece of a band.  Lanes take consecutive entries (one
+// coalesced load of packed ids and coefficients per instruction; the pixels
+// they gather are nearly consecutive in the row-major image) and add each
+// product to the accumulator of the entry's bin within the band.  The R
+// accumulators are then reduced over the workgroup in a fixed tree and
+// written to the piece's R partial slots.
+template <class T, class Acc, int BLOCK, int R>
+__global__ __launch_bounds__(BLOCK) void k_band(const BandPiece* __restrict__ pieces,
+                                                int32_t npieces,
+                                                const int32_t* __restrict__ packed,
+                                                const T* __restrict__ coef,
+                                                const T* __restrict__ x,
+                                                Acc* __restrict__ parts) {
+    constexpr int U = 4;
+    constexpr int32_t kMask = (1 << kBandShift) - 1;
+    __shared__ Acc red[BLOCK / kWave][R];
+    const int tid = threadIdx.x;
+    const int32_t g = blockIdx.x, Gd = gridDim.x;
+    int32_t t_begin, t_end, t_step;
+    if (Gd < 8) {
+        t_begin = g; t_end = npieces; t_step = Gd;
+    } else {
+        const int32_t xcd = g & 7, q = g >> 3, nq = (Gd - xcd + 7) >> 3;
+        const int32_t per = npieces >> 3, rem = npieces & 7;
+        const int32_t t0 = xcd * per + min(xcd, rem);
+        t_begin = t0 + q; t_end = t0 + per + (xcd < rem ? 1 : 0); t_step = nq;
+    }
+    for (int32_t ti = t_begin; ti < t_end; ti += t_step) {
+        const BandPiece pc = pieces[ti];
+        const T* xb = x + pc.pix_off;
+        Acc a[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) a[r].zero();
+        for (int32_t z = pc.z0 + tid; z < pc.z1; z += BLOCK * U) {
+            int32_t pk[U];
+            T cv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int32_t zz = z + u * BLOCK;
+                if (zz < pc.z1) {
+                    pk[u] = __builtin_nontemporal_load(packed + zz);
+                    cv[u] = __builtin_nontemporal_load(coef + zz);
+                }
+            }
+            T xv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) xv[u] = (z + u * BLOCK < pc.z1) ? xb[pk[u] & kMask] : T(0);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (z + u * BLOCK < pc.z1) {
+                    const int row = pk[u] >> kBandShift;
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        if (r == row) a[r].add(cv[u], xv[u]);
+                }
+            }
+        }
+        const int wave = tid / kWave, lane = tid & (kWave - 1);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            group_reduce(a[r], kWave);
+            if (lane == 0) red[wave][r] = a[r];
+        }
+        __syncthreads();
+        if (tid < R) {
+            Acc sacc = red[0][tid];
+            for (int k = 1; k < BLOCK / kWave; ++k) sacc.merge(red[k][tid]);
+            parts[pc.slot0 + tid] = sacc;
+        }
+        __syncthreads();
+    }
+}
+
+// One wavefront per bin adds the partial sums of its band's pieces (slots
+// first, first + R, ...) in a fixed order and writes W, U and I.
+template <class T, class Acc>
+__global__ void k_band_reduce(const int32_t* __restrict__ bin_slot,
+                              const int32_t* __restrict__ bin_count, int32_t R, int64_t b0,
+                              int64_t b1, const Acc* __restrict__ parts, T* __restrict__ I,
+                              T* __restrict__ W, T* __restrict__ U, double empty) {
+    const int64_t b = b0 + (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (b >= b1) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    Acc a;
+    a.zero();
+    const int32_t first = bin_slot[b], cnt = bin_count[b];
+    for (int32_t k = lane; k < cnt; k += kWave) a.merge(parts[first + (int64_t)k * R]);
+    group_reduce(a, kWave);
+    if (lane == 0) write_row((int32_t)b, a, I, W, U, empty);
+}
+
+// ---------------------------------------------------------------------------
+// Blocked form: one workgroup per image tile
+// ---------------------------------------------------------------------------
+
+// Reads the tile's pixels row-major (coalesced), applies the cast and the
+// correction map of Section 6.4 on the way (dark / norm may be null), keeps
+// the corrected values in LDS, then sums every bin the tile feeds over its
+// entries -- a small gather product from LDS -- into that (tile, bin)'s
+// partial slot.  A group of G lanes takes one bin row at a time.
+template <class R, class T, class Acc, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_block(const BlockTile* __restrict__ tiles,
+                                                 int32_t ntiles,
+                                                 const BlockRow* __restrict__ rows,
+                                                 const uint16_t* __restrict__ lp,
+                                                 const T* __restrict__ coef,
+                                                 const R* __restrict__ img,
+                                                 const T* __restrict__ dark,
+                                                 const T* __restrict__ norm,
+                                                 Acc* __restrict__ parts) {
+    constexpr int U = 4;
+    __shared__ T xs[kStageTileH * kStageTileW];
+    const int tid = threadIdx.x;
+    const int32_t g = blockIdx.x, Gd = gridDim.x;
+    // XCD-contiguous ranges of tiles, as in k_spmv
+    int32_t t_begin, t_end, t_step;
+    if (Gd < 8) {
+        t_begin = g; t_end = ntiles; t_step = Gd;
+    } else {
+        const int32_t xcd = g & 7, q = g >> 3, nq = (Gd - xcd + 7) >> 3;
+        const int32_t per = ntiles >> 3, rem = ntiles & 7;
+        const int32_t t0 = xcd * per + min(xcd, rem);
+        t_begin = t0 + q; t_end = t0 + per + (xcd < rem ? 1 : 0); t_step = nq;
+    }
+    for (int32_t ti = t_begin; ti < t_end; ti += t_step) {
+        const BlockTile t = tiles[ti];
+        const int32_t n = t.th * t.tw;
+        for (int32_t e = tid; e < n; e += BLOCK) {
+            const int32_t r = e / t.tw, c = e - r * t.tw;
+            const int64_t p = t.img_off + (int64_t)(t.i0 + r) * t.w + t.j0 + c;
+            T v = (T)img[p];
+            if (dark) v = v - dark[p];
+            if (norm) v = v / norm[p];
+            xs[e] = v;
+        }
+        __syncthreads();
+        const BlockRow* tr = rows + t.row_off;
+        const uint16_t* tl = lp + t.ent_off;
+        const T* tc = coef + t.ent_off;
+        const int32_t nr = t.nrows;
+        const int32_t nent = nr > 0 ? tr[nr - 1].end : 0;
+        const int32_t avg = nr > 0 ? (nent + nr - 1) / nr : 0;
+        int G = 1;
+        while (G < kWave && 2 * G < avg) G <<= 1;
+        while (G < kWave && nr * G < BLOCK) G <<= 1;
+        const int ngroups = BLOCK / G;
+        const int grp = tid / G, lane = tid & (G - 1);
+        for (int32_t r = grp; r < nr; r += ngroups) {
+            const BlockRow row = tr[r];
+            Acc a;
+            a.zero();
+            for (int32_t k = row.start + lane; k < row.end; k += G * U) {
+                uint16_t li[U];
+                T cv[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int32_t kk = k + u * G;
+                    if (kk < row.end) {
+                        li[u] = tl[kk];
+                        cv[u] = tc[kk];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (k + u * G < row.end) a.add(cv[u], xs[li[u]]);
+            }
+            group_reduce(a, G);
+            if (lane == 0) parts[row.slot] = a;
+        }
+        __syncthreads();
+    }
+}
+
+// One wavefront per bin adds the bin's partial sums (fixed lanes, fixed
+// tree: deterministic) and writes W, U and I.
+template <class T, class Acc>
+__global__ void k_block_reduce(const int32_t* __restrict__ bin_ptr, int64_t b0, int64_t b1,
+                               const Acc* __restrict__ parts, T* __restrict__ I,
+                               T* __restrict__ W, T* __restrict__ U, double empty) {
+    const int64_t b = b0 + (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (b >= b1) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    Acc a;
+    a.zero();
+    for (int32_t k = bin_ptr[b] + lane; k < bin_ptr[b + 1]; k += kWave) a.merge(parts[k]);
+    group_reduce(a, kWave);
+    if (lane == 0) write_row((int32_t)b, a, I, W, U, empty);
+}
+
+// ---------------------------------------------------------------------------
 // Correction map (Section 6.4)
 // ---------------------------------------------------------------------------
 
+// Workgroup g runs on XCD g % 8; this maps it to a block index so that each
+// XCD walks one contiguous eighth of the blocks (a bijection on [0, n)).
+__device__ inline int64_t xcd_block(int64_t g, int64_t n) {
+    if (n < 8) return g;
+    const int64_t xcd = g & 7, q = g >> 3;
+    const int64_t per = n >> 3, rem = n & 7;
+    return xcd * per + (xcd < rem ? xcd : rem) + q;
+}
+
+// x[i] = (T(raw[src]) - dark[i]) / norm[i], src = order ? order[i] : i.
+// With a ring order the output is the image in ring positions (and dark and
+// norm are given in that order too); without one it is row-major.
 template <class R, class T>
-__global__ void k_correct(const R* __restrict__ raw, const T* __restrict__ dark,
-                          const T* __restrict__ norm, T* __restrict__ x, int64_t n) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        T v = (T)raw[i];
-        if (dark) v = v - dark[i];
-        if (norm) v = v / norm[i];
-        x[i] = v;
+__global__ void k_correct(const R* __restrict__ raw, const int32_t* __restrict__ order,
+                          const T* __restrict__ dark, const T* __restrict__ norm,
+                          T* __restrict__ x, int64_t n) {
+    const int64_t b = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t i0 = b * (int64_t)blockDim.x * 4 + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t i = i0 + (int64_t)k * blockDim.x;
+        if (i < n) {
+            T v = (T)raw[order ? (int64_t)order[i] : i];
+            if (dark) v = v - dark[i];
+            if (norm) v = v / norm[i];
+            x[i] = v;
+        }
     }
+}
+
+// Ring staging, scatter form: pixels [p0, p1) are read row-major (coalesced)
+// and written to their ring positions x[pos[p]].
+template <class R, class T>
+__global__ void k_stage_scatter(const R* __restrict__ raw, const int32_t* __restrict__ pos,
+                                const T* __restrict__ dark, const T* __restrict__ norm,
+                                T* __restrict__ x, int64_t p0, int64_t p1) {
+    const int64_t b = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t i0 = p0 + b * (int64_t)blockDim.x * 4 + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t p = i0 + (int64_t)k * blockDim.x;
+        if (p < p1) {
+            T v = (T)raw[p];
+            if (dark) v = v - dark[p];
+            if (norm) v = v / norm[p];
+            x[pos[p]] = v;
+        }
+    }
+}
+
+// Ring staging through LDS: one workgroup per image tile reads the tile's
+// pixels row-major (coalesced), drops each corrected value at its rank among
+// the tile's ring positions, then writes the ranks out in order -- runs of
+// consecutive ring positions, so the stores are contiguous too.
+template <class R, class T, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_stage_tile(const StageTile* __restrict__ tiles,
+                                                      const R* __restrict__ raw,
+                                                      const uint16_t* __restrict__ lidx,
+                                                      const int32_t* __restrict__ dest,
+                                                      const T* __restrict__ dark,
+                                                      const T* __restrict__ norm,
+                                                      T* __restrict__ x) {
+    __shared__ T buf[kStageTileH * kStageTileW];
+    const StageTile st = tiles[xcd_block(blockIdx.x, gridDim.x)];
+    const int32_t n = st.th * st.tw;
+    for (int32_t e = threadIdx.x; e < n; e += BLOCK) {
+        const int32_t r = e / st.tw, c = e - r * st.tw;
+        const int64_t p = st.img_off + (int64_t)(st.i0 + r) * st.w + st.j0 + c;
+        T v = (T)raw[p];
+        if (dark) v = v - dark[p];
+        if (norm) v = v / norm[p];
+        buf[lidx[st.k_off + e]] = v;
+    }
+    __syncthreads();
+    for (int32_t k = threadIdx.x; k < n; k += BLOCK) x[dest[st.k_off + k]] = buf[k];
 }
 
 template <class T>
@@ -326,12 +652,11 @@ int grid_for(int64_t n, int block) {
     return (int)g;
 }
 
-template <class T, class Acc, int BLOCK>
+template <class T, class Acc, int BLOCK, int VAR>
 hipError_t forward_impl(const ForwardLaunch& a, hipStream_t s) {
-    constexpr int UNROLL = 2;
     if (a.ntiles > 0) {
         const int grid = a.grid > 0 ? a.grid : a.ntiles;
-        hipLaunchKernelGGL((k_spmv<T, Acc, BLOCK, UNROLL>), dim3(grid), dim3(BLOCK), 0, s,
+        hipLaunchKernelGGL((k_spmv<T, Acc, BLOCK, VAR>), dim3(grid), dim3(BLOCK), 0, s,
                            a.tiles, a.ntiles, a.rowptr, a.indices,
                            static_cast<const T*>(a.data), static_cast<const T*>(a.x),
                            static_cast<T*>(a.I), static_cast<T*>(a.W), static_cast<T*>(a.U),
@@ -349,36 +674,183 @@ hipError_t forward_impl(const ForwardLaunch& a, hipStream_t s) {
     return hipSuccess;
 }
 
+template <class T, class Acc, int VAR>
+hipError_t forward_var(const ForwardLaunch& a, hipStream_t s) {
+    switch (a.block) {
+        case 64: return forward_impl<T, Acc, 64, VAR>(a, s);
+        case 128: return forward_impl<T, Acc, 128, VAR>(a, s);
+        case 256: return forward_impl<T, Acc, 256, VAR>(a, s);
+        case 512: return forward_impl<T, Acc, 512, VAR>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <class T, class Acc>
 hipError_t forward_block(const ForwardLaunch& a, hipStream_t s) {
-    switch (a.block) {
-        case 64: return forward_impl<T, Acc, 64>(a, s);
-        case 128: return forward_impl<T, Acc, 128>(a, s);
-        case 256: return forward_impl<T, Acc, 256>(a, s);
-        case 512: return forward_impl<T, Acc, 512>(a, s);
+    static_assert(kVariants == kNumVariants, "variant table");
+    switch (a.variant) {
+        case 0: return forward_var<T, Acc, 0>(a, s);
+        case 1: return forward_var<T, Acc, 1>(a, s);
+        case 2: return forward_var<T, Acc, 2>(a, s);
+        case 3: return forward_var<T, Acc, 3>(a, s);
+        case 4: return forward_var<T, Acc, 4>(a, s);
+        case 5: return forward_var<T, Acc, 5>(a, s);
+        case 6: return forward_var<T, Acc, 6>(a, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <class R, class T>
-hipError_t correct_impl(const void* raw, const void* dark, const void* norm, void* x, int64_t n,
-                        hipStream_t s) {
-    hipLaunchKernelGGL((k_correct<R, T>), dim3(grid_for(n, 256)), dim3(256), 0, s,
-                       static_cast<const R*>(raw), static_cast<const T*>(dark),
+hipError_t correct_impl(const void* raw, const int32_t* order, const void* dark, const void* norm,
+                        void* x, int64_t n, hipStream_t s) {
+    const int64_t blocks = (n + 1023) / 1024;
+    if (blocks > INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_correct<R, T>), dim3((unsigned)blocks), dim3(256), 0, s,
+                       static_cast<const R*>(raw), order, static_cast<const T*>(dark),
                        static_cast<const T*>(norm), static_cast<T*>(x), n);
     return hipGetLastError();
 }
 
 template <class T>
-hipError_t correct_raw(const void* raw, int32_t raw_dtype, const void* dark, const void* norm,
-                       void* x, int64_t n, hipStream_t s) {
+hipError_t correct_raw(const void* raw, int32_t raw_dtype, const int32_t* order, const void* dark,
+                       const void* norm, void* x, int64_t n, hipStream_t s) {
     switch (raw_dtype) {
-        case AZI_I16: return correct_impl<int16_t, T>(raw, dark, norm, x, n, s);
-        case AZI_U16: return correct_impl<uint16_t, T>(raw, dark, norm, x, n, s);
-        case AZI_I32: return correct_impl<int32_t, T>(raw, dark, norm, x, n, s);
-        case AZI_U32: return correct_impl<uint32_t, T>(raw, dark, norm, x, n, s);
-        case AZI_F32: return correct_impl<float, T>(raw, dark, norm, x, n, s);
-        case AZI_F64: return correct_impl<double, T>(raw, dark, norm, x, n, s);
+        case AZI_I16: return correct_impl<int16_t, T>(raw, order, dark, norm, x, n, s);
+        case AZI_U16: return correct_impl<uint16_t, T>(raw, order, dark, norm, x, n, s);
+        case AZI_I32: return correct_impl<int32_t, T>(raw, order, dark, norm, x, n, s);
+        case AZI_U32: return correct_impl<uint32_t, T>(raw, order, dark, norm, x, n, s);
+        case AZI_F32: return correct_impl<float, T>(raw, order, dark, norm, x, n, s);
+        case AZI_F64: return correct_impl<double, T>(raw, order, dark, norm, x, n, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <class R, class T>
+hipError_t stage_impl(const StageLaunch& a, hipStream_t s) {
+    const R* raw = static_cast<const R*>(a.raw);
+    const T* dark = static_cast<const T*>(a.dark);
+    const T* norm = static_cast<const T*>(a.norm);
+    T* x = static_cast<T*>(a.x);
+    if (a.mode == kStageScatter) {
+        const int64_t n = a.p1 - a.p0;
+        if (n <= 0) return hipSuccess;
+        const int64_t blocks = (n + 1023) / 1024;
+        hipLaunchKernelGGL((k_stage_scatter<R, T>), dim3((unsigned)blocks), dim3(256), 0, s, raw,
+                           a.pos, dark, norm, x, a.p0, a.p1);
+    } else {
+        if (a.ntiles <= 0) return hipSuccess;
+        hipLaunchKernelGGL((k_stage_tile<R, T, 256>), dim3((unsigned)a.ntiles), dim3(256), 0, s,
+                           a.tiles, raw, a.lidx, a.dest, dark, norm, x);
+    }
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t stage_raw(const StageLaunch& a, hipStream_t s) {
+    switch (a.raw_dtype) {
+        case AZI_I16: return stage_impl<int16_t, T>(a, s);
+        case AZI_U16: return stage_impl<uint16_t, T>(a, s);
+        case AZI_I32: return stage_impl<int32_t, T>(a, s);
+        case AZI_U32: return stage_impl<uint32_t, T>(a, s);
+        case AZI_F32: return stage_impl<float, T>(a, s);
+        case AZI_F64: return stage_impl<double, T>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <class T, class Acc, int BLOCK, int R>
+hipError_t band_launch(const BandLaunch& a, hipStream_t s) {
+    const int grid = a.grid > 0 ? a.grid : a.npieces;
+    hipLaunchKernelGGL((k_band<T, Acc, BLOCK, R>), dim3(grid), dim3(BLOCK), 0, s, a.pieces,
+                       a.npieces, a.packed, static_cast<const T*>(a.coef),
+                       static_cast<const T*>(a.x), static_cast<Acc*>(a.parts));
+    return hipGetLastError();
+}
+
+template <class T, class Acc, int R>
+hipError_t band_block(const BandLaunch& a, hipStream_t s) {
+    switch (a.block) {
+        case 64:
+        case 128: return band_launch<T, Acc, 128, R>(a, s);
+        case 256: return band_launch<T, Acc, 256, R>(a, s);
+        case 512: return band_launch<T, Acc, 512, R>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <class T, class Acc>
+hipError_t band_impl(const BandLaunch& a, hipStream_t s) {
+    if (a.npieces > 0) {
+        hipError_t e;
+        switch (a.R) {
+            case 4: e = band_block<T, Acc, 4>(a, s); break;
+            case 8: e = band_block<T, Acc, 8>(a, s); break;
+            case 16: e = band_block<T, Acc, 16>(a, s); break;
+            default: return hipErrorInvalidValue;
+        }
+        if (e != hipSuccess) return e;
+    }
+    const int64_t nb = a.b1 - a.b0;
+    if (nb > 0) {
+        hipLaunchKernelGGL((k_band_reduce<T, Acc>), dim3((unsigned)((nb + 3) / 4)), dim3(256), 0,
+                           s, a.bin_slot, a.bin_count, a.R, a.b0, a.b1,
+                           static_cast<const Acc*>(a.parts), static_cast<T*>(a.I),
+                           static_cast<T*>(a.W), static_cast<T*>(a.U), a.empty);
+        return hipGetLastError();
+    }
+    return hipSuccess;
+}
+
+template <class R, class T, class Acc>
+hipError_t block_impl(const BlockLaunch& a, hipStream_t s) {
+    if (a.ntiles > 0) {
+        const int grid = a.grid > 0 ? a.grid : a.ntiles;
+        const R* img = static_cast<const R*>(a.img);
+        const T* dark = static_cast<const T*>(a.dark);
+        const T* norm = static_cast<const T*>(a.norm);
+        const T* coef = static_cast<const T*>(a.coef);
+        Acc* parts = static_cast<Acc*>(a.parts);
+        switch (a.block) {
+            case 64:   // a tile needs more than one wavefront: smallest is 128
+            case 128:
+                hipLaunchKernelGGL((k_block<R, T, Acc, 128>), dim3(grid), dim3(128), 0, s, a.tiles,
+                                   a.ntiles, a.rows, a.lp, coef, img, dark, norm, parts);
+                break;
+            case 256:
+                hipLaunchKernelGGL((k_block<R, T, Acc, 256>), dim3(grid), dim3(256), 0, s, a.tiles,
+                                   a.ntiles, a.rows, a.lp, coef, img, dark, norm, parts);
+                break;
+            case 512:
+                hipLaunchKernelGGL((k_block<R, T, Acc, 512>), dim3(grid), dim3(512), 0, s, a.tiles,
+                                   a.ntiles, a.rows, a.lp, coef, img, dark, norm, parts);
+                break;
+            default:
+                return hipErrorInvalidValue;
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const int64_t nb = a.b1 - a.b0;
+    if (nb > 0) {
+        const int64_t blocks = (nb + 3) / 4;
+        hipLaunchKernelGGL((k_block_reduce<T, Acc>), dim3((unsigned)blocks), dim3(256), 0, s,
+                           a.bin_ptr, a.b0, a.b1, static_cast<const Acc*>(a.parts),
+                           static_cast<T*>(a.I), static_cast<T*>(a.W), static_cast<T*>(a.U),
+                           a.empty);
+        return hipGetLastError();
+    }
+    return hipSuccess;
+}
+
+template <class T, class Acc>
+hipError_t block_raw(const BlockLaunch& a, hipStream_t s) {
+    switch (a.img_dtype) {
+        case AZI_I16: return block_impl<int16_t, T, Acc>(a, s);
+        case AZI_U16: return block_impl<uint16_t, T, Acc>(a, s);
+        case AZI_I32: return block_impl<int32_t, T, Acc>(a, s);
+        case AZI_U32: return block_impl<uint32_t, T, Acc>(a, s);
+        case AZI_F32: return block_impl<float, T, Acc>(a, s);
+        case AZI_F64: return block_impl<double, T, Acc>(a, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -413,11 +885,31 @@ hipError_t launch_backward(const BackwardLaunch& a, hipStream_t s) {
     return a.dtype == AZI_F64 ? backward_impl<double>(a, s) : backward_impl<float>(a, s);
 }
 
-hipError_t launch_correct(const void* raw, int32_t raw_dtype, const void* dark, const void* norm,
-                          void* x, int32_t dtype, int64_t n, hipStream_t s) {
+hipError_t launch_correct(const void* raw, int32_t raw_dtype, const int32_t* order,
+                          const void* dark, const void* norm, void* x, int32_t dtype, int64_t n,
+                          hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    return dtype == AZI_F64 ? correct_raw<double>(raw, raw_dtype, dark, norm, x, n, s)
-                            : correct_raw<float>(raw, raw_dtype, dark, norm, x, n, s);
+    return dtype == AZI_F64 ? correct_raw<double>(raw, raw_dtype, order, dark, norm, x, n, s)
+                            : correct_raw<float>(raw, raw_dtype, order, dark, norm, x, n, s);
+}
+
+hipError_t launch_band(const BandLaunch& a, hipStream_t s) {
+    if (a.dtype == AZI_F64) return band_impl<double, AccF64>(a, s);
+    if (a.accum == AZI_ACC_KAHAN32) return band_impl<float, AccK32>(a, s);
+    return band_impl<float, AccF64>(a, s);
+}
+
+hipError_t launch_block(const BlockLaunch& a, hipStream_t s) {
+    if (a.dtype == AZI_F64) return block_raw<double, AccF64>(a, s);
+    if (a.accum == AZI_ACC_KAHAN32) return block_raw<float, AccK32>(a, s);
+    return block_raw<float, AccF64>(a, s);
+}
+
+hipError_t launch_stage(const StageLaunch& a, hipStream_t s) {
+    if (a.mode == kStageGather)
+        return launch_correct(a.raw, a.raw_dtype, a.order, a.dark, a.norm, a.x, a.dtype, a.p1 - a.p0,
+                              s);
+    return a.dtype == AZI_F64 ? stage_raw<double>(a, s) : stage_raw<float>(a, s);
 }
 
 hipError_t launch_norm(const void* flat, const void* solid, const void* polar, void* norm,

@@ -169,30 +169,213 @@ int build_matrix(const azi_geom& g, int32_t npt, int32_t unit, int32_t split,
     return AZI_OK;
 }
 
+void build_ring(const HostMatrix& m, RingLayout& r) {
+    const int64_t npix = m.npix;
+    const int32_t npt = m.npt;
+    // counting sort of pixels by first bin (pixels feeding no bin go last)
+    std::vector<int64_t> start(npt + 2, 0);
+    for (int64_t p = 0; p < npix; ++p) {
+        const int32_t key = m.colptr[p] < m.colptr[p + 1] ? m.rowidx[m.colptr[p]] : npt;
+        start[key + 1]++;
+    }
+    for (int32_t b = 0; b <= npt; ++b) start[b + 1] += start[b];
+    r.used = start[npt];
+    r.order.assign(npix, 0);
+    r.pos.assign(npix, 0);
+    for (int64_t p = 0; p < npix; ++p) {
+        const int32_t key = m.colptr[p] < m.colptr[p + 1] ? m.rowidx[m.colptr[p]] : npt;
+        r.pos[p] = (int32_t)start[key];
+        r.order[start[key]++] = (int32_t)p;
+    }
+    // rows in ring order: visiting positions in ascending order keeps each
+    // row's positions ascending
+    const int64_t nnz = m.nnz();
+    r.indices.assign(nnz, 0);
+    r.data.assign(nnz, 0.0);
+    std::vector<int32_t> cursor(m.indptr.begin(), m.indptr.end() - 1);
+    for (int64_t q = 0; q < npix; ++q) {
+        const int32_t p = r.order[q];
+        for (int32_t k = m.colptr[p]; k < m.colptr[p + 1]; ++k) {
+            const int32_t pos = cursor[m.rowidx[k]]++;
+            r.indices[pos] = (int32_t)q;
+            r.data[pos] = m.cdata[k];
+        }
+    }
+}
+
+void build_stage_tiles(int32_t h, int32_t w, const int32_t* pos, int64_t img_off, int64_t q_off,
+                       int64_t k_off, std::vector<StageTile>& tiles, std::vector<uint16_t>& lidx,
+                       std::vector<int32_t>& dest) {
+    std::vector<int32_t> key;
+    std::vector<int32_t> perm;
+    for (int32_t i0 = 0; i0 < h; i0 += kStageTileH) {
+        const int32_t th = std::min(kStageTileH, h - i0);
+        for (int32_t j0 = 0; j0 < w; j0 += kStageTileW) {
+            const int32_t tw = std::min(kStageTileW, w - j0);
+            const int32_t n = th * tw;
+            key.resize(n);
+            perm.resize(n);
+            for (int32_t e = 0; e < n; ++e) {
+                const int64_t p = (int64_t)(i0 + e / tw) * w + (j0 + e % tw);
+                key[e] = pos[p];
+                perm[e] = e;
+            }
+            std::sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+            const size_t base = lidx.size();
+            lidx.resize(base + n);
+            dest.resize(base + n);
+            for (int32_t k = 0; k < n; ++k) {
+                lidx[base + perm[k]] = (uint16_t)k;
+                dest[base + k] = (int32_t)(key[perm[k]] + q_off);
+            }
+            tiles.push_back(StageTile{i0, j0, th, tw, w, 0, img_off, k_off + (int64_t)base});
+        }
+    }
+}
+
+void build_blocks(const HostMatrix& m, int32_t h, int32_t w, int64_t img_off, int64_t bin_off,
+                  BlockMatrix& bm) {
+    struct Ent { int32_t bin; uint16_t lp; double c; };
+    std::vector<Ent> ents;
+    for (int32_t i0 = 0; i0 < h; i0 += kStageTileH) {
+        const int32_t th = std::min(kStageTileH, h - i0);
+        for (int32_t j0 = 0; j0 < w; j0 += kStageTileW) {
+            const int32_t tw = std::min(kStageTileW, w - j0);
+            ents.clear();
+            for (int32_t e = 0; e < th * tw; ++e) {
+                const int64_t p = (int64_t)(i0 + e / tw) * w + (j0 + e % tw);
+                for (int32_t k = m.colptr[p]; k < m.colptr[p + 1]; ++k)
+                    ents.push_back(Ent{m.rowidx[k], (uint16_t)e, m.cdata[k]});
+            }
+            // rows in ascending bin order, entries of a row in pixel order
+            std::stable_sort(ents.begin(), ents.end(),
+                             [](const Ent& a, const Ent& b) { return a.bin < b.bin; });
+            BlockTile t{i0, j0, th, tw, w, 0, img_off, (int64_t)bm.rows.size(),
+                        (int64_t)bm.lp.size()};
+            int32_t k = 0;
+            const int32_t n = (int32_t)ents.size();
+            while (k < n) {
+                int32_t e = k;
+                while (e < n && ents[e].bin == ents[k].bin) ++e;
+                // slot filled in by finish_blocks; keep the bin for now
+                bm.rows.push_back(BlockRow{-1, k, e, (int32_t)(ents[k].bin + bin_off)});
+                ++t.nrows;
+                k = e;
+            }
+            for (const Ent& en : ents) {
+                bm.lp.push_back(en.lp);
+                bm.coef.push_back(en.c);
+            }
+            bm.tiles.push_back(t);
+        }
+    }
+}
+
+void finish_blocks(int64_t npt_total, BlockMatrix& bm) {
+    bm.bin_ptr.assign(npt_total + 1, 0);
+    for (const BlockRow& r : bm.rows) bm.bin_ptr[r.bin + 1]++;
+    for (int64_t b = 0; b < npt_total; ++b) bm.bin_ptr[b + 1] += bm.bin_ptr[b];
+    std::vector<int32_t> cursor(bm.bin_ptr.begin(), bm.bin_ptr.end() - 1);
+    // rows are stored tile by tile, so slots of a bin follow tile order
+    for (BlockRow& r : bm.rows) r.slot = cursor[r.bin]++;
+}
+
+bool build_bands(const HostMatrix& m, int32_t R, int32_t piece_nnz, int64_t pix_off,
+                 int64_t bin_off, BandMatrix& bm) {
+    if (m.npix >= ((int64_t)1 << kBandShift)) return false;
+    const int32_t npt = m.npt;
+    const int32_t nbands = (npt + R - 1) / R;
+    // counting sort of the CSC entries by band; pixels ascending keeps each
+    // band's entries in (pixel, bin) order
+    std::vector<int64_t> start(nbands + 1, 0);
+    for (int64_t k = 0; k < m.nnz(); ++k) start[m.rowidx[k] / R + 1]++;
+    for (int32_t b = 0; b < nbands; ++b) start[b + 1] += start[b];
+    // instance entries begin on a multiple of 64 of the flat arrays
+    while (bm.packed.size() % 64) {
+        bm.packed.push_back(0);
+        bm.coef.push_back(0.0);
+    }
+    const int64_t base = (int64_t)bm.packed.size();
+    bm.packed.resize(base + m.nnz());
+    bm.coef.resize(base + m.nnz());
+    std::vector<int64_t> cur(start.begin(), start.end() - 1);
+    for (int64_t p = 0; p < m.npix; ++p) {
+        for (int32_t k = m.colptr[p]; k < m.colptr[p + 1]; ++k) {
+            const int32_t b = m.rowidx[k];
+            const int64_t z = base + cur[b / R]++;
+            bm.packed[z] = ((b % R) << kBandShift) | (int32_t)p;
+            bm.coef[z] = m.cdata[k];
+        }
+    }
+    if (bm.bin_slot.size() < (size_t)(bin_off + npt)) {
+        bm.bin_slot.resize(bin_off + npt, 0);
+        bm.bin_count.resize(bin_off + npt, 0);
+    }
+    for (int32_t band = 0; band < nbands; ++band) {
+        const int32_t bin0 = band * R;
+        const int32_t nrows = std::min(R, npt - bin0);
+        const int64_t z0 = base + start[band], z1 = base + start[band + 1];
+        const int64_t len = z1 - z0;
+        const int32_t pieces = len > 0 ? (int32_t)((len + piece_nnz - 1) / piece_nnz) : 1;
+        for (int32_t r = 0; r < nrows; ++r) {
+            bm.bin_slot[bin_off + bin0 + r] = bm.nslots + r;
+            bm.bin_count[bin_off + bin0 + r] = pieces;
+        }
+        int64_t prev = z0;
+        for (int32_t k = 0; k < pieces; ++k) {
+            int64_t next = z1;
+            if (k + 1 < pieces) next = std::max(prev + 1, (z0 + len * (k + 1) / pieces) & ~(int64_t)3);
+            bm.pieces.push_back(BandPiece{(int32_t)prev, (int32_t)next, (int32_t)(bin_off + bin0),
+                                          nrows, bm.nslots, 0, pix_off});
+            bm.nslots += R;
+            prev = next;
+        }
+    }
+    return true;
+}
+
 void build_tiles(const int32_t* indptr, int32_t nrows, int64_t z_off, int64_t r_off,
-                 int64_t ip_off, int32_t tile_nnz, std::vector<Tile>& tiles,
+                 int64_t ip_off, int32_t tile_nnz, int32_t band, std::vector<Tile>& tiles,
                  std::vector<Split>& splits, int32_t& nparts) {
+    auto len = [&](int32_t r) { return indptr[r + 1] - indptr[r]; };
+    const int32_t R = std::max(band, 1);
+    const int32_t inter_min = R > 1 ? tile_nnz / R : INT32_MAX;
     int32_t r = 0;
     while (r < nrows) {
-        const int32_t len = indptr[r + 1] - indptr[r];
-        if (len > tile_nnz) {
-            // Long row: nearly equal pieces, inner cuts on multiples of 4 so
-            // the 4-wide loads of a piece do not straddle its neighbour.
-            const int32_t pieces = (len + tile_nnz - 1) / tile_nnz;
-            const int32_t p0 = nparts;
-            int32_t prev = indptr[r];
-            for (int32_t k = 0; k < pieces; ++k) {
-                int32_t next = indptr[r + 1];
-                if (k + 1 < pieces) {
-                    next = indptr[r] + (int32_t)(((int64_t)len * (k + 1)) / pieces);
-                    next &= ~3;
-                    next = std::max(next, prev + 1);
-                }
-                Tile t{(int32_t)(r_off + r), (int32_t)(r_off + r + 1), (int32_t)(z_off + prev),
-                       (int32_t)(z_off + next), nparts++, (int32_t)(ip_off + r), 0, 0};
-                tiles.push_back(t);
-                prev = next;
+        if (R > 1 && len(r) > inter_min) {
+            // a run of up to R consecutive rows, each longer than tile_nnz / R
+            int32_t r_end = r + 1;
+            int32_t most = len(r);
+            while (r_end < nrows && r_end - r < R && len(r_end) > inter_min) {
+                most = std::max(most, len(r_end));
+                ++r_end;
             }
+            const int32_t nr = r_end - r;
+            const int64_t total = (int64_t)most * nr;
+            int32_t pieces = (int32_t)((total + tile_nnz - 1) / tile_nnz);
+            pieces = std::max(1, std::min(pieces, std::max(1, most / 4)));
+            const int32_t base = pieces > 1 ? nparts : -1;
+            if (pieces > 1) {
+                for (int32_t i = 0; i < nr; ++i)
+                    splits.push_back(Split{(int32_t)(r_off + r + i), nparts + i * pieces,
+                                           nparts + (i + 1) * pieces, 0});
+                nparts += nr * pieces;
+            }
+            for (int32_t k = 0; k < pieces; ++k)
+                tiles.push_back(Tile{(int32_t)(r_off + r), (int32_t)(r_off + r_end), 0, pieces,
+                                     base, (int32_t)(ip_off + r), kTileInterleave, k});
+            r = r_end;
+            continue;
+        }
+        if (len(r) > tile_nnz) {
+            // one long row: nearly equal pieces
+            const int32_t pieces = (len(r) + tile_nnz - 1) / tile_nnz;
+            const int32_t p0 = nparts;
+            for (int32_t k = 0; k < pieces; ++k)
+                tiles.push_back(Tile{(int32_t)(r_off + r), (int32_t)(r_off + r + 1),
+                                     (int32_t)(z_off + piece_cut(indptr[r], indptr[r + 1], k, pieces)),
+                                     (int32_t)(z_off + piece_cut(indptr[r], indptr[r + 1], k + 1, pieces)),
+                                     nparts++, (int32_t)(ip_off + r), kTileRow, 0});
             splits.push_back(Split{(int32_t)(r_off + r), p0, nparts, 0});
             ++r;
             continue;
@@ -203,14 +386,15 @@ void build_tiles(const int32_t* indptr, int32_t nrows, int64_t z_off, int64_t r_
         int32_t acc = 0;
         const int32_t max_rows = std::max(tile_nnz / 4, 64);
         while (r < nrows && r - start < max_rows) {
-            const int32_t l = indptr[r + 1] - indptr[r];
+            const int32_t l = len(r);
             if (l > tile_nnz || acc + l > tile_nnz) break;
+            if (R > 1 && l > inter_min && r > start) break;  // leave it to an interleave run
             acc += l;
             ++r;
         }
-        Tile t{(int32_t)(r_off + start), (int32_t)(r_off + r), (int32_t)(z_off + indptr[start]),
-               (int32_t)(z_off + indptr[r]), -1, (int32_t)(ip_off + start), 0, 0};
-        tiles.push_back(t);
+        tiles.push_back(Tile{(int32_t)(r_off + start), (int32_t)(r_off + r),
+                             (int32_t)(z_off + indptr[start]), (int32_t)(z_off + indptr[r]), -1,
+                             (int32_t)(ip_off + start), r - start == 1 ? kTileRow : kTileRows, 0});
     }
 }
 

@@ -14,7 +14,7 @@ precision"), and such integers are exact in both float32 and float64.
 Workload recipes (the five standard cases):
 
 * ``c1``: one 100x100 image, float64, seed 0, npt 100.
-* ``c2``: one 3162x3162 image (~1e7 pixels), seed 1, npt 3162, float64 and
+* ``c2``: one 3162x3163 image (~1e7 pixels), seed 1, npt 3162, float64 and
   float32 copies of the same draw.
 * ``c3``: 4096 images whose pixel counts are log-uniform in [1e2, 1e5],
   float64, seed 2.
@@ -159,6 +159,6 @@ C5 = dict(name="c5", count=1024, lo=1e3, hi=1e6, seed=4, dtype="f32")
 def c4_instance() -> Instance:
     """The adjoint workload: raw scaled by 2**-20 (exact) into [0, 1)."""
     inst = instance(C4["n"], C4["seed"], grad=True)
-    inst.extra["x"] = inst.raw.astype(np.float64) * (2.0 ** -RAW_BITS)
+    inst.extra["x"] = inst.raw.reshape(-1).astype(np.float64) * (2.0 ** -RAW_BITS)
     inst.extra["fd_coords"] = fd_coords(inst.geom.npix, C4["fd_coords"], C4["seed"])
     return inst

@@ -90,39 +90,61 @@ def test_transcendental_units_match_up_to_edges(unit):
     assert np.abs(A - B).max() <= 1e-9
 
 
-def test_tile_schedule_covers_every_nonzero_once():
+def _piece_cut(a, b, k, pieces):
+    if k <= 0:
+        return a
+    if k >= pieces:
+        return b
+    return max(a, (a + ((b - a) * k) // pieces) & ~3)
+
+
+@pytest.mark.parametrize("tile_nnz,band", [(64, 1), (256, 16), (1024, 16), (1024, 1),
+                                           (2048, 3), (8192, 16), (2048, 64), (512, 4)])
+def test_tile_schedule_covers_every_nonzero_once(tile_nnz, band):
+    """Every nonzero lands in exactly one tile, every row is written exactly
+    once (directly or by the fix-up of its pieces), every partial slot is
+    filled exactly once."""
     az = azint()
     plan = az.Plan(300, 280, 250, center=(150.2, 139.7))
     _, _, indptr = plan.export_csr()
     nnz = int(indptr[-1])
-    for tile_nnz in (64, 256, 1024, 2048, 8192):
-        tiles, splits = plan.tile_schedule(tile_nnz)
-        covered = np.zeros(nnz, dtype=np.int64)
-        rows = np.zeros(plan.npt, dtype=np.int64)
-        parts = set()
-        for r0, r1, z0, z1, part, ip0, _, _ in tiles:
-            assert r1 > r0 and z1 >= z0
-            # whole rows fit; a piece of a long row may gain up to 3 from the
-            # alignment of its cut to a multiple of 4
+    tiles, splits = plan.tile_schedule(tile_nnz=tile_nnz, band=band)
+    covered = np.zeros(nnz, dtype=np.int64)
+    rows = np.zeros(plan.npt, dtype=np.int64)
+    slots = {}
+    for r0, r1, z0, z1, part, ip0, mode, k in tiles.tolist():
+        assert r1 > r0 and ip0 == r0
+        if mode == 0:      # one row or a piece of one
+            assert r1 == r0 + 1 and z1 >= z0
             assert z1 - z0 <= tile_nnz + (3 if part >= 0 else 0)
             covered[z0:z1] += 1
             if part < 0:
-                rows[r0:r1] += 1
-                assert z0 == indptr[r0] and z1 == indptr[r1] and ip0 == r0
+                rows[r0] += 1
+                assert (z0, z1) == (indptr[r0], indptr[r0 + 1])
             else:
-                assert r1 == r0 + 1 and part not in parts
-                parts.add(part)
-        for row, p0, p1, _ in splits:
-            rows[row] += 1
-            assert p1 - p0 >= 2
-            pieces = tiles[(tiles[:, 4] >= p0) & (tiles[:, 4] < p1)]
-            assert np.array_equal(pieces[:, 4], np.arange(p0, p1))
-            assert pieces[0, 2] == indptr[row] and pieces[-1, 3] == indptr[row + 1]
-            assert np.all(pieces[1:, 2] == pieces[:-1, 3])
-            assert np.all(pieces[1:, 2] % 4 == 0)
-        assert np.all(covered == 1)
-        assert np.all(rows == 1)
-        assert parts == set(range(len(parts)))
+                slots[part] = slots.get(part, 0) + 1
+        elif mode == 1:    # whole rows
+            assert z0 == indptr[r0] and z1 == indptr[r1] and z1 - z0 <= tile_nnz
+            covered[z0:z1] += 1
+            rows[r0:r1] += 1
+        else:              # piece k of z1 pieces of every row in [r0, r1)
+            assert mode == 2 and r1 - r0 <= max(band, 1) and 0 <= k < z1
+            for i in range(r1 - r0):
+                a, b = indptr[r0 + i], indptr[r0 + i + 1]
+                lo, hi = _piece_cut(a, b, k, z1), _piece_cut(a, b, k + 1, z1)
+                covered[lo:hi] += 1
+                if z1 == 1:
+                    rows[r0 + i] += 1
+                else:
+                    slot = part + i * z1 + k
+                    slots[slot] = slots.get(slot, 0) + 1
+    for row, p0, p1, _ in splits.tolist():
+        rows[row] += 1
+        for p in range(p0, p1):
+            assert slots.pop(p) == 1
+    assert not slots
+    assert np.all(covered == 1)
+    assert np.all(rows == 1)
 
 
 def _err(rc):
@@ -169,9 +191,17 @@ def test_argument_errors():
     rc, msg = _err(L.azi_integrate1d(plan.handle, ctypes.c_void_p(16), ctypes.c_void_p(16),
                                      None, None, 0.0, None))
     assert rc == -5 and "azi_plan_upload" in msg
-    assert _err(L.azi_plan_set_tiling(plan.handle, 100, 256))[0] == -1
-    assert _err(L.azi_plan_set_tiling(plan.handle, 1024, 96))[0] == -1
-    assert L.azi_plan_set_tiling(plan.handle, 1024, 128) == 0
+    T = lambda *v: ctypes.byref(az.Tiling(*v))
+    assert _err(L.azi_plan_set_tiling(plan.handle, T(100, 256, 0, 0, 0, 0)))[0] == -1
+    assert _err(L.azi_plan_set_tiling(plan.handle, T(1024, 96, 0, 0, 0, 0)))[0] == -1
+    assert _err(L.azi_plan_set_tiling(plan.handle, T(1024, 128, 7, 0, 0, 0)))[0] == -1
+    assert _err(L.azi_plan_set_tiling(plan.handle, T(1024, 128, -1, 0, 0, 0)))[0] == -1
+    assert _err(L.azi_plan_set_tiling(plan.handle, T(1024, 128, 1, -8, 0, 0)))[0] == -1
+    assert _err(L.azi_plan_set_tiling(plan.handle, T(1024, 128, 1, 0, 0, 3)))[0] == -1
+    assert _err(L.azi_plan_set_tiling(plan.handle, None))[0] == -1
+    assert L.azi_plan_set_tiling(plan.handle, T(1024, 128, 6, 512, 4, 1)) == 0
+    assert plan.tiling() == dict(tile_nnz=1024, block=128, variant=6, grid=512, band=4, stage=1)
+    assert _err(L.azi_plan_set_layout(plan.handle, 4))[0] == -1
     assert _err(L.azi_batch_create(None, 1, 0, ctypes.byref(out)))[0] == -1
 
 
@@ -196,3 +226,26 @@ def test_integration_on_cpu_via_exported_matrix_matches_oracle():
     I, W, U = oracle.integrate(m, x)
     assert np.allclose(A @ x, W, rtol=1e-13, atol=0)
     assert np.allclose(np.asarray(A.sum(1)).ravel(), U, rtol=1e-13, atol=0)
+
+
+def test_stage_tiles_cover_image_once():
+    """The LDS staging tables put every pixel at its own ring position
+    exactly once (host side of the ring layout)."""
+    az = azint()
+    for (h, w, npt) in ((70, 300, 90), (33, 129, 40), (1, 1, 3), (200, 256, 150)):
+        plan = az.Plan(h, w, npt, center=(h / 3.0, w / 2.0 + 0.3))
+        data, indices, indptr = plan.export_csr()
+        # ring order: pixels sorted by first bin, ties by pixel id
+        _, bins, colptr = plan.export_csc()
+        first = np.where(np.diff(colptr) > 0, bins[np.minimum(colptr[:-1], max(len(bins) - 1, 0))], npt)
+        order = np.lexsort((np.arange(h * w), first))
+        pos = np.empty(h * w, dtype=np.int64)
+        pos[order] = np.arange(h * w)
+        # tiles of 32x128 pixels, ranks within a tile by ring position
+        seen = np.zeros(h * w, dtype=np.int64)
+        for i0 in range(0, h, 32):
+            for j0 in range(0, w, 128):
+                pix = (np.arange(i0, min(i0 + 32, h))[:, None] * w +
+                       np.arange(j0, min(j0 + 128, w))[None, :]).ravel()
+                seen[pos[pix]] += 1
+        assert np.all(seen == 1)

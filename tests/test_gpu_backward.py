@@ -118,7 +118,8 @@ def test_autograd_function_gradcheck(dev):
         I, W, _ = az.Integrate1d.apply(x, plan, 0.0)
         return I, W
 
-    assert torch.autograd.gradcheck(f, (x,), eps=1e-6, atol=1e-9, rtol=1e-7)
+    # W ~ 30 here: its rounding (~4e-15) over 2*eps gives ~2e-9 of FD noise
+    assert torch.autograd.gradcheck(f, (x,), eps=1e-6, atol=2e-8, rtol=1e-7)
 
 
 def test_backward_wrt_raw_with_corrections(dev):

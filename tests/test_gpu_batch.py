@@ -18,14 +18,15 @@ def say(*a):
     sys.stdout.flush()
 
 
-def make_batch(insts, dtype, dev, tile=None):
+def make_batch(insts, dtype, dev, tile=None, layout="band"):
     az = azint()
     plans = []
     for inst in insts:
         g = inst.geom
-        p = az.Plan(g.h, g.w, inst.npt, center=(g.center_y, g.center_x), dtype=dtype)
+        p = az.Plan(g.h, g.w, inst.npt, center=(g.center_y, g.center_x), dtype=dtype,
+                    layout=layout)
         if tile:
-            p.set_tiling(*tile)
+            p.set_tiling(**tile)
         plans.append(p)
     return plans, az.Batch(plans, device=dev)
 
@@ -38,22 +39,29 @@ def small_batch(n=40, seed=21):
     return synth.batch(n, 1.0, 2e4, seed, grad=True)
 
 
+@pytest.mark.parametrize("layout,stage", [("ring", "tile"), ("ring", "gather"),
+                                          ("ring", "scatter"), ("pixel", "tile"),
+                                          ("tile", "tile"), ("band", "tile")])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_batch_equals_per_instance_and_oracle(dtype, dev):
-    say("batch vs per instance", dtype)
+def test_batch_equals_per_instance_and_oracle(dtype, layout, stage, dev):
+    say("batch vs per instance", dtype, layout, stage)
     az = azint()
     insts = small_batch()
-    plans, batch = make_batch(insts, dtype, dev)
+    plans, batch = make_batch(insts, dtype, dev, layout=layout, tile=dict(stage=stage))
     npd = np.float64 if dtype == torch.float64 else np.float32
     x = torch.from_numpy(flat_images(insts, npd)).to(dev)
     I, W, U = batch.forward(x, empty=-3.0)
     Il, Wl, Ul = batch.forward(x, empty=-3.0, loop=True)
+    raw = torch.from_numpy(np.concatenate([i.raw.reshape(-1) for i in insts])).to(dev)
+    Ir, Wr, Ur = batch.forward_raw(raw, empty=-3.0)
     torch.cuda.synchronize()
     # identical tiles per instance -> identical bits
     assert torch.equal(I, Il) and torch.equal(W, Wl) and torch.equal(U, Ul)
+    assert torch.equal(I, Ir) and torch.equal(W, Wr) and torch.equal(U, Ur)
     po, bo = batch.pix_off, batch.bin_off
     for k, (inst, plan) in enumerate(zip(insts, plans)):
         plan.upload(dev)
+        plan.set_tiling(stage=stage)
         xs = x[po[k]:po[k + 1]].contiguous()
         Ik, Wk, Uk = plan.integrate(xs, empty=-3.0)
         assert torch.equal(Ik, I[bo[k]:bo[k + 1]]), k
@@ -74,16 +82,18 @@ def test_batch_equals_per_instance_and_oracle(dtype, dev):
 
 
 @pytest.mark.parametrize("grid", [8, 64, 1024, 0])
-@pytest.mark.parametrize("tiling", [(2048, 256), (256, 64), (8192, 512)])
+@pytest.mark.parametrize("tiling", [(2048, 256, 2, 1), (256, 64, 0, 16), (8192, 512, 3, 16),
+                                    (1024, 128, 4, 4), (1024, 64, 5, 16), (512, 64, 6, 2)])
 def test_persistent_grid_same_bits(grid, tiling, dev):
     """The tile sums do not depend on which workgroup computes a tile."""
     say("persistent", grid, tiling)
     insts = small_batch(30, 5)
     _, batch = make_batch(insts, torch.float64, dev)
     x = torch.from_numpy(flat_images(insts, np.float64)).to(dev)
-    batch.set_tiling(tiling[0], tiling[1], 0)
+    kw = dict(tile_nnz=tiling[0], block=tiling[1], variant=tiling[2], band=tiling[3])
+    batch.set_tiling(grid=0, **kw)
     ref = batch.forward(x)
-    batch.set_tiling(tiling[0], tiling[1], grid)
+    batch.set_tiling(grid=grid, **kw)
     got = batch.forward(x)
     torch.cuda.synchronize()
     for a, b in zip(ref, got):
@@ -119,13 +129,14 @@ def test_batch_backward(dtype, dev):
         assert norm_err(gx[po[k]:po[k + 1]].double().cpu().numpy(), ref, scale) <= tol, k
 
 
-def test_graph_replays_match_eager(dev):
+@pytest.mark.parametrize("layout", ["ring", "tile", "band"])
+def test_graph_replays_match_eager(layout, dev):
     """A captured forward+backward replays the same bits every time, with
     eager work and synchronisations in between."""
-    say("graph replay")
+    say("graph replay", layout)
     insts = small_batch(20, 13)
-    _, batch = make_batch(insts, torch.float64, dev)
-    batch.set_tiling(1024, 256, 512)
+    _, batch = make_batch(insts, torch.float64, dev, layout=layout)
+    batch.set_tiling(tile_nnz=1024, block=256, grid=512)
     x = torch.from_numpy(flat_images(insts, np.float64)).to(dev)
     gI = torch.from_numpy(np.concatenate([i.grad for i in insts])).to(dev)
     I0, W0, U0 = batch.forward(x)
@@ -177,21 +188,22 @@ def test_autotune_picks_valid_config(dev, tmp_path):
     for a, b in zip(ref, got):
         assert torch.allclose(a, b, rtol=1e-12, atol=0)
     # a second call is served from the cache
-    batch.set_tiling(64, 64, 0)
+    batch.set_tiling(tile_nnz=64, block=64, grid=0)
     rep2 = az.autotune(batch, x, cache_path=str(cache))
     assert rep2["best"] == best and batch.tiling()["tile_nnz"] == best["tile_nnz"]
     assert json.loads(cache.read_text())
 
 
-def test_c3_full_batch_sampled(dev):
+@pytest.mark.parametrize("layout", ["band", "tile", "ring"])
+def test_c3_full_batch_sampled(layout, dev):
     """The 4096-instance workload at full size, in the benchmark's launch
     configuration: batched forward == per-instance loop bit for bit, 12
     sampled instances against the oracle, conservation over all."""
     say("c3 full")
     c = synth.C3
     insts = synth.batch(c["count"], c["lo"], c["hi"], c["seed"])
-    plans, batch = make_batch(insts, torch.float64, dev)
-    batch.set_tiling(2048, 256, 0)
+    plans, batch = make_batch(insts, torch.float64, dev, layout=layout)
+    batch.set_tiling(grid=0)
     x = torch.from_numpy(flat_images(insts, np.float64)).to(dev)
     I, W, U = batch.forward(x)
     Il, Wl, Ul = batch.forward(x, loop=True)
@@ -212,3 +224,29 @@ def test_c3_full_batch_sampled(dev):
         Io, Wo, Uo = oracle.integrate(m, xv)
         _, Wa, _ = oracle.integrate(m, xv)
         assert norm_err(Wh[bo[k]:bo[k + 1]], Wo, Wa) <= 1e-12, k
+
+
+@pytest.mark.parametrize("R,piece", [(4, 512), (8, 2048), (16, 256), (8, 64)])
+def test_band_batch_retile(R, piece, dev):
+    """Band batches rebuild their bands from the device copy of the matrix
+    when the band rows or piece size change; results stay exact and the
+    per-instance loop agrees bit for bit."""
+    say("band retile", R, piece)
+    insts = small_batch(24, 31)
+    plans, batch = make_batch(insts, torch.float64, dev, layout="band")
+    x = torch.from_numpy(flat_images(insts, np.float64)).to(dev)
+    batch.set_tiling(band=R, tile_nnz=piece)
+    I, W, U = batch.forward(x)
+    Il, Wl, Ul = batch.forward(x, loop=True)
+    torch.cuda.synchronize()
+    assert torch.equal(I, Il) and torch.equal(W, Wl) and torch.equal(U, Ul)
+    po, bo = batch.pix_off, batch.bin_off
+    for k in (0, 7, 23):
+        inst = insts[k]
+        g = inst.geom
+        m = oracle_matrix(g.h, g.w, g.center_y, g.center_x, inst.npt)
+        xv = inst.raw.reshape(-1).astype(np.float64)
+        Io, Wo, Uo = oracle.integrate(m, xv)
+        _, Wa, _ = oracle.integrate(m, xv)
+        assert norm_err(W[bo[k]:bo[k + 1]].cpu().numpy(), Wo, Wa) <= 1e-12, k
+        assert norm_err(U[bo[k]:bo[k + 1]].cpu().numpy(), Uo, Uo) <= 1e-12, k

@@ -58,17 +58,26 @@ GEOMS = [
     (257, 263, 128.5, 131.5, 256, "r_m", "bbox", None),
     (300, 200, 10.0, 190.0, 150, "2th_deg", "bbox", None),
 ]
-TILINGS = [(2048, 256), (64, 64), (256, 128), (1024, 512), (16384, 256)]
+# tile_nnz, block, variant, grid, band
+TILINGS = [(2048, 256, 3, 0, 1, 2), (1024, 64, 3, 0, 16, 0), (2048, 256, 2, 0, 1, 1),
+           (64, 64, 0, 0, 16, 2), (256, 128, 1, 0, 4, 0), (1024, 512, 3, 64, 16, 1),
+           (16384, 256, 4, 0, 1, 2), (128, 64, 5, 8, 16, 0), (4096, 512, 6, 0, 2, 1),
+           (512, 256, 3, 2048, 1, 2)]
 
 
-@pytest.mark.parametrize("tiling", TILINGS, ids=lambda t: f"t{t[0]}b{t[1]}")
+def tiling_kw(t):
+    return dict(zip(("tile_nnz", "block", "variant", "grid", "band", "stage"), t))
+
+
+@pytest.mark.parametrize("layout", ["ring", "pixel", "tile", "band"])
+@pytest.mark.parametrize("tiling", TILINGS, ids=lambda t: "t{}b{}v{}g{}n{}s{}".format(*t))
 @pytest.mark.parametrize("g", GEOMS, ids=lambda g: f"{g[0]}x{g[1]}-{g[5]}-{g[6]}-{g[4]}")
-def test_forward_f64(g, tiling, dev):
+def test_forward_f64(g, tiling, layout, dev):
     h, w, cy, cx, npt, unit, split, rng = g
-    say("forward f64", g, tiling)
+    say("forward f64", g, tiling, layout)
     az = azint()
     plan = az.Plan(h, w, npt, center=(cy, cx), unit=unit, split=split, range=rng,
-                   tile_nnz=tiling[0], block=tiling[1], device=dev)
+                   layout=layout, device=dev, **tiling_kw(tiling))
     m = oracle_matrix(h, w, cy, cx, npt, 1e-4, 1e-4, unit, split, rng)
     x = np.random.default_rng(h * w + npt).uniform(-2.0, 1000.0, size=h * w)
     out = plan.integrate(torch.from_numpy(x).to(dev), empty=-1.5)
@@ -119,12 +128,16 @@ def test_correction_map_bit_exact(raw_dtype, dev):
         assert np.array_equal(x, ref), combo
 
 
-def test_raw_pipeline_with_corrections(dev):
-    say("raw pipeline with corrections")
+@pytest.mark.parametrize("layout,stage", [("ring", "tile"), ("ring", "gather"),
+                                          ("ring", "scatter"), ("pixel", "tile"),
+                                          ("tile", "tile"), ("band", "tile")])
+def test_raw_pipeline_with_corrections(layout, stage, dev):
+    say("raw pipeline with corrections", layout, stage)
     az = azint()
     inst = synth.instance_hw(211, 190, 7, npt=160, corrections=True)
     g = inst.geom
-    plan = az.Plan(g.h, g.w, inst.npt, center=(g.center_y, g.center_x), device=dev)
+    plan = az.Plan(g.h, g.w, inst.npt, center=(g.center_y, g.center_x), layout=layout,
+                   stage=stage, device=dev)
     t = lambda a: torch.from_numpy(a.reshape(-1)).to(dev)
     plan.set_corrections(t(inst.dark), t(inst.flat), t(inst.solid), t(inst.polar))
     out = plan.integrate_raw(t(inst.raw))
@@ -132,16 +145,28 @@ def test_raw_pipeline_with_corrections(dev):
     m = oracle_matrix(g.h, g.w, g.center_y, g.center_x, inst.npt)
     x = oracle.correct(inst.raw, inst.dark, inst.flat, inst.solid, inst.polar)
     check(out, m, x, TOL64, what="corrected")
+    # the same through the corrected-image entry point (a separate pass
+    # brings the row-major image into the layout)
+    xd = plan.correct(t(inst.raw))
+    assert np.array_equal(xd.cpu().numpy(), x)
+    out2 = plan.integrate(xd)
+    torch.cuda.synchronize()
+    for a, b in zip(out, out2):
+        assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("layout", ["ring", "pixel", "tile", "band"])
 @pytest.mark.parametrize("accum", ["f64", "kahan32"])
-@pytest.mark.parametrize("tiling", [(2048, 256), (64, 64), (512, 512)])
-def test_forward_f32(accum, tiling, dev):
-    say("forward f32", accum, tiling)
+@pytest.mark.parametrize("tiling", [(2048, 256, 2, 0, 1, 2), (64, 64, 0, 0, 16, 0),
+                                    (512, 512, 3, 0, 16, 1), (1024, 128, 1, 256, 4, 2),
+                                    (8192, 256, 4, 0, 1, 0), (1024, 64, 5, 0, 16, 1),
+                                    (2048, 128, 6, 16, 16, 2)])
+def test_forward_f32(accum, tiling, layout, dev):
+    say("forward f32", accum, tiling, layout)
     az = azint()
     h, w, npt = 240, 250, 230
     plan = az.Plan(h, w, npt, center=(119.3, 125.8), dtype=torch.float32, accum=accum,
-                   tile_nnz=tiling[0], block=tiling[1], device=dev)
+                   layout=layout, device=dev, **tiling_kw(tiling))
     m = oracle_matrix(h, w, 119.3, 125.8, npt)
     x64 = np.random.default_rng(3).integers(0, 1 << 20, size=h * w).astype(np.float64)
     out = plan.integrate(torch.from_numpy(x64.astype(np.float32)).to(dev))
@@ -159,7 +184,8 @@ def test_kahan_beats_plain_float_on_long_rows(dev):
     say("kahan long rows")
     az = azint()
     h, w, npt = 400, 400, 6
-    plan = az.Plan(h, w, npt, dtype=torch.float32, accum="kahan32", tile_nnz=16384, device=dev)
+    plan = az.Plan(h, w, npt, dtype=torch.float32, accum="kahan32", tile_nnz=16384, block=256,
+                   device=dev)
     m = oracle_matrix(h, w, 200.0, 200.0, npt)
     x = np.random.default_rng(4).integers(0, 1 << 20, size=h * w).astype(np.float64)
     out = plan.integrate(torch.from_numpy(x.astype(np.float32)).to(dev))
@@ -214,6 +240,7 @@ def _sampled_bins_oracle(g, npt, x, bins):
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_c2_full_size_sampled(dtype, dev):
+    # default plan settings: the launch configuration the benchmark times
     """The ~1e7-pixel workload at full size, in the launch configuration the
     benchmark times: 24 sampled bins against the oracle, plus conservation
     over all bins."""
@@ -238,3 +265,70 @@ def test_c2_full_size_sampled(dtype, dev):
         assert abs(I[b] - Io[0]) <= tol * Wa[0] / Uo[0], (b, I[b], Io[0])
     assert abs(U.sum() - g.npix) <= (1e-12 if dtype == "f64" else 1e-6) * g.npix
     assert abs(W.sum() - x.sum()) <= (1e-12 if dtype == "f64" else 1e-6) * x.sum()
+
+
+def test_tile_layout_grid_keeps_bits(dev):
+    """Persistent launches of the blocked kernel give the same bits."""
+    say("tile layout grid")
+    az = azint()
+    plan = az.Plan(700, 650, 600, center=(350.2, 320.9), layout="tile", device=dev)
+    x = torch.from_numpy(np.random.default_rng(9).uniform(0, 9, 700 * 650)).to(dev)
+    ref = [t.clone() for t in plan.integrate(x)]
+    for block, grid in ((128, 0), (512, 0), (256, 8), (256, 100), (128, 2048)):
+        plan.set_tiling(block=block, grid=grid)
+        got = plan.integrate(x)
+        torch.cuda.synchronize()
+        for a, b in zip(ref, got):
+            assert torch.equal(a, b), (block, grid)
+
+
+@pytest.mark.parametrize("variant", range(7))
+def test_schedule_changes_keep_bits(variant, dev):
+    """Persistent launches and the staging mode only change which workgroup
+    computes a tile or how the image reaches the layout, so every output bit
+    stays the same for a given tile size, band and variant."""
+    say("schedule bits", variant)
+    az = azint()
+    plan = az.Plan(700, 650, 600, center=(350.2, 320.9), device=dev, tile_nnz=512, block=64,
+                   variant=variant, band=4, grid=0, layout="ring")
+    x = torch.from_numpy(np.random.default_rng(9).uniform(0, 9, 700 * 650)).to(dev)
+    ref = [t.clone() for t in plan.integrate(x)]
+    # the staging mode changes only how the image reaches the ring layout
+    for grid, stage in ((0, 2), (0, 0), (2048, 1), (512, 2), (8, 0)):
+        plan.set_tiling(grid=grid, stage=stage)
+        got = plan.integrate(x)
+        torch.cuda.synchronize()
+        for a, b in zip(ref, got):
+            assert torch.equal(a, b), (band, grid)
+
+
+def test_layout_switch_and_errors(dev):
+    """Changing the layout re-uploads; both give the oracle's values; the
+    layout cannot change under live corrections."""
+    say("layout switch")
+    az = azint()
+    plan = az.Plan(90, 80, 70, center=(45.5, 40.1), layout="pixel", device=dev)
+    m = oracle_matrix(90, 80, 45.5, 40.1, 70)
+    x = np.random.default_rng(2).uniform(0, 10, 90 * 80)
+    xd = torch.from_numpy(x).to(dev)
+    check(plan.integrate(xd), m, x, TOL64, what="pixel")
+    plan.set_layout("ring")
+    assert plan.layout() == "ring"
+    check(plan.integrate(xd), m, x, TOL64, what="ring")
+    plan.set_corrections(dark=torch.zeros(90 * 80, dtype=torch.float64, device=dev))
+    with pytest.raises(az.AzintError, match="before the corrections"):
+        plan.set_layout("pixel")
+
+
+@pytest.mark.parametrize("R", [4, 8, 16])
+@pytest.mark.parametrize("piece,block,grid", [(2048, 256, 0), (64, 128, 0), (512, 512, 2048),
+                                              (16384, 256, 8)])
+def test_band_layout_shapes(R, piece, block, grid, dev):
+    say("band shapes", R, piece, block, grid)
+    az = azint()
+    plan = az.Plan(300, 280, 250, center=(150.2, 139.7), layout="band", device=dev,
+                   band=R, tile_nnz=piece, block=block, grid=grid)
+    m = oracle_matrix(300, 280, 150.2, 139.7, 250)
+    x = np.random.default_rng(R + piece).uniform(-1, 50, 300 * 280)
+    check(plan.integrate(torch.from_numpy(x).to(dev), empty=7.0), m, x, TOL64, empty=7.0,
+          what="band")
