@@ -45,6 +45,13 @@ R6  every inner bin receives 1 / (fh - fl): the overlap of a whole bin over
     distributed" amounts to for uniform bins.
 R7  an empty bin (U = 0) yields the caller's ``empty`` value (default 0.0).
 R9  units: r in m or mm, 2theta in rad or deg, q in 1/nm.
+R13 full pixel splitting (Section 4.2): the four pixel corners are mapped
+    to (pos0, pos1) = (output unit, azimuth chi = atan2(y, x)), the edges
+    between them taken as straight lines; bin b receives the area of that
+    quadrilateral lying in the bin's pos0 slab over the quadrilateral's
+    whole area.  The corner azimuths are unwrapped to within pi of corner 0;
+    a pixel whose square holds the beam centre (lo == 0), where the
+    quadrilateral is undefined, falls back to the bounding box.
 """
 from __future__ import annotations
 
@@ -53,11 +60,12 @@ import math
 import numpy as np
 
 UNITS = ("r_m", "r_mm", "2th_rad", "2th_deg", "q_nm")
-SPLITS = ("none", "bbox")
+SPLITS = ("none", "bbox", "full")
 
 __all__ = [
     "UNITS", "SPLITS", "unit_of_radius", "pixel_extents", "pixel_extents_loop",
     "default_range", "bbox_entries", "bbox_entries_loop", "nosplit_entries",
+    "pixel_corners", "full_entries", "polygon_area", "clip_slab",
     "entries_to_csr", "build_matrix", "correct", "integrate", "integrate_loop",
     "integrate_vjp", "kahan_sum_f32", "positions",
 ]
@@ -148,7 +156,7 @@ def pixel_extents_loop(h, w, pixel_y, pixel_x, center_y, center_x, dist,
 
 def default_range(lo, hi, centre, split):
     """Reading R3: [min lo, max hi] with splitting, [min c, max c] without."""
-    if split == "bbox":
+    if split in ("bbox", "full"):
         return float(np.min(lo)), float(np.max(hi))
     return float(np.min(centre)), float(np.max(centre))
 
@@ -243,6 +251,99 @@ def bbox_entries(lo, hi, npt, pmin, pmax):
     return np.concatenate(out_p), np.concatenate(out_b), np.concatenate(out_c)
 
 
+def pixel_corners(h, w, pixel_y, pixel_x, center_y, center_x, dist, wavelength, unit="r_m"):
+    """Corner coordinates (pos0, pos1) of every pixel, shape (h*w, 4, 2), in
+    the order (j, i), (j+1, i), (j+1, i+1), (j, i+1): pos0 is the output unit
+    of the corner radius, pos1 its azimuth atan2(y, x) unwrapped to within pi
+    of the first corner (reading R13)."""
+    i = np.arange(h, dtype=np.int64)[:, None]
+    j = np.arange(w, dtype=np.int64)[None, :]
+    out = np.empty((h, w, 4, 2))
+    for k, (a, b) in enumerate(((0, 0), (1, 0), (1, 1), (0, 1))):
+        x = ((j + a) - center_x) * pixel_x
+        y = ((i + b) - center_y) * pixel_y
+        r = np.sqrt(x * x + y * y)
+        out[:, :, k, 0] = unit_of_radius(r, unit, dist, wavelength)
+        out[:, :, k, 1] = np.arctan2(y, x)
+    chi0 = out[:, :, :1, 1]
+    turns = np.round((chi0 - out[:, :, :, 1]) / (2.0 * math.pi))
+    out[:, :, :, 1] = out[:, :, :, 1] + turns * (2.0 * math.pi)
+    return out.reshape(h * w, 4, 2)
+
+
+def clip_slab(poly, x0, x1):
+    """The part of polygon `poly` (list of (x, y)) with x0 <= x <= x1, by
+    clipping against the two vertical lines in turn (Sutherland-Hodgman).
+    Works on floats or Fractions alike."""
+    def clip(pts, inside, cross):
+        out = []
+        n = len(pts)
+        for k in range(n):
+            p, q = pts[k], pts[(k + 1) % n]
+            pin, qin = inside(p), inside(q)
+            if pin:
+                out.append(p)
+            if pin != qin:
+                out.append(cross(p, q))
+        return out
+
+    def at(xc):
+        def cross(p, q):
+            t = (xc - p[0]) / (q[0] - p[0])
+            return (xc, p[1] + t * (q[1] - p[1]))
+        return cross
+
+    pts = clip(list(poly), lambda p: p[0] >= x0, at(x0))
+    if not pts:
+        return []
+    return clip(pts, lambda p: p[0] <= x1, at(x1))
+
+
+def polygon_area(poly):
+    """Absolute shoelace area."""
+    s = 0
+    n = len(poly)
+    for k in range(n):
+        (x0, y0), (x1, y1) = poly[k], poly[(k + 1) % n]
+        s += x0 * y1 - x1 * y0
+    return abs(s) / 2
+
+
+def full_entries(corners, lo, hi, npt, pmin, pmax):
+    """Full pixel splitting (Section 4.2, reading R13), one pixel at a time:
+    bin b gets area(quadrilateral within bin b's slab) / area(quadrilateral).
+    Pixels holding the beam centre use the bounding box of Section 4.1."""
+    delta = (pmax - pmin) / npt
+    pix, bins, coef = [], [], []
+    for p in range(len(corners)):
+        if float(lo[p]) == 0.0:
+            bp, bb, bc = bbox_entries_loop(lo[p:p + 1], hi[p:p + 1], npt, pmin, pmax)
+            pix += [p] * len(bb)
+            bins += bb.tolist()
+            coef += bc.tolist()
+            continue
+        xs = [float(c[0]) for c in corners[p]]
+        fl = (min(xs) - pmin) / delta
+        fh = (max(xs) - pmin) / delta
+        # areas are taken relative to the first corner (translation leaves
+        # them unchanged and keeps the products small)
+        x0, y0 = float(corners[p][0][0]), float(corners[p][0][1])
+        quad = [(float(c[0]) - x0, float(c[1]) - y0) for c in corners[p]]
+        area = polygon_area(quad)
+        if area == 0.0 or fh == fl:
+            continue
+        b0 = max(math.floor(fl), 0)
+        b1 = min(math.ceil(fh) - 1, npt - 1)
+        for b in range(b0, b1 + 1):
+            e0 = (pmin + b * delta) - x0
+            e1 = (pmin + (b + 1) * delta) - x0
+            c = polygon_area(clip_slab(quad, e0, e1)) / area
+            if c > 0.0:
+                pix.append(p); bins.append(b); coef.append(c)
+    return (np.asarray(pix, dtype=np.int64), np.asarray(bins, dtype=np.int64),
+            np.asarray(coef, dtype=np.float64))
+
+
 def nosplit_entries(centre, npt, pmin, pmax):
     """No splitting (Section 3.3): each pixel goes whole to the bin holding
     its centre; the last bin is closed (reading R3)."""
@@ -274,6 +375,10 @@ def build_matrix(h, w, pixel_y, pixel_x, center_y, center_x, dist, wavelength,
         raise ValueError("empty integration range")
     if split == "bbox":
         ent = (bbox_entries_loop if loop else bbox_entries)(lo, hi, npt, pmin, pmax)
+    elif split == "full":
+        corners = pixel_corners(h, w, pixel_y, pixel_x, center_y, center_x, dist, wavelength,
+                                unit)
+        ent = full_entries(corners, lo, hi, npt, pmin, pmax)
     elif split == "none":
         ent = nosplit_entries(rc, npt, pmin, pmax)
     else:

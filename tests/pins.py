@@ -367,7 +367,114 @@ def pin_correction(O):
     assert np.array_equal(O.correct(raw, solid=solid, polar=polar), [5.0, 7.0, 1.5, 4000.0])
 
 
+FULL_CASES = [
+    # (h, w, center_y, center_x, npt, pixel_y, pixel_x)
+    (5, 6, 2.5, 3.0, 9, 1e-4, 1e-4),
+    (6, 5, 7.3, -2.1, 8, 1e-4, 1e-4),      # beam off the detector, left of it
+    (4, 7, 1.7, 3.2, 15, 1.5e-4, 1e-4),
+    (7, 7, 3.5, 3.5, 4, 1e-4, 1e-4),
+]
+
+
+def pin_full_exact(O):
+    """P12: full-splitting coefficients equal the exact area fractions of the
+    corner quadrilaterals (clipped exactly in rational arithmetic from the
+    float64 corner coordinates), bbox where the pixel holds the centre."""
+    for case in FULL_CASES:
+        h, w, cy, cx, npt, py, px = case
+        args = _geom_args(case)
+        m = O.build_matrix(npt=npt, split="full", **args)
+        corners = O.pixel_corners(h, w, py, px, cy, cx, DIST, WL, "r_m")
+        pmin, pmax = F(m["pmin"]), F(m["pmax"])
+        d = (pmax - pmin) / npt
+        got = {(b, p): c for b, p, c in zip(m["bins"].tolist(), m["pix"].tolist(),
+                                              m["coef"].tolist())}
+        exact = {}
+        for p in range(h * w):
+            if m["lo"][p] == 0.0:
+                continue
+            quad = [(F(float(a)), F(float(b))) for a, b in corners[p]]
+            area = O.polygon_area(quad)
+            for b in range(npt):
+                a_b = O.polygon_area(O.clip_slab(quad, pmin + b * d, pmin + (b + 1) * d))
+                if a_b > 0:
+                    exact[(b, p)] = a_b / area
+        for key, ref in exact.items():
+            assert abs(got.get(key, 0.0) - float(ref)) <= 1e-12, (case, key)
+        for key, c in got.items():
+            p = key[1]
+            if m["lo"][p] != 0.0:
+                assert abs(c - float(exact.get(key, 0))) <= 1e-12, (case, key)
+
+
+def pin_full_physical_area(O):
+    """P13: away from the beam the corner quadrilateral in (r, chi) is close
+    to the pixel's image, so its split follows the physical area of the pixel
+    square inside each annulus (Monte Carlo, 4e5 points per pixel)."""
+    rng = np.random.default_rng(3)
+    # second geometry: beam right of the detector, so the middle rows straddle
+    # the azimuth cut at +-pi
+    for (h, w, cy, cx, npt, pixels) in ((6, 6, -40.0, -35.0, 12, (0, 7, 14, 21, 35)),
+                                        (6, 6, 3.0, 46.0, 10, (12, 13, 15, 17, 3))):
+        args = dict(h=h, w=w, pixel_y=1e-4, pixel_x=1e-4, center_y=cy, center_x=cx,
+                    dist=DIST, wavelength=WL)
+        m = O.build_matrix(npt=npt, split="full", **args)
+        delta = (m["pmax"] - m["pmin"]) / npt
+        for p in pixels:
+            i, j = divmod(p, w)
+            u = rng.uniform(0, 1, size=(400000, 2))
+            x = (j + u[:, 0] - cx) * 1e-4
+            y = (i + u[:, 1] - cy) * 1e-4
+            fb = np.floor((np.sqrt(x * x + y * y) - m["pmin"]) / delta).astype(int)
+            frac = np.bincount(np.clip(fb, 0, npt - 1), minlength=npt) / len(fb)
+            sel = m["pix"] == p
+            got = np.zeros(npt)
+            got[m["bins"][sel]] = m["coef"][sel]
+            assert np.abs(got - frac).max() < 5e-3, (cy, cx, p, got, frac)
+
+
+def pin_full_conservation(O):
+    """P14: full splitting conserves pixels and signal like the bounding box
+    (Section 4), and a pixel inside one bin goes there whole."""
+    rng = np.random.default_rng(4)
+    for (h, w, npt, cy, cx) in [(30, 25, 40, 14.6, 12.2), (20, 20, 3, 10.0, 10.0)]:
+        m = O.build_matrix(h=h, w=w, pixel_y=1e-4, pixel_x=1e-4, center_y=cy, center_x=cx,
+                           dist=DIST, wavelength=WL, npt=npt, split="full")
+        x = rng.uniform(0, 5, size=h * w)
+        I, W, U = O.integrate(m, x)
+        assert abs(U.sum() - h * w) <= 1e-12 * h * w
+        assert abs(W.sum() - x.sum()) <= 1e-12 * x.sum()
+        s = np.zeros(h * w)
+        np.add.at(s, m["pix"], m["coef"])
+        assert np.abs(s - 1.0).max() <= 1e-13
+        single = np.bincount(m["pix"], minlength=h * w) == 1
+        assert np.all(m["coef"][single[m["pix"]]] == 1.0)
+
+
+def pin_full_rotation(O):
+    """P15: turning the detector by 180 degrees about the beam shifts every
+    azimuth by pi and leaves every radius alone, so each pixel's full split
+    equals that of its twin -- including pixels whose corners straddle the
+    +-pi cut on one side and not on the other (reading R13's unwrapping)."""
+    for (n, cy, cx, npt) in ((6, 3.0, 3.3, 11), (7, 2.0, 4.6, 13), (5, 1.0, 2.5, 9)):
+        def mat(cy_, cx_):
+            m = O.build_matrix(h=n, w=n, pixel_y=1e-4, pixel_x=1e-4, center_y=cy_,
+                               center_x=cx_, dist=DIST, wavelength=WL, npt=npt, split="full")
+            A = np.zeros((npt, n * n))
+            A[m["bins"], m["pix"]] = m["coef"]
+            return A, m
+        A, m = mat(cy, cx)
+        B, mb = mat(n - cy, n - cx)
+        assert abs(m["pmin"] - mb["pmin"]) <= 1e-18 and abs(m["pmax"] - mb["pmax"]) <= 1e-18
+        for p in range(n * n):
+            i, j = divmod(p, n)
+            q = (n - 1 - i) * n + (n - 1 - j)
+            assert np.abs(A[:, p] - B[:, q]).max() <= 1e-9, (n, cy, cx, p, A[:, p], B[:, q])
+
+
 ALL_PINS = [pin_extents_exact, pin_bbox_bruteforce, pin_results_exact,
             pin_nosplit_histogram, pin_naive_mean, pin_conservation, pin_unit_weights,
             pin_constant_image, pin_symmetry, pin_scipy_csr, pin_adjoint, pin_kahan,
-            pin_closed_forms, pin_bbox_clipped, pin_correction]
+            pin_closed_forms, pin_bbox_clipped, pin_correction,
+            pin_full_exact, pin_full_physical_area, pin_full_conservation,
+            pin_full_rotation]

@@ -15,7 +15,32 @@ from tests import pins
 
 _orig = {name: getattr(O, name) for name in
          ("pixel_extents", "bbox_entries", "nosplit_entries", "integrate",
-          "integrate_vjp", "kahan_sum_f32", "unit_of_radius", "correct")}
+          "integrate_vjp", "kahan_sum_f32", "unit_of_radius", "correct",
+          "pixel_corners", "full_entries", "polygon_area")}
+
+
+def _corners_no_unwrap(h, w, pixel_y, pixel_x, center_y, center_x, dist, wavelength,
+                       unit="r_m"):
+    # azimuths left in (-pi, pi]: a pixel across the cut becomes a bow tie
+    i = np.arange(h)[:, None]
+    j = np.arange(w)[None, :]
+    out = np.empty((h, w, 4, 2))
+    for k, (a, b) in enumerate(((0, 0), (1, 0), (1, 1), (0, 1))):
+        x = ((j + a) - center_x) * pixel_x
+        y = ((i + b) - center_y) * pixel_y
+        out[:, :, k, 0] = O.unit_of_radius(np.sqrt(x * x + y * y), unit, dist, wavelength)
+        out[:, :, k, 1] = np.arctan2(y, x)
+    return out.reshape(h * w, 4, 2)
+
+
+def _corners_wrong_order(*a, **k):
+    # corners visited (0, 0), (1, 1), (1, 0), (0, 1): a self-crossing outline
+    c = _orig["pixel_corners"](*a, **k)
+    return c[:, [0, 2, 1, 3], :]
+
+
+def _area_halved(poly):
+    return _orig["polygon_area"](poly) / (2 if len(poly) == 4 else 1)
 
 
 def _bbox_drop_inner(lo, hi, npt, pmin, pmax):
@@ -164,6 +189,9 @@ MUTANTS = {
     "unit_wrong_conversion": ("unit_of_radius", _unit_deg_wrong),
     "correct_dark_sign": ("correct", _correct_dark_sign),
     "correct_multiplies": ("correct", _correct_norm_order),
+    "full_no_unwrap": ("pixel_corners", _corners_no_unwrap),
+    "full_corner_order": ("pixel_corners", _corners_wrong_order),
+    "full_area_of_pixel_wrong": ("polygon_area", _area_halved),
 }
 
 
