@@ -348,7 +348,7 @@ def main():
         torch.cuda.empty_cache()
     if run("c3"):
         result["lines"]["c3"] = batch_line(az, torch, np, synth, dev, synth.C3, "f64",
-                                           False, False)
+                                           False, True)
         log(f"[c3] {json.dumps(result['lines']['c3'])}")
     if run("c4"):
         result["lines"]["c4"] = adjoint_line(az, torch, np, synth, dev)
