@@ -60,9 +60,15 @@ extern "C" {
 #define AZI_UNIT_2TH_DEG 3  /* the same in degrees                  */
 #define AZI_UNIT_Q_NM    4  /* q = 4 pi sin(2theta/2) / lambda, 1/nm */
 
-/* Pixel splitting (Section 3.3 histogram, Section 4.1 bounding box). */
+/* Pixel splitting: AZI_SPLIT_NONE, whole pixels by their midpoint (Section
+ * 3.3 histogram); AZI_SPLIT_BBOX, the radial bounding box of each pixel
+ * (Section 4.1); AZI_SPLIT_FULL, the area of the pixel's corner
+ * quadrilateral in (output unit, azimuth) space with straight edges, shared
+ * by area (Section 4.2) -- pixels holding the beam centre use the bounding
+ * box, where that quadrilateral is undefined. */
 #define AZI_SPLIT_NONE 0
 #define AZI_SPLIT_BBOX 1
+#define AZI_SPLIT_FULL 2
 
 /* Element types. */
 #define AZI_I16 0
@@ -103,8 +109,8 @@ const char* azi_last_error(void);
 
 /*
  * Build the coefficient matrix of one geometry on the host (Section 4.1 for
- * AZI_SPLIT_BBOX, Section 3.3 for AZI_SPLIT_NONE; Section 5.2 turns the
- * per-pixel contributions into a per-bin gather).  For every pixel the
+ * AZI_SPLIT_BBOX, 4.2 for AZI_SPLIT_FULL, 3.3 for AZI_SPLIT_NONE; Section
+ * 5.2 turns the per-pixel contributions into a per-bin gather).  For every pixel the
  * radial extent [lo, hi] of the pixel square is mapped to the output unit;
  * bins are npt uniform intervals over range2 = {min, max} (host, may be NULL
  * for the data's own range: [min lo, max hi] with splitting, the range of

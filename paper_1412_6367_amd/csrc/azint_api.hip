@@ -451,7 +451,8 @@ int azi_plan_create(const azi_geom* geom, int32_t npt, int32_t unit, int32_t spl
     if (!std::isfinite(geom->center_x_px) || !std::isfinite(geom->center_y_px))
         return fail(AZI_EINVAL, "beam centre must be finite");
     if (unit < AZI_UNIT_R_M || unit > AZI_UNIT_Q_NM) return fail(AZI_EINVAL, "unknown unit");
-    if (split != AZI_SPLIT_NONE && split != AZI_SPLIT_BBOX) return fail(AZI_EINVAL, "unknown split");
+    if (split != AZI_SPLIT_NONE && split != AZI_SPLIT_BBOX && split != AZI_SPLIT_FULL)
+        return fail(AZI_EINVAL, "unknown split");
     if (dtype != AZI_F32 && dtype != AZI_F64) return fail(AZI_EINVAL, "dtype must be AZI_F32 or AZI_F64");
     if (accum != AZI_ACC_F64 && accum != AZI_ACC_KAHAN32) return fail(AZI_EINVAL, "unknown accumulation");
     if (accum == AZI_ACC_KAHAN32 && dtype != AZI_F32)

@@ -82,6 +82,70 @@ inline void bbox_pixel(double lo, double hi, double pmin, double delta, int32_t 
     emit(b1, (fhc - (double)b1) / width);
 }
 
+// Full splitting (Section 4.2): the pixel's four corners, mapped to
+// (output unit, azimuth) and joined by straight edges, form a
+// quadrilateral; bin b gets the part of its area within the bin's slab of
+// the output unit over its whole area.  The area within a slab is the sum,
+// over the four edges, of the integral of the edge's line over the slab
+// (the vertical edges of the clipped polygon add nothing), in absolute
+// value.  Coordinates are taken relative to the first corner.
+struct Quad { double x[4], y[4]; };
+
+inline double edge_integral(const Quad& q, double e0, double e1) {
+    double s = 0.0;
+    for (int k = 0; k < 4; ++k) {
+        const double ax = q.x[k], ay = q.y[k];
+        const double bx = q.x[(k + 1) & 3], by = q.y[(k + 1) & 3];
+        if (ax == bx) continue;
+        const double lo = std::max(std::min(ax, bx), e0);
+        const double hi = std::min(std::max(ax, bx), e1);
+        if (!(hi > lo)) continue;
+        const double slope = (by - ay) / (bx - ax);
+        const double ylo = ay + (lo - ax) * slope;
+        const double yhi = ay + (hi - ax) * slope;
+        const double part = (hi - lo) * (ylo + yhi) / 2.0;
+        s += bx > ax ? part : -part;
+    }
+    return std::fabs(s);
+}
+
+template <class Emit>
+inline void full_pixel(int64_t i, int64_t j, const azi_geom& g, int32_t unit, double lo, double hi,
+                       double pmin, double delta, int32_t npt, Emit&& emit) {
+    if (lo == 0.0) {  // the beam centre lies on this pixel
+        bbox_pixel(lo, hi, pmin, delta, npt, emit);
+        return;
+    }
+    const int da[4] = {0, 1, 1, 0}, db[4] = {0, 0, 1, 1};
+    double p0[4], p1[4];
+    for (int k = 0; k < 4; ++k) {
+        const double x = ((double)(j + da[k]) - g.center_x_px) * g.pixel_x_m;
+        const double y = ((double)(i + db[k]) - g.center_y_px) * g.pixel_y_m;
+        p0[k] = to_unit(std::sqrt(x * x + y * y), unit, g.dist_m, g.wavelength_m);
+        p1[k] = std::atan2(y, x);
+    }
+    for (int k = 1; k < 4; ++k)
+        p1[k] += std::nearbyint((p1[0] - p1[k]) / (2.0 * M_PI)) * (2.0 * M_PI);
+    const double mn = std::min(std::min(p0[0], p0[1]), std::min(p0[2], p0[3]));
+    const double mx = std::max(std::max(p0[0], p0[1]), std::max(p0[2], p0[3]));
+    Quad q;
+    for (int k = 0; k < 4; ++k) {
+        q.x[k] = p0[k] - p0[0];
+        q.y[k] = p1[k] - p1[0];
+    }
+    const double area = edge_integral(q, -HUGE_VAL, HUGE_VAL);
+    const double fl = (mn - pmin) / delta, fh = (mx - pmin) / delta;
+    if (area == 0.0 || fh == fl) return;
+    const int32_t b0 = std::max((int32_t)std::floor(fl), 0);
+    const int32_t b1 = std::min((int32_t)std::ceil(fh) - 1, npt - 1);
+    for (int32_t b = b0; b <= b1; ++b) {
+        const double e0 = (pmin + b * delta) - p0[0];
+        const double e1 = (pmin + (b + 1) * delta) - p0[0];
+        const double c = edge_integral(q, e0, e1) / area;
+        if (c > 0.0) emit(b, c);
+    }
+}
+
 }  // namespace
 
 int build_matrix(const azi_geom& g, int32_t npt, int32_t unit, int32_t split,
@@ -91,15 +155,16 @@ int build_matrix(const azi_geom& g, int32_t npt, int32_t unit, int32_t split,
         err = "image has 2^31 pixels or more";
         return AZI_EOVERFLOW;
     }
+    const bool boxes = split == AZI_SPLIT_BBOX || split == AZI_SPLIT_FULL;
     std::vector<double> lo, hi;
-    if (split == AZI_SPLIT_BBOX) { lo.resize(npix); hi.resize(npix); }
+    if (boxes) { lo.resize(npix); hi.resize(npix); }
     else { lo.resize(npix); }  // pixel-midpoint values
     double mn = std::numeric_limits<double>::infinity(), mx = -mn;
     for (int64_t i = 0; i < h; ++i) {
         for (int64_t j = 0; j < w; ++j) {
             const int64_t p = i * w + j;
             const Extent e = pixel_extent(i, j, g);
-            if (split == AZI_SPLIT_BBOX) {
+            if (boxes) {
                 lo[p] = to_unit(e.lo, unit, g.dist_m, g.wavelength_m);
                 hi[p] = to_unit(e.hi, unit, g.dist_m, g.wavelength_m);
                 mn = std::min(mn, lo[p]);
@@ -127,15 +192,18 @@ int build_matrix(const azi_geom& g, int32_t npt, int32_t unit, int32_t split,
     m.colptr.assign(npix + 1, 0);
     m.rowidx.clear();
     m.cdata.clear();
-    m.rowidx.reserve(split == AZI_SPLIT_BBOX ? npix * 3 : npix);
+    m.rowidx.reserve(boxes ? npix * 3 : npix);
     m.cdata.reserve(m.rowidx.capacity());
     const int64_t limit = std::numeric_limits<int32_t>::max();
+    auto push = [&](int32_t b, double c) {
+        m.rowidx.push_back(b);
+        m.cdata.push_back(c);
+    };
     for (int64_t p = 0; p < npix; ++p) {
         if (split == AZI_SPLIT_BBOX) {
-            bbox_pixel(lo[p], hi[p], pmin, delta, npt, [&](int32_t b, double c) {
-                m.rowidx.push_back(b);
-                m.cdata.push_back(c);
-            });
+            bbox_pixel(lo[p], hi[p], pmin, delta, npt, push);
+        } else if (split == AZI_SPLIT_FULL) {
+            full_pixel(p / w, p % w, g, unit, lo[p], hi[p], pmin, delta, npt, push);
         } else {
             const double fc = (lo[p] - pmin) / delta;
             if (fc >= 0.0 && fc <= (double)npt) {

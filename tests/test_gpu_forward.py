@@ -57,6 +57,8 @@ GEOMS = [
     (1, 17, 0.5, 8.5, 5, "r_m", "bbox", None),
     (257, 263, 128.5, 131.5, 256, "r_m", "bbox", None),
     (300, 200, 10.0, 190.0, 150, "2th_deg", "bbox", None),
+    (120, 130, 60.2, 64.9, 140, "r_m", "full", None),
+    (90, 70, -10.0, 35.0, 80, "q_nm", "full", None),
 ]
 # tile_nnz, block, variant, grid, band
 TILINGS = [(2048, 256, 3, 0, 1, 2), (1024, 64, 3, 0, 16, 0), (2048, 256, 2, 0, 1, 1),
