@@ -1,4 +1,4 @@
-"""FP64 CPU oracle: 1-D azimuthal integration with bounding-box pixel splitting.
+"""FP64 CPU oracle: azimuthal integration with pixel splitting, 1-D and 2-D.
 
 TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
 benchmark's CPU-baseline leg, never by the product path.  It is written from
@@ -10,8 +10,9 @@ What is computed (each function cites the passage it follows):
 
 * per-pixel radial coordinate and its extent over the pixel area
   (Section 3, coordinate list; Section 3.1 test case; Section 4.1),
-* the pixel-to-bin coefficients of bounding-box splitting (Section 4.1), or
-  of plain histogramming (Section 3.3),
+* the pixel-to-bin coefficients of bounding-box splitting (Section 4.1), of
+  full pixel splitting (Section 4.2), or of plain histogramming (Section
+  3.3), and their two-dimensional (radius x azimuth) forms (Section 4),
 * the per-pixel correction map (Section 6.4, "Kernel timings"),
 * the weighted histogram W, the unweighted histogram U and their ratio
   I = W / U (Section 3.3; Section 5.2 states the same sums as a sparse
@@ -44,6 +45,9 @@ R6  every inner bin receives 1 / (fh - fl): the overlap of a whole bin over
     the box width, which is what "the remaining contribution, evenly
     distributed" amounts to for uniform bins.
 R7  an empty bin (U = 0) yields the caller's ``empty`` value (default 0.0).
+R8  the azimuth chi = tan^-1(y/x) of the coordinate list is atan2(y, x) in
+    (-pi, pi], x along pixel columns, y along pixel rows, both measured
+    from the beam in metres.
 R9  units: r in m or mm, 2theta in rad or deg, q in 1/nm.
 R13 full pixel splitting (Section 4.2): the four pixel corners are mapped
     to (pos0, pos1) = (output unit, azimuth chi = atan2(y, x)), the edges
@@ -52,6 +56,14 @@ R13 full pixel splitting (Section 4.2): the four pixel corners are mapped
     whole area.  The corner azimuths are unwrapped to within pi of corner 0;
     a pixel whose square holds the beam centre (lo == 0), where the
     quadrilateral is undefined, falls back to the bounding box.
+R14 two-dimensional integration: npt_azim equal wedges of the periodic
+    circle [-pi, pi) times the radial bins; bin (radial a, azimuthal c) is
+    row c * npt_rad + a.  The bounding box becomes [lo, hi] x [chi_lo,
+    chi_hi], the azimuthal extent being the range of the corner azimuths
+    unwrapped to corner 0 (the whole circle for a pixel holding the beam);
+    its share of a bin is the product of the radial and azimuthal shares.
+    Full splitting clips the corner quadrilateral to the bin's rectangle,
+    the wedge repeated every 2 pi.
 """
 from __future__ import annotations
 
@@ -66,7 +78,8 @@ __all__ = [
     "UNITS", "SPLITS", "unit_of_radius", "pixel_extents", "pixel_extents_loop",
     "default_range", "bbox_entries", "bbox_entries_loop", "nosplit_entries",
     "pixel_corners", "full_entries", "polygon_area", "clip_slab",
-    "entries_to_csr", "build_matrix", "correct", "integrate", "integrate_loop",
+    "entries_to_csr", "build_matrix", "correct", "corner_azimuth", "azimuth_extents",
+    "azimuth_entries_loop", "bbox2d_entries", "full2d_entries", "build_matrix2d", "integrate", "integrate_loop",
     "integrate_vjp", "kahan_sum_f32", "positions",
 ]
 
@@ -251,20 +264,32 @@ def bbox_entries(lo, hi, npt, pmin, pmax):
     return np.concatenate(out_p), np.concatenate(out_b), np.concatenate(out_c)
 
 
+_atan2 = np.frompyfunc(math.atan2, 2, 1)
+
+
+def corner_azimuth(y, x):
+    """Azimuth chi = atan2(y, x) in (-pi, pi] (Section 3 coordinate list;
+    reading R8), evaluated by the C library's atan2 so that the bin a corner
+    falls in is decided by the same rounding wherever the plan is built."""
+    return np.asarray(_atan2(y, x), dtype=np.float64)
+
+
 def pixel_corners(h, w, pixel_y, pixel_x, center_y, center_x, dist, wavelength, unit="r_m"):
     """Corner coordinates (pos0, pos1) of every pixel, shape (h*w, 4, 2), in
     the order (j, i), (j+1, i), (j+1, i+1), (j, i+1): pos0 is the output unit
     of the corner radius, pos1 its azimuth atan2(y, x) unwrapped to within pi
     of the first corner (reading R13)."""
-    i = np.arange(h, dtype=np.int64)[:, None]
-    j = np.arange(w, dtype=np.int64)[None, :]
+    gi = np.arange(h + 1, dtype=np.int64)[:, None]
+    gj = np.arange(w + 1, dtype=np.int64)[None, :]
+    x = np.broadcast_to((gj - center_x) * pixel_x, (h + 1, w + 1))
+    y = np.broadcast_to((gi - center_y) * pixel_y, (h + 1, w + 1))
+    r = np.sqrt(x * x + y * y)
+    pos0 = unit_of_radius(r, unit, dist, wavelength)
+    chi = corner_azimuth(y, x)
     out = np.empty((h, w, 4, 2))
     for k, (a, b) in enumerate(((0, 0), (1, 0), (1, 1), (0, 1))):
-        x = ((j + a) - center_x) * pixel_x
-        y = ((i + b) - center_y) * pixel_y
-        r = np.sqrt(x * x + y * y)
-        out[:, :, k, 0] = unit_of_radius(r, unit, dist, wavelength)
-        out[:, :, k, 1] = np.arctan2(y, x)
+        out[:, :, k, 0] = pos0[b:b + h, a:a + w]
+        out[:, :, k, 1] = chi[b:b + h, a:a + w]
     chi0 = out[:, :, :1, 1]
     turns = np.round((chi0 - out[:, :, :, 1]) / (2.0 * math.pi))
     out[:, :, :, 1] = out[:, :, :, 1] + turns * (2.0 * math.pi)
@@ -354,6 +379,170 @@ def nosplit_entries(centre, npt, pmin, pmax):
     pid = np.arange(c.size, dtype=np.int64)[m]
     b = np.minimum(np.floor(fc[m]), npt - 1).astype(np.int64)
     return pid, b, np.ones(pid.size)
+
+
+# ----------------------------------------------------------------------------
+# Two-dimensional integration (Section 4, "2D integration"; reading R14)
+# ----------------------------------------------------------------------------
+
+def azimuth_extents(h, w, pixel_y, pixel_x, center_y, center_x, lo):
+    """Azimuthal extent [chi_lo, chi_hi] of every pixel square (reading R14).
+
+    Along a straight edge that misses the beam the azimuth is monotone, so
+    the extremes over the square sit at its corners: min and max of the four
+    corner azimuths, unwrapped to within pi of the first corner.  A pixel
+    whose square holds the beam (lo == 0) covers the whole circle: flagged
+    in ``whole`` (its chi_lo, chi_hi are then meaningless)."""
+    c = pixel_corners(h, w, pixel_y, pixel_x, center_y, center_x, 1.0, 1.0, "r_m")
+    chi = c[:, :, 1]
+    whole = np.asarray(lo, dtype=np.float64).reshape(-1) == 0.0
+    return chi.min(axis=1), chi.max(axis=1), whole
+
+
+def azimuth_entries_loop(chi_lo, chi_hi, whole, npt_azim):
+    """Azimuthal shares of every pixel (reading R14), one pixel at a time.
+
+    The circle [-pi, pi) is cut into npt_azim equal bins and is periodic: an
+    extent in bin units [gl, gh] covers unwrapped bins floor(gl) ..
+    ceil(gh) - 1, bin k meaning bin k mod npt_azim; the outer two get their
+    overlap over (gh - gl), the inner ones 1 / (gh - gl), as along the
+    radius (readings R5, R6).  A pixel holding the beam gives 1 / npt_azim
+    to every bin."""
+    delta = (2.0 * math.pi) / npt_azim
+    pix, bins, coef = [], [], []
+    for p in range(len(chi_lo)):
+        if whole[p]:
+            for k in range(npt_azim):
+                pix.append(p); bins.append(k); coef.append(1.0 / npt_azim)
+            continue
+        gl = (float(chi_lo[p]) + math.pi) / delta
+        gh = (float(chi_hi[p]) + math.pi) / delta
+        width = gh - gl
+        k0 = math.floor(gl)
+        k1 = math.ceil(gh) - 1
+        if width == 0.0:
+            k1 = k0
+        for k in range(k0, max(k1, k0) + 1):
+            if k0 == k1:
+                c = 1.0
+            elif k == k0:
+                c = ((k0 + 1) - gl) / width
+            elif k == k1:
+                c = (gh - k1) / width
+            else:
+                c = 1.0 / width
+            if c > 0.0:
+                pix.append(p); bins.append(k % npt_azim); coef.append(c)
+    return (np.asarray(pix, dtype=np.int64), np.asarray(bins, dtype=np.int64),
+            np.asarray(coef, dtype=np.float64))
+
+
+def bbox2d_entries(rad, azi, npt_rad):
+    """Two-dimensional bounding box (Section 4.1 in two dimensions, reading
+    R14): the share of the box in (radial bin a, azimuthal bin c) is the
+    product of its radial and azimuthal shares, stored in row
+    c * npt_rad + a.  ``rad`` and ``azi`` are (pix, bin, coef) triples."""
+    rp, rb, rc = rad
+    ap, ab, ac = azi
+    order_r = np.argsort(rp, kind="stable")
+    order_a = np.argsort(ap, kind="stable")
+    rp, rb, rc = rp[order_r], rb[order_r], rc[order_r]
+    ap, ab, ac = ap[order_a], ab[order_a], ac[order_a]
+    npix = int(max(rp.max(initial=-1), ap.max(initial=-1))) + 1
+    ncount = np.bincount(ap, minlength=npix)
+    astart = np.concatenate(([0], np.cumsum(ncount)))
+    reps = ncount[rp]
+    pix = np.repeat(rp, reps)
+    rbin = np.repeat(rb, reps)
+    rcoef = np.repeat(rc, reps)
+    # index of the azimuthal entry paired with each repeated radial entry
+    first = np.repeat(astart[rp], reps)
+    offs = np.arange(pix.size) - np.repeat(np.cumsum(reps) - reps, reps)
+    k = first + offs
+    return pix, ab[k] * npt_rad + rbin, rcoef * ac[k]
+
+
+def full2d_entries(corners, lo, hi, npt_rad, npt_azim, pmin, pmax):
+    """Full pixel splitting in two dimensions (Section 4.2, readings R13,
+    R14): bin (a, c) gets area(quadrilateral within radial slab a and
+    azimuthal slab c, the latter repeated every 2 pi) / area(quadrilateral).
+    Pixels holding the beam use the two-dimensional bounding box."""
+    delta = (pmax - pmin) / npt_rad
+    dchi = (2.0 * math.pi) / npt_azim
+    pix, bins, coef = [], [], []
+
+    def swap(poly):
+        return [(q[1], q[0]) for q in poly]
+
+    for p in range(len(corners)):
+        if float(lo[p]) == 0.0:
+            rad = bbox_entries_loop(lo[p:p + 1], hi[p:p + 1], npt_rad, pmin, pmax)
+            azi = azimuth_entries_loop([0.0], [0.0], [True], npt_azim)
+            bp, bb, bc = bbox2d_entries(rad, azi, npt_rad)
+            pix += [p] * len(bb)
+            bins += bb.tolist()
+            coef += bc.tolist()
+            continue
+        xs = [float(c[0]) for c in corners[p]]
+        ys = [float(c[1]) for c in corners[p]]
+        fl = (min(xs) - pmin) / delta
+        fh = (max(xs) - pmin) / delta
+        gl = (min(ys) + math.pi) / dchi
+        gh = (max(ys) + math.pi) / dchi
+        x0, y0 = xs[0], ys[0]
+        quad = [(xs[k] - x0, ys[k] - y0) for k in range(4)]
+        area = polygon_area(quad)
+        if area == 0.0 or fh == fl:
+            continue
+        b0 = max(math.floor(fl), 0)
+        b1 = min(math.ceil(fh) - 1, npt_rad - 1)
+        k0 = math.floor(gl)
+        k1 = max(math.ceil(gh) - 1, k0)
+        for b in range(b0, b1 + 1):
+            e0 = (pmin + b * delta) - x0
+            e1 = (pmin + (b + 1) * delta) - x0
+            slab = clip_slab(quad, e0, e1)
+            if not slab:
+                continue
+            for k in range(k0, k1 + 1):
+                t0 = (-math.pi + k * dchi) - y0
+                t1 = (-math.pi + (k + 1) * dchi) - y0
+                c = polygon_area(clip_slab(swap(slab), t0, t1)) / area
+                if c > 0.0:
+                    pix.append(p); bins.append((k % npt_azim) * npt_rad + b); coef.append(c)
+    return (np.asarray(pix, dtype=np.int64), np.asarray(bins, dtype=np.int64),
+            np.asarray(coef, dtype=np.float64))
+
+
+def build_matrix2d(h, w, pixel_y, pixel_x, center_y, center_x, dist, wavelength,
+                   npt_rad, npt_azim, unit="r_m", split="bbox", range_=None):
+    """Geometry -> coefficients -> CSR for two-dimensional integration: rows
+    c * npt_rad + a for azimuthal bin c of [-pi, pi) and radial bin a of the
+    radial range (readings R3, R14).  Splits "bbox" and "full"."""
+    lo, hi, rc = pixel_extents(h, w, pixel_y, pixel_x, center_y, center_x, dist,
+                               wavelength, unit)
+    pmin, pmax = default_range(lo, hi, rc, split) if range_ is None else map(float, range_)
+    if not pmax > pmin:
+        raise ValueError("empty integration range")
+    npt = npt_rad * npt_azim
+    if split == "bbox":
+        rad = bbox_entries(lo, hi, npt_rad, pmin, pmax)
+        chi_lo, chi_hi, whole = azimuth_extents(h, w, pixel_y, pixel_x, center_y, center_x, lo)
+        azi = azimuth_entries_loop(chi_lo, chi_hi, whole, npt_azim)
+        ent = bbox2d_entries(rad, azi, npt_rad)
+    elif split == "full":
+        corners = pixel_corners(h, w, pixel_y, pixel_x, center_y, center_x, dist, wavelength,
+                                unit)
+        ent = full2d_entries(corners, lo, hi, npt_rad, npt_azim, pmin, pmax)
+    else:
+        raise ValueError(f"unknown two-dimensional split {split!r}")
+    indptr, indices, data = entries_to_csr(*ent, npt)
+    dchi = (2.0 * math.pi) / npt_azim
+    return dict(npt=npt, npt_rad=npt_rad, npt_azim=npt_azim, npix=h * w, pmin=pmin,
+                pmax=pmax, lo=lo, hi=hi, centre=rc, pix=ent[0], bins=ent[1], coef=ent[2],
+                indptr=indptr, indices=indices, data=data,
+                positions=positions(npt_rad, pmin, pmax),
+                azimuths=-math.pi + (np.arange(npt_azim) + 0.5) * dchi)
 
 
 def entries_to_csr(pix, bins, coef, npt):

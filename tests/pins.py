@@ -472,9 +472,178 @@ def pin_full_rotation(O):
             assert np.abs(A[:, p] - B[:, q]).max() <= 1e-9, (n, cy, cx, p, A[:, p], B[:, q])
 
 
+# ----------------------------------------------------------------------------
+# Two-dimensional integration (reading R14)
+# ----------------------------------------------------------------------------
+
+CASES_2D = [
+    # (h, w, center_y, center_x, npt_rad, npt_azim)
+    (5, 6, 2.5, 3.0, 6, 8),
+    (6, 6, 3.5, 46.0, 5, 360),     # beam right of the detector: rows across +-pi
+    (7, 5, 3.3, 2.2, 7, 12),       # beam inside a pixel, off the pixel grid
+    (4, 7, -3.0, 2.5, 4, 36),      # beam above the detector
+]
+
+
+def _dense(m, npix):
+    A = np.zeros((m["npt"], npix))
+    A[m["bins"], m["pix"]] = m["coef"]
+    return A
+
+
+def _args2d(h, w, cy, cx):
+    return dict(h=h, w=w, pixel_y=1e-4, pixel_x=1e-4, center_y=cy, center_x=cx,
+                dist=DIST, wavelength=WL)
+
+
+def pin_2d_marginal(O):
+    """P16: summing a two-dimensional split over the azimuthal bins gives
+    back the one-dimensional split of the same pixels (the azimuthal shares
+    of a pixel add up to one), for the bounding box and for full splitting."""
+    for (h, w, cy, cx, nr, na) in CASES_2D:
+        args = _args2d(h, w, cy, cx)
+        for split in ("bbox", "full"):
+            m2 = O.build_matrix2d(npt_rad=nr, npt_azim=na, split=split, **args)
+            m1 = O.build_matrix(npt=nr, split=split, **args)
+            A2 = _dense(m2, h * w).reshape(na, nr, h * w).sum(axis=0)
+            A1 = _dense(m1, h * w)
+            assert np.abs(A2 - A1).max() <= 1e-12, (h, w, cy, cx, split)
+
+
+def pin_2d_azimuth_extent(O):
+    """P17: a pixel's azimuthal extent is the range of atan2 over its
+    outline (dense sampling of the four edges, unwrapped around the pixel
+    centre's azimuth), and the whole circle exactly when the beam lies in
+    the closed pixel square."""
+    for (h, w, cy, cx, nr, na) in CASES_2D:
+        lo, hi, rc = O.pixel_extents(h, w, 1e-4, 1e-4, cy, cx, DIST, WL, "r_m")
+        chi_lo, chi_hi, whole = O.azimuth_extents(h, w, 1e-4, 1e-4, cy, cx, lo)
+        t = np.linspace(0.0, 1.0, 401)
+        for p in range(h * w):
+            i, j = divmod(p, w)
+            inside = (i <= cy <= i + 1) and (j <= cx <= j + 1)
+            assert bool(whole[p]) == inside, (cy, cx, p)
+            if inside:
+                continue
+            xs = np.concatenate([j + t, np.full_like(t, j + 1), j + 1 - t, np.full_like(t, j)])
+            ys = np.concatenate([np.full_like(t, i), i + t, np.full_like(t, i + 1), i + 1 - t])
+            chi = np.arctan2((ys - cy) * 1e-4, (xs - cx) * 1e-4)
+            mid = math.atan2((i + 0.5 - cy) * 1e-4, (j + 0.5 - cx) * 1e-4)
+            chi = mid + np.remainder(chi - mid + math.pi, 2 * math.pi) - math.pi
+            lo_s, hi_s = chi.min(), chi.max()
+            shift = round((chi_lo[p] - lo_s) / (2 * math.pi)) * 2 * math.pi
+            assert abs(chi_lo[p] - shift - lo_s) <= 1e-12, (cy, cx, p)
+            assert abs(chi_hi[p] - shift - hi_s) <= 1e-12, (cy, cx, p)
+
+
+def pin_2d_bbox_bruteforce(O):
+    """P18: two-dimensional bounding-box coefficients equal the exact
+    (rational) area of the box [lo, hi] x [chi_lo, chi_hi] inside each
+    (radial bin x azimuthal wedge, repeated every 2 pi) over the box area,
+    in row c * npt_rad + a; 1 / npt_azim per wedge for a pixel holding the
+    beam."""
+    pi = F(math.pi)
+    for (h, w, cy, cx, nr, na) in CASES_2D:
+        args = _args2d(h, w, cy, cx)
+        m = O.build_matrix2d(npt_rad=nr, npt_azim=na, split="bbox", **args)
+        lo, hi = m["lo"], m["hi"]
+        chi_lo, chi_hi, whole = O.azimuth_extents(h, w, 1e-4, 1e-4, cy, cx, lo)
+        pmin, pmax = F(m["pmin"]), F(m["pmax"])
+        dr = (pmax - pmin) / nr
+        dc = 2 * pi / na
+        A = _dense(m, h * w)
+        for p in range(h * w):
+            l, u = F(float(lo[p])), F(float(hi[p]))
+            rad = [max(F(0), min(u, pmin + (a + 1) * dr) - max(l, pmin + a * dr)) / (u - l)
+                   for a in range(nr)]
+            if whole[p]:
+                azi = [F(1, na)] * na
+            else:
+                cl, ch = F(float(chi_lo[p])), F(float(chi_hi[p]))
+                azi = []
+                for c in range(na):
+                    ov = F(0)
+                    for turn in (-1, 0, 1):
+                        e0 = -pi + c * dc + 2 * pi * turn
+                        ov += max(F(0), min(ch, e0 + dc) - max(cl, e0))
+                    azi.append(ov / (ch - cl))
+            for c in range(na):
+                for a in range(nr):
+                    ref = float(rad[a] * azi[c])
+                    assert abs(A[c * nr + a, p] - ref) <= 1e-12, (h, w, cy, cx, p, a, c)
+
+
+def pin_2d_physical_area(O):
+    """P19: away from the beam, full two-dimensional splitting follows the
+    area in (r, chi) of the pixel's image: Monte Carlo over the pixel square
+    with weight 1/r (the Jacobian of (x, y) -> (r, chi)), each point binned by
+    its own radius and azimuth."""
+    rng = np.random.default_rng(5)
+    for (h, w, cy, cx, nr, na, pixels) in ((6, 6, 3.5, 46.0, 8, 360, (18, 19, 21, 12, 5)),
+                                           (6, 6, -40.0, -35.0, 9, 720, (0, 7, 14, 35))):
+        args = _args2d(h, w, cy, cx)
+        m = O.build_matrix2d(npt_rad=nr, npt_azim=na, split="full", **args)
+        dr = (m["pmax"] - m["pmin"]) / nr
+        dc = 2 * math.pi / na
+        for p in pixels:
+            i, j = divmod(p, w)
+            u = rng.uniform(0, 1, size=(400000, 2))
+            x = (j + u[:, 0] - cx) * 1e-4
+            y = (i + u[:, 1] - cy) * 1e-4
+            r = np.sqrt(x * x + y * y)
+            a = np.clip(np.floor((r - m["pmin"]) / dr).astype(int), 0, nr - 1)
+            c = np.floor((np.arctan2(y, x) + math.pi) / dc).astype(int) % na
+            frac = np.bincount(c * nr + a, weights=1.0 / r, minlength=nr * na)
+            frac /= frac.sum()
+            sel = m["pix"] == p
+            got = np.zeros(nr * na)
+            got[m["bins"][sel]] = m["coef"][sel]
+            assert np.abs(got - frac).max() < 5e-3, (cy, cx, p)
+
+
+def pin_2d_conservation(O):
+    """P20: two-dimensional splits conserve pixels and signal (Section 4),
+    and a constant image integrates to that constant in every bin with
+    pixels."""
+    rng = np.random.default_rng(6)
+    for (h, w, cy, cx, nr, na) in CASES_2D:
+        args = _args2d(h, w, cy, cx)
+        for split in ("bbox", "full"):
+            m = O.build_matrix2d(npt_rad=nr, npt_azim=na, split=split, **args)
+            s = np.zeros(h * w)
+            np.add.at(s, m["pix"], m["coef"])
+            assert np.abs(s - 1.0).max() <= 1e-13, (h, w, cy, cx, split)
+            x = rng.uniform(0, 5, size=h * w)
+            I, W, U = O.integrate(m, x)
+            assert abs(U.sum() - h * w) <= 1e-12 * h * w
+            assert abs(W.sum() - x.sum()) <= 1e-12 * x.sum()
+            I, W, U = O.integrate(m, np.full(h * w, 2.5))
+            assert np.all(np.abs(I[U > 0] - 2.5) <= 1e-13)
+
+
+def pin_2d_rotation(O):
+    """P21: a half turn of the detector about the beam adds pi to every
+    azimuth, so with an even number of wedges each pixel's two-dimensional
+    split equals its twin's shifted by half the wedges."""
+    for (n, cy, cx, nr, na) in ((6, 3.0, 3.3, 5, 8), (7, 2.0, 4.6, 4, 12)):
+        for split in ("bbox", "full"):
+            ma = O.build_matrix2d(npt_rad=nr, npt_azim=na, split=split, **_args2d(n, n, cy, cx))
+            mb = O.build_matrix2d(npt_rad=nr, npt_azim=na, split=split,
+                                  **_args2d(n, n, n - cy, n - cx))
+            A = _dense(ma, n * n).reshape(na, nr, n * n)
+            B = _dense(mb, n * n).reshape(na, nr, n * n)
+            for p in range(n * n):
+                i, j = divmod(p, n)
+                q = (n - 1 - i) * n + (n - 1 - j)
+                diff = np.abs(A[:, :, p] - np.roll(B[:, :, q], -na // 2, axis=0)).max()
+                assert diff <= 1e-9, (n, cy, cx, split, p)
+
+
 ALL_PINS = [pin_extents_exact, pin_bbox_bruteforce, pin_results_exact,
             pin_nosplit_histogram, pin_naive_mean, pin_conservation, pin_unit_weights,
             pin_constant_image, pin_symmetry, pin_scipy_csr, pin_adjoint, pin_kahan,
             pin_closed_forms, pin_bbox_clipped, pin_correction,
             pin_full_exact, pin_full_physical_area, pin_full_conservation,
-            pin_full_rotation]
+            pin_full_rotation, pin_2d_marginal, pin_2d_azimuth_extent,
+            pin_2d_bbox_bruteforce, pin_2d_physical_area, pin_2d_conservation,
+            pin_2d_rotation]

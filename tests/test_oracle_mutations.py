@@ -16,7 +16,8 @@ from tests import pins
 _orig = {name: getattr(O, name) for name in
          ("pixel_extents", "bbox_entries", "nosplit_entries", "integrate",
           "integrate_vjp", "kahan_sum_f32", "unit_of_radius", "correct",
-          "pixel_corners", "full_entries", "polygon_area")}
+          "pixel_corners", "full_entries", "polygon_area", "corner_azimuth",
+          "azimuth_entries_loop", "bbox2d_entries", "full2d_entries", "azimuth_extents")}
 
 
 def _corners_no_unwrap(h, w, pixel_y, pixel_x, center_y, center_x, dist, wavelength,
@@ -172,6 +173,55 @@ def _correct_norm_order(raw, dark=None, flat=None, solid=None, polar=None):
     return x
 
 
+def _azimuth_mirrored(y, x):
+    # atan2 with its arguments in the wrong order's sign: chi -> -chi
+    return _orig["corner_azimuth"](-y, x)
+
+
+def _azimuth_no_wrap(chi_lo, chi_hi, whole, npt_azim):
+    # shares falling past -pi or pi are dropped instead of wrapped round
+    p, b, c = _orig["azimuth_entries_loop"](chi_lo, chi_hi, whole, npt_azim)
+    delta = 2 * math.pi / npt_azim
+    keep = np.ones(p.size, dtype=bool)
+    for e in range(p.size):
+        if whole[p[e]]:
+            continue
+        gl = (float(chi_lo[p[e]]) + math.pi) / delta
+        gh = (float(chi_hi[p[e]]) + math.pi) / delta
+        if (gl < 0 and b[e] >= math.floor(gl) % npt_azim) or \
+           (gh > npt_azim and b[e] <= (math.ceil(gh) - 1) % npt_azim):
+            keep[e] = False
+    return p[keep], b[keep], c[keep]
+
+
+def _bbox2d_rows_transposed(rad, azi, npt_rad):
+    # row a * npt_azim + c instead of c * npt_rad + a
+    p, rows, c = _orig["bbox2d_entries"](rad, azi, npt_rad)
+    npt_azim = int(azi[1].max()) + 1 if azi[1].size else 1
+    a, cc = rows % npt_rad, rows // npt_rad
+    return p, a * npt_azim + cc, c
+
+
+def _bbox2d_sum(rad, azi, npt_rad):
+    # shares averaged instead of multiplied
+    p, rows, c = _orig["bbox2d_entries"](rad, (azi[0], azi[1], np.ones_like(azi[2])), npt_rad)
+    p2, rows2, c2 = _orig["bbox2d_entries"]((rad[0], rad[1], np.ones_like(rad[2])), azi, npt_rad)
+    return p, rows, 0.5 * (c + c2)
+
+
+def _full2d_wedge_offset(corners, lo, hi, npt_rad, npt_azim, pmin, pmax):
+    # wedges counted from 0 instead of from -pi: every share half a turn off
+    p, b, c = _orig["full2d_entries"](corners, lo, hi, npt_rad, npt_azim, pmin, pmax)
+    a, k = b % npt_rad, b // npt_rad
+    return p, ((k + npt_azim // 2) % npt_azim) * npt_rad + a, c
+
+
+def _extents_never_whole(h, w, pixel_y, pixel_x, center_y, center_x, lo):
+    chi_lo, chi_hi, whole = _orig["azimuth_extents"](h, w, pixel_y, pixel_x, center_y,
+                                                     center_x, lo)
+    return chi_lo, chi_hi, np.zeros_like(whole)
+
+
 MUTANTS = {
     "bbox_drop_inner": ("bbox_entries", _bbox_drop_inner),
     "bbox_b1_plus_one": ("bbox_entries", _bbox_b1_plus_one),
@@ -192,6 +242,12 @@ MUTANTS = {
     "full_no_unwrap": ("pixel_corners", _corners_no_unwrap),
     "full_corner_order": ("pixel_corners", _corners_wrong_order),
     "full_area_of_pixel_wrong": ("polygon_area", _area_halved),
+    "2d_azimuth_mirrored": ("corner_azimuth", _azimuth_mirrored),
+    "2d_azimuth_no_wrap": ("azimuth_entries_loop", _azimuth_no_wrap),
+    "2d_rows_transposed": ("bbox2d_entries", _bbox2d_rows_transposed),
+    "2d_shares_averaged": ("bbox2d_entries", _bbox2d_sum),
+    "2d_full_wedge_offset": ("full2d_entries", _full2d_wedge_offset),
+    "2d_beam_pixel_not_whole": ("azimuth_extents", _extents_never_whole),
 }
 
 
