@@ -79,7 +79,7 @@ __all__ = [
     "default_range", "bbox_entries", "bbox_entries_loop", "nosplit_entries",
     "pixel_corners", "full_entries", "polygon_area", "clip_slab",
     "entries_to_csr", "build_matrix", "correct", "corner_azimuth", "azimuth_extents",
-    "azimuth_entries_loop", "bbox2d_entries", "full2d_entries", "build_matrix2d", "integrate", "integrate_loop",
+    "azimuth_entries_loop", "bbox2d_entries", "full2d_entries", "nosplit2d_entries", "build_matrix2d", "integrate", "integrate_loop",
     "integrate_vjp", "kahan_sum_f32", "positions",
 ]
 
@@ -462,6 +462,22 @@ def bbox2d_entries(rad, azi, npt_rad):
     return pix, ab[k] * npt_rad + rbin, rcoef * ac[k]
 
 
+def nosplit2d_entries(h, w, pixel_y, pixel_x, center_y, center_x, centre, npt_rad, npt_azim,
+                      pmin, pmax):
+    """Two-dimensional histogram without splitting (Section 3.3 in two
+    dimensions, readings R3, R8, R14): each pixel goes whole to the bin of
+    its midpoint's radius and azimuth; the azimuth wedge is periodic."""
+    rp, rb, _ = nosplit_entries(centre, npt_rad, pmin, pmax)
+    i = np.arange(h, dtype=np.int64)[:, None]
+    j = np.arange(w, dtype=np.int64)[None, :]
+    xc = np.broadcast_to(((j + 0.5) - center_x) * pixel_x, (h, w)).reshape(-1)
+    yc = np.broadcast_to(((i + 0.5) - center_y) * pixel_y, (h, w)).reshape(-1)
+    chi = corner_azimuth(yc[rp], xc[rp])
+    dchi = (2.0 * math.pi) / npt_azim
+    c = np.floor((chi + math.pi) / dchi).astype(np.int64) % npt_azim
+    return rp, c * npt_rad + rb, np.ones(rp.size)
+
+
 def full2d_entries(corners, lo, hi, npt_rad, npt_azim, pmin, pmax):
     """Full pixel splitting in two dimensions (Section 4.2, readings R13,
     R14): bin (a, c) gets area(quadrilateral within radial slab a and
@@ -518,14 +534,17 @@ def build_matrix2d(h, w, pixel_y, pixel_x, center_y, center_x, dist, wavelength,
                    npt_rad, npt_azim, unit="r_m", split="bbox", range_=None):
     """Geometry -> coefficients -> CSR for two-dimensional integration: rows
     c * npt_rad + a for azimuthal bin c of [-pi, pi) and radial bin a of the
-    radial range (readings R3, R14).  Splits "bbox" and "full"."""
+    radial range (readings R3, R14).  Splits "none", "bbox" and "full"."""
     lo, hi, rc = pixel_extents(h, w, pixel_y, pixel_x, center_y, center_x, dist,
                                wavelength, unit)
     pmin, pmax = default_range(lo, hi, rc, split) if range_ is None else map(float, range_)
     if not pmax > pmin:
         raise ValueError("empty integration range")
     npt = npt_rad * npt_azim
-    if split == "bbox":
+    if split == "none":
+        ent = nosplit2d_entries(h, w, pixel_y, pixel_x, center_y, center_x, rc, npt_rad,
+                                npt_azim, pmin, pmax)
+    elif split == "bbox":
         rad = bbox_entries(lo, hi, npt_rad, pmin, pmax)
         chi_lo, chi_hi, whole = azimuth_extents(h, w, pixel_y, pixel_x, center_y, center_x, lo)
         azi = azimuth_entries_loop(chi_lo, chi_hi, whole, npt_azim)

@@ -639,6 +639,34 @@ def pin_2d_rotation(O):
                 assert diff <= 1e-9, (n, cy, cx, split, p)
 
 
+def pin_2d_histogram(O):
+    """P22: two-dimensional integration without splitting equals numpy's
+    weighted and unweighted 2-D histograms of (midpoint radius, midpoint
+    azimuth) over [pmin, pmax] x [-pi, pi] (Section 3.3), except pixels
+    within rounding of a bin edge."""
+    rng = np.random.default_rng(7)
+    for (h, w, cy, cx, nr, na) in ((37, 41, 18.8, 20.3, 23, 36), (30, 20, -4.2, 9.7, 17, 72)):
+        args = _args2d(h, w, cy, cx)
+        m = O.build_matrix2d(npt_rad=nr, npt_azim=na, split="none", **args)
+        x = rng.integers(0, 1 << 20, size=h * w).astype(np.float64)
+        I, W, U = O.integrate(m, x)
+        i, j = np.divmod(np.arange(h * w), w)
+        xc, yc = (j + 0.5 - cx) * 1e-4, (i + 0.5 - cy) * 1e-4
+        chi = np.arctan2(yc, xc)
+        r = m["centre"]
+        rngs = [[m["pmin"], m["pmax"]], [-math.pi, math.pi]]
+        hu = np.histogram2d(r, chi, bins=[nr, na], range=rngs)[0]
+        hw = np.histogram2d(r, chi, bins=[nr, na], range=rngs, weights=x)[0]
+        fr = (r - m["pmin"]) / ((m["pmax"] - m["pmin"]) / nr)
+        fc = (chi + math.pi) / (2 * math.pi / na)
+        # the range ends are no bin edges: the extreme pixels sit on them
+        inner = (np.round(fr) > 0) & (np.round(fr) < nr)
+        near = ((np.abs(fr - np.round(fr)) < 1e-9) & inner) | (np.abs(fc - np.round(fc)) < 1e-9)
+        assert not near.any()
+        assert np.array_equal(U.reshape(na, nr), hu.T)
+        assert np.allclose(W.reshape(na, nr), hw.T, rtol=1e-15, atol=0)
+
+
 ALL_PINS = [pin_extents_exact, pin_bbox_bruteforce, pin_results_exact,
             pin_nosplit_histogram, pin_naive_mean, pin_conservation, pin_unit_weights,
             pin_constant_image, pin_symmetry, pin_scipy_csr, pin_adjoint, pin_kahan,
@@ -646,4 +674,4 @@ ALL_PINS = [pin_extents_exact, pin_bbox_bruteforce, pin_results_exact,
             pin_full_exact, pin_full_physical_area, pin_full_conservation,
             pin_full_rotation, pin_2d_marginal, pin_2d_azimuth_extent,
             pin_2d_bbox_bruteforce, pin_2d_physical_area, pin_2d_conservation,
-            pin_2d_rotation]
+            pin_2d_rotation, pin_2d_histogram]

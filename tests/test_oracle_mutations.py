@@ -17,7 +17,8 @@ _orig = {name: getattr(O, name) for name in
          ("pixel_extents", "bbox_entries", "nosplit_entries", "integrate",
           "integrate_vjp", "kahan_sum_f32", "unit_of_radius", "correct",
           "pixel_corners", "full_entries", "polygon_area", "corner_azimuth",
-          "azimuth_entries_loop", "bbox2d_entries", "full2d_entries", "azimuth_extents")}
+          "azimuth_entries_loop", "bbox2d_entries", "full2d_entries", "azimuth_extents",
+          "nosplit2d_entries")}
 
 
 def _corners_no_unwrap(h, w, pixel_y, pixel_x, center_y, center_x, dist, wavelength,
@@ -216,6 +217,16 @@ def _full2d_wedge_offset(corners, lo, hi, npt_rad, npt_azim, pmin, pmax):
     return p, ((k + npt_azim // 2) % npt_azim) * npt_rad + a, c
 
 
+def _nosplit2d_rows_swapped(h, w, pixel_y, pixel_x, center_y, center_x, centre, npt_rad,
+                            npt_azim, pmin, pmax):
+    # radial and azimuthal bins swapped in the row number where they fit
+    p, rows, c = _orig["nosplit2d_entries"](h, w, pixel_y, pixel_x, center_y, center_x, centre,
+                                             npt_rad, npt_azim, pmin, pmax)
+    a, k = rows % npt_rad, rows // npt_rad
+    ok = (k < npt_rad) & (a < npt_azim)
+    return p, np.where(ok, a * npt_rad + k, rows), c
+
+
 def _extents_never_whole(h, w, pixel_y, pixel_x, center_y, center_x, lo):
     chi_lo, chi_hi, whole = _orig["azimuth_extents"](h, w, pixel_y, pixel_x, center_y,
                                                      center_x, lo)
@@ -248,6 +259,7 @@ MUTANTS = {
     "2d_shares_averaged": ("bbox2d_entries", _bbox2d_sum),
     "2d_full_wedge_offset": ("full2d_entries", _full2d_wedge_offset),
     "2d_beam_pixel_not_whole": ("azimuth_extents", _extents_never_whole),
+    "2d_nosplit_rows_swapped": ("nosplit2d_entries", _nosplit2d_rows_swapped),
 }
 
 
