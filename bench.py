@@ -11,8 +11,10 @@ goes to stderr.
 
 Extra lines in the same JSON object (``lines``): the float32-storage copy,
 a cold-cache timing of the integration kernel, the 4096-instance batch (one
-persistent graph launch vs a per-instance loop), the 1e6-pixel adjoint, and
-the 1024-instance float32 forward+adjoint batch with autotuned tiles.
+persistent graph launch vs a per-instance loop), the 1e6-pixel adjoint, the
+1024-instance float32 forward+adjoint batch with autotuned tiles, the
+matrix-free (fused) kernel on the same frame, two-dimensional integration of
+the frame (1000 x 360 bins), and host- vs device-built plans.
 """
 import argparse
 import json
@@ -250,6 +252,107 @@ def adjoint_line(az, torch, np, synth, dev, reps=50):
                 backward_gbs=bwd_bytes(nnz, g.npix, inst.npt, 8) / (b * 1e6))
 
 
+def _timed(torch, fn, reps=20, flush=None):
+    fn()
+    pairs = []
+    for _ in range(reps):
+        if flush is not None:
+            flush.fill_(1.0)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        pairs.append((a, b))
+    torch.cuda.synchronize()
+    return mean_event_ms(pairs)
+
+
+def fused_line(az, torch, np, synth, dev, reps=50):
+    """Matrix-free integration of the c2 frame (float64): the bounding-box
+    coefficients recomputed from the geometry per frame.  Times the kernel on
+    a corrected image (warm and after a 1 GiB flush) and the whole raw-frame
+    pipeline (cast + correction + integration) in its one kernel.  Bytes per
+    launch: the image read and the three outputs written (the per-(tile, bin)
+    partial sums are the kernel's own traffic, not counted)."""
+    c = synth.C2
+    inst = synth.instance(c["n"], c["seed"], corrections=True)
+    g = inst.geom
+    plan = az.Plan(g.h, g.w, inst.npt, center=(g.center_y, g.center_x), layout="fused",
+                   device=dev)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a).reshape(-1).astype(np.float64)).to(dev)
+    x = t(inst.raw)
+    outs = tuple(torch.empty(inst.npt, dtype=torch.float64, device=dev) for _ in range(3))
+    flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    warm = _timed(torch, lambda: plan.integrate(x, out=outs), reps)
+    cold = _timed(torch, lambda: plan.integrate(x, out=outs), reps, flush)
+    plan.set_corrections(t(inst.dark), t(inst.flat), t(inst.solid), t(inst.polar))
+    raw = torch.from_numpy(inst.raw.reshape(-1)).to(dev)
+    pipe = _timed(torch, lambda: plan.integrate_raw(raw, out=outs), reps)
+    by = g.npix * 8 + 3 * inst.npt * 8
+    raw_by = g.npix * (4 + 8 + 8) + 3 * inst.npt * 8
+    line = dict(npix=g.npix, npt=inst.npt, integrate_ms=warm, integrate_cold_ms=cold,
+                integrate_bytes=by, integrate_gbs=by / (warm * 1e6),
+                integrate_frac=by / (warm * 1e6) / HBM_PEAK_GBS,
+                integrate_elements_per_s=g.npix / (warm * 1e-3),
+                pipeline_ms=pipe, pipeline_elements_per_s=g.npix / (pipe * 1e-3),
+                pipeline_bytes=raw_by, pipeline_gbs=raw_by / (pipe * 1e6),
+                plan_device_bytes=plan.device_bytes())
+    del plan
+    torch.cuda.empty_cache()
+    return line
+
+
+def two_d_line(az, torch, np, synth, dev, nr=1000, na=360, reps=30):
+    """Two-dimensional integration of the c2 frame (float64): 1000 radial
+    bins x 360 azimuthal wedges, bounding-box split, default layout."""
+    c = synth.C2
+    inst = synth.instance(c["n"], c["seed"])
+    g = inst.geom
+    t0 = time.perf_counter()
+    plan = az.Plan(g.h, g.w, nr, npt_azim=na, center=(g.center_y, g.center_x), device=dev)
+    build_s = time.perf_counter() - t0
+    x = torch.from_numpy(inst.raw.reshape(-1).astype(np.float64)).to(dev)
+    outs = tuple(torch.empty(plan.npt, dtype=torch.float64, device=dev) for _ in range(3))
+    flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    warm = _timed(torch, lambda: plan.integrate(x, out=outs), reps)
+    cold = _timed(torch, lambda: plan.integrate(x, out=outs), reps, flush)
+    nnz = plan.nnz
+    by = spmv_bytes(nnz, g.npix, plan.npt, 8)
+    line = dict(npix=g.npix, npt_rad=nr, npt_azim=na, nnz=nnz, layout=plan.layout(),
+                build_s=build_s, integrate_ms=warm, integrate_cold_ms=cold,
+                integrate_bytes=by, integrate_gbs=by / (warm * 1e6),
+                integrate_frac=by / (warm * 1e6) / HBM_PEAK_GBS,
+                integrate_cold_frac=by / (cold * 1e6) / HBM_PEAK_GBS,
+                elements_per_s=g.npix / (warm * 1e-3))
+    del plan
+    torch.cuda.empty_cache()
+    return line
+
+
+def plan_build_line(az, torch, np, synth, dev):
+    """Building the c2 plan (matrix + default device layout) with the host
+    builder and with the device builder."""
+    c = synth.C2
+    inst = synth.instance(c["n"], c["seed"])
+    g = inst.geom
+    t0 = time.perf_counter()
+    hp = az.Plan(g.h, g.w, inst.npt, center=(g.center_y, g.center_x), device=dev)
+    torch.cuda.synchronize()
+    host_s = time.perf_counter() - t0
+    del hp
+    az.Plan.on_device(g.h, g.w, inst.npt, center=(g.center_y, g.center_x), device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dp = az.Plan.on_device(g.h, g.w, inst.npt, center=(g.center_y, g.center_x), device=dev)
+    torch.cuda.synchronize()
+    dev_s = time.perf_counter() - t0
+    line = dict(npix=g.npix, npt=inst.npt, nnz=dp.nnz, host_build_upload_s=host_s,
+                device_build_s=dev_s, speedup=host_s / dev_s)
+    del dp
+    torch.cuda.empty_cache()
+    return line
+
+
 def cpu_baseline(np, synth):
     """The FP64 oracle on the host: one full ~1e7-pixel frame per repetition
     (correction + integration; the matrix is built beforehand, untimed, as
@@ -357,6 +460,11 @@ def main():
         result["lines"]["c5"] = batch_line(az, torch, np, synth, dev, synth.C5, "f32",
                                            True, True)
         log(f"[c5] {json.dumps(result['lines']['c5'])}")
+    for name, fn in (("c2_fused", fused_line), ("c2_2d", two_d_line),
+                     ("c2_plan_build", plan_build_line)):
+        if run(name):
+            result["lines"][name] = fn(az, torch, np, synth, dev)
+            log(f"[{name}] {json.dumps(result['lines'][name])}")
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(np, synth)
         log(f"[cpu] {json.dumps(result['cpu_baseline'])}")

@@ -1,18 +1,21 @@
 /*
  * azint.h -- C ABI of the MI355X (gfx950) azimuthal-integration library.
  *
- * The library reduces a 2-D detector image to a 1-D profile by bounding-box
- * pixel splitting (Kieffer & Ashiotis, "PyFAI: a Python library for high
- * performance azimuthal integration on GPU", EuroSciPy 2014).  The image is
- * corrected pixel by pixel (Section 6.4), then each output bin b receives
+ * The library reduces a 2-D detector image to a 1-D profile over the radial
+ * coordinate, or to a 2-D (azimuth x radius) map, with pixel splitting
+ * (Kieffer & Ashiotis, "PyFAI: a Python library for high performance
+ * azimuthal integration on GPU", EuroSciPy 2014).  The image is corrected
+ * pixel by pixel (Section 6.4), then each output bin b receives
  *
  *     W_b = sum_p A_bp x_p      (weighted histogram)
  *     U_b = sum_p A_bp          (unweighted histogram)
  *     I_b = W_b / U_b           (their ratio, the profile)
  *
- * where A is the pixel-to-bin coefficient matrix of Section 4.1, built once
+ * where A is the pixel-to-bin coefficient matrix of Section 4, built once
  * per geometry and applied per frame as a CSR sparse-matrix / dense-vector
- * product in "gather" form (Section 5.2, 5.2.1).
+ * product in "gather" form (Section 5.2, 5.2.1).  Every per-frame call
+ * below works on one- and two-dimensional plans alike: a plan's bins are
+ * its "npt" rows (npt_rad * npt_azim for a two-dimensional plan).
  *
  * Conventions shared by every call:
  *   - Return value: AZI_OK (0) on success, a negative AZI_E* code otherwise;
@@ -125,16 +128,65 @@ const char* azi_last_error(void);
 int azi_plan_create(const azi_geom* geom, int32_t npt, int32_t unit, int32_t split,
                     const double* range2, int32_t dtype, int32_t accum, azi_plan** out);
 
+/*
+ * Two-dimensional integration (Section 4, where pixel splitting is said to
+ * matter most for the 2-D case): bins are npt_azim equal wedges of the azimuth chi =
+ * atan2(y, x) over the periodic circle [-pi, pi) (x along pixel columns, y
+ * along pixel rows, from the beam) times npt_rad radial bins chosen as in
+ * azi_plan_create; bin (wedge c, radial bin a) is row c * npt_rad + a, so
+ * every output is an npt_azim x npt_rad row-major map.  AZI_SPLIT_NONE puts a
+ * pixel whole into the bin of its midpoint; AZI_SPLIT_BBOX gives bin (a, c)
+ * the product of the radial share of azi_plan_create and the azimuthal
+ * share of the box [chi_lo, chi_hi] spanned by the pixel's corner azimuths
+ * (the whole circle, evenly, for a pixel holding the beam); AZI_SPLIT_FULL
+ * the area of the corner quadrilateral inside the bin's rectangle over the
+ * quadrilateral's area (bounding box for a pixel holding the beam).
+ * Errors as azi_plan_create, plus AZI_EINVAL for npt_azim < 2 and
+ * AZI_EOVERFLOW if npt_rad * npt_azim >= 2^31.
+ */
+int azi_plan_create2d(const azi_geom* geom, int32_t npt_rad, int32_t npt_azim, int32_t unit,
+                      int32_t split, const double* range2, int32_t dtype, int32_t accum,
+                      azi_plan** out);
+
+/*
+ * Build a one-dimensional plan on a device (Section 5.2 scatter-to-gather,
+ * Section 5.2.1 CSR, done by the GPU): per-pixel extents and entries are
+ * computed by device kernels from the same operations as azi_plan_create,
+ * the pixel-major (CSC) order comes from a scan of the per-pixel counts and
+ * the bin-major (CSR) and band orders from a stable radix sort by bin, so
+ * the matrix is the one azi_plan_create builds (bit for bit with
+ * AZI_UNIT_R_M / _R_MM and the bounding box or no split; coefficients to
+ * rounding otherwise).  The plan comes back uploaded to `device` in the band
+ * layout, ready for per-frame calls, with a host copy of its matrix for the
+ * export and layout calls.  Work is enqueued on `stream` (NULL = null stream)
+ * and the call synchronises it before returning.  Errors as azi_plan_create,
+ * plus AZI_EDEVICE (no such device, HIP failure) and AZI_ENOMEM (device
+ * memory: about 50 bytes per nonzero during the build).
+ */
+int azi_plan_create_device(const azi_geom* geom, int32_t npt, int32_t unit, int32_t split,
+                           const double* range2, int32_t dtype, int32_t accum, int32_t device,
+                           void* stream, azi_plan** out);
+
 /* Free a plan and its device memory.  NULL is accepted (no-op). */
 int azi_plan_destroy(azi_plan* plan);
 
-/* Sizes of a plan (host outputs, each may be NULL).  range2 receives the
- * {min, max} actually used. */
+/* Sizes of a plan (host outputs, each may be NULL): npt = bins (rows of
+ * the matrix, npt_rad * npt_azim for a two-dimensional plan).  range2
+ * receives the radial {min, max} actually used. */
 int azi_plan_info(const azi_plan* plan, int32_t* npt, int64_t* npix, int64_t* nnz,
                   double* range2);
 
-/* Bin centres min + (b + 0.5) * (max - min) / npt, npt doubles (host). */
+/* Radial bins npt_rad and azimuthal wedges npt_azim (0 for a
+ * one-dimensional plan); host outputs, each may be NULL. */
+int azi_plan_shape(const azi_plan* plan, int32_t* npt_rad, int32_t* npt_azim);
+
+/* Radial bin centres min + (a + 0.5) * (max - min) / npt_rad, npt_rad
+ * doubles (host). */
 int azi_plan_positions(const azi_plan* plan, double* positions);
+
+/* Wedge centres -pi + (c + 0.5) * 2 pi / npt_azim in radians, npt_azim
+ * doubles (host).  AZI_ESTATE for a one-dimensional plan. */
+int azi_plan_azimuths(const azi_plan* plan, double* chi);
 
 /* Copy the matrix out in CSR form (host buffers): data[nnz] of the storage
  * type, indices[nnz] pixel ids ascending within a row, indptr[npt + 1]; the
@@ -214,12 +266,23 @@ int azi_plan_tile_schedule(const azi_plan* plan, const azi_tiling* tiling, int32
  * order, a few nearly full cache lines per image row; pieces of tile_nnz
  * entries add into per-bin partial sums that a second kernel adds in order.
  * Images up to 2^27 pixels.
+ * AZI_LAYOUT_FUSED (one-dimensional plans, AZI_SPLIT_BBOX or _NONE): no
+ * matrix is read per frame.  Each workgroup takes a 16 x 64 image tile,
+ * recomputes its pixels' radial extents and bounding-box shares from the
+ * plan's geometry with the operations of the plan builder (Sections 3, 4.1;
+ * the coefficients are the stored matrix's, bit for bit for the radial
+ * units, to rounding where atan / sin enter), and sums every bin
+ * of the tile's window into a per-(tile, bin) partial; a second kernel adds
+ * each bin's partials in tile order.  With azi_integrate1d_raw the cast and
+ * correction happen in the same kernel.  Only the tiling's grid applies.
+ * Batches do not take this layout.
  * Set before azi_plan_upload (a later call re-uploads).
  */
 #define AZI_LAYOUT_PIXEL 0
 #define AZI_LAYOUT_RING 1
 #define AZI_LAYOUT_TILE 2
 #define AZI_LAYOUT_BAND 3
+#define AZI_LAYOUT_FUSED 4
 int azi_plan_set_layout(azi_plan* plan, int32_t layout);
 int azi_plan_get_layout(const azi_plan* plan, int32_t* layout);
 

@@ -42,8 +42,8 @@ R4  boxes partly outside the range are clipped; the weights stay normalised
 R5  a box [fl, fh] in fractional-bin units covers bins floor(fl) ..
     ceil(fh) - 1, so no zero coefficient is ever produced.
 R6  every inner bin receives 1 / (fh - fl): the overlap of a whole bin over
-    the box width, which is what "the remaining contribution, evenly
-    distributed" amounts to for uniform bins.
+    the box width, which equals an even split of what the two outer bins
+    leave, for uniform bins.
 R7  an empty bin (U = 0) yields the caller's ``empty`` value (default 0.0).
 R8  the azimuth chi = tan^-1(y/x) of the coordinate list is atan2(y, x) in
     (-pi, pi], x along pixel columns, y along pixel rows, both measured
@@ -382,7 +382,7 @@ def nosplit_entries(centre, npt, pmin, pmax):
 
 
 # ----------------------------------------------------------------------------
-# Two-dimensional integration (Section 4, "2D integration"; reading R14)
+# Two-dimensional integration (Section 4; reading R14)
 # ----------------------------------------------------------------------------
 
 def azimuth_extents(h, w, pixel_y, pixel_x, center_y, center_x, lo):

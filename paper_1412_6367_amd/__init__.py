@@ -19,14 +19,14 @@ import os
 import numpy as np
 import torch
 
-__all__ = ["lib", "AzintError", "Plan", "Batch", "Graph", "Integrate1d", "integrate1d",
+__all__ = ["lib", "AzintError", "Plan", "Batch", "Graph", "Integrate1d", "integrate1d", "integrate2d",
            "autotune", "UNITS", "SPLITS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libazint.so")
 
 UNITS = {"r_m": 0, "r_mm": 1, "2th_rad": 2, "2th_deg": 3, "q_nm": 4}
-LAYOUTS = {"pixel": 0, "ring": 1, "tile": 2, "band": 3}
+LAYOUTS = {"pixel": 0, "ring": 1, "tile": 2, "band": 3, "fused": 4}
 SPLITS = {"none": 0, "bbox": 1, "full": 2}
 _DT = {torch.int16: 0, torch.int32: 2, torch.float32: 4, torch.float64: 5}
 for _name, _code in (("uint16", 1), ("uint32", 3)):
@@ -81,6 +81,12 @@ _SIGS = {
     "azi_last_error": (ctypes.c_char_p, []),
     "azi_plan_create": (ctypes.c_int, [ctypes.POINTER(_Geom), _I32, _I32, _I32, _P, _I32, _I32,
                                        ctypes.POINTER(_P)]),
+    "azi_plan_create2d": (ctypes.c_int, [ctypes.POINTER(_Geom), _I32, _I32, _I32, _I32, _P, _I32,
+                                         _I32, ctypes.POINTER(_P)]),
+    "azi_plan_create_device": (ctypes.c_int, [ctypes.POINTER(_Geom), _I32, _I32, _I32, _P, _I32,
+                                              _I32, _I32, _P, ctypes.POINTER(_P)]),
+    "azi_plan_shape": (ctypes.c_int, [_P, _P, _P]),
+    "azi_plan_azimuths": (ctypes.c_int, [_P, _P]),
     "azi_plan_destroy": (ctypes.c_int, [_P]),
     "azi_plan_info": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "azi_plan_positions": (ctypes.c_int, [_P, _P]),
@@ -169,18 +175,24 @@ def _need(t, dtype, n, device, name):
 
 
 class Plan:
-    """Coefficient matrix of one detector geometry (Sections 3, 4.1, 5.2.1).
+    """Coefficient matrix of one detector geometry (Sections 3, 4, 5.2.1).
 
     ``pixel`` is a size in metres or a (y, x) pair; ``center`` the beam centre
     (row, column) in pixel units (default: the middle of the detector).
+    ``npt`` radial bins; with ``npt_azim`` (>= 2) the plan integrates in two
+    dimensions, bins (wedge c, radial bin a) in row c * npt + a, and
+    ``self.npt`` counts all of them.
     """
 
-    def __init__(self, h, w, npt, *, pixel=1e-4, center=None, dist=0.1, wavelength=1e-10,
-                 unit="r_m", split="bbox", range=None, dtype=torch.float64, accum="f64",
-                 layout="band", device=None, **tiling):
+    def __init__(self, h, w, npt, *, npt_azim=None, pixel=1e-4, center=None, dist=0.1,
+                 wavelength=1e-10, unit="r_m", split="bbox", range=None, dtype=torch.float64,
+                 accum="f64", layout="band", device=None, **tiling):
         py, px = (pixel, pixel) if np.isscalar(pixel) else pixel
         cy, cx = (h / 2.0, w / 2.0) if center is None else center
-        self.h, self.w, self.npt = int(h), int(w), int(npt)
+        self.npt_rad = int(npt)
+        self.npt_azim = int(npt_azim) if npt_azim else 0
+        self.h, self.w = int(h), int(w)
+        self.npt = self.npt_rad * max(self.npt_azim, 1)
         self.dtype = dtype
         self.accum = accum
         self._h = None
@@ -188,9 +200,15 @@ class Plan:
                   float(wavelength))
         rng = None if range is None else (ctypes.c_double * 2)(float(range[0]), float(range[1]))
         out = ctypes.c_void_p()
-        _check(lib().azi_plan_create(ctypes.byref(g), int(npt), UNITS[unit], SPLITS[split],
-                                     ctypes.cast(rng, ctypes.c_void_p) if rng else None,
-                                     _STORAGE[dtype], _ACCUM[accum], ctypes.byref(out)))
+        rng_p = ctypes.cast(rng, ctypes.c_void_p) if rng else None
+        if self.npt_azim:
+            _check(lib().azi_plan_create2d(ctypes.byref(g), self.npt_rad, self.npt_azim,
+                                           UNITS[unit], SPLITS[split], rng_p, _STORAGE[dtype],
+                                           _ACCUM[accum], ctypes.byref(out)))
+        else:
+            _check(lib().azi_plan_create(ctypes.byref(g), self.npt_rad, UNITS[unit],
+                                         SPLITS[split], rng_p, _STORAGE[dtype], _ACCUM[accum],
+                                         ctypes.byref(out)))
         self._h = out
         self.device = None
         if layout != "band":
@@ -199,6 +217,34 @@ class Plan:
             self.set_tiling(**tiling)
         if device is not None:
             self.upload(device)
+
+    @classmethod
+    def on_device(cls, h, w, npt, *, device, pixel=1e-4, center=None, dist=0.1,
+                  wavelength=1e-10, unit="r_m", split="bbox", range=None, dtype=torch.float64,
+                  accum="f64", stream=None):
+        """A one-dimensional plan built by the device plan builder on
+        ``device`` (returned uploaded there, band layout)."""
+        dev = torch.device(device) if not isinstance(device, torch.device) else device
+        idx = dev.index if dev.index is not None else torch.cuda.current_device()
+        py, px = (pixel, pixel) if np.isscalar(pixel) else pixel
+        cy, cx = (h / 2.0, w / 2.0) if center is None else center
+        self = cls.__new__(cls)
+        self.npt_rad, self.npt_azim = int(npt), 0
+        self.h, self.w, self.npt = int(h), int(w), int(npt)
+        self.dtype, self.accum = dtype, accum
+        self._h = None
+        g = _Geom(int(h), int(w), float(py), float(px), float(cy), float(cx), float(dist),
+                  float(wavelength))
+        rng = None if range is None else (ctypes.c_double * 2)(float(range[0]), float(range[1]))
+        out = ctypes.c_void_p()
+        with torch.cuda.device(idx):
+            _check(lib().azi_plan_create_device(
+                ctypes.byref(g), int(npt), UNITS[unit], SPLITS[split],
+                ctypes.cast(rng, ctypes.c_void_p) if rng else None, _STORAGE[dtype],
+                _ACCUM[accum], idx, _stream(stream), ctypes.byref(out)))
+        self._h = out
+        self.device = torch.device("cuda", idx)
+        return self
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
@@ -225,9 +271,22 @@ class Plan:
         return self.info()["nnz"]
 
     def positions(self):
-        out = np.empty(self.npt, dtype=np.float64)
+        """Radial bin centres (npt_rad values)."""
+        out = np.empty(self.npt_rad, dtype=np.float64)
         _check(lib().azi_plan_positions(self._h, out.ctypes.data))
         return out
+
+    def azimuths(self):
+        """Wedge centres in radians (two-dimensional plans)."""
+        out = np.empty(self.npt_azim, dtype=np.float64)
+        _check(lib().azi_plan_azimuths(self._h, out.ctypes.data))
+        return out
+
+    def shape(self):
+        """(npt_rad, npt_azim) as the library reports them (npt_azim 0 in 1-D)."""
+        a, b = _I32(), _I32()
+        _check(lib().azi_plan_shape(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     def _np_dtype(self):
         return np.float64 if self.dtype == torch.float64 else np.float32
@@ -399,6 +458,15 @@ def integrate1d(image, plan, *, empty=0.0):
     else:
         I, _, _ = plan.integrate_raw(x.contiguous(), empty=empty)
     return plan.positions(), I
+
+
+def integrate2d(image, plan, *, empty=0.0):
+    """(radial positions, wedge centres, I as an npt_azim x npt_rad map) of
+    a two-dimensional plan (Section 4)."""
+    if not plan.npt_azim:
+        raise ValueError("integrate2d needs a plan made with npt_azim")
+    _, I = integrate1d(image, plan, empty=empty)
+    return plan.positions(), plan.azimuths(), I.reshape(plan.npt_azim, plan.npt_rad)
 
 
 class Graph:

@@ -1,8 +1,8 @@
 """Builds libazint.so in the package directory for gfx950.
 
 Host plan builder: g++ without floating-point contraction (its integer
-results must be reproducible).  Kernels and the C ABI: hipcc for gfx950 with
-packed-fp32 instructions disabled.
+results must be reproducible); the device plan builder likewise.  Kernels
+and the C ABI: hipcc for gfx950 with packed-fp32 instructions disabled.
 """
 from __future__ import annotations
 
@@ -48,9 +48,13 @@ def build(verbose: bool = False) -> str:
     host = os.path.join(BUILD, "plan_builder.o")
     _run(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, "plan_builder.cpp"), "-o", host], verbose)
     objs.append(host)
-    for name in ("kernels.hip", "azint_api.hip"):
+    for name in ("kernels.hip", "azint_api.hip", "plan_device.hip", "fused.hip"):
         obj = os.path.join(BUILD, name.replace(".hip", ".o"))
-        _run([hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, name), "-o", obj], verbose)
+        # the device plan builder and the matrix-free kernel decide bin
+        # indices: no contraction, as on the host
+        extra = (["-ffp-contract=off", "-fno-fast-math"]
+                 if name in ("plan_device.hip", "fused.hip") else [])
+        _run([hipcc, *HIP_FLAGS, *extra, "-c", os.path.join(CSRC, name), "-o", obj], verbose)
         objs.append(obj)
     tmp = LIB + ".tmp"
     _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp], verbose)

@@ -14,6 +14,8 @@
 
 #include "internal.h"
 #include "kernels.h"
+#include "plan_device.h"
+#include "fused.h"
 
 namespace {
 
@@ -145,8 +147,9 @@ struct azi_plan {
     int64_t used = 0;  // ring layout: pixels feeding at least one bin
     DevBuf rowptr, indices, data, colptr, rowidx, cdata, tiles, splits, parts, dark, norm, xwork,
         vwork, order, dark_r, norm_r, pos, stiles, lidx, dest, btiles, brows, blp, bcoef, bin_ptr,
-        bparts, npieces_buf, npacked, ncoef, bin_slot, bin_count, nparts_buf;
-    int32_t nstiles = 0, nbtiles = 0, npieces = 0, band_rows = 8;
+        bparts, npieces_buf, npacked, ncoef, bin_slot, bin_count, nparts_buf, ftiles, fslots,
+        fbin_ptr, fparts;
+    int32_t nstiles = 0, nbtiles = 0, npieces = 0, band_rows = 8, nftiles = 0;
     int32_t ntiles = 0, nsplits = 0, nparts = 0;
     bool has_dark = false, has_norm = false;
 };
@@ -357,6 +360,54 @@ azi::BlockLaunch plan_block_args(const azi_plan* p, const void* img, int32_t img
     return a;
 }
 
+azi::FusedLaunch plan_fused_args(const azi_plan* p, const void* img, int32_t img_dtype,
+                                 bool correct, void* I, void* W, void* U, double empty) {
+    azi::FusedLaunch a;
+    a.tiles = p->ftiles.as<azi::FusedTile>();
+    a.ntiles = p->nftiles;
+    a.slots = p->fslots.as<int32_t>();
+    a.bin_ptr = p->fbin_ptr.as<int32_t>();
+    a.geom = p->geom;
+    a.unit = p->unit;
+    a.split = p->split;
+    a.pmin = p->m.pmin;
+    a.delta = (p->m.pmax - p->m.pmin) / p->m.npt;
+    a.npt = p->m.npt;
+    a.img = img;
+    a.img_dtype = img_dtype;
+    if (correct && p->has_dark) a.dark = p->dark.p;
+    if (correct && p->has_norm) a.norm = p->norm.p;
+    a.parts = p->fparts.p;
+    a.I = I;
+    a.W = W;
+    a.U = U;
+    a.empty = empty;
+    a.grid = p->tiling.grid;
+    a.dtype = p->dtype;
+    a.accum = p->accum;
+    return a;
+}
+
+int plan_upload_fused(azi_plan* p) {
+    try {
+        std::vector<azi::FusedTile> tiles;
+        std::vector<int32_t> slots, bin_ptr;
+        azi::build_fused(p->m, p->geom.h, p->geom.w, tiles, slots, bin_ptr);
+        if (tiles.size() >= (size_t)INT32_MAX || slots.size() >= (size_t)INT32_MAX)
+            return fail(AZI_EOVERFLOW, "fused schedule exceeds 2^31 tiles or slots");
+        AZI_HIP(p->ftiles.upload(tiles.data(), tiles.size() * sizeof(azi::FusedTile), p->device),
+                "fused tiles");
+        AZI_HIP(p->fslots.upload(slots.data(), slots.size() * 4, p->device), "fused slots");
+        AZI_HIP(p->fbin_ptr.upload(bin_ptr.data(), bin_ptr.size() * 4, p->device), "fused bins");
+        AZI_HIP(p->fparts.alloc(std::max<size_t>(slots.size(), 1) * 16, p->device),
+                "fused partials");
+        p->nftiles = (int32_t)tiles.size();
+    } catch (const std::bad_alloc&) {
+        return fail(AZI_ENOMEM, "out of host memory building the fused schedule");
+    }
+    return AZI_OK;
+}
+
 // Staging of a (raw or corrected) row-major image into the plan's ring work
 // image, with the plan's corrections when `correct` is set.
 azi::StageLaunch plan_stage_args(const azi_plan* p, const void* img, int32_t img_dtype,
@@ -439,12 +490,19 @@ int32_t azi_version(void) { return AZI_ABI_VERSION; }
 
 const char* azi_last_error(void) { return g_err.c_str(); }
 
-int azi_plan_create(const azi_geom* geom, int32_t npt, int32_t unit, int32_t split,
-                    const double* range2, int32_t dtype, int32_t accum, azi_plan** out) {
+namespace {
+int plan_build_device(azi_plan* p, int32_t npt, const double* range2, int device, hipStream_t s);
+
+// device < 0: the host builder; otherwise the device builder on that device
+// (one-dimensional plans), leaving the plan uploaded there.
+int plan_create(const azi_geom* geom, int32_t npt, int32_t npt_azim, int32_t unit, int32_t split,
+                const double* range2, int32_t dtype, int32_t accum, azi_plan** out,
+                int32_t device = -1, hipStream_t stream = nullptr) {
     if (!geom || !out) return fail(AZI_EINVAL, "geom and out must not be NULL");
     *out = nullptr;
     if (geom->h < 1 || geom->w < 1) return fail(AZI_EINVAL, "image shape must be at least 1x1");
     if (npt < 1) return fail(AZI_EINVAL, "npt must be >= 1");
+    if (npt_azim == 1 || npt_azim < 0) return fail(AZI_EINVAL, "npt_azim must be >= 2");
     if (!(geom->pixel_x_m > 0) || !(geom->pixel_y_m > 0) || !(geom->dist_m > 0) ||
         !(geom->wavelength_m > 0))
         return fail(AZI_EINVAL, "pixel sizes, distance and wavelength must be positive");
@@ -465,16 +523,223 @@ int azi_plan_create(const azi_geom* geom, int32_t npt, int32_t unit, int32_t spl
     p->accum = accum;
     p->unit = unit;
     p->split = split;
+    if (device >= 0) {
+        const int rc = plan_build_device(p.get(), npt, range2, device, stream);
+        if (rc != AZI_OK) return rc;
+        *out = p.release();
+        return AZI_OK;
+    }
     std::string err;
     int rc;
     try {
-        rc = azi::build_matrix(*geom, npt, unit, split, range2, p->m, err);
+        rc = azi::build_matrix(*geom, npt, npt_azim, unit, split, range2, p->m, err);
     } catch (const std::bad_alloc&) {
         return fail(AZI_ENOMEM, "out of host memory building the matrix");
     }
     if (rc != AZI_OK) return fail(rc, err);
     *out = p.release();
     return AZI_OK;
+}
+
+int bit_length(int64_t v) {
+    int b = 0;
+    while (v > 0) {
+        ++b;
+        v >>= 1;
+    }
+    return b;
+}
+
+extern "C++" {
+template <class T>
+int download(std::vector<T>& dst, const void* src, int64_t n, hipStream_t s) {
+    dst.resize((size_t)n);
+    if (n > 0)
+        AZI_HIP(hipMemcpyAsync(dst.data(), src, (size_t)n * sizeof(T), hipMemcpyDeviceToHost, s),
+                "download the matrix");
+    return AZI_OK;
+}
+}  // extern "C++"
+
+// Band layout from the pixel-major entries: a stable sort by band orders
+// each band's entries by (pixel, bin); the pieces come from the band starts,
+// which are the row pointers of the bands' first rows.
+int plan_device_bands(azi_plan* p, const int32_t* rowidx, const int32_t* pix, const double* cdata,
+                      int64_t nnz, DevBuf& work, DevBuf& skeys, DevBuf& perm, hipStream_t s) {
+    const int32_t R = band_rows_of(p->tiling);
+    p->band_rows = R;
+    if (p->m.npix >= ((int64_t)1 << azi::kBandShift))
+        return fail(AZI_EOVERFLOW, "the band layout takes images below 2^27 pixels");
+    if (nnz + kPad >= (int64_t)INT32_MAX)
+        return fail(AZI_EOVERFLOW, "band matrix exceeds 2^31 entries or pieces");
+    const int32_t npt = p->m.npt;
+    const int32_t nbands = (npt + R - 1) / R;
+    const int dev = p->device;
+    const size_t es = elem_size(p->dtype);
+    DevBuf keys;
+    AZI_HIP(keys.alloc((size_t)std::max<int64_t>(nnz, 1) * 4, dev), "band keys");
+    AZI_HIP(azi::launch_div(rowidx, nnz, R, keys.as<int32_t>(), s), "band keys");
+    AZI_HIP(azi::launch_sort(keys.as<int32_t>(), nnz, bit_length(nbands - 1), skeys.as<int32_t>(),
+                             perm.as<int32_t>(), work.p, s), "band sort");
+    AZI_HIP(p->npacked.alloc((size_t)(nnz + kPad) * 4, dev), "band entries");
+    AZI_HIP(p->ncoef.alloc((size_t)(nnz + kPad) * es, dev), "band coefficients");
+    AZI_HIP(azi::launch_band_entries(perm.as<int32_t>(), nnz, nnz + kPad, rowidx, pix, cdata, R,
+                                     p->npacked.as<int32_t>(), p->ncoef.p, p->dtype, s),
+            "band entries");
+    try {
+        std::vector<int64_t> start((size_t)nbands + 1);
+        for (int32_t b = 0; b < nbands; ++b) start[b] = p->m.indptr[(size_t)b * R];
+        start[nbands] = nnz;
+        azi::BandMatrix bm;
+        azi::band_pieces(start.data(), nbands, npt, R, p->tiling.tile_nnz, 0, 0, 0, bm);
+        AZI_HIP(p->npieces_buf.upload(bm.pieces.data(), bm.pieces.size() * sizeof(azi::BandPiece),
+                                      dev), "band pieces");
+        AZI_HIP(p->bin_slot.upload(bm.bin_slot.data(), bm.bin_slot.size() * 4, dev), "bin slots");
+        AZI_HIP(p->bin_count.upload(bm.bin_count.data(), bm.bin_count.size() * 4, dev),
+                "bin counts");
+        AZI_HIP(p->nparts_buf.alloc((size_t)std::max(bm.nslots, 1) * 16, dev), "band partials");
+        p->npieces = (int32_t)bm.pieces.size();
+    } catch (const std::bad_alloc&) {
+        return fail(AZI_ENOMEM, "out of host memory building the band pieces");
+    }
+    AZI_HIP(hipStreamSynchronize(s), "band layout");
+    return AZI_OK;
+}
+
+int plan_build_device(azi_plan* p, int32_t npt, const double* range2, int device, hipStream_t s) {
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count < 1)
+        return fail(AZI_EDEVICE, "no HIP device available");
+    if (device >= count) return fail(AZI_EDEVICE, "no such HIP device");
+    DeviceGuard guard(device);
+    if (guard.err != hipSuccess) return hip_fail(guard.err, "set device");
+    const azi_geom& g = p->geom;
+    const int64_t npix = (int64_t)g.h * g.w;
+    if (npix >= (int64_t)INT32_MAX) return fail(AZI_EOVERFLOW, "image has 2^31 pixels or more");
+    p->device = device;
+    azi::HostMatrix& m = p->m;
+    m.npt = m.npt_rad = npt;
+    m.npt_azim = 1;
+    m.two_d = false;
+    m.npix = npix;
+    const bool boxes = p->split != AZI_SPLIT_NONE;
+    const int64_t nblk = (npix + azi::kBuildBlock - 1) / azi::kBuildBlock;
+    DevBuf lo, hi, bmin, bmax, r2, cnt, scanw, tot;
+    AZI_HIP(lo.alloc((size_t)npix * 8, device), "extents");
+    AZI_HIP(hi.alloc(boxes ? (size_t)npix * 8 : 8, device), "extents");
+    AZI_HIP(bmin.alloc((size_t)nblk * 8, device), "block minima");
+    AZI_HIP(bmax.alloc((size_t)nblk * 8, device), "block maxima");
+    AZI_HIP(azi::launch_extents(g, p->unit, p->split, lo.as<double>(), hi.as<double>(),
+                                bmin.as<double>(), bmax.as<double>(), s), "extents");
+    double pr[2];
+    if (range2) {
+        pr[0] = range2[0];
+        pr[1] = range2[1];
+    } else {
+        AZI_HIP(r2.alloc(16, device), "range");
+        AZI_HIP(azi::launch_minmax(bmin.as<double>(), bmax.as<double>(), nblk, r2.as<double>(), s),
+                "range");
+        AZI_HIP(hipMemcpyAsync(pr, r2.p, 16, hipMemcpyDeviceToHost, s), "range");
+        AZI_HIP(hipStreamSynchronize(s), "range");
+    }
+    if (!(pr[1] > pr[0]) || !std::isfinite(pr[0]) || !std::isfinite(pr[1]))
+        return fail(AZI_EINVAL, "integration range is empty or not finite");
+    m.pmin = pr[0];
+    m.pmax = pr[1];
+    const double delta = (m.pmax - m.pmin) / npt;
+    AZI_HIP(cnt.alloc((size_t)npix * 4, device), "entry counts");
+    AZI_HIP(azi::launch_count(g, p->unit, p->split, lo.as<double>(), hi.as<double>(), m.pmin, delta,
+                              npt, cnt.as<int32_t>(), s), "entry counts");
+    AZI_HIP(p->colptr.alloc((size_t)(npix + 1) * 4, device), "colptr");
+    AZI_HIP(scanw.alloc(azi::scan_work_bytes(npix), device), "scan work");
+    AZI_HIP(tot.alloc(8, device), "scan total");
+    AZI_HIP(azi::launch_scan(cnt.as<int32_t>(), npix, p->colptr.as<int32_t>(), tot.as<int64_t>(),
+                             scanw.p, s), "scan");
+    int64_t nnz = 0;
+    AZI_HIP(hipMemcpyAsync(&nnz, tot.p, 8, hipMemcpyDeviceToHost, s), "scan total");
+    AZI_HIP(hipStreamSynchronize(s), "scan total");
+    if (nnz >= (int64_t)INT32_MAX - 2 * kPad)
+        return fail(AZI_EOVERFLOW, "matrix has 2^31 nonzeros or more");
+    cnt.release();
+    const int64_t nnz_alloc = round_up(nnz, kPad) + kPad;
+    const size_t es = elem_size(p->dtype);
+    const size_t n1 = (size_t)std::max<int64_t>(nnz, 1);
+    DevBuf cdata64, pix, work, skeys, perm, data64;
+    AZI_HIP(p->rowidx.alloc(n1 * 4, device), "rowidx");
+    AZI_HIP(cdata64.alloc(n1 * 8, device), "coefficients");
+    AZI_HIP(pix.alloc(n1 * 4, device), "pixel ids");
+    AZI_HIP(azi::launch_fill(g, p->unit, p->split, lo.as<double>(), hi.as<double>(), m.pmin, delta,
+                             npt, p->colptr.as<int32_t>(), p->rowidx.as<int32_t>(),
+                             cdata64.as<double>(), pix.as<int32_t>(), s), "fill");
+    // bin-major order: stable sort of the pixel-major entries by bin
+    AZI_HIP(work.alloc(azi::sort_work_bytes(nnz), device), "sort work");
+    AZI_HIP(skeys.alloc(n1 * 4, device), "sorted bins");
+    AZI_HIP(perm.alloc(n1 * 4, device), "permutation");
+    AZI_HIP(azi::launch_sort(p->rowidx.as<int32_t>(), nnz, bit_length(npt - 1),
+                             skeys.as<int32_t>(), perm.as<int32_t>(), work.p, s), "sort");
+    AZI_HIP(p->rowptr.alloc((size_t)(npt + 1) * 4, device), "indptr");
+    AZI_HIP(azi::launch_bounds(skeys.as<int32_t>(), nnz, npt, p->rowptr.as<int32_t>(), s),
+            "indptr");
+    AZI_HIP(p->indices.alloc((size_t)nnz_alloc * 4, device), "indices");
+    AZI_HIP(p->data.alloc((size_t)nnz_alloc * es, device), "data");
+    if (p->dtype != AZI_F64) AZI_HIP(data64.alloc(n1 * 8, device), "data (double)");
+    AZI_HIP(azi::launch_gather(perm.as<int32_t>(), nnz, nnz_alloc, pix.as<int32_t>(),
+                               cdata64.as<double>(), p->indices.as<int32_t>(), p->data.p,
+                               p->dtype, p->dtype != AZI_F64 ? data64.as<double>() : nullptr, s),
+            "gather");
+    AZI_HIP(p->cdata.alloc(n1 * es, device), "cdata");
+    AZI_HIP(azi::launch_to_storage(cdata64.as<double>(), nnz, p->cdata.p, p->dtype, s), "cdata");
+    // host copy of the matrix, for export and for the host-side layouts
+    try {
+        int rc = download(m.colptr, p->colptr.p, npix + 1, s);
+        if (rc == AZI_OK) rc = download(m.rowidx, p->rowidx.p, nnz, s);
+        if (rc == AZI_OK) rc = download(m.cdata, cdata64.p, nnz, s);
+        if (rc == AZI_OK) rc = download(m.indptr, p->rowptr.p, (int64_t)npt + 1, s);
+        if (rc == AZI_OK) rc = download(m.indices, p->indices.p, nnz, s);
+        if (rc == AZI_OK)
+            rc = download(m.data, p->dtype == AZI_F64 ? p->data.p : data64.p, nnz, s);
+        if (rc != AZI_OK) return rc;
+        AZI_HIP(hipStreamSynchronize(s), "download the matrix");
+    } catch (const std::bad_alloc&) {
+        return fail(AZI_ENOMEM, "out of host memory for the matrix copy");
+    }
+    data64.release();
+    p->order.release();
+    p->used = npix;
+    AZI_HIP(p->xwork.alloc((size_t)npix * es, device), "work image");
+    AZI_HIP(p->vwork.alloc((size_t)npt * 8, device), "work vector");
+    p->layout = AZI_LAYOUT_BAND;
+    int rc = plan_device_bands(p, p->rowidx.as<int32_t>(), pix.as<int32_t>(), cdata64.as<double>(),
+                               nnz, work, skeys, perm, s);
+    if (rc != AZI_OK) return rc;
+    return plan_upload_tiles(p);
+}
+}  // namespace
+
+int azi_plan_create(const azi_geom* geom, int32_t npt, int32_t unit, int32_t split,
+                    const double* range2, int32_t dtype, int32_t accum, azi_plan** out) {
+    return plan_create(geom, npt, 0, unit, split, range2, dtype, accum, out);
+}
+
+int azi_plan_create_device(const azi_geom* geom, int32_t npt, int32_t unit, int32_t split,
+                           const double* range2, int32_t dtype, int32_t accum, int32_t device,
+                           void* stream, azi_plan** out) {
+    if (device < 0) {
+        if (out) *out = nullptr;
+        return fail(AZI_EDEVICE, "no such HIP device");
+    }
+    return plan_create(geom, npt, 0, unit, split, range2, dtype, accum, out, device,
+                       static_cast<hipStream_t>(stream));
+}
+
+int azi_plan_create2d(const azi_geom* geom, int32_t npt_rad, int32_t npt_azim, int32_t unit,
+                      int32_t split, const double* range2, int32_t dtype, int32_t accum,
+                      azi_plan** out) {
+    if (npt_azim < 2) {
+        if (out) *out = nullptr;
+        return fail(AZI_EINVAL, "npt_azim must be >= 2");
+    }
+    return plan_create(geom, npt_rad, npt_azim, unit, split, range2, dtype, accum, out);
 }
 
 int azi_plan_destroy(azi_plan* plan) {
@@ -496,8 +761,23 @@ int azi_plan_info(const azi_plan* p, int32_t* npt, int64_t* npix, int64_t* nnz, 
 
 int azi_plan_positions(const azi_plan* p, double* pos) {
     if (!p || !pos) return fail(AZI_EINVAL, "plan and positions must not be NULL");
-    const double delta = (p->m.pmax - p->m.pmin) / p->m.npt;
-    for (int32_t b = 0; b < p->m.npt; ++b) pos[b] = p->m.pmin + (b + 0.5) * delta;
+    const double delta = (p->m.pmax - p->m.pmin) / p->m.npt_rad;
+    for (int32_t b = 0; b < p->m.npt_rad; ++b) pos[b] = p->m.pmin + (b + 0.5) * delta;
+    return AZI_OK;
+}
+
+int azi_plan_shape(const azi_plan* p, int32_t* npt_rad, int32_t* npt_azim) {
+    if (!p) return fail(AZI_EINVAL, "plan is NULL");
+    if (npt_rad) *npt_rad = p->m.npt_rad;
+    if (npt_azim) *npt_azim = p->m.two_d ? p->m.npt_azim : 0;
+    return AZI_OK;
+}
+
+int azi_plan_azimuths(const azi_plan* p, double* chi) {
+    if (!p || !chi) return fail(AZI_EINVAL, "plan and chi must not be NULL");
+    if (!p->m.two_d) return fail(AZI_ESTATE, "the plan is one-dimensional");
+    const double dchi = (2.0 * M_PI) / p->m.npt_azim;
+    for (int32_t c = 0; c < p->m.npt_azim; ++c) chi[c] = -M_PI + (c + 0.5) * dchi;
     return AZI_OK;
 }
 
@@ -567,8 +847,11 @@ int azi_plan_tile_schedule(const azi_plan* p, const azi_tiling* tl, int32_t* nti
 
 int azi_plan_set_layout(azi_plan* p, int32_t layout) {
     if (!p) return fail(AZI_EINVAL, "plan is NULL");
-    if (layout < AZI_LAYOUT_PIXEL || layout > AZI_LAYOUT_BAND)
-        return fail(AZI_EINVAL, "layout must be one of AZI_LAYOUT_PIXEL/RING/TILE/BAND");
+    if (layout < AZI_LAYOUT_PIXEL || layout > AZI_LAYOUT_FUSED)
+        return fail(AZI_EINVAL, "layout must be one of AZI_LAYOUT_PIXEL/RING/TILE/BAND/FUSED");
+    if (layout == AZI_LAYOUT_FUSED && (p->m.two_d || p->split == AZI_SPLIT_FULL))
+        return fail(AZI_EINVAL,
+                    "the fused layout takes one-dimensional plans without full splitting");
     if (layout == p->layout) return AZI_OK;
     p->layout = layout;
     if (p->device >= 0) {
@@ -646,6 +929,10 @@ int azi_plan_upload(azi_plan* p, int32_t device) {
             int rc2 = plan_upload_bands(p);
             if (rc2 != AZI_OK) return rc2;
         }
+        if (p->layout == AZI_LAYOUT_FUSED) {
+            int rc2 = plan_upload_fused(p);
+            if (rc2 != AZI_OK) return rc2;
+        }
         if (p->layout == AZI_LAYOUT_TILE) {
             try {
                 azi::BlockMatrix bm;
@@ -668,7 +955,8 @@ int azi_plan_upload(azi_plan* p, int32_t device) {
 
 int64_t azi_plan_device_bytes(const azi_plan* p) {
     if (!p) return 0;
-    const DevBuf* bufs[] = {&p->rowptr, &p->indices, &p->data, &p->colptr, &p->rowidx,
+    const DevBuf* bufs[] = {&p->ftiles, &p->fslots, &p->fbin_ptr, &p->fparts,
+                            &p->rowptr, &p->indices, &p->data, &p->colptr, &p->rowidx,
                             &p->cdata, &p->tiles, &p->splits, &p->parts, &p->dark,
                             &p->norm, &p->xwork, &p->vwork, &p->order, &p->dark_r,
                             &p->norm_r, &p->pos, &p->stiles, &p->lidx, &p->dest,
@@ -747,6 +1035,11 @@ int azi_integrate1d(const azi_plan* p, const void* x, void* I, void* W, void* U,
     DeviceGuard g(p->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "set device");
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (p->layout == AZI_LAYOUT_FUSED) {
+        AZI_HIP(azi::launch_fused(plan_fused_args(p, x, p->dtype, false, I, W, U, empty), s),
+                "fused forward kernels");
+        return AZI_OK;
+    }
     if (p->layout == AZI_LAYOUT_TILE) {
         AZI_HIP(azi::launch_block(plan_block_args(p, x, p->dtype, false, I, W, U, empty), s),
                 "blocked forward kernels");
@@ -791,6 +1084,12 @@ int azi_integrate1d_staged(const azi_plan* p, void* I, void* W, void* U, double 
     if (!I) return fail(AZI_EINVAL, "out_I must not be NULL");
     DeviceGuard g(p->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "set device");
+    if (p->layout == AZI_LAYOUT_FUSED) {
+        AZI_HIP(azi::launch_fused(plan_fused_args(p, p->xwork.p, p->dtype, false, I, W, U, empty),
+                                  static_cast<hipStream_t>(stream)),
+                "fused forward kernels");
+        return AZI_OK;
+    }
     if (p->layout == AZI_LAYOUT_TILE) {
         AZI_HIP(azi::launch_block(plan_block_args(p, p->xwork.p, p->dtype, false, I, W, U, empty),
                                   static_cast<hipStream_t>(stream)),
@@ -812,6 +1111,17 @@ int azi_integrate1d_staged(const azi_plan* p, void* I, void* W, void* U, double 
 int azi_integrate1d_raw(const azi_plan* p, const void* raw, int32_t raw_dtype, void* I, void* W,
                         void* U, double empty, void* stream) {
     if (!I) return fail(AZI_EINVAL, "out_I must not be NULL");
+    if (p && p->layout == AZI_LAYOUT_FUSED && p->device >= 0) {
+        // cast, correction and integration in one kernel
+        if (!raw) return fail(AZI_EINVAL, "raw must not be NULL");
+        if (!valid_raw_dtype(raw_dtype)) return fail(AZI_EINVAL, "unknown raw dtype");
+        DeviceGuard g(p->device);
+        if (g.err != hipSuccess) return hip_fail(g.err, "set device");
+        AZI_HIP(azi::launch_fused(plan_fused_args(p, raw, raw_dtype, true, I, W, U, empty),
+                                  static_cast<hipStream_t>(stream)),
+                "fused forward kernels");
+        return AZI_OK;
+    }
     if (p && p->layout == AZI_LAYOUT_TILE && p->device >= 0) {
         // cast and correction fused into the blocked kernel
         if (!raw) return fail(AZI_EINVAL, "raw must not be NULL");
@@ -861,6 +1171,8 @@ int azi_batch_create(azi_plan* const* plans, int32_t n, int32_t device, azi_batc
         if (plans[k]->dtype != plans[0]->dtype || plans[k]->accum != plans[0]->accum ||
             plans[k]->layout != plans[0]->layout)
             return fail(AZI_EINVAL, "plans of a batch must share dtype, accumulation and layout");
+    if (plans[0]->layout == AZI_LAYOUT_FUSED)
+        return fail(AZI_EINVAL, "batches take the pixel, ring, tile or band layout");
     }
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || count < 1)

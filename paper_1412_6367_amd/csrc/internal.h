@@ -47,7 +47,9 @@ struct Split {
 // double (the builder's exact output) and rounded to the storage type on
 // export or upload.
 struct HostMatrix {
-    int32_t npt = 0;
+    int32_t npt = 0;               // rows: npt_rad * npt_azim
+    int32_t npt_rad = 0, npt_azim = 1;
+    bool two_d = false;            // rows are (azimuthal wedge, radial bin) pairs
     int64_t npix = 0;
     double pmin = 0.0, pmax = 0.0;
     std::vector<int32_t> indptr;   // CSR, npt + 1
@@ -94,9 +96,11 @@ void build_stage_tiles(int32_t h, int32_t w, const int32_t* pos, int64_t img_off
                        int64_t k_off, std::vector<StageTile>& tiles, std::vector<uint16_t>& lidx,
                        std::vector<int32_t>& dest);
 
-// Geometry -> radial extents -> coefficients -> CSC and CSR.  Returns an
-// AZI_* code and fills `err` on failure.
-int build_matrix(const azi_geom& g, int32_t npt, int32_t unit, int32_t split,
+// Geometry -> extents -> coefficients -> CSC and CSR.  npt_azim == 0 builds
+// the one-dimensional matrix of npt radial bins; npt_azim >= 2 the
+// two-dimensional one, row c * npt + a for wedge c of [-pi, pi) and radial
+// bin a.  Returns an AZI_* code and fills `err` on failure.
+int build_matrix(const azi_geom& g, int32_t npt, int32_t npt_azim, int32_t unit, int32_t split,
                  const double* range2, HostMatrix& m, std::string& err);
 
 // Matrix blocked by image tiles: the tile layout.  Every tile of
@@ -163,6 +167,26 @@ struct BandMatrix {
 // or more.
 bool build_bands(const HostMatrix& m, int32_t R, int32_t piece_nnz, int64_t pix_off,
                  int64_t bin_off, BandMatrix& bm);
+// The pieces, slots and per-bin slot ranges of one instance whose band b
+// holds entries [base + start[b], base + start[b + 1]) (the second half of
+// build_bands, also used when the entries were ordered on the device).
+void band_pieces(const int64_t* start, int32_t nbands, int32_t npt, int32_t R, int32_t piece_nnz,
+                 int64_t base, int64_t pix_off, int64_t bin_off, BandMatrix& bm);
+
+// Matrix-free ("fused") schedule: the image cut into kFusedH x kFusedW
+// tiles; tile t feeds the bin window [wlo, wlo + nwin) and writes the partial
+// sums of bin wlo + k to slot slots[slot_off + k]; bin b owns slots
+// [bin_ptr[b], bin_ptr[b + 1]), one per tile whose window holds it, in tile
+// order.  Windows come from the pixel-major entries of the plan's matrix.
+constexpr int32_t kFusedH = 16, kFusedW = 64;
+struct FusedTile {
+    int32_t i0, j0, th, tw;
+    int32_t wlo, nwin;
+    int64_t slot_off;
+};
+static_assert(sizeof(FusedTile) == 32, "fused tile layout");
+void build_fused(const HostMatrix& m, int32_t h, int32_t w, std::vector<FusedTile>& tiles,
+                 std::vector<int32_t>& slots, std::vector<int32_t>& bin_ptr);
 
 // Appends the tile schedule of one instance.  `indptr` holds the instance's
 // own row pointers (starting at 0); z_off / r_off / ip_off shift nonzeros,

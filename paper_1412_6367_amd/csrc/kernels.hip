@@ -19,81 +19,13 @@
 // (sum, compensation) pairs are merged across lanes with Knuth's TwoSum.
 #include <hip/hip_runtime.h>
 
+#include "accum.h"
 #include "kernels.h"
 
 namespace azi {
 namespace {
 
-constexpr int kWave = 64;
 
-// ---------------------------------------------------------------------------
-// Accumulators
-// ---------------------------------------------------------------------------
-
-struct AccF64 {
-    double w, u;
-    __device__ void zero() { w = 0.0; u = 0.0; }
-    template <class T>
-    __device__ void add(T c, T x) {
-        w = __fma_rn((double)c, (double)x, w);
-        u += (double)c;
-    }
-    __device__ void merge(const AccF64& o) { w += o.w; u += o.u; }
-    __device__ AccF64 shfl_xor(int m) const {
-        AccF64 r;
-        r.w = __shfl_xor(w, m, kWave);
-        r.u = __shfl_xor(u, m, kWave);
-        return r;
-    }
-    __device__ double W() const { return w; }
-    __device__ double U() const { return u; }
-};
-
-// Kahan (1965) compensated float sums; merge keeps the rounding error of the
-// addition of the two leading parts (TwoSum) in the compensation term.
-struct AccK32 {
-    float ws, wc, us, uc;  // running sum and compensation (to be added)
-    __device__ void zero() { ws = wc = us = uc = 0.0f; }
-    __device__ static void kadd(float& s, float& c, float v) {
-        const float y = __fsub_rn(v, c);
-        const float t = __fadd_rn(s, y);
-        c = __fsub_rn(__fsub_rn(t, s), y);
-        s = t;
-    }
-    __device__ static void two_sum(float a, float b, float& s, float& e) {
-        s = __fadd_rn(a, b);
-        const float bb = __fsub_rn(s, a);
-        e = __fadd_rn(__fsub_rn(a, __fsub_rn(s, bb)), __fsub_rn(b, bb));
-    }
-    template <class T>
-    __device__ void add(T c, T x) {
-        kadd(ws, wc, __fmul_rn((float)c, (float)x));
-        kadd(us, uc, (float)c);
-    }
-    // Here wc / uc hold the amount ALREADY SUBTRACTED (Kahan's c): the value
-    // of a pair is s - c.
-    __device__ void merge(const AccK32& o) {
-        float s, e;
-        two_sum(ws, o.ws, s, e);
-        wc = __fsub_rn(__fadd_rn(wc, o.wc), e);
-        ws = s;
-        two_sum(us, o.us, s, e);
-        uc = __fsub_rn(__fadd_rn(uc, o.uc), e);
-        us = s;
-    }
-    __device__ AccK32 shfl_xor(int m) const {
-        AccK32 r;
-        r.ws = __shfl_xor(ws, m, kWave);
-        r.wc = __shfl_xor(wc, m, kWave);
-        r.us = __shfl_xor(us, m, kWave);
-        r.uc = __shfl_xor(uc, m, kWave);
-        return r;
-    }
-    __device__ float W() const { return __fsub_rn(ws, wc); }
-    __device__ float U() const { return __fsub_rn(us, uc); }
-};
-
-static_assert(sizeof(AccF64) == 16 && sizeof(AccK32) == 16, "partial slot is 16 bytes");
 
 // ---------------------------------------------------------------------------
 // Loads
@@ -210,21 +142,6 @@ __device__ inline void accumulate_var(Acc& a, int32_t zlo, int32_t zhi, int lane
     using V = Variant<VAR>;
     if constexpr (V::x4) accumulate<V::unroll>(a, zlo, zhi, lane, lanes, idx, dat, x);
     else accumulate_strided<V::unroll, V::nt>(a, zlo, zhi, lane, lanes, idx, dat, x);
-}
-
-template <class Acc>
-__device__ inline void group_reduce(Acc& a, int lanes) {
-    for (int m = lanes >> 1; m > 0; m >>= 1) a.merge(a.shfl_xor(m));
-}
-
-template <class T, class Acc>
-__device__ inline void write_row(int32_t r, const Acc& a, T* __restrict__ I, T* __restrict__ W,
-                                 T* __restrict__ U, double empty) {
-    const auto w = a.W();
-    const auto u = a.U();
-    if (W) W[r] = (T)w;
-    if (U) U[r] = (T)u;
-    I[r] = (u != 0) ? (T)(w / u) : (T)empty;
 }
 
 template <class T, class Acc, int BLOCK, int VAR>
@@ -502,34 +419,11 @@ __global__ __launch_bounds__(BLOCK) void k_block(const BlockTile* __restrict__ t
     }
 }
 
-// One wavefront per bin adds the bin's partial sums (fixed lanes, fixed
-// tree: deterministic) and writes W, U and I.
-template <class T, class Acc>
-__global__ void k_block_reduce(const int32_t* __restrict__ bin_ptr, int64_t b0, int64_t b1,
-                               const Acc* __restrict__ parts, T* __restrict__ I,
-                               T* __restrict__ W, T* __restrict__ U, double empty) {
-    const int64_t b = b0 + (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    if (b >= b1) return;
-    const int lane = threadIdx.x & (kWave - 1);
-    Acc a;
-    a.zero();
-    for (int32_t k = bin_ptr[b] + lane; k < bin_ptr[b + 1]; k += kWave) a.merge(parts[k]);
-    group_reduce(a, kWave);
-    if (lane == 0) write_row((int32_t)b, a, I, W, U, empty);
-}
 
 // ---------------------------------------------------------------------------
 // Correction map (Section 6.4)
 // ---------------------------------------------------------------------------
 
-// Workgroup g runs on XCD g % 8; this maps it to a block index so that each
-// XCD walks one contiguous eighth of the blocks (a bijection on [0, n)).
-__device__ inline int64_t xcd_block(int64_t g, int64_t n) {
-    if (n < 8) return g;
-    const int64_t xcd = g & 7, q = g >> 3;
-    const int64_t per = n >> 3, rem = n & 7;
-    return xcd * per + (xcd < rem ? xcd : rem) + q;
-}
 
 // x[i] = (T(raw[src]) - dark[i]) / norm[i], src = order ? order[i] : i.
 // With a ring order the output is the image in ring positions (and dark and

@@ -1,7 +1,9 @@
-// Host plan builder: detector geometry -> per-pixel radial extent ->
-// bounding-box coefficients (Section 4.1) or whole-pixel histogram entries
-// (Section 3.3) -> pixel-major (CSC) and bin-major (CSR, Section 5.2.1)
-// matrices -> tile schedule for the gather kernels.
+// Host plan builder: detector geometry -> per-pixel radial (and azimuthal)
+// extent -> bounding-box coefficients (Section 4.1), full-splitting areas
+// (Section 4.2) or whole-pixel histogram entries (Section 3.3), in one
+// dimension (radius) or two (radius x azimuth) -> pixel-major (CSC) and
+// bin-major (CSR, Section 5.2.1) matrices -> tile schedule for the gather
+// kernels.
 //
 // Compiled without floating-point contraction: every quantity that decides
 // a bin index is formed by the same sequence of correctly rounded IEEE
@@ -12,86 +14,87 @@
 #include <limits>
 
 #include "internal.h"
+#include "pixel_math.h"
 
 namespace azi {
 namespace {
 
-// Output coordinate of a radius r in metres (Section 3 coordinate list):
-// 2theta = atan(r / d), q = 4 pi sin(2theta / 2) / lambda with lambda in nm.
-inline double to_unit(double r, int32_t unit, double dist, double wl) {
-    switch (unit) {
-        case AZI_UNIT_R_M: return r;
-        case AZI_UNIT_R_MM: return r * 1e3;
-        default: break;
+// Azimuths chi = atan2(y, x) of the four corners of pixel (i, j), in the
+// order (j, i), (j+1, i), (j+1, i+1), (j, i+1), unwrapped to within pi of
+// the first corner; p0 (optional) receives the corners' output coordinate.
+inline void pixel_corners(int64_t i, int64_t j, const azi_geom& g, int32_t unit, double* p0,
+                          double* p1) {
+    const int da[4] = {0, 1, 1, 0}, db[4] = {0, 0, 1, 1};
+    for (int k = 0; k < 4; ++k) {
+        const double x = ((double)(j + da[k]) - g.center_x_px) * g.pixel_x_m;
+        const double y = ((double)(i + db[k]) - g.center_y_px) * g.pixel_y_m;
+        if (p0) p0[k] = to_unit(std::sqrt(x * x + y * y), unit, g.dist_m, g.wavelength_m);
+        p1[k] = std::atan2(y, x);
     }
-    const double tth = std::atan(r / dist);
-    if (unit == AZI_UNIT_2TH_RAD) return tth;
-    if (unit == AZI_UNIT_2TH_DEG) return tth * (180.0 / M_PI);
-    return (4.0 * M_PI) * std::sin(tth / 2.0) / (wl * 1e9);
+    for (int k = 1; k < 4; ++k)
+        p1[k] += std::nearbyint((p1[0] - p1[k]) / (2.0 * M_PI)) * (2.0 * M_PI);
 }
 
-// Radial extent of pixel (i, j) = the square [j, j+1] x [i, i+1]: the
-// farthest corner and the nearest point of the square from the beam centre
-// (the box circumscribing the pixel in the radial direction), and the
-// radius of the pixel midpoint.
-struct Extent { double lo, hi, mid; };
+inline int32_t wrap(int64_t k, int32_t n) { return (int32_t)(((k % n) + n) % n); }
 
-inline Extent pixel_extent(int64_t i, int64_t j, const azi_geom& g) {
-    const double cx = g.center_x_px, cy = g.center_y_px;
-    const double px = g.pixel_x_m, py = g.pixel_y_m;
-    const double x0 = ((double)j - cx) * px, x1 = ((double)(j + 1) - cx) * px;
-    const double y0 = ((double)i - cy) * py, y1 = ((double)(i + 1) - cy) * py;
-    const double a = x0 * x0, b = x1 * x1, c = y0 * y0, d = y1 * y1;
-    const double s = std::max(std::max(a + c, b + c), std::max(a + d, b + d));
-    const double ex = std::max(std::max((double)j - cx, cx - (double)(j + 1)), 0.0) * px;
-    const double ey = std::max(std::max((double)i - cy, cy - (double)(i + 1)), 0.0) * py;
-    const double xm = ((double)j + 0.5 - cx) * px, ym = ((double)i + 0.5 - cy) * py;
-    Extent e;
-    e.hi = std::sqrt(s);
-    e.lo = std::sqrt(ex * ex + ey * ey);
-    e.mid = std::sqrt(xm * xm + ym * ym);
-    return e;
-}
-
-// Entries of one pixel for a box [lo, hi] over bins of width delta from
-// pmin: fractional positions fl, fh; the inside part [flc, fhc] of [0, npt];
-// bins floor(flc) .. ceil(fhc) - 1; weight = overlap / (fh - fl).
+// Azimuthal shares of a pixel whose azimuth spans [clo, chi] (corner
+// extremes: along a straight edge missing the beam the azimuth is
+// monotone): wedges of width dchi from -pi, periodic; outer wedges get
+// their overlap over the span, inner ones 1 / span.  A pixel holding the
+// beam (whole) spreads evenly over all wedges.
 template <class Emit>
-inline void bbox_pixel(double lo, double hi, double pmin, double delta, int32_t npt,
-                       Emit&& emit) {
-    const double fl = (lo - pmin) / delta;
-    const double fh = (hi - pmin) / delta;
-    const double n = (double)npt;
-    if (fh == fl) {  // zero-width box: whole weight to its bin
-        if (fl >= 0.0 && fl <= n) emit(std::min((int32_t)std::floor(fl), npt - 1), 1.0);
+inline void azimuth_shares(bool whole, double clo, double chi, int32_t nazim, double dchi,
+                           Emit&& emit) {
+    if (whole) {
+        for (int32_t k = 0; k < nazim; ++k) emit(k, 1.0 / nazim);
         return;
     }
-    const double flc = std::max(fl, 0.0);
-    const double fhc = std::min(fh, n);
-    if (!(fhc > flc)) return;
-    const double width = fh - fl;
-    const int32_t b0 = (int32_t)std::floor(flc);
-    const int32_t b1 = (int32_t)std::ceil(fhc) - 1;
-    if (b0 == b1) {
-        emit(b0, (fhc - flc) / width);
-        return;
+    const double gl = (clo + M_PI) / dchi;
+    const double gh = (chi + M_PI) / dchi;
+    const double width = gh - gl;
+    const int64_t k0 = (int64_t)std::floor(gl);
+    int64_t k1 = (int64_t)std::ceil(gh) - 1;
+    if (width == 0.0 || k1 < k0) k1 = k0;
+    for (int64_t k = k0; k <= k1; ++k) {
+        double c;
+        if (k0 == k1) c = 1.0;
+        else if (k == k0) c = ((double)(k0 + 1) - gl) / width;
+        else if (k == k1) c = (gh - (double)k1) / width;
+        else c = 1.0 / width;
+        if (c > 0.0) emit(wrap(k, nazim), c);
     }
-    emit(b0, ((double)(b0 + 1) - flc) / width);
-    const double inner = 1.0 / width;
-    for (int32_t b = b0 + 1; b < b1; ++b) emit(b, inner);
-    emit(b1, (fhc - (double)b1) / width);
 }
 
-// Full splitting (Section 4.2): the pixel's four corners, mapped to
-// (output unit, azimuth) and joined by straight edges, form a
-// quadrilateral; bin b gets the part of its area within the bin's slab of
-// the output unit over its whole area.  The area within a slab is the sum,
-// over the four edges, of the integral of the edge's line over the slab
-// (the vertical edges of the clipped polygon add nothing), in absolute
-// value.  Coordinates are taken relative to the first corner.
-struct Quad { double x[4], y[4]; };
+// Integral over [a, b] of clamp(y0 + (x - x0) * slope, t0, t1): the
+// interval is cut where the line meets t0 and t1, and the clamped line is
+// linear on every piece, so each piece is an exact trapezoid.
+inline double clamped_line(double x0, double y0, double slope, double a, double b, double t0,
+                           double t1) {
+    double cut[4];
+    int n = 0;
+    cut[n++] = a;
+    if (slope != 0.0) {
+        double xa = x0 + (t0 - y0) / slope, xb = x0 + (t1 - y0) / slope;
+        if (xa > xb) std::swap(xa, xb);
+        if (xa > a && xa < b) cut[n++] = xa;
+        if (xb > a && xb < b) cut[n++] = xb;
+    }
+    cut[n++] = b;
+    double s = 0.0;
+    for (int k = 0; k + 1 < n; ++k) {
+        const double u = cut[k], v = cut[k + 1];
+        const double yu = std::min(std::max(y0 + (u - x0) * slope, t0), t1);
+        const double yv = std::min(std::max(y0 + (v - x0) * slope, t0), t1);
+        s += (v - u) * (yu + yv) / 2.0;
+    }
+    return s;
+}
 
-inline double edge_integral(const Quad& q, double e0, double e1) {
+// Area of the quadrilateral inside [e0, e1] x [t0, t1]: over every x of the
+// slab, the boundary's lower and upper crossings bound the section, and
+// clamp(upper) - clamp(lower) is the part of it inside [t0, t1]; summing the
+// clamped edge lines with the edge's direction as sign gives that total.
+inline double edge_integral_box(const Quad& q, double e0, double e1, double t0, double t1) {
     double s = 0.0;
     for (int k = 0; k < 4; ++k) {
         const double ax = q.x[k], ay = q.y[k];
@@ -100,57 +103,92 @@ inline double edge_integral(const Quad& q, double e0, double e1) {
         const double lo = std::max(std::min(ax, bx), e0);
         const double hi = std::min(std::max(ax, bx), e1);
         if (!(hi > lo)) continue;
-        const double slope = (by - ay) / (bx - ax);
-        const double ylo = ay + (lo - ax) * slope;
-        const double yhi = ay + (hi - ax) * slope;
-        const double part = (hi - lo) * (ylo + yhi) / 2.0;
+        const double part = clamped_line(ax, ay, (by - ay) / (bx - ax), lo, hi, t0, t1);
         s += bx > ax ? part : -part;
     }
     return std::fabs(s);
 }
 
+// One pixel of two-dimensional integration; emit(row, coefficient) with
+// row = azimuthal wedge * nrad + radial bin.
+struct Grid2d {
+    double pmin, delta, dchi;
+    int32_t nrad, nazim;
+};
+
 template <class Emit>
-inline void full_pixel(int64_t i, int64_t j, const azi_geom& g, int32_t unit, double lo, double hi,
-                       double pmin, double delta, int32_t npt, Emit&& emit) {
-    if (lo == 0.0) {  // the beam centre lies on this pixel
-        bbox_pixel(lo, hi, pmin, delta, npt, emit);
+inline void bbox2d_pixel(int64_t i, int64_t j, const azi_geom& g, double lo, double hi,
+                         const Grid2d& G, std::vector<std::pair<int32_t, double>>& rad,
+                         Emit&& emit) {
+    rad.clear();
+    bbox_pixel(lo, hi, G.pmin, G.delta, G.nrad,
+               [&](int32_t b, double c) { rad.emplace_back(b, c); });
+    if (rad.empty()) return;
+    const bool whole = lo == 0.0;
+    double clo = 0.0, chi = 0.0;
+    if (!whole) {
+        double p1[4];
+        pixel_corners(i, j, g, AZI_UNIT_R_M, nullptr, p1);
+        clo = std::min(std::min(p1[0], p1[1]), std::min(p1[2], p1[3]));
+        chi = std::max(std::max(p1[0], p1[1]), std::max(p1[2], p1[3]));
+    }
+    azimuth_shares(whole, clo, chi, G.nazim, G.dchi, [&](int32_t k, double ac) {
+        for (const auto& e : rad) emit(k * G.nrad + e.first, e.second * ac);
+    });
+}
+
+template <class Emit>
+inline void full2d_pixel(int64_t i, int64_t j, const azi_geom& g, int32_t unit, double lo,
+                         double hi, const Grid2d& G,
+                         std::vector<std::pair<int32_t, double>>& rad, Emit&& emit) {
+    if (lo == 0.0) {  // the beam lies on this pixel
+        bbox2d_pixel(i, j, g, lo, hi, G, rad, emit);
         return;
     }
-    const int da[4] = {0, 1, 1, 0}, db[4] = {0, 0, 1, 1};
     double p0[4], p1[4];
-    for (int k = 0; k < 4; ++k) {
-        const double x = ((double)(j + da[k]) - g.center_x_px) * g.pixel_x_m;
-        const double y = ((double)(i + db[k]) - g.center_y_px) * g.pixel_y_m;
-        p0[k] = to_unit(std::sqrt(x * x + y * y), unit, g.dist_m, g.wavelength_m);
-        p1[k] = std::atan2(y, x);
-    }
-    for (int k = 1; k < 4; ++k)
-        p1[k] += std::nearbyint((p1[0] - p1[k]) / (2.0 * M_PI)) * (2.0 * M_PI);
+    pixel_corners(i, j, g, unit, p0, p1);
     const double mn = std::min(std::min(p0[0], p0[1]), std::min(p0[2], p0[3]));
     const double mx = std::max(std::max(p0[0], p0[1]), std::max(p0[2], p0[3]));
+    const double cmn = std::min(std::min(p1[0], p1[1]), std::min(p1[2], p1[3]));
+    const double cmx = std::max(std::max(p1[0], p1[1]), std::max(p1[2], p1[3]));
     Quad q;
     for (int k = 0; k < 4; ++k) {
         q.x[k] = p0[k] - p0[0];
         q.y[k] = p1[k] - p1[0];
     }
     const double area = edge_integral(q, -HUGE_VAL, HUGE_VAL);
-    const double fl = (mn - pmin) / delta, fh = (mx - pmin) / delta;
+    const double fl = (mn - G.pmin) / G.delta, fh = (mx - G.pmin) / G.delta;
     if (area == 0.0 || fh == fl) return;
     const int32_t b0 = std::max((int32_t)std::floor(fl), 0);
-    const int32_t b1 = std::min((int32_t)std::ceil(fh) - 1, npt - 1);
+    const int32_t b1 = std::min((int32_t)std::ceil(fh) - 1, G.nrad - 1);
+    const int64_t k0 = (int64_t)std::floor((cmn + M_PI) / G.dchi);
+    const int64_t k1 = std::max((int64_t)std::ceil((cmx + M_PI) / G.dchi) - 1, k0);
     for (int32_t b = b0; b <= b1; ++b) {
-        const double e0 = (pmin + b * delta) - p0[0];
-        const double e1 = (pmin + (b + 1) * delta) - p0[0];
-        const double c = edge_integral(q, e0, e1) / area;
-        if (c > 0.0) emit(b, c);
+        const double e0 = (G.pmin + b * G.delta) - p0[0];
+        const double e1 = (G.pmin + (b + 1) * G.delta) - p0[0];
+        for (int64_t k = k0; k <= k1; ++k) {
+            const double t0 = (-M_PI + (double)k * G.dchi) - p1[0];
+            const double t1 = (-M_PI + (double)(k + 1) * G.dchi) - p1[0];
+            const double c = edge_integral_box(q, e0, e1, t0, t1) / area;
+            if (c > 0.0) emit(wrap(k, G.nazim) * G.nrad + b, c);
+        }
     }
 }
 
 }  // namespace
 
-int build_matrix(const azi_geom& g, int32_t npt, int32_t unit, int32_t split,
+int build_matrix(const azi_geom& g, int32_t npt, int32_t npt_azim, int32_t unit, int32_t split,
                  const double* range2, HostMatrix& m, std::string& err) {
     const int64_t h = g.h, w = g.w, npix = h * w;
+    const bool two_d = npt_azim > 0;
+    const int32_t nrad = npt;
+    if (two_d) {
+        if ((int64_t)nrad * npt_azim >= (int64_t)std::numeric_limits<int32_t>::max()) {
+            err = "npt_rad * npt_azim is 2^31 or more";
+            return AZI_EOVERFLOW;
+        }
+        npt = nrad * npt_azim;
+    }
     if (npix >= (int64_t)std::numeric_limits<int32_t>::max()) {
         err = "image has 2^31 pixels or more";
         return AZI_EOVERFLOW;
@@ -182,8 +220,11 @@ int build_matrix(const azi_geom& g, int32_t npt, int32_t unit, int32_t split,
         err = "integration range is empty or not finite";
         return AZI_EINVAL;
     }
-    const double delta = (pmax - pmin) / npt;
+    const double delta = (pmax - pmin) / nrad;
     m.npt = npt;
+    m.npt_rad = nrad;
+    m.npt_azim = two_d ? npt_azim : 1;
+    m.two_d = two_d;
     m.npix = npix;
     m.pmin = pmin;
     m.pmax = pmax;
@@ -199,8 +240,34 @@ int build_matrix(const azi_geom& g, int32_t npt, int32_t unit, int32_t split,
         m.rowidx.push_back(b);
         m.cdata.push_back(c);
     };
+    const Grid2d G{pmin, delta, two_d ? (2.0 * M_PI) / npt_azim : 0.0, nrad, m.npt_azim};
+    std::vector<std::pair<int32_t, double>> rad, ents;
+    auto collect = [&](int32_t row, double c) { ents.emplace_back(row, c); };
     for (int64_t p = 0; p < npix; ++p) {
-        if (split == AZI_SPLIT_BBOX) {
+        if (two_d) {
+            // a pixel's entries in ascending row order
+            ents.clear();
+            const int64_t i = p / w, j = p % w;
+            if (split == AZI_SPLIT_BBOX) {
+                bbox2d_pixel(i, j, g, lo[p], hi[p], G, rad, collect);
+            } else if (split == AZI_SPLIT_FULL) {
+                full2d_pixel(i, j, g, unit, lo[p], hi[p], G, rad, collect);
+            } else {
+                const double fc = (lo[p] - pmin) / delta;
+                if (fc >= 0.0 && fc <= (double)nrad) {
+                    const double xc = ((double)j + 0.5 - g.center_x_px) * g.pixel_x_m;
+                    const double yc = ((double)i + 0.5 - g.center_y_px) * g.pixel_y_m;
+                    const int64_t k = (int64_t)std::floor((std::atan2(yc, xc) + M_PI) / G.dchi);
+                    collect(wrap(k, npt_azim) * nrad + std::min((int32_t)std::floor(fc), nrad - 1),
+                            1.0);
+                }
+            }
+            std::sort(ents.begin(), ents.end(),
+                      [](const std::pair<int32_t, double>& a, const std::pair<int32_t, double>& b) {
+                          return a.first < b.first;
+                      });
+            for (const auto& e : ents) push(e.first, e.second);
+        } else if (split == AZI_SPLIT_BBOX) {
             bbox_pixel(lo[p], hi[p], pmin, delta, npt, push);
         } else if (split == AZI_SPLIT_FULL) {
             full_pixel(p / w, p % w, g, unit, lo[p], hi[p], pmin, delta, npt, push);
@@ -375,6 +442,12 @@ bool build_bands(const HostMatrix& m, int32_t R, int32_t piece_nnz, int64_t pix_
             bm.coef[z] = m.cdata[k];
         }
     }
+    band_pieces(start.data(), nbands, npt, R, piece_nnz, base, pix_off, bin_off, bm);
+    return true;
+}
+
+void band_pieces(const int64_t* start, int32_t nbands, int32_t npt, int32_t R, int32_t piece_nnz,
+                 int64_t base, int64_t pix_off, int64_t bin_off, BandMatrix& bm) {
     if (bm.bin_slot.size() < (size_t)(bin_off + npt)) {
         bm.bin_slot.resize(bin_off + npt, 0);
         bm.bin_count.resize(bin_off + npt, 0);
@@ -399,7 +472,42 @@ bool build_bands(const HostMatrix& m, int32_t R, int32_t piece_nnz, int64_t pix_
             prev = next;
         }
     }
-    return true;
+}
+
+void build_fused(const HostMatrix& m, int32_t h, int32_t w, std::vector<FusedTile>& tiles,
+                 std::vector<int32_t>& slots, std::vector<int32_t>& bin_ptr) {
+    tiles.clear();
+    slots.clear();
+    bin_ptr.assign((size_t)m.npt + 1, 0);
+    for (int32_t i0 = 0; i0 < h; i0 += kFusedH) {
+        const int32_t th = std::min(kFusedH, h - i0);
+        for (int32_t j0 = 0; j0 < w; j0 += kFusedW) {
+            const int32_t tw = std::min(kFusedW, w - j0);
+            int32_t lo = std::numeric_limits<int32_t>::max(), hi = -1;
+            for (int32_t r = 0; r < th; ++r) {
+                for (int32_t c = 0; c < tw; ++c) {
+                    const int64_t p = (int64_t)(i0 + r) * w + j0 + c;
+                    if (m.colptr[p] < m.colptr[p + 1]) {
+                        lo = std::min(lo, m.rowidx[m.colptr[p]]);
+                        hi = std::max(hi, m.rowidx[m.colptr[p + 1] - 1]);
+                    }
+                }
+            }
+            FusedTile t{i0, j0, th, tw, 0, 0, 0};
+            if (hi >= lo) {
+                t.wlo = lo;
+                t.nwin = hi - lo + 1;
+                for (int32_t b = lo; b <= hi; ++b) bin_ptr[b + 1]++;
+            }
+            tiles.push_back(t);
+        }
+    }
+    for (int32_t b = 0; b < m.npt; ++b) bin_ptr[b + 1] += bin_ptr[b];
+    std::vector<int32_t> cur(bin_ptr.begin(), bin_ptr.end() - 1);
+    for (FusedTile& t : tiles) {
+        t.slot_off = (int64_t)slots.size();
+        for (int32_t k = 0; k < t.nwin; ++k) slots.push_back(cur[t.wlo + k]++);
+    }
 }
 
 void build_tiles(const int32_t* indptr, int32_t nrows, int64_t z_off, int64_t r_off,

@@ -201,7 +201,7 @@ def test_argument_errors():
     assert _err(L.azi_plan_set_tiling(plan.handle, None))[0] == -1
     assert L.azi_plan_set_tiling(plan.handle, T(1024, 128, 6, 512, 4, 1)) == 0
     assert plan.tiling() == dict(tile_nnz=1024, block=128, variant=6, grid=512, band=4, stage=1)
-    assert _err(L.azi_plan_set_layout(plan.handle, 4))[0] == -1
+    assert _err(L.azi_plan_set_layout(plan.handle, 5))[0] == -1
     assert _err(L.azi_batch_create(None, 1, 0, ctypes.byref(out)))[0] == -1
 
 
@@ -269,3 +269,93 @@ def test_full_split_matches_oracle(g):
     assert np.abs(A - B).max() <= 1e-13
     assert plan.info()["range"] == (m["pmin"], m["pmax"]) or unit != "r_m"
     assert np.abs(A.sum(axis=0) - 1.0).max() <= 1e-13
+
+
+GEOMS_2D = [
+    # h, w, center_y, center_x, npt_rad, npt_azim, unit, split
+    (40, 50, 20.5, 24.3, 30, 36, "r_m", "bbox"),
+    (32, 32, 16.0, 16.0, 20, 8, "r_m", "bbox"),        # beam on a pixel corner
+    (30, 40, -10.0, 15.0, 20, 72, "r_m", "bbox"),      # beam above the detector
+    (24, 24, 12.5, 60.0, 10, 360, "r_m", "bbox"),      # rows across the +-pi cut
+    (27, 33, 13.2, 16.7, 25, 90, "2th_deg", "bbox"),
+    (40, 50, 20.5, 24.3, 30, 36, "r_m", "none"),
+    (24, 24, 12.5, 60.0, 10, 360, "r_m", "none"),
+    (40, 50, 20.5, 24.3, 30, 36, "r_m", "full"),
+    (32, 32, 16.0, 16.0, 20, 8, "r_m", "full"),
+    (24, 24, 12.5, 60.0, 10, 360, "r_m", "full"),
+    (30, 40, -10.0, 15.0, 20, 72, "q_nm", "full"),
+]
+
+
+def _oracle2d(h, w, cy, cx, nr, na, unit, split):
+    return oracle.build_matrix2d(h=h, w=w, pixel_y=1e-4, pixel_x=1e-4, center_y=cy,
+                                 center_x=cx, dist=0.1, wavelength=1e-10, npt_rad=nr,
+                                 npt_azim=na, unit=unit, split=split)
+
+
+@pytest.mark.parametrize("g", GEOMS_2D, ids=lambda g: f"{g[0]}x{g[1]}-{g[7]}-{g[6]}-{g[5]}")
+def test_plan2d_matches_oracle(g):
+    """Two-dimensional plans: the integer structure (and, where every step is
+    a correctly rounded operation or the same libm call, the coefficients)
+    equals the oracle's bit for bit; full splitting (edge integrals against
+    polygon clipping) agrees to rounding."""
+    import scipy.sparse as sp
+    h, w, cy, cx, nr, na, unit, split = g
+    az = azint()
+    plan = az.Plan(h, w, nr, npt_azim=na, center=(cy, cx), unit=unit, split=split)
+    m = _oracle2d(h, w, cy, cx, nr, na, unit, split)
+    assert plan.shape() == (nr, na)
+    assert plan.info()["npt"] == nr * na == m["npt"]
+    assert np.array_equal(plan.positions(), m["positions"])
+    assert np.array_equal(plan.azimuths(), m["azimuths"])
+    d, i, p = plan.export_csr()
+    if split == "full":
+        A = sp.csr_matrix((d, i, p), shape=(nr * na, h * w)).toarray()
+        B = sp.csr_matrix((m["data"], m["indices"], m["indptr"]),
+                          shape=(nr * na, h * w)).toarray()
+        assert np.abs(A - B).max() <= 1e-13
+    elif unit == "r_m":
+        assert np.array_equal(p, m["indptr"])
+        assert np.array_equal(i, m["indices"])
+        assert np.array_equal(d, m["data"])
+    else:
+        # transcendental units: bins agree except where a box edge sits
+        # within rounding of a bin edge; coefficients to rounding
+        A = sp.csr_matrix((d, i, p), shape=(nr * na, h * w)).toarray()
+        B = sp.csr_matrix((m["data"], m["indices"], m["indptr"]),
+                          shape=(nr * na, h * w)).toarray()
+        assert np.abs(A - B).max() <= 1e-9
+    cdata, bins, colptr = plan.export_csc()
+    for q in range(h * w):
+        seg = bins[colptr[q]:colptr[q + 1]]
+        assert np.all(np.diff(seg) > 0), q
+    assert np.abs(np.bincount(np.repeat(np.arange(h * w), np.diff(colptr)), weights=cdata,
+                              minlength=h * w) - 1.0).max() <= 1e-13
+
+
+def test_plan2d_argument_errors():
+    az = azint()
+    for bad in (1, -3):
+        with pytest.raises(az.AzintError):
+            az.Plan(8, 8, 4, npt_azim=bad)
+    plan = az.Plan(8, 8, 4)
+    assert plan.shape() == (4, 0)
+    with pytest.raises(az.AzintError):
+        plan.azimuths()
+    with pytest.raises(az.AzintError):
+        az.Plan(8, 8, 1 << 16, npt_azim=1 << 16)
+
+
+@pytest.mark.skipif(torch.cuda.is_available(), reason="checks the no-GPU error path")
+def test_device_plan_builder_without_gpu_fails_cleanly():
+    az = azint()
+    L = az.lib()
+    g = az._Geom(8, 8, 1e-4, 1e-4, 4.0, 4.0, 0.1, 1e-10)
+    out = ctypes.c_void_p()
+    rc = L.azi_plan_create_device(ctypes.byref(g), 8, 0, 1, None, 5, 0, 0, None,
+                                  ctypes.byref(out))
+    assert rc == -4 and not out.value
+    assert b"device" in L.azi_last_error().lower()
+    rc = L.azi_plan_create_device(ctypes.byref(g), 8, 0, 1, None, 5, 0, -1, None,
+                                  ctypes.byref(out))
+    assert rc == -4

@@ -1,0 +1,125 @@
+"""Device plan builder vs the host plan builder and the FP64 oracle.
+
+The device builder computes per-pixel extents and entries with the same IEEE
+operations as the host builder and orders them with a stable radix sort, so
+its matrix must equal the host builder's bit for bit wherever every step is
+correctly rounded (radius units, bounding box or no split), and to rounding
+where a library transcendental (atan2, atan, sin) enters.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from tests.helpers import azint, oracle_matrix
+from tests.test_gpu_forward import TOL64, check
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dense(csr, shape):
+    import scipy.sparse as sp
+    return sp.csr_matrix(csr, shape=shape).toarray()
+
+
+GEOMS = [
+    # h, w, center_y, center_x, npt, unit, split, range, dtype
+    (100, 100, 50.0, 50.0, 100, "r_m", "bbox", None, "f64"),
+    (37, 53, 10.25, 40.5, 61, "r_m", "bbox", None, "f64"),
+    (64, 48, -5.0, 70.0, 40, "r_mm", "bbox", None, "f32"),
+    (31, 29, 15.5, 14.5, 300, "r_m", "bbox", None, "f64"),     # bins finer than pixels
+    (50, 60, 25.0, 30.0, 37, "r_m", "bbox", (5e-4, 2.5e-3), "f64"),  # clipped range
+    (50, 60, 25.3, 30.7, 37, "r_m", "none", None, "f64"),
+    (1, 1, 0.5, 0.5, 4, "r_m", "bbox", None, "f64"),
+    (1, 17, 0.5, 8.5, 5, "r_m", "bbox", None, "f32"),
+    (20, 20, 10.0, 10.0, 1, "r_m", "bbox", None, "f64"),       # one bin
+    (257, 263, 128.5, 131.5, 256, "r_m", "bbox", None, "f64"),
+    (120, 130, 60.2, 64.9, 140, "r_m", "full", None, "f64"),
+    (300, 200, 10.0, 190.0, 150, "2th_deg", "bbox", None, "f64"),
+    (90, 70, -10.0, 35.0, 80, "q_nm", "full", None, "f64"),
+]
+EXACT = lambda g: g[5] in ("r_m", "r_mm") and g[6] in ("bbox", "none")
+
+
+@pytest.mark.parametrize("g", GEOMS, ids=lambda g: f"{g[0]}x{g[1]}-{g[5]}-{g[6]}-{g[4]}-{g[8]}")
+def test_device_plan_equals_host_plan(g, dev):
+    h, w, cy, cx, npt, unit, split, rng, dt = g
+    say("device build", g)
+    az = azint()
+    dtype = torch.float64 if dt == "f64" else torch.float32
+    kw = dict(center=(cy, cx), unit=unit, split=split, range=rng, dtype=dtype)
+    hp = az.Plan(h, w, npt, **kw)
+    dp = az.Plan.on_device(h, w, npt, device=dev, **kw)
+    ih, idv = hp.info(), dp.info()
+    assert idv["npt"] == npt and idv["npix"] == h * w
+    assert idv["range"] == ih["range"] or not EXACT(g)
+    dh, dd = hp.export_csr(), dp.export_csr()
+    ch, cd = hp.export_csc(), dp.export_csc()
+    if EXACT(g):
+        for a, b in zip(dh + ch, dd + cd):
+            assert np.array_equal(a, b)
+    else:
+        A = dense(dh, (npt, h * w))
+        B = dense(dd, (npt, h * w))
+        assert np.abs(A - B).max() <= (1e-13 if unit == "r_m" else 1e-9)
+    # the device-built plan integrates like the oracle (and, where the
+    # matrices are equal, bitwise like the host-built plan in the same layout)
+    x = np.random.default_rng(h * w).uniform(-2.0, 1000.0, size=h * w)
+    xt = torch.from_numpy(x.astype(np.float64 if dt == "f64" else np.float32)).to(dev)
+    hp.upload(dev)
+    out_d = dp.integrate(xt, empty=-1.5)
+    out_h = hp.integrate(xt, empty=-1.5)
+    torch.cuda.synchronize()
+    if EXACT(g):
+        for a, b in zip(out_d, out_h):
+            assert torch.equal(a, b)
+    if dt == "f64" and unit == "r_m":
+        check(out_d, oracle_matrix(h, w, cy, cx, npt, 1e-4, 1e-4, unit, split, rng), x, TOL64,
+              empty=-1.5, what=str(g))
+
+
+def test_device_plan_layout_switch_and_backward(dev):
+    """A device-built plan switched to the other layouts (through its host
+    copy) and differentiated gives the host-built plan's results."""
+    say("device build layouts")
+    az = azint()
+    h, w, npt = 150, 170, 120
+    dp = az.Plan.on_device(h, w, npt, device=dev)
+    hp = az.Plan(h, w, npt, device=dev)
+    x = torch.from_numpy(np.random.default_rng(5).uniform(0, 10, size=h * w)).to(dev)
+    for layout in ("pixel", "ring", "tile", "band"):
+        dp.set_layout(layout)
+        hp.set_layout(layout)
+        a, b = dp.integrate(x), hp.integrate(x)
+        torch.cuda.synchronize()
+        for u, v in zip(a, b):
+            assert torch.equal(u, v), layout
+    g = torch.from_numpy(np.random.default_rng(6).standard_normal(npt)).to(dev)
+    _, _, U = dp.integrate(x)
+    assert torch.equal(dp.backward(U, g), hp.backward(U, g))
+
+
+def test_device_plan_c2_size(dev):
+    """The 10-Mpixel detector: the device builder reproduces the host
+    builder's matrix bit for bit; both build times are printed."""
+    say("device build c2")
+    az = azint()
+    inst = synth.instance(synth.C2["n"], synth.C2["seed"])
+    g = inst.geom
+    t0 = time.perf_counter()
+    hp = az.Plan(g.h, g.w, inst.npt, center=(g.center_y, g.center_x))
+    t1 = time.perf_counter()
+    dp = az.Plan.on_device(g.h, g.w, inst.npt, center=(g.center_y, g.center_x), device=dev)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    say(f"host build {t1 - t0:.3f} s, device build {t2 - t1:.3f} s")
+    for a, b in zip(hp.export_csr() + hp.export_csc(), dp.export_csr() + dp.export_csc()):
+        assert np.array_equal(a, b)
