@@ -41,16 +41,26 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+TRAFFIC_SOURCES = ("kernels.hip", "accum.h")
+
+
+def kernel_source_hash():
+    """sha256 over the sources of the integration kernels."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in TRAFFIC_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1412_6367_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(workload):
     """HBM bytes per launch of the integration kernel from the committed
     rocprofv3 FETCH_SIZE / WRITE_SIZE record (scaled by a plain copy's
     reading), or None when the record is missing or was taken on other
     kernel source than the one built now."""
-    import hashlib
     try:
         rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[workload]
-        src = os.path.join(ROOT, "paper_1412_6367_amd", "csrc", "kernels.hip")
-        if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["kernels_sha256"]:
+        if kernel_source_hash() != rec["kernels_sha256"]:
             return None
         return rec["fetch_bytes"] + rec["write_bytes"]
     except (OSError, KeyError, ValueError):

@@ -186,7 +186,7 @@ class Plan:
 
     def __init__(self, h, w, npt, *, npt_azim=None, pixel=1e-4, center=None, dist=0.1,
                  wavelength=1e-10, unit="r_m", split="bbox", range=None, dtype=torch.float64,
-                 accum="f64", layout="band", device=None, **tiling):
+                 accum="f64", layout=None, device=None, **tiling):
         py, px = (pixel, pixel) if np.isscalar(pixel) else pixel
         cy, cx = (h / 2.0, w / 2.0) if center is None else center
         self.npt_rad = int(npt)
@@ -211,7 +211,7 @@ class Plan:
                                          ctypes.byref(out)))
         self._h = out
         self.device = None
-        if layout != "band":
+        if layout is not None:
             self.set_layout(layout)
         if tiling:
             self.set_tiling(**tiling)

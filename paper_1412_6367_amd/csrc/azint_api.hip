@@ -122,6 +122,7 @@ bool valid_tiling(const azi_tiling& t) {
 
 // Fastest measured on the ~1e7-pixel, 3162-bin workload (float64 and float32).
 constexpr azi_tiling kDefaultTiling = {2048, 256, 5, 0, 4, AZI_STAGE_GATHER};
+constexpr azi_tiling kDefaultTiling2d = {4096, 256, 3, 0, 1, AZI_STAGE_GATHER};
 
 // Converts double coefficients to the storage type into a padded buffer.
 std::vector<char> to_storage(const double* src, int64_t n, int64_t n_alloc, int32_t dtype) {
@@ -537,6 +538,12 @@ int plan_create(const azi_geom* geom, int32_t npt, int32_t npt_azim, int32_t uni
         return fail(AZI_ENOMEM, "out of host memory building the matrix");
     }
     if (rc != AZI_OK) return fail(rc, err);
+    if (p->m.two_d) {
+        // short rows (tens of entries): the plain CSR with whole rows per
+        // tile beats the band order, whose per-band pieces would be tiny
+        p->layout = AZI_LAYOUT_PIXEL;
+        p->tiling = kDefaultTiling2d;
+    }
     *out = p.release();
     return AZI_OK;
 }

@@ -13,10 +13,11 @@
 //   have radial extents that grow monotonically away from it, so the pixels
 //   feeding bin b form one contiguous run per side.  A table per row gives
 //   the first pixel of that run (filled race-free: each bin by the one pixel
-//   where the running last bin passes it), and one thread per (bin, half of
-//   the rows) walks the runs, rows in order, left side then right side.
-// Phase 3: the two halves are merged and written to the bin's slot;
-//   k_block_reduce adds the slots of each bin in tile order.
+//   where the running last bin passes it).  A wavefront takes four bins at a
+//   time, one lane per (bin, tile row): each lane walks its row's runs, left
+//   side then right side, and the 16 row sums of a bin are merged by a fixed
+//   shuffle tree and written to the bin's slot; k_block_reduce adds the
+//   slots of each bin in tile order.
 #include "fused.h"
 
 #include "accum.h"
@@ -28,12 +29,20 @@ namespace {
 constexpr int kFB = 256;                   // threads per workgroup
 constexpr int kFPix = kFusedH * kFusedW;   // pixels per tile
 constexpr int kFWin = 128;                 // bins per pass over a tile
-constexpr int kGroups = kFB / kFWin;       // row groups in phase 2
+constexpr int kBinsPerWave = kWave / kFusedH;
 constexpr int32_t kBig = 1 << 30;          // bin of pixels outside the range
 static_assert(kFusedW <= 127, "column index kept in int8");
-static_assert(kFusedH % kGroups == 0, "row groups");
+static_assert(kWave % kFusedH == 0, "a wavefront holds whole bins");
 
-template <class R, class T, class Acc>
+// Output coordinate of a radius: the plan builder's to_unit; kTrig false
+// compiles only the radial units (no atan / sin code, fewer registers).
+template <bool kTrig>
+__device__ inline double unit_of(double r, int32_t unit, const azi_geom& g) {
+    if constexpr (kTrig) return to_unit(r, unit, g.dist_m, g.wavelength_m);
+    else return unit == AZI_UNIT_R_MM ? r * 1e3 : r;
+}
+
+template <class R, class T, class Acc, bool kTrig>
 __global__ __launch_bounds__(kFB) void k_fused(const FusedTile* __restrict__ tiles,
                                                int32_t ntiles, const int32_t* __restrict__ slots,
                                                azi_geom g, int32_t unit, int32_t split,
@@ -46,8 +55,9 @@ __global__ __launch_bounds__(kFB) void k_fused(const FusedTile* __restrict__ til
     __shared__ T cls[kFPix], cis[kFPix], crs[kFPix];
     __shared__ int32_t b0s[kFPix], b1s[kFPix];
     __shared__ int8_t first_r[kFusedH][kFWin], first_l[kFusedH][kFWin];
-    __shared__ Acc red[kFB];
     const int tid = threadIdx.x;
+    const int wave = tid / kWave, lane = tid % kWave;
+    const int row = lane % kFusedH, sub = lane / kFusedH;
     const int32_t gi = blockIdx.x, Gd = gridDim.x;
     int32_t t_begin, t_end, t_step;
     if (Gd < 8) {
@@ -62,7 +72,9 @@ __global__ __launch_bounds__(kFB) void k_fused(const FusedTile* __restrict__ til
     for (int32_t ti = t_begin; ti < t_end; ti += t_step) {
         const FusedTile t = tiles[ti];
         if (t.nwin == 0) continue;  // uniform over the workgroup
-        // phase 1: values and shares
+        // phase 1: values and shares (one pixel at a time per thread keeps
+        // the double-precision square roots and divisions in few registers)
+#pragma unroll 1
         for (int e = tid; e < kFPix; e += kFB) {
             const int r = e / kFusedW, c = e - r * kFusedW;
             int32_t b0 = kBig, b1 = kBig;
@@ -76,7 +88,7 @@ __global__ __launch_bounds__(kFB) void k_fused(const FusedTile* __restrict__ til
                 xv = v;
                 const Extent ex = pixel_extent(i, j, g);
                 if (split == AZI_SPLIT_NONE) {
-                    const double fc = (to_unit(ex.mid, unit, g.dist_m, g.wavelength_m) - pmin) / delta;
+                    const double fc = (unit_of<kTrig>(ex.mid, unit, g) - pmin) / delta;
                     if (fc >= 0.0 && fc <= (double)npt) {
                         b0 = b1 = vmin((int32_t)::floor(fc), npt - 1);
                         cl = T(1);
@@ -84,9 +96,9 @@ __global__ __launch_bounds__(kFB) void k_fused(const FusedTile* __restrict__ til
                         b0 = b1 = fc < 0.0 ? -kBig : kBig;
                     }
                 } else {
-                    const BoxTerms bt = bbox_terms(to_unit(ex.lo, unit, g.dist_m, g.wavelength_m),
-                                                   to_unit(ex.hi, unit, g.dist_m, g.wavelength_m),
-                                                   pmin, delta, npt);
+                    const BoxTerms bt = bbox_terms(unit_of<kTrig>(ex.lo, unit, g),
+                                                   unit_of<kTrig>(ex.hi, unit, g), pmin, delta,
+                                                   npt);
                     if (bt.b0 > bt.b1) {
                         b0 = b1 = bt.fl >= (double)npt ? kBig : -kBig;
                     } else {
@@ -131,38 +143,31 @@ __global__ __launch_bounds__(kFB) void k_fused(const FusedTile* __restrict__ til
                 }
             }
             __syncthreads();
-            // phase 2: (bin, row group) walks
-            const int q = tid % kFWin, grp = tid / kFWin;
-            Acc a;
-            a.zero();
-            if (q < nw) {
-                const int32_t b = w0 + q;
-                constexpr int kRows = kFusedH / kGroups;
-                for (int r = grp * kRows; r < (grp + 1) * kRows && r < t.th; ++r) {
-                    for (int c = first_l[r][q]; c >= 0; --c) {
-                        const int e = r * kFusedW + c;
+            // phase 2: one lane per (bin, row); four bins per wavefront pass
+            for (int32_t q0 = wave * kBinsPerWave; q0 < nw; q0 += (kFB / kWave) * kBinsPerWave) {
+                const int32_t q = q0 + sub;
+                Acc a;
+                a.zero();
+                if (q < nw && row < t.th) {
+                    const int32_t b = w0 + q;
+                    for (int c = first_l[row][q]; c >= 0; --c) {
+                        const int e = row * kFusedW + c;
                         if (b0s[e] > b) break;
                         const T cv = b == b0s[e] ? cls[e] : (b == b1s[e] ? crs[e] : cis[e]);
                         a.add(cv, xs[e]);
                     }
-                    const int c0 = first_r[r][q];
+                    const int c0 = first_r[row][q];
                     if (c0 >= 0) {
                         for (int c = c0; c < t.tw; ++c) {
-                            const int e = r * kFusedW + c;
+                            const int e = row * kFusedW + c;
                             if (b0s[e] > b) break;
                             const T cv = b == b0s[e] ? cls[e] : (b == b1s[e] ? crs[e] : cis[e]);
                             a.add(cv, xs[e]);
                         }
                     }
                 }
-            }
-            red[tid] = a;
-            __syncthreads();
-            // phase 3: halves in order, then the tile's partial of each bin
-            if (tid < nw) {
-                Acc s = red[tid];
-                for (int k = 1; k < kGroups; ++k) s.merge(red[tid + k * kFWin]);
-                parts[slots[t.slot_off + (w0 - t.wlo) + tid]] = s;
+                group_reduce(a, kFusedH);
+                if (row == 0 && q < nw) parts[slots[t.slot_off + (w0 - t.wlo) + q]] = a;
             }
             __syncthreads();
         }
@@ -172,11 +177,21 @@ __global__ __launch_bounds__(kFB) void k_fused(const FusedTile* __restrict__ til
 template <class R, class T, class Acc>
 hipError_t run(const FusedLaunch& a, hipStream_t s) {
     const int32_t grid = a.grid > 0 ? min(a.grid, a.ntiles) : a.ntiles;
-    if (a.ntiles > 0)
-        hipLaunchKernelGGL((k_fused<R, T, Acc>), dim3((unsigned)grid), dim3(kFB), 0, s, a.tiles,
-                           a.ntiles, a.slots, a.geom, a.unit, a.split, a.pmin, a.delta, a.npt,
-                           static_cast<const R*>(a.img), static_cast<const T*>(a.dark),
-                           static_cast<const T*>(a.norm), static_cast<Acc*>(a.parts));
+    const bool trig = a.unit != AZI_UNIT_R_M && a.unit != AZI_UNIT_R_MM;
+    if (a.ntiles > 0) {
+        if (trig)
+            hipLaunchKernelGGL((k_fused<R, T, Acc, true>), dim3((unsigned)grid), dim3(kFB), 0, s,
+                               a.tiles, a.ntiles, a.slots, a.geom, a.unit, a.split, a.pmin,
+                               a.delta, a.npt, static_cast<const R*>(a.img),
+                               static_cast<const T*>(a.dark), static_cast<const T*>(a.norm),
+                               static_cast<Acc*>(a.parts));
+        else
+            hipLaunchKernelGGL((k_fused<R, T, Acc, false>), dim3((unsigned)grid), dim3(kFB), 0, s,
+                               a.tiles, a.ntiles, a.slots, a.geom, a.unit, a.split, a.pmin,
+                               a.delta, a.npt, static_cast<const R*>(a.img),
+                               static_cast<const T*>(a.dark), static_cast<const T*>(a.norm),
+                               static_cast<Acc*>(a.parts));
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (a.npt > 0) {

@@ -68,7 +68,7 @@ def test_fused_f64(g, grid, dev):
     assert norm_err(out[2].cpu().numpy(), ref[2].cpu().numpy(), Ub) <= 2 * TOL64
 
 
-@pytest.mark.parametrize("accum", ["f64", "kahan"])
+@pytest.mark.parametrize("accum", ["f64", "kahan32"])
 def test_fused_f32(accum, dev):
     h, w, cy, cx, npt = 150, 170, 70.3, 85.9, 120
     say("fused f32", accum)
