@@ -269,7 +269,7 @@ int azi_plan_tile_schedule(const azi_plan* plan, const azi_tiling* tiling, int32
  * entries add into per-bin partial sums that a second kernel adds in order.
  * Images up to 2^27 pixels.
  * AZI_LAYOUT_FUSED (one-dimensional plans, AZI_SPLIT_BBOX or _NONE): no
- * matrix is read per frame.  Each workgroup takes a 16 x 64 image tile,
+ * matrix is read per frame.  Each workgroup takes an 8 x 64 image tile,
  * recomputes its pixels' radial extents and bounding-box shares from the
  * plan's geometry with the operations of the plan builder (Sections 3, 4.1;
  * the coefficients are the stored matrix's, bit for bit for the radial

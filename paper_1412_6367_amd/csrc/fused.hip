@@ -13,9 +13,9 @@
 //   have radial extents that grow monotonically away from it, so the pixels
 //   feeding bin b form one contiguous run per side.  A table per row gives
 //   the first pixel of that run (filled race-free: each bin by the one pixel
-//   where the running last bin passes it).  A wavefront takes four bins at a
-//   time, one lane per (bin, tile row): each lane walks its row's runs, left
-//   side then right side, and the 16 row sums of a bin are merged by a fixed
+//   where the running last bin passes it).  A wavefront takes 64 / rows bins
+//   at a time, one lane per (bin, tile row): each lane walks its row's runs, left
+//   side then right side, and the row sums of a bin are merged by a fixed
 //   shuffle tree and written to the bin's slot; k_block_reduce adds the
 //   slots of each bin in tile order.
 #include "fused.h"
@@ -28,7 +28,10 @@ namespace {
 
 constexpr int kFB = 256;                   // threads per workgroup
 constexpr int kFPix = kFusedH * kFusedW;   // pixels per tile
+constexpr int kPitch = kFusedW + 1;        // LDS row pitch: rows of a column in distinct banks
+constexpr int kLdsPix = kFusedH * kPitch;
 constexpr int kFWin = 128;                 // bins per pass over a tile
+constexpr int kTPitch = kFWin + 4;         // table row pitch (bytes), same reason
 constexpr int kBinsPerWave = kWave / kFusedH;
 constexpr int32_t kBig = 1 << 30;          // bin of pixels outside the range
 static_assert(kFusedW <= 127, "column index kept in int8");
@@ -51,10 +54,10 @@ __global__ __launch_bounds__(kFB) void k_fused(const FusedTile* __restrict__ til
                                                const T* __restrict__ dark,
                                                const T* __restrict__ norm,
                                                Acc* __restrict__ parts) {
-    __shared__ T xs[kFPix];
-    __shared__ T cls[kFPix], cis[kFPix], crs[kFPix];
-    __shared__ int32_t b0s[kFPix], b1s[kFPix];
-    __shared__ int8_t first_r[kFusedH][kFWin], first_l[kFusedH][kFWin];
+    __shared__ T xs[kLdsPix];
+    __shared__ T cls[kLdsPix], cis[kLdsPix], crs[kLdsPix];
+    __shared__ int32_t b0s[kLdsPix], b1s[kLdsPix];
+    __shared__ int8_t first_r[kFusedH][kTPitch], first_l[kFusedH][kTPitch];
     const int tid = threadIdx.x;
     const int wave = tid / kWave, lane = tid % kWave;
     const int row = lane % kFusedH, sub = lane / kFusedH;
@@ -110,21 +113,22 @@ __global__ __launch_bounds__(kFB) void k_fused(const FusedTile* __restrict__ til
                     }
                 }
             }
-            xs[e] = xv;
-            cls[e] = cl;
-            cis[e] = ci;
-            crs[e] = cr;
-            b0s[e] = b0;
-            b1s[e] = b1;
+            const int l = r * kPitch + c;
+            xs[l] = xv;
+            cls[l] = cl;
+            cis[l] = ci;
+            crs[l] = cr;
+            b0s[l] = b0;
+            b1s[l] = b1;
         }
         // columns [0, cs) lie left of the beam column, [cs, tw) right of it
         const int cs = (int)vmin(vmax(beam_col - (double)t.j0, 0.0), (double)t.tw);
         for (int32_t w0 = t.wlo; w0 < t.wlo + t.nwin; w0 += kFWin) {
             const int32_t nw = min(kFWin, t.wlo + t.nwin - w0);
             const int32_t w1 = w0 + nw - 1;
-            for (int e = tid; e < kFusedH * kFWin; e += kFB) {
-                first_r[e / kFWin][e % kFWin] = -1;
-                first_l[e / kFWin][e % kFWin] = -1;
+            for (int e = tid; e < kFusedH * kTPitch; e += kFB) {
+                first_r[e / kTPitch][e % kTPitch] = -1;
+                first_l[e / kTPitch][e % kTPitch] = -1;
             }
             __syncthreads();
             // each bin is claimed by the pixel of the run where the running
@@ -132,11 +136,12 @@ __global__ __launch_bounds__(kFB) void k_fused(const FusedTile* __restrict__ til
             for (int e = tid; e < kFPix; e += kFB) {
                 const int r = e / kFusedW, c = e - r * kFusedW;
                 if (r >= t.th || c >= t.tw) continue;
+                const int l = r * kPitch + c;
                 const bool right = c >= cs;
                 const bool first = right ? c == cs : c == cs - 1;
-                const int32_t prev = first ? -kBig : b1s[right ? e - 1 : e + 1];
+                const int32_t prev = first ? -kBig : b1s[right ? l - 1 : l + 1];
                 const int32_t lo_b = max(prev + 1, w0);
-                const int32_t hi_b = min(b1s[e], w1);
+                const int32_t hi_b = min(b1s[l], w1);
                 for (int32_t b = lo_b; b <= hi_b; ++b) {
                     if (right) first_r[r][b - w0] = (int8_t)c;
                     else first_l[r][b - w0] = (int8_t)c;
@@ -151,7 +156,7 @@ __global__ __launch_bounds__(kFB) void k_fused(const FusedTile* __restrict__ til
                 if (q < nw && row < t.th) {
                     const int32_t b = w0 + q;
                     for (int c = first_l[row][q]; c >= 0; --c) {
-                        const int e = row * kFusedW + c;
+                        const int e = row * kPitch + c;
                         if (b0s[e] > b) break;
                         const T cv = b == b0s[e] ? cls[e] : (b == b1s[e] ? crs[e] : cis[e]);
                         a.add(cv, xs[e]);
@@ -159,7 +164,7 @@ __global__ __launch_bounds__(kFB) void k_fused(const FusedTile* __restrict__ til
                     const int c0 = first_r[row][q];
                     if (c0 >= 0) {
                         for (int c = c0; c < t.tw; ++c) {
-                            const int e = row * kFusedW + c;
+                            const int e = row * kPitch + c;
                             if (b0s[e] > b) break;
                             const T cv = b == b0s[e] ? cls[e] : (b == b1s[e] ? crs[e] : cis[e]);
                             a.add(cv, xs[e]);

@@ -178,7 +178,7 @@ void band_pieces(const int64_t* start, int32_t nbands, int32_t npt, int32_t R, i
 // sums of bin wlo + k to slot slots[slot_off + k]; bin b owns slots
 // [bin_ptr[b], bin_ptr[b + 1]), one per tile whose window holds it, in tile
 // order.  Windows come from the pixel-major entries of the plan's matrix.
-constexpr int32_t kFusedH = 16, kFusedW = 64;
+constexpr int32_t kFusedH = 8, kFusedW = 64;
 struct FusedTile {
     int32_t i0, j0, th, tw;
     int32_t wlo, nwin;
