@@ -312,6 +312,33 @@ def fused_line(az, torch, np, synth, dev, reps=50):
     return line
 
 
+def fuse_stage_line(az, torch, np, synth, dev, reps=40):
+    """The corrected c2 pipeline as one call (integrate_raw), two passes
+    (correction kernel, then the band kernel on the corrected image) against
+    the band kernel that casts and corrects what it gathers (stage fuse)."""
+    c = synth.C2
+    inst = synth.instance(c["n"], c["seed"], corrections=True)
+    g = inst.geom
+    raw = torch.from_numpy(inst.raw.reshape(-1)).to(dev)
+    line = {}
+    for dt in ("f64", "f32"):
+        tdt = torch.float64 if dt == "f64" else torch.float32
+        npd = np.float64 if dt == "f64" else np.float32
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a).reshape(-1).astype(npd)).to(dev)
+        for stage in ("gather", "fuse"):
+            plan = az.Plan(g.h, g.w, inst.npt, center=(g.center_y, g.center_x), dtype=tdt,
+                           device=dev, stage=stage)
+            plan.set_corrections(t(inst.dark), t(inst.flat), t(inst.solid), t(inst.polar))
+            outs = tuple(torch.empty(inst.npt, dtype=tdt, device=dev) for _ in range(3))
+            ms = _timed(torch, lambda: plan.integrate_raw(raw, out=outs), reps)
+            name = f"{dt}_{'two_pass' if stage == 'gather' else 'fused_correction'}"
+            line[name + "_ms"] = ms
+            line[name + "_elements_per_s"] = g.npix / (ms * 1e-3)
+            del plan
+    torch.cuda.empty_cache()
+    return line
+
+
 def two_d_line(az, torch, np, synth, dev, nr=1000, na=360, reps=30):
     """Two-dimensional integration of the c2 frame (float64): 1000 radial
     bins x 360 azimuthal wedges, bounding-box split, default layout."""
@@ -470,8 +497,8 @@ def main():
         result["lines"]["c5"] = batch_line(az, torch, np, synth, dev, synth.C5, "f32",
                                            True, True)
         log(f"[c5] {json.dumps(result['lines']['c5'])}")
-    for name, fn in (("c2_fused", fused_line), ("c2_2d", two_d_line),
-                     ("c2_plan_build", plan_build_line)):
+    for name, fn in (("c2_fuse_stage", fuse_stage_line), ("c2_fused", fused_line),
+                     ("c2_2d", two_d_line), ("c2_plan_build", plan_build_line)):
         if run(name):
             result["lines"][name] = fn(az, torch, np, synth, dev)
             log(f"[{name}] {json.dumps(result['lines'][name])}")

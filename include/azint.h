@@ -219,12 +219,19 @@ int azi_plan_export_csc(const azi_plan* plan, void* data, int32_t* bins, int32_t
  *             AZI_STAGE_GATHER reads each ring position's pixel; _SCATTER
  *             reads row-major and writes each pixel's ring position;
  *             _TILE reads 32x128-pixel tiles row-major and writes them out in
- *             ring order through LDS.
+ *             ring order through LDS.  AZI_STAGE_FUSE (band layout): the
+ *             raw-frame calls (azi_integrate1d_raw, azi_batch_forward_raw)
+ *             run one band kernel that casts and corrects every pixel it
+ *             gathers -- the same operations as azi_correct, so the results
+ *             equal the two-pass ones bit for bit -- and never write the
+ *             corrected image (256 threads per workgroup).  azi_plan_stage
+ *             and the staged call keep the two passes.
  */
 #define AZI_NUM_VARIANTS 7
 #define AZI_STAGE_GATHER 0
 #define AZI_STAGE_SCATTER 1
 #define AZI_STAGE_TILE 2
+#define AZI_STAGE_FUSE 3
 typedef struct azi_tiling {
     int32_t tile_nnz, block, variant, grid, band, stage;
 } azi_tiling;

@@ -53,7 +53,7 @@ class Tiling(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
-STAGES = {"gather": 0, "scatter": 1, "tile": 2}
+STAGES = {"gather": 0, "scatter": 1, "tile": 2, "fuse": 3}
 DEFAULT_TILING = dict(tile_nnz=2048, block=256, variant=5, grid=0, band=4, stage=0)
 
 

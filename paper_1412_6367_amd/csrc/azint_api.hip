@@ -117,11 +117,13 @@ bool valid_tiling(const azi_tiling& t) {
     return t.tile_nnz >= 64 && t.tile_nnz <= 16384 && t.tile_nnz % 64 == 0 &&
            (t.block == 64 || t.block == 128 || t.block == 256 || t.block == 512) &&
            t.variant >= 0 && t.variant < azi::kNumVariants && t.grid >= 0 && t.band >= 0 &&
-           t.stage >= AZI_STAGE_GATHER && t.stage <= AZI_STAGE_TILE;
+           t.stage >= AZI_STAGE_GATHER && t.stage <= AZI_STAGE_FUSE;
 }
 
-// Fastest measured on the ~1e7-pixel, 3162-bin workload (float64 and float32).
+// Fastest measured on the ~1e7-pixel, 3162-bin workload: float64 takes
+// pieces of 2048 entries, float32 (fewer bytes per entry) pieces of 4096.
 constexpr azi_tiling kDefaultTiling = {2048, 256, 5, 0, 4, AZI_STAGE_GATHER};
+constexpr azi_tiling kDefaultTiling32 = {4096, 256, 5, 0, 4, AZI_STAGE_GATHER};
 constexpr azi_tiling kDefaultTiling2d = {4096, 256, 3, 0, 1, AZI_STAGE_GATHER};
 
 // Converts double coefficients to the storage type into a padded buffer.
@@ -522,6 +524,7 @@ int plan_create(const azi_geom* geom, int32_t npt, int32_t npt_azim, int32_t uni
     p->geom = *geom;
     p->dtype = dtype;
     p->accum = accum;
+    if (dtype == AZI_F32) p->tiling = kDefaultTiling32;
     p->unit = unit;
     p->split = split;
     if (device >= 0) {
@@ -1140,6 +1143,21 @@ int azi_integrate1d_raw(const azi_plan* p, const void* raw, int32_t raw_dtype, v
                 "blocked forward kernels");
         return AZI_OK;
     }
+    if (p && p->layout == AZI_LAYOUT_BAND && p->tiling.stage == AZI_STAGE_FUSE &&
+        p->device >= 0) {
+        // cast and correction in the band kernel's gather
+        if (!raw) return fail(AZI_EINVAL, "raw must not be NULL");
+        if (!valid_raw_dtype(raw_dtype)) return fail(AZI_EINVAL, "unknown raw dtype");
+        DeviceGuard g(p->device);
+        if (g.err != hipSuccess) return hip_fail(g.err, "set device");
+        azi::BandLaunch a = plan_band_args(p, nullptr, I, W, U, empty);
+        a.raw = raw;
+        a.raw_dtype = raw_dtype;
+        a.dark = p->has_dark ? p->dark.p : nullptr;
+        a.norm = p->has_norm ? p->norm.p : nullptr;
+        AZI_HIP(azi::launch_band(a, static_cast<hipStream_t>(stream)), "band forward kernels");
+        return AZI_OK;
+    }
     int rc = azi_plan_stage(p, raw, raw_dtype, stream);
     if (rc != AZI_OK) return rc;
     return azi_integrate1d_staged(p, I, W, U, empty, stream);
@@ -1557,6 +1575,13 @@ int azi_batch_forward_raw(azi_batch* b, const void* raw, int32_t raw_dtype, void
     if (b->layout == AZI_LAYOUT_TILE) {
         AZI_HIP(azi::launch_block(batch_block_args(b, raw, raw_dtype, 0, b->n, I, W, U, empty), s),
                 "batched blocked kernels");
+        return AZI_OK;
+    }
+    if (b->layout == AZI_LAYOUT_BAND && b->tiling.stage == AZI_STAGE_FUSE) {
+        azi::BandLaunch a = batch_band_args(b, nullptr, 0, b->n, I, W, U, empty);
+        a.raw = raw;
+        a.raw_dtype = raw_dtype;
+        AZI_HIP(azi::launch_band(a, s), "batched band kernels");
         return AZI_OK;
     }
     int rc = batch_stage(b, raw, raw_dtype, 0, b->n, s);

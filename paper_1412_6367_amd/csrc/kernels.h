@@ -68,6 +68,12 @@ struct BandLaunch {
     int32_t R = 8;
     int64_t b0 = 0, b1 = 0;
     const void* x = nullptr;
+    // raw-frame form: when `raw` is set, x is ignored and each gathered pixel
+    // is (T(raw) - dark) / norm (dark / norm may be null); 256 threads
+    const void* raw = nullptr;
+    int32_t raw_dtype = AZI_I32;
+    const void* dark = nullptr;
+    const void* norm = nullptr;
     void* parts = nullptr;
     void* I = nullptr;
     void* W = nullptr;

@@ -252,13 +252,20 @@ __global__ void k_fixup(const Split* __restrict__ splits, int32_t nsplits,
 // product to the accumulator of the entry's bin within the band.  The R
 // accumulators are then reduced over the workgroup in a fixed tree and
 // written to the piece's R partial slots.
-template <class T, class Acc, int BLOCK, int R>
+// With kCorr the image is the raw frame: every gathered pixel is cast and
+// corrected on the way, (T(raw) - dark) / norm, the operations of k_correct,
+// so the sums equal those over the corrected image bit for bit and the
+// corrected image is never written.
+template <class T, class Acc, int BLOCK, int R, class RawT = T, bool kCorr = false>
 __global__ __launch_bounds__(BLOCK) void k_band(const BandPiece* __restrict__ pieces,
                                                 int32_t npieces,
                                                 const int32_t* __restrict__ packed,
                                                 const T* __restrict__ coef,
                                                 const T* __restrict__ x,
-                                                Acc* __restrict__ parts) {
+                                                Acc* __restrict__ parts,
+                                                const RawT* __restrict__ raw = nullptr,
+                                                const T* __restrict__ dark = nullptr,
+                                                const T* __restrict__ norm = nullptr) {
     constexpr int U = 4;
     constexpr int32_t kMask = (1 << kBandShift) - 1;
     __shared__ Acc red[BLOCK / kWave][R];
@@ -275,7 +282,10 @@ __global__ __launch_bounds__(BLOCK) void k_band(const BandPiece* __restrict__ pi
     }
     for (int32_t ti = t_begin; ti < t_end; ti += t_step) {
         const BandPiece pc = pieces[ti];
-        const T* xb = x + pc.pix_off;
+        const T* xb = kCorr ? nullptr : x + pc.pix_off;
+        const RawT* rb = kCorr ? raw + pc.pix_off : nullptr;
+        const T* db = (kCorr && dark) ? dark + pc.pix_off : nullptr;
+        const T* nb = (kCorr && norm) ? norm + pc.pix_off : nullptr;
         Acc a[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) a[r].zero();
@@ -292,7 +302,20 @@ __global__ __launch_bounds__(BLOCK) void k_band(const BandPiece* __restrict__ pi
             }
             T xv[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) xv[u] = (z + u * BLOCK < pc.z1) ? xb[pk[u] & kMask] : T(0);
+            for (int u = 0; u < U; ++u) {
+                if constexpr (kCorr) {
+                    T v = T(0);
+                    if (z + u * BLOCK < pc.z1) {
+                        const int32_t pix = pk[u] & kMask;
+                        v = (T)rb[pix];
+                        if (db) v = v - db[pix];
+                        if (nb) v = v / nb[pix];
+                    }
+                    xv[u] = v;
+                } else {
+                    xv[u] = (z + u * BLOCK < pc.z1) ? xb[pk[u] & kMask] : T(0);
+                }
+            }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (z + u * BLOCK < pc.z1) {
@@ -676,12 +699,40 @@ hipError_t band_launch(const BandLaunch& a, hipStream_t s) {
     const int grid = a.grid > 0 ? a.grid : a.npieces;
     hipLaunchKernelGGL((k_band<T, Acc, BLOCK, R>), dim3(grid), dim3(BLOCK), 0, s, a.pieces,
                        a.npieces, a.packed, static_cast<const T*>(a.coef),
-                       static_cast<const T*>(a.x), static_cast<Acc*>(a.parts));
+                       static_cast<const T*>(a.x), static_cast<Acc*>(a.parts),
+                       static_cast<const T*>(nullptr), static_cast<const T*>(nullptr),
+                       static_cast<const T*>(nullptr));
+    return hipGetLastError();
+}
+
+// Raw-frame form (256 threads): cast and correction in the gather.
+template <class T, class Acc, int R, class RawT>
+hipError_t band_launch_raw(const BandLaunch& a, hipStream_t s) {
+    const int grid = a.grid > 0 ? a.grid : a.npieces;
+    hipLaunchKernelGGL((k_band<T, Acc, 256, R, RawT, true>), dim3(grid), dim3(256), 0, s,
+                       a.pieces, a.npieces, a.packed, static_cast<const T*>(a.coef),
+                       static_cast<const T*>(nullptr), static_cast<Acc*>(a.parts),
+                       static_cast<const RawT*>(a.raw), static_cast<const T*>(a.dark),
+                       static_cast<const T*>(a.norm));
     return hipGetLastError();
 }
 
 template <class T, class Acc, int R>
+hipError_t band_raw(const BandLaunch& a, hipStream_t s) {
+    switch (a.raw_dtype) {
+        case AZI_I16: return band_launch_raw<T, Acc, R, int16_t>(a, s);
+        case AZI_U16: return band_launch_raw<T, Acc, R, uint16_t>(a, s);
+        case AZI_I32: return band_launch_raw<T, Acc, R, int32_t>(a, s);
+        case AZI_U32: return band_launch_raw<T, Acc, R, uint32_t>(a, s);
+        case AZI_F32: return band_launch_raw<T, Acc, R, float>(a, s);
+        case AZI_F64: return band_launch_raw<T, Acc, R, double>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <class T, class Acc, int R>
 hipError_t band_block(const BandLaunch& a, hipStream_t s) {
+    if (a.raw) return band_raw<T, Acc, R>(a, s);
     switch (a.block) {
         case 64:
         case 128: return band_launch<T, Acc, 128, R>(a, s);

@@ -250,3 +250,42 @@ def test_band_batch_retile(R, piece, dev):
         _, Wa, _ = oracle.integrate(m, xv)
         assert norm_err(W[bo[k]:bo[k + 1]].cpu().numpy(), Wo, Wa) <= 1e-12, k
         assert norm_err(U[bo[k]:bo[k + 1]].cpu().numpy(), Uo, Uo) <= 1e-12, k
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_band_fused_correction_bitwise(dtype, dev):
+    """The band kernel with cast and correction in its gather (stage
+    "fuse") gives the two-pass results bit for bit: plan with all four
+    corrections, and a batch of raw frames."""
+    say("band fuse", dtype)
+    az = azint()
+    npd = np.float64 if dtype == torch.float64 else np.float32
+    inst = synth.instance_hw(130, 170, 5, npt=110, corrections=True)
+    g = inst.geom
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a).reshape(-1).astype(npd)).to(dev)
+    plans = []
+    for stage in ("gather", "fuse"):
+        p = az.Plan(g.h, g.w, inst.npt, center=(g.center_y, g.center_x), dtype=dtype,
+                    device=dev, stage=stage)
+        p.set_corrections(t(inst.dark), t(inst.flat), t(inst.solid), t(inst.polar))
+        plans.append(p)
+    raw = torch.from_numpy(inst.raw.reshape(-1)).to(dev)
+    a = plans[0].integrate_raw(raw)
+    b = plans[1].integrate_raw(raw)
+    torch.cuda.synchronize()
+    for u, v in zip(a, b):
+        assert torch.equal(u, v)
+    insts = small_batch(30, 23)
+    _, b0 = make_batch(insts, dtype, dev)
+    _, b1 = make_batch(insts, dtype, dev, tile=dict(stage="fuse"))
+    rawb = torch.from_numpy(np.concatenate([i.raw.reshape(-1) for i in insts])).to(dev)
+    for u, v in zip(b0.forward_raw(rawb), b1.forward_raw(rawb)):
+        assert torch.equal(u, v)
+    # graph capture of the one-kernel path
+    I0, W0, U0 = b
+    I, W, U = (torch.full_like(I0, np.nan) for _ in range(3))
+    graph = plans[1].graph(raw, I, W, U)
+    for _ in range(3):
+        graph.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(I, I0) and torch.equal(W, W0) and torch.equal(U, U0)

@@ -164,3 +164,31 @@ def test_fused_c2_full_size(dev):
         assert abs(W[b] - Wo[0]) <= TOL64 * Wa[0], (b, W[b], Wo[0])
         assert abs(U[b] - Uo[0]) <= TOL64 * Uo[0], (b, U[b], Uo[0])
         assert abs(I[b] - Io[0]) <= TOL64 * Wa[0] / Uo[0], (b, I[b], Io[0])
+
+
+@pytest.mark.parametrize("layout", ["fused", "pixel"])
+def test_plan_graph_replays(layout, dev):
+    """The raw pipeline captured in a HIP graph (the fused layout's one
+    kernel, and a 2-D plan in its default layout for the pixel case)
+    replays the eager bits every time, with eager work in between."""
+    say("plan graph", layout)
+    az = azint()
+    rng = np.random.default_rng(14)
+    h, w = 160, 150
+    raw = torch.from_numpy(rng.integers(0, 1 << 20, size=h * w).astype(np.int32)).to(dev)
+    dark = torch.from_numpy(rng.integers(0, 64, size=h * w).astype(np.float64)).to(dev)
+    if layout == "fused":
+        plan = az.Plan(h, w, 120, layout="fused", device=dev)
+    else:
+        plan = az.Plan(h, w, 60, npt_azim=36, device=dev)
+    plan.set_corrections(dark=dark)
+    I0, W0, U0 = plan.integrate_raw(raw)
+    I, W, U = (torch.full_like(I0, np.nan) for _ in range(3))
+    graph = plan.graph(raw, I, W, U)
+    for rep in range(4):
+        for t in (I, W, U):
+            t.fill_(np.nan)
+        graph.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(I, I0) and torch.equal(W, W0) and torch.equal(U, U0), rep
+        _ = (raw * 2).sum().item()
