@@ -200,7 +200,11 @@ int azi_plan_export_csc(const azi_plan* plan, void* data, int32_t* bins, int32_t
 
 /*
  * Launch and tile schedule of the forward kernel (tuning only: results
- * change at most in the order of the floating-point additions).
+ * change at most in the order of the floating-point additions, and, for
+ * the stage, by the one rounding of the fused correction).  A new plan
+ * starts at tile_nnz 4096, block 256, variant 5, grid 0, band 4, stage
+ * AZI_STAGE_FUSE (two-dimensional plans: 4096, 256, 3, 0, 1,
+ * AZI_STAGE_GATHER).
  *   tile_nnz  most nonzeros one workgroup sums per tile (64..16384, a
  *             multiple of 64); rows longer than that are cut into pieces
  *             whose sums are added in order by a small fix-up kernel.
@@ -222,9 +226,12 @@ int azi_plan_export_csc(const azi_plan* plan, void* data, int32_t* bins, int32_t
  *             ring order through LDS.  AZI_STAGE_FUSE (band layout): the
  *             raw-frame calls (azi_integrate1d_raw, azi_batch_forward_raw)
  *             run one band kernel that casts and corrects every pixel it
- *             gathers -- the same operations as azi_correct, so the results
- *             equal the two-pass ones bit for bit -- and never write the
- *             corrected image (256 threads per workgroup).  azi_plan_stage
+ *             gathers as (raw - dark) * (1 / norm), dark and the reciprocal
+ *             of norm (formed once per correction set, held as one pair per
+ *             pixel: 2 storage values) read in one load, and never write the
+ *             corrected image (256 threads per workgroup).  The product by
+ *             the rounded reciprocal differs from the quotient of
+ *             azi_correct by at most one rounding per pixel.  azi_plan_stage
  *             and the staged call keep the two passes.
  */
 #define AZI_NUM_VARIANTS 7

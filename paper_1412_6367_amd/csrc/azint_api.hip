@@ -120,10 +120,10 @@ bool valid_tiling(const azi_tiling& t) {
            t.stage >= AZI_STAGE_GATHER && t.stage <= AZI_STAGE_FUSE;
 }
 
-// Fastest measured on the ~1e7-pixel, 3162-bin workload: float64 takes
-// pieces of 2048 entries, float32 (fewer bytes per entry) pieces of 4096.
-constexpr azi_tiling kDefaultTiling = {2048, 256, 5, 0, 4, AZI_STAGE_GATHER};
-constexpr azi_tiling kDefaultTiling32 = {4096, 256, 5, 0, 4, AZI_STAGE_GATHER};
+// Fastest measured on the ~1e7-pixel, 3162-bin workload: bands of 4 bins,
+// pieces of 4096 entries, raw frames corrected in the band gather.
+constexpr azi_tiling kDefaultTiling = {4096, 256, 5, 0, 4, AZI_STAGE_FUSE};
+constexpr azi_tiling kDefaultTiling32 = {4096, 256, 5, 0, 4, AZI_STAGE_FUSE};
 constexpr azi_tiling kDefaultTiling2d = {4096, 256, 3, 0, 1, AZI_STAGE_GATHER};
 
 // Converts double coefficients to the storage type into a padded buffer.
@@ -151,7 +151,7 @@ struct azi_plan {
     DevBuf rowptr, indices, data, colptr, rowidx, cdata, tiles, splits, parts, dark, norm, xwork,
         vwork, order, dark_r, norm_r, pos, stiles, lidx, dest, btiles, brows, blp, bcoef, bin_ptr,
         bparts, npieces_buf, npacked, ncoef, bin_slot, bin_count, nparts_buf, ftiles, fslots,
-        fbin_ptr, fparts;
+        fbin_ptr, fparts, corr;
     int32_t nstiles = 0, nbtiles = 0, npieces = 0, band_rows = 8, nftiles = 0;
     int32_t ntiles = 0, nsplits = 0, nparts = 0;
     bool has_dark = false, has_norm = false;
@@ -411,12 +411,29 @@ int plan_upload_fused(azi_plan* p) {
     return AZI_OK;
 }
 
+// (dark, 1 / norm) pairs for the band kernel's fused gather, formed when
+// the plan integrates raw frames with AZI_STAGE_FUSE and has corrections.
+int plan_corr_pair(azi_plan* p, hipStream_t s) {
+    p->corr.release();
+    if (p->layout != AZI_LAYOUT_BAND || p->tiling.stage != AZI_STAGE_FUSE ||
+        !(p->has_dark || p->has_norm))
+        return AZI_OK;
+    AZI_HIP(p->corr.alloc((size_t)p->m.npix * 2 * elem_size(p->dtype), p->device),
+            "correction pairs");
+    AZI_HIP(azi::launch_corr_pair(p->has_dark ? p->dark.p : nullptr,
+                                  p->has_norm ? p->norm.p : nullptr, p->corr.p, p->dtype,
+                                  p->m.npix, s), "correction pairs");
+    AZI_HIP(hipStreamSynchronize(s), "correction pairs");
+    return AZI_OK;
+}
+
 // Staging of a (raw or corrected) row-major image into the plan's ring work
 // image, with the plan's corrections when `correct` is set.
 azi::StageLaunch plan_stage_args(const azi_plan* p, const void* img, int32_t img_dtype,
                                  bool correct) {
     azi::StageLaunch a;
-    a.mode = p->tiling.stage;
+    // AZI_STAGE_FUSE concerns the band layout; the ring staging then gathers
+    a.mode = p->tiling.stage == AZI_STAGE_FUSE ? AZI_STAGE_GATHER : p->tiling.stage;
     a.raw = img;
     a.raw_dtype = img_dtype;
     a.order = p->order.as<int32_t>();
@@ -819,7 +836,15 @@ int azi_plan_set_tiling(azi_plan* p, const azi_tiling* t) {
     if (!p || !t) return fail(AZI_EINVAL, "plan and tiling must not be NULL");
     if (!valid_tiling(*t)) return fail(AZI_EINVAL, kTilingRule);
     const bool retile = t->tile_nnz != p->tiling.tile_nnz || t->band != p->tiling.band;
+    const bool restage = t->stage != p->tiling.stage;
     p->tiling = *t;
+    if (p->device >= 0 && restage) {
+        DeviceGuard g(p->device);
+        if (g.err != hipSuccess) return hip_fail(g.err, "set device");
+        AZI_HIP(hipDeviceSynchronize(), "synchronise before changing the stage");
+        const int rc = plan_corr_pair(p, nullptr);
+        if (rc != AZI_OK) return rc;
+    }
     if (p->device >= 0 && retile) {
         DeviceGuard g(p->device);
         if (g.err != hipSuccess) return hip_fail(g.err, "set device");
@@ -965,7 +990,7 @@ int azi_plan_upload(azi_plan* p, int32_t device) {
 
 int64_t azi_plan_device_bytes(const azi_plan* p) {
     if (!p) return 0;
-    const DevBuf* bufs[] = {&p->ftiles, &p->fslots, &p->fbin_ptr, &p->fparts,
+    const DevBuf* bufs[] = {&p->ftiles, &p->fslots, &p->fbin_ptr, &p->fparts, &p->corr,
                             &p->rowptr, &p->indices, &p->data, &p->colptr, &p->rowidx,
                             &p->cdata, &p->tiles, &p->splits, &p->parts, &p->dark,
                             &p->norm, &p->xwork, &p->vwork, &p->order, &p->dark_r,
@@ -1020,7 +1045,7 @@ int azi_plan_set_corrections(azi_plan* p, const void* dark, const void* flat, co
         }
     }
     AZI_HIP(hipStreamSynchronize(s), "corrections");
-    return AZI_OK;
+    return plan_corr_pair(p, s);
 }
 
 int azi_correct(const azi_plan* p, const void* raw, int32_t raw_dtype, void* x, void* stream) {
@@ -1153,8 +1178,7 @@ int azi_integrate1d_raw(const azi_plan* p, const void* raw, int32_t raw_dtype, v
         azi::BandLaunch a = plan_band_args(p, nullptr, I, W, U, empty);
         a.raw = raw;
         a.raw_dtype = raw_dtype;
-        a.dark = p->has_dark ? p->dark.p : nullptr;
-        a.norm = p->has_norm ? p->norm.p : nullptr;
+        a.corr = (p->has_dark || p->has_norm) ? p->corr.p : nullptr;
         AZI_HIP(azi::launch_band(a, static_cast<hipStream_t>(stream)), "band forward kernels");
         return AZI_OK;
     }
@@ -1508,7 +1532,7 @@ int batch_stage(azi_batch* b, const void* img, int32_t img_dtype, int32_t k0, in
         return AZI_OK;
     }
     azi::StageLaunch a;
-    a.mode = b->tiling.stage;
+    a.mode = b->tiling.stage == AZI_STAGE_FUSE ? AZI_STAGE_GATHER : b->tiling.stage;
     a.raw = img;
     a.raw_dtype = img_dtype;
     a.dtype = b->dtype;

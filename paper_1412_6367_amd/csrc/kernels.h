@@ -69,11 +69,11 @@ struct BandLaunch {
     int64_t b0 = 0, b1 = 0;
     const void* x = nullptr;
     // raw-frame form: when `raw` is set, x is ignored and each gathered pixel
-    // is (T(raw) - dark) / norm (dark / norm may be null); 256 threads
+    // is (T(raw) - corr.x) * corr.y with corr the (dark, 1 / norm) pairs of
+    // launch_corr_pair, or just T(raw) when corr is null; 256 threads
     const void* raw = nullptr;
     int32_t raw_dtype = AZI_I32;
-    const void* dark = nullptr;
-    const void* norm = nullptr;
+    const void* corr = nullptr;
     void* parts = nullptr;
     void* I = nullptr;
     void* W = nullptr;
@@ -86,6 +86,11 @@ struct BandLaunch {
 };
 
 hipError_t launch_band(const BandLaunch& a, hipStream_t s);
+
+// pair[i] = (dark[i], 1 / norm[i]) in the storage type (0 and 1 where the
+// array is null): the per-pixel correction of the fused band gather.
+hipError_t launch_corr_pair(const void* dark, const void* norm, void* pair, int32_t dtype,
+                            int64_t n, hipStream_t s);
 
 // Blocked (image-tile) integration: k_block over tiles [0, ntiles) fills the
 // partial slots, then k_block_reduce finishes bins [b0, b1).  `img` is the

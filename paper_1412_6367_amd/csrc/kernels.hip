@@ -252,9 +252,13 @@ __global__ void k_fixup(const Split* __restrict__ splits, int32_t nsplits,
 // product to the accumulator of the entry's bin within the band.  The R
 // accumulators are then reduced over the workgroup in a fixed tree and
 // written to the piece's R partial slots.
+template <class T> struct Pair2;
+template <> struct Pair2<double> { using type = double2; };
+template <> struct Pair2<float> { using type = float2; };
+
 // With kCorr the image is the raw frame: every gathered pixel is cast and
-// corrected on the way, (T(raw) - dark) / norm, the operations of k_correct,
-// so the sums equal those over the corrected image bit for bit and the
+// corrected on the way, (T(raw) - dark) * (1 / norm), dark and the
+// reciprocal of norm coming as one pair per pixel (one load), so the
 // corrected image is never written.
 template <class T, class Acc, int BLOCK, int R, class RawT = T, bool kCorr = false>
 __global__ __launch_bounds__(BLOCK) void k_band(const BandPiece* __restrict__ pieces,
@@ -264,8 +268,8 @@ __global__ __launch_bounds__(BLOCK) void k_band(const BandPiece* __restrict__ pi
                                                 const T* __restrict__ x,
                                                 Acc* __restrict__ parts,
                                                 const RawT* __restrict__ raw = nullptr,
-                                                const T* __restrict__ dark = nullptr,
-                                                const T* __restrict__ norm = nullptr) {
+                                                const typename Pair2<T>::type* __restrict__ corr =
+                                                    nullptr) {
     constexpr int U = 4;
     constexpr int32_t kMask = (1 << kBandShift) - 1;
     __shared__ Acc red[BLOCK / kWave][R];
@@ -284,8 +288,7 @@ __global__ __launch_bounds__(BLOCK) void k_band(const BandPiece* __restrict__ pi
         const BandPiece pc = pieces[ti];
         const T* xb = kCorr ? nullptr : x + pc.pix_off;
         const RawT* rb = kCorr ? raw + pc.pix_off : nullptr;
-        const T* db = (kCorr && dark) ? dark + pc.pix_off : nullptr;
-        const T* nb = (kCorr && norm) ? norm + pc.pix_off : nullptr;
+        const typename Pair2<T>::type* cb = (kCorr && corr) ? corr + pc.pix_off : nullptr;
         Acc a[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) a[r].zero();
@@ -308,8 +311,10 @@ __global__ __launch_bounds__(BLOCK) void k_band(const BandPiece* __restrict__ pi
                     if (z + u * BLOCK < pc.z1) {
                         const int32_t pix = pk[u] & kMask;
                         v = (T)rb[pix];
-                        if (db) v = v - db[pix];
-                        if (nb) v = v / nb[pix];
+                        if (cb) {
+                            const auto c = cb[pix];
+                            v = (v - c.x) * c.y;
+                        }
                     }
                     xv[u] = v;
                 } else {
@@ -700,8 +705,8 @@ hipError_t band_launch(const BandLaunch& a, hipStream_t s) {
     hipLaunchKernelGGL((k_band<T, Acc, BLOCK, R>), dim3(grid), dim3(BLOCK), 0, s, a.pieces,
                        a.npieces, a.packed, static_cast<const T*>(a.coef),
                        static_cast<const T*>(a.x), static_cast<Acc*>(a.parts),
-                       static_cast<const T*>(nullptr), static_cast<const T*>(nullptr),
-                       static_cast<const T*>(nullptr));
+                       static_cast<const T*>(nullptr),
+                       static_cast<const typename Pair2<T>::type*>(nullptr));
     return hipGetLastError();
 }
 
@@ -712,8 +717,8 @@ hipError_t band_launch_raw(const BandLaunch& a, hipStream_t s) {
     hipLaunchKernelGGL((k_band<T, Acc, 256, R, RawT, true>), dim3(grid), dim3(256), 0, s,
                        a.pieces, a.npieces, a.packed, static_cast<const T*>(a.coef),
                        static_cast<const T*>(nullptr), static_cast<Acc*>(a.parts),
-                       static_cast<const RawT*>(a.raw), static_cast<const T*>(a.dark),
-                       static_cast<const T*>(a.norm));
+                       static_cast<const RawT*>(a.raw),
+                       static_cast<const typename Pair2<T>::type*>(a.corr));
     return hipGetLastError();
 }
 
@@ -857,6 +862,36 @@ hipError_t launch_correct(const void* raw, int32_t raw_dtype, const int32_t* ord
     if (n <= 0) return hipSuccess;
     return dtype == AZI_F64 ? correct_raw<double>(raw, raw_dtype, order, dark, norm, x, n, s)
                             : correct_raw<float>(raw, raw_dtype, order, dark, norm, x, n, s);
+}
+
+namespace {
+// pair[i] = (dark[i] or 0, 1 / norm[i] or 1): the fused gather's correction.
+template <class T>
+__global__ void k_corr_pair(const T* __restrict__ dark, const T* __restrict__ norm,
+                            typename Pair2<T>::type* __restrict__ pair, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    typename Pair2<T>::type v;
+    v.x = dark ? dark[i] : T(0);
+    v.y = norm ? T(1) / norm[i] : T(1);
+    pair[i] = v;
+}
+}  // namespace
+
+hipError_t launch_corr_pair(const void* dark, const void* norm, void* pair, int32_t dtype,
+                            int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    if (blocks > INT32_MAX) return hipErrorInvalidValue;
+    if (dtype == AZI_F64)
+        hipLaunchKernelGGL(k_corr_pair<double>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           static_cast<const double*>(dark), static_cast<const double*>(norm),
+                           static_cast<double2*>(pair), n);
+    else
+        hipLaunchKernelGGL(k_corr_pair<float>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           static_cast<const float*>(dark), static_cast<const float*>(norm),
+                           static_cast<float2*>(pair), n);
+    return hipGetLastError();
 }
 
 hipError_t launch_band(const BandLaunch& a, hipStream_t s) {

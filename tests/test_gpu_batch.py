@@ -253,10 +253,14 @@ def test_band_batch_retile(R, piece, dev):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_band_fused_correction_bitwise(dtype, dev):
+def test_band_fused_correction(dtype, dev):
     """The band kernel with cast and correction in its gather (stage
-    "fuse") gives the two-pass results bit for bit: plan with all four
-    corrections, and a batch of raw frames."""
+    "fuse"): against the FP64 oracle and within one rounding per pixel of
+    the two-pass results for a plan with all four corrections (the gather
+    multiplies by the reciprocal of norm); bit for bit for a batch of raw
+    frames without corrections (a plain cast either way)."""
+    import oracle
+    from tests.test_gpu_forward import TOL32_F64, TOL64, check
     say("band fuse", dtype)
     az = azint()
     npd = np.float64 if dtype == torch.float64 else np.float32
@@ -273,7 +277,20 @@ def test_band_fused_correction_bitwise(dtype, dev):
     a = plans[0].integrate_raw(raw)
     b = plans[1].integrate_raw(raw)
     torch.cuda.synchronize()
-    for u, v in zip(a, b):
+    m = oracle.build_matrix(h=g.h, w=g.w, pixel_y=g.pixel_y, pixel_x=g.pixel_x,
+                            center_y=g.center_y, center_x=g.center_x, dist=g.dist,
+                            wavelength=g.wavelength, npt=inst.npt)
+    f = lambda v: np.ascontiguousarray(v).reshape(-1).astype(npd).astype(np.float64)
+    x = oracle.correct(inst.raw.reshape(-1).astype(np.float64), f(inst.dark), f(inst.flat),
+                       f(inst.solid), f(inst.polar))
+    tol = TOL64 if dtype == torch.float64 else TOL32_F64
+    check(b, m, x, tol, what="fused")
+    check(a, m, x, tol, what="two pass")
+    # switching the stage after the corrections builds the pairs then
+    plans[0].set_tiling(stage="fuse")
+    c = plans[0].integrate_raw(raw)
+    torch.cuda.synchronize()
+    for u, v in zip(b, c):
         assert torch.equal(u, v)
     insts = small_batch(30, 23)
     _, b0 = make_batch(insts, dtype, dev)

@@ -132,7 +132,8 @@ def test_correction_map_bit_exact(raw_dtype, dev):
 
 @pytest.mark.parametrize("layout,stage", [("ring", "tile"), ("ring", "gather"),
                                           ("ring", "scatter"), ("pixel", "tile"),
-                                          ("tile", "tile"), ("band", "tile")])
+                                          ("tile", "tile"), ("band", "tile"),
+                                          ("band", "fuse"), ("ring", "fuse")])
 def test_raw_pipeline_with_corrections(layout, stage, dev):
     say("raw pipeline with corrections", layout, stage)
     az = azint()
@@ -153,8 +154,13 @@ def test_raw_pipeline_with_corrections(layout, stage, dev):
     assert np.array_equal(xd.cpu().numpy(), x)
     out2 = plan.integrate(xd)
     torch.cuda.synchronize()
-    for a, b in zip(out, out2):
-        assert torch.equal(a, b)
+    if layout == "band" and stage == "fuse":
+        # the fused gather multiplies by the reciprocal of norm: one rounding
+        # per pixel away from the corrected image's quotient
+        check(out2, m, x, TOL64, what="corrected image")
+    else:
+        for a, b in zip(out, out2):
+            assert torch.equal(a, b)
 
 
 @pytest.mark.parametrize("layout", ["ring", "pixel", "tile", "band"])
