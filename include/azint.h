@@ -203,8 +203,8 @@ int azi_plan_export_csc(const azi_plan* plan, void* data, int32_t* bins, int32_t
  * change at most in the order of the floating-point additions, and, for
  * the stage, by the one rounding of the fused correction).  A new plan
  * starts at tile_nnz 4096, block 256, variant 5, grid 0, band 4, stage
- * AZI_STAGE_FUSE (two-dimensional plans: 4096, 256, 3, 0, 1,
- * AZI_STAGE_GATHER).
+ * AZI_STAGE_FUSE; below 2^22 nonzeros at tile_nnz 2048
+ * (two-dimensional plans: 4096, 256, 3, 0, 1, AZI_STAGE_GATHER).
  *   tile_nnz  most nonzeros one workgroup sums per tile (64..16384, a
  *             multiple of 64); rows longer than that are cut into pieces
  *             whose sums are added in order by a small fix-up kernel.
@@ -292,6 +292,12 @@ int azi_plan_tile_schedule(const azi_plan* plan, const azi_tiling* tiling, int32
  * each bin's partials in tile order.  With azi_integrate1d_raw the cast and
  * correction happen in the same kernel.  Only the tiling's grid applies.
  * Batches do not take this layout.
+ * AZI_LAYOUT_RECORD (one-dimensional plans): bands of 4 bins as in
+ * AZI_LAYOUT_BAND, but one record per (pixel, run of consecutive bins of
+ * the band): a 4-byte header and the run's coefficients, so each pixel is
+ * gathered (and, for raw frames with AZI_STAGE_FUSE, corrected) once per
+ * band instead of once per entry.  Pieces hold tile_nnz / 2 records (a
+ * multiple of 64); 256 threads.  Batches do not take this layout.
  * Set before azi_plan_upload (a later call re-uploads).
  */
 #define AZI_LAYOUT_PIXEL 0
@@ -299,6 +305,7 @@ int azi_plan_tile_schedule(const azi_plan* plan, const azi_tiling* tiling, int32
 #define AZI_LAYOUT_TILE 2
 #define AZI_LAYOUT_BAND 3
 #define AZI_LAYOUT_FUSED 4
+#define AZI_LAYOUT_RECORD 5
 int azi_plan_set_layout(azi_plan* plan, int32_t layout);
 int azi_plan_get_layout(const azi_plan* plan, int32_t* layout);
 
