@@ -292,12 +292,6 @@ int azi_plan_tile_schedule(const azi_plan* plan, const azi_tiling* tiling, int32
  * each bin's partials in tile order.  With azi_integrate1d_raw the cast and
  * correction happen in the same kernel.  Only the tiling's grid applies.
  * Batches do not take this layout.
- * AZI_LAYOUT_RECORD (one-dimensional plans): bands of 4 bins as in
- * AZI_LAYOUT_BAND, but one record per (pixel, run of consecutive bins of
- * the band): a 4-byte header and the run's coefficients, so each pixel is
- * gathered (and, for raw frames with AZI_STAGE_FUSE, corrected) once per
- * band instead of once per entry.  Pieces hold tile_nnz / 2 records (a
- * multiple of 64); 256 threads.  Batches do not take this layout.
  * Set before azi_plan_upload (a later call re-uploads).
  */
 #define AZI_LAYOUT_PIXEL 0
@@ -305,7 +299,6 @@ int azi_plan_tile_schedule(const azi_plan* plan, const azi_tiling* tiling, int32
 #define AZI_LAYOUT_TILE 2
 #define AZI_LAYOUT_BAND 3
 #define AZI_LAYOUT_FUSED 4
-#define AZI_LAYOUT_RECORD 5
 int azi_plan_set_layout(azi_plan* plan, int32_t layout);
 int azi_plan_get_layout(const azi_plan* plan, int32_t* layout);
 

@@ -158,8 +158,8 @@ struct azi_plan {
     DevBuf rowptr, indices, data, colptr, rowidx, cdata, tiles, splits, parts, dark, norm, xwork,
         vwork, order, dark_r, norm_r, pos, stiles, lidx, dest, btiles, brows, blp, bcoef, bin_ptr,
         bparts, npieces_buf, npacked, ncoef, bin_slot, bin_count, nparts_buf, ftiles, fslots,
-        fbin_ptr, fparts, corr, rpieces, rmeta, rcbase, rcoef, rbin_slot, rbin_count, rparts;
-    int32_t nstiles = 0, nbtiles = 0, npieces = 0, band_rows = 8, nftiles = 0, nrpieces = 0;
+        fbin_ptr, fparts, corr;
+    int32_t nstiles = 0, nbtiles = 0, npieces = 0, band_rows = 8, nftiles = 0;
     int32_t ntiles = 0, nsplits = 0, nparts = 0;
     bool has_dark = false, has_norm = false;
 };
@@ -418,63 +418,12 @@ int plan_upload_fused(azi_plan* p) {
     return AZI_OK;
 }
 
-int plan_upload_records(azi_plan* p) {
-    try {
-        azi::RecordMatrix rm;
-        const int32_t per = std::max(64, p->tiling.tile_nnz / 2 / 64 * 64);
-        if (!azi::build_records(p->m, per, 0, 0, rm))
-            return fail(AZI_EOVERFLOW, "the record layout takes images below 2^27 pixels");
-        const int dev = p->device;
-        AZI_HIP(p->rpieces.upload(rm.pieces.data(), rm.pieces.size() * sizeof(azi::BandPiece), dev),
-                "record pieces");
-        rm.meta.resize(rm.meta.size() + kPad, 0);
-        AZI_HIP(p->rmeta.upload(rm.meta.data(), rm.meta.size() * 4, dev), "record headers");
-        rm.cbase.push_back(0);
-        AZI_HIP(p->rcbase.upload(rm.cbase.data(), rm.cbase.size() * 4, dev), "record chunks");
-        std::vector<char> c = to_storage(rm.coef.data(), (int64_t)rm.coef.size(),
-                                         (int64_t)rm.coef.size() + kPad, p->dtype);
-        AZI_HIP(p->rcoef.upload(c.data(), c.size(), dev), "record coefficients");
-        AZI_HIP(p->rbin_slot.upload(rm.bin_slot.data(), rm.bin_slot.size() * 4, dev), "bin slots");
-        AZI_HIP(p->rbin_count.upload(rm.bin_count.data(), rm.bin_count.size() * 4, dev),
-                "bin counts");
-        AZI_HIP(p->rparts.alloc((size_t)std::max(rm.nslots, 1) * 16, dev), "record partials");
-        p->nrpieces = (int32_t)rm.pieces.size();
-    } catch (const std::bad_alloc&) {
-        return fail(AZI_ENOMEM, "out of host memory building the record layout");
-    }
-    return AZI_OK;
-}
-
-azi::RecordLaunch plan_record_args(const azi_plan* p, const void* x, void* I, void* W, void* U,
-                                   double empty) {
-    azi::RecordLaunch a;
-    a.pieces = p->rpieces.as<azi::BandPiece>();
-    a.npieces = p->nrpieces;
-    a.meta = p->rmeta.as<int32_t>();
-    a.cbase = p->rcbase.as<int32_t>();
-    a.coef = p->rcoef.p;
-    a.bin_slot = p->rbin_slot.as<int32_t>();
-    a.bin_count = p->rbin_count.as<int32_t>();
-    a.b0 = 0;
-    a.b1 = p->m.npt;
-    a.x = x;
-    a.parts = p->rparts.p;
-    a.I = I;
-    a.W = W;
-    a.U = U;
-    a.empty = empty;
-    a.grid = p->tiling.grid;
-    a.dtype = p->dtype;
-    a.accum = p->accum;
-    return a;
-}
-
 // (dark, 1 / norm) pairs for the band kernel's fused gather, formed when
 // the plan integrates raw frames with AZI_STAGE_FUSE and has corrections.
 int plan_corr_pair(azi_plan* p, hipStream_t s) {
     p->corr.release();
-    if ((p->layout != AZI_LAYOUT_BAND && p->layout != AZI_LAYOUT_RECORD) ||
-        p->tiling.stage != AZI_STAGE_FUSE || !(p->has_dark || p->has_norm))
+    if (p->layout != AZI_LAYOUT_BAND || p->tiling.stage != AZI_STAGE_FUSE ||
+        !(p->has_dark || p->has_norm))
         return AZI_OK;
     AZI_HIP(p->corr.alloc((size_t)p->m.npix * 2 * elem_size(p->dtype), p->device),
             "correction pairs");
@@ -917,10 +866,6 @@ int azi_plan_set_tiling(azi_plan* p, const azi_tiling* t) {
             int rc = plan_upload_bands(p);
             if (rc != AZI_OK) return rc;
         }
-        if (p->layout == AZI_LAYOUT_RECORD) {
-            int rc = plan_upload_records(p);
-            if (rc != AZI_OK) return rc;
-        }
         return plan_upload_tiles(p);
     }
     return AZI_OK;
@@ -950,9 +895,8 @@ int azi_plan_tile_schedule(const azi_plan* p, const azi_tiling* tl, int32_t* nti
 
 int azi_plan_set_layout(azi_plan* p, int32_t layout) {
     if (!p) return fail(AZI_EINVAL, "plan is NULL");
-    if (layout < AZI_LAYOUT_PIXEL || layout > AZI_LAYOUT_RECORD)
-        return fail(AZI_EINVAL,
-                    "layout must be one of AZI_LAYOUT_PIXEL/RING/TILE/BAND/FUSED/RECORD");
+    if (layout < AZI_LAYOUT_PIXEL || layout > AZI_LAYOUT_FUSED)
+        return fail(AZI_EINVAL, "layout must be one of AZI_LAYOUT_PIXEL/RING/TILE/BAND/FUSED");
     if (layout == AZI_LAYOUT_FUSED && (p->m.two_d || p->split == AZI_SPLIT_FULL))
         return fail(AZI_EINVAL,
                     "the fused layout takes one-dimensional plans without full splitting");
@@ -1037,10 +981,6 @@ int azi_plan_upload(azi_plan* p, int32_t device) {
             int rc2 = plan_upload_fused(p);
             if (rc2 != AZI_OK) return rc2;
         }
-        if (p->layout == AZI_LAYOUT_RECORD) {
-            int rc2 = plan_upload_records(p);
-            if (rc2 != AZI_OK) return rc2;
-        }
         if (p->layout == AZI_LAYOUT_TILE) {
             try {
                 azi::BlockMatrix bm;
@@ -1064,8 +1004,6 @@ int azi_plan_upload(azi_plan* p, int32_t device) {
 int64_t azi_plan_device_bytes(const azi_plan* p) {
     if (!p) return 0;
     const DevBuf* bufs[] = {&p->ftiles, &p->fslots, &p->fbin_ptr, &p->fparts, &p->corr,
-                            &p->rpieces, &p->rmeta, &p->rcbase, &p->rcoef, &p->rbin_slot,
-                            &p->rbin_count, &p->rparts,
                             &p->rowptr, &p->indices, &p->data, &p->colptr, &p->rowidx,
                             &p->cdata, &p->tiles, &p->splits, &p->parts, &p->dark,
                             &p->norm, &p->xwork, &p->vwork, &p->order, &p->dark_r,
@@ -1150,11 +1088,6 @@ int azi_integrate1d(const azi_plan* p, const void* x, void* I, void* W, void* U,
                 "fused forward kernels");
         return AZI_OK;
     }
-    if (p->layout == AZI_LAYOUT_RECORD) {
-        AZI_HIP(azi::launch_record(plan_record_args(p, x, I, W, U, empty), s),
-                "record forward kernels");
-        return AZI_OK;
-    }
     if (p->layout == AZI_LAYOUT_TILE) {
         AZI_HIP(azi::launch_block(plan_block_args(p, x, p->dtype, false, I, W, U, empty), s),
                 "blocked forward kernels");
@@ -1205,12 +1138,6 @@ int azi_integrate1d_staged(const azi_plan* p, void* I, void* W, void* U, double 
                 "fused forward kernels");
         return AZI_OK;
     }
-    if (p->layout == AZI_LAYOUT_RECORD) {
-        AZI_HIP(azi::launch_record(plan_record_args(p, p->xwork.p, I, W, U, empty),
-                                   static_cast<hipStream_t>(stream)),
-                "record forward kernels");
-        return AZI_OK;
-    }
     if (p->layout == AZI_LAYOUT_TILE) {
         AZI_HIP(azi::launch_block(plan_block_args(p, p->xwork.p, p->dtype, false, I, W, U, empty),
                                   static_cast<hipStream_t>(stream)),
@@ -1252,19 +1179,6 @@ int azi_integrate1d_raw(const azi_plan* p, const void* raw, int32_t raw_dtype, v
         AZI_HIP(azi::launch_block(plan_block_args(p, raw, raw_dtype, true, I, W, U, empty),
                                   static_cast<hipStream_t>(stream)),
                 "blocked forward kernels");
-        return AZI_OK;
-    }
-    if (p && p->layout == AZI_LAYOUT_RECORD && p->tiling.stage == AZI_STAGE_FUSE &&
-        p->device >= 0) {
-        if (!raw) return fail(AZI_EINVAL, "raw must not be NULL");
-        if (!valid_raw_dtype(raw_dtype)) return fail(AZI_EINVAL, "unknown raw dtype");
-        DeviceGuard g(p->device);
-        if (g.err != hipSuccess) return hip_fail(g.err, "set device");
-        azi::RecordLaunch a = plan_record_args(p, nullptr, I, W, U, empty);
-        a.raw = raw;
-        a.raw_dtype = raw_dtype;
-        a.corr = (p->has_dark || p->has_norm) ? p->corr.p : nullptr;
-        AZI_HIP(azi::launch_record(a, static_cast<hipStream_t>(stream)), "record forward kernels");
         return AZI_OK;
     }
     if (p && p->layout == AZI_LAYOUT_BAND && p->tiling.stage == AZI_STAGE_FUSE &&
@@ -1319,7 +1233,7 @@ int azi_batch_create(azi_plan* const* plans, int32_t n, int32_t device, azi_batc
         if (plans[k]->dtype != plans[0]->dtype || plans[k]->accum != plans[0]->accum ||
             plans[k]->layout != plans[0]->layout)
             return fail(AZI_EINVAL, "plans of a batch must share dtype, accumulation and layout");
-    if (plans[0]->layout == AZI_LAYOUT_FUSED || plans[0]->layout == AZI_LAYOUT_RECORD)
+    if (plans[0]->layout == AZI_LAYOUT_FUSED)
         return fail(AZI_EINVAL, "batches take the pixel, ring, tile or band layout");
     }
     int count = 0;

@@ -161,31 +161,6 @@ struct BandMatrix {
     int32_t nslots = 0;
 };
 
-// Band records: bands of 4 bins as in the band layout, but each band holds
-// one record per (pixel, run of consecutive bins): a header word
-// (first row << 29 | (count - 1) << 27 | local pixel id) and `count`
-// coefficients, concatenated in record order.  A pixel is then read once
-// per band instead of once per entry.  Records of a band start on a multiple
-// of 64 (gaps are never read); cbase[q / 64] is the offset of the first
-// coefficient of record q's 64-record chunk, so a wavefront finds its
-// lanes' coefficients by a prefix sum of the counts.  Pieces cover whole
-// 64-record chunks of one band; slots and per-bin slot ranges as in the
-// band layout (BandPiece z0 / z1 are record indices).
-constexpr int32_t kRecRows = 4;
-struct RecordMatrix {
-    std::vector<BandPiece> pieces;
-    std::vector<int32_t> meta;     // per record (gaps hold 0)
-    std::vector<double> coef;      // per entry, record order
-    std::vector<int32_t> cbase;    // per 64-record chunk
-    std::vector<int32_t> bin_slot, bin_count;
-    int32_t nslots = 0;
-};
-// Appends one instance (CSC `m`, pixel ids below 2^27).  Pieces hold at most
-// piece_records records (a multiple of 64).  Returns false if the image has
-// 2^27 pixels or more or an array would reach 2^31 entries.
-bool build_records(const HostMatrix& m, int32_t piece_records, int64_t pix_off, int64_t bin_off,
-                   RecordMatrix& rm);
-
 // Appends one instance (CSC `m`) to `bm`.  Bands of R bins, pieces of at
 // most piece_nnz entries (cut on multiples of 4); entries start on a
 // multiple of 64 per instance.  Returns false if the image has 2^27 pixels

@@ -87,33 +87,6 @@ struct BandLaunch {
 
 hipError_t launch_band(const BandLaunch& a, hipStream_t s);
 
-// Band-record integration (k_brec over pieces of records, then
-// k_band_reduce for bins [b0, b1)); x, or raw + corr as in BandLaunch.
-struct RecordLaunch {
-    const BandPiece* pieces = nullptr;
-    int32_t npieces = 0;
-    const int32_t* meta = nullptr;
-    const int32_t* cbase = nullptr;
-    const void* coef = nullptr;
-    const int32_t* bin_slot = nullptr;
-    const int32_t* bin_count = nullptr;
-    int64_t b0 = 0, b1 = 0;
-    const void* x = nullptr;
-    const void* raw = nullptr;
-    int32_t raw_dtype = AZI_I32;
-    const void* corr = nullptr;
-    void* parts = nullptr;
-    void* I = nullptr;
-    void* W = nullptr;
-    void* U = nullptr;
-    double empty = 0.0;
-    int32_t grid = 0;
-    int32_t dtype = AZI_F64;
-    int32_t accum = AZI_ACC_F64;
-};
-
-hipError_t launch_record(const RecordLaunch& a, hipStream_t s);
-
 // pair[i] = (dark[i], 1 / norm[i]) in the storage type (0 and 1 where the
 // array is null): the per-pixel correction of the fused band gather.
 hipError_t launch_corr_pair(const void* dark, const void* norm, void* pair, int32_t dtype,

@@ -699,141 +699,6 @@ hipError_t stage_raw(const StageLaunch& a, hipStream_t s) {
     }
 }
 
-// Band records: one lane per record (pixel, run of consecutive bins of the
-// band): the pixel is gathered once (cast and corrected when kCorr, as in
-// k_band) and its coefficients go to the run's rows.  A wavefront takes 64
-// consecutive records; their coefficients are consecutive from the chunk's
-// cbase, each lane's offset being the prefix sum of the counts below it
-// (four ballots, counts being 1..4).
-template <class T, class Acc, class RawT, bool kCorr>
-__global__ __launch_bounds__(256) void k_brec(const BandPiece* __restrict__ pieces,
-                                              int32_t npieces,
-                                              const int32_t* __restrict__ meta,
-                                              const int32_t* __restrict__ cbase,
-                                              const T* __restrict__ coef,
-                                              const T* __restrict__ x,
-                                              Acc* __restrict__ parts,
-                                              const RawT* __restrict__ raw,
-                                              const typename Pair2<T>::type* __restrict__ corr) {
-    constexpr int BLOCK = 256, R = kRecRows;
-    constexpr int32_t kMask = (1 << kBandShift) - 1;
-    __shared__ Acc red[BLOCK / kWave][R];
-    const int tid = threadIdx.x;
-    const int wave = tid / kWave, lane = tid & (kWave - 1);
-    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
-    const int32_t g = blockIdx.x, Gd = gridDim.x;
-    int32_t t_begin, t_end, t_step;
-    if (Gd < 8) {
-        t_begin = g; t_end = npieces; t_step = Gd;
-    } else {
-        const int32_t xcd = g & 7, q = g >> 3, nq = (Gd - xcd + 7) >> 3;
-        const int32_t per = npieces >> 3, rem = npieces & 7;
-        const int32_t t0 = xcd * per + min(xcd, rem);
-        t_begin = t0 + q; t_end = t0 + per + (xcd < rem ? 1 : 0); t_step = nq;
-    }
-    for (int32_t ti = t_begin; ti < t_end; ti += t_step) {
-        const BandPiece pc = pieces[ti];
-        const T* xb = kCorr ? nullptr : x + pc.pix_off;
-        const RawT* rb = kCorr ? raw + pc.pix_off : nullptr;
-        const typename Pair2<T>::type* cb = (kCorr && corr) ? corr + pc.pix_off : nullptr;
-        Acc a[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) a[r].zero();
-        // chunks of 64 records; the loop bound is uniform over a wavefront
-        for (int32_t q0 = pc.z0 + wave * kWave; q0 < pc.z1; q0 += BLOCK) {
-            const int32_t q = q0 + lane;
-            const bool valid = q < pc.z1;
-            const int32_t mt = valid ? __builtin_nontemporal_load(meta + q) : 0;
-            const int cnt = valid ? ((mt >> 27) & 3) + 1 : 0;
-            const int off = __popcll(__ballot(cnt >= 1) & below) +
-                            __popcll(__ballot(cnt >= 2) & below) +
-                            __popcll(__ballot(cnt >= 3) & below) +
-                            __popcll(__ballot(cnt >= 4) & below);
-            const int32_t base = cbase[q0 >> 6] + off;
-            T xv = T(0);
-            T cv[R];
-#pragma unroll
-            for (int k = 0; k < R; ++k) cv[k] = k < cnt ? __builtin_nontemporal_load(coef + base + k) : T(0);
-            if (valid) {
-                const int32_t pix = mt & kMask;
-                if constexpr (kCorr) {
-                    T v = (T)rb[pix];
-                    if (cb) {
-                        const auto c = cb[pix];
-                        v = (v - c.x) * c.y;
-                    }
-                    xv = v;
-                } else {
-                    xv = xb[pix];
-                }
-            }
-            const int first = (mt >> 29) & 3;
-#pragma unroll
-            for (int k = 0; k < R; ++k) {
-                if (k < cnt) {
-                    const int row = first + k;
-#pragma unroll
-                    for (int r = 0; r < R; ++r)
-                        if (r == row) a[r].add(cv[k], xv);
-                }
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            group_reduce(a[r], kWave);
-            if (lane == 0) red[wave][r] = a[r];
-        }
-        __syncthreads();
-        if (tid < R) {
-            Acc sacc = red[0][tid];
-            for (int k = 1; k < BLOCK / kWave; ++k) sacc.merge(red[k][tid]);
-            parts[pc.slot0 + tid] = sacc;
-        }
-        __syncthreads();
-    }
-}
-
-template <class T, class Acc, class RawT, bool kCorr>
-hipError_t rec_launch(const RecordLaunch& a, hipStream_t s) {
-    const int grid = a.grid > 0 ? a.grid : a.npieces;
-    hipLaunchKernelGGL((k_brec<T, Acc, RawT, kCorr>), dim3(grid), dim3(256), 0, s, a.pieces,
-                       a.npieces, a.meta, a.cbase, static_cast<const T*>(a.coef),
-                       static_cast<const T*>(a.x), static_cast<Acc*>(a.parts),
-                       static_cast<const RawT*>(a.raw),
-                       static_cast<const typename Pair2<T>::type*>(a.corr));
-    return hipGetLastError();
-}
-
-template <class T, class Acc>
-hipError_t rec_impl(const RecordLaunch& a, hipStream_t s) {
-    if (a.npieces > 0) {
-        hipError_t e;
-        if (!a.raw) {
-            e = rec_launch<T, Acc, T, false>(a, s);
-        } else {
-            switch (a.raw_dtype) {
-                case AZI_I16: e = rec_launch<T, Acc, int16_t, true>(a, s); break;
-                case AZI_U16: e = rec_launch<T, Acc, uint16_t, true>(a, s); break;
-                case AZI_I32: e = rec_launch<T, Acc, int32_t, true>(a, s); break;
-                case AZI_U32: e = rec_launch<T, Acc, uint32_t, true>(a, s); break;
-                case AZI_F32: e = rec_launch<T, Acc, float, true>(a, s); break;
-                case AZI_F64: e = rec_launch<T, Acc, double, true>(a, s); break;
-                default: return hipErrorInvalidValue;
-            }
-        }
-        if (e != hipSuccess) return e;
-    }
-    const int64_t nb = a.b1 - a.b0;
-    if (nb > 0) {
-        hipLaunchKernelGGL((k_band_reduce<T, Acc>), dim3((unsigned)((nb + 3) / 4)), dim3(256), 0,
-                           s, a.bin_slot, a.bin_count, kRecRows, a.b0, a.b1,
-                           static_cast<const Acc*>(a.parts), static_cast<T*>(a.I),
-                           static_cast<T*>(a.W), static_cast<T*>(a.U), a.empty);
-        return hipGetLastError();
-    }
-    return hipSuccess;
-}
-
 template <class T, class Acc, int BLOCK, int R>
 hipError_t band_launch(const BandLaunch& a, hipStream_t s) {
     const int grid = a.grid > 0 ? a.grid : a.npieces;
@@ -1027,12 +892,6 @@ hipError_t launch_corr_pair(const void* dark, const void* norm, void* pair, int3
                            static_cast<const float*>(dark), static_cast<const float*>(norm),
                            static_cast<float2*>(pair), n);
     return hipGetLastError();
-}
-
-hipError_t launch_record(const RecordLaunch& a, hipStream_t s) {
-    if (a.dtype == AZI_F64) return rec_impl<double, AccF64>(a, s);
-    if (a.accum == AZI_ACC_KAHAN32) return rec_impl<float, AccK32>(a, s);
-    return rec_impl<float, AccF64>(a, s);
 }
 
 hipError_t launch_band(const BandLaunch& a, hipStream_t s) {

@@ -446,84 +446,6 @@ bool build_bands(const HostMatrix& m, int32_t R, int32_t piece_nnz, int64_t pix_
     return true;
 }
 
-bool build_records(const HostMatrix& m, int32_t piece_records, int64_t pix_off, int64_t bin_off,
-                   RecordMatrix& rm) {
-    if (m.npix >= ((int64_t)1 << kBandShift)) return false;
-    const int32_t R = kRecRows;
-    const int32_t npt = m.npt;
-    const int32_t nbands = (npt + R - 1) / R;
-    // records per band: a pixel's entries in a band split into runs of
-    // consecutive bins
-    std::vector<int64_t> nrec((size_t)nbands + 1, 0), ncoef((size_t)nbands + 1, 0);
-    auto for_runs = [&](int64_t p, auto&& fn) {
-        int32_t k = m.colptr[p];
-        const int32_t k1 = m.colptr[p + 1];
-        while (k < k1) {
-            const int32_t band = m.rowidx[k] / R;
-            int32_t e = k + 1;
-            while (e < k1 && m.rowidx[e] / R == band && m.rowidx[e] == m.rowidx[e - 1] + 1) ++e;
-            fn(band, k, e);
-            k = e;
-        }
-    };
-    for (int64_t p = 0; p < m.npix; ++p)
-        for_runs(p, [&](int32_t band, int32_t k, int32_t e) {
-            nrec[band]++;
-            ncoef[band] += e - k;
-        });
-    // record and coefficient starts: records of a band on a multiple of 64
-    const int64_t rbase = (int64_t)rm.meta.size(), cbase0 = (int64_t)rm.coef.size();
-    std::vector<int64_t> rstart((size_t)nbands + 1), cstart((size_t)nbands + 1);
-    int64_t rq = rbase, cq = cbase0;
-    for (int32_t b = 0; b < nbands; ++b) {
-        rstart[b] = rq;
-        cstart[b] = cq;
-        rq += (nrec[b] + 63) / 64 * 64;
-        cq += ncoef[b];
-    }
-    rstart[nbands] = rq;
-    cstart[nbands] = cq;
-    if (rq + 64 >= (int64_t)INT32_MAX || cq + 64 >= (int64_t)INT32_MAX) return false;
-    rm.meta.resize((size_t)rq, 0);
-    rm.coef.resize((size_t)cq, 0.0);
-    rm.cbase.resize((size_t)(rq / 64), 0);
-    std::vector<int64_t> rcur(rstart.begin(), rstart.end() - 1), ccur(cstart.begin(), cstart.end() - 1);
-    for (int64_t p = 0; p < m.npix; ++p)
-        for_runs(p, [&](int32_t band, int32_t k, int32_t e) {
-            const int64_t q = rcur[band]++;
-            const int64_t c = ccur[band];
-            if (q % 64 == 0) rm.cbase[(size_t)(q / 64)] = (int32_t)c;
-            const int32_t first = m.rowidx[k] - band * R;
-            rm.meta[(size_t)q] = (first << 29) | ((e - k - 1) << 27) | (int32_t)p;
-            for (int32_t j = k; j < e; ++j) rm.coef[(size_t)(ccur[band]++)] = m.cdata[j];
-            (void)c;
-        });
-    // pieces: whole 64-record chunks of one band
-    if (rm.bin_slot.size() < (size_t)(bin_off + npt)) {
-        rm.bin_slot.resize(bin_off + npt, 0);
-        rm.bin_count.resize(bin_off + npt, 0);
-    }
-    const int64_t per = std::max<int64_t>(64, piece_records / 64 * 64);
-    for (int32_t band = 0; band < nbands; ++band) {
-        const int32_t bin0 = band * R;
-        const int32_t nrows = std::min(R, npt - bin0);
-        const int64_t z0 = rstart[band], z1 = rstart[band] + nrec[band];
-        const int64_t len = z1 - z0;
-        const int32_t pieces = len > 0 ? (int32_t)((len + per - 1) / per) : 1;
-        for (int32_t r = 0; r < nrows; ++r) {
-            rm.bin_slot[bin_off + bin0 + r] = rm.nslots + r;
-            rm.bin_count[bin_off + bin0 + r] = pieces;
-        }
-        for (int32_t k = 0; k < pieces; ++k) {
-            const int64_t a = z0 + k * per, b = std::min(z1, a + per);
-            rm.pieces.push_back(BandPiece{(int32_t)a, (int32_t)std::max(a, b), (int32_t)(bin_off + bin0),
-                                          nrows, rm.nslots, 0, pix_off});
-            rm.nslots += R;
-        }
-    }
-    return true;
-}
-
 void band_pieces(const int64_t* start, int32_t nbands, int32_t npt, int32_t R, int32_t piece_nnz,
                  int64_t base, int64_t pix_off, int64_t bin_off, BandMatrix& bm) {
     if (bm.bin_slot.size() < (size_t)(bin_off + npt)) {

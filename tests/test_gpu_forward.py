@@ -71,7 +71,7 @@ def tiling_kw(t):
     return dict(zip(("tile_nnz", "block", "variant", "grid", "band", "stage"), t))
 
 
-@pytest.mark.parametrize("layout", ["ring", "pixel", "tile", "band", "record"])
+@pytest.mark.parametrize("layout", ["ring", "pixel", "tile", "band"])
 @pytest.mark.parametrize("tiling", TILINGS, ids=lambda t: "t{}b{}v{}g{}n{}s{}".format(*t))
 @pytest.mark.parametrize("g", GEOMS, ids=lambda g: f"{g[0]}x{g[1]}-{g[5]}-{g[6]}-{g[4]}")
 def test_forward_f64(g, tiling, layout, dev):
@@ -133,8 +133,7 @@ def test_correction_map_bit_exact(raw_dtype, dev):
 @pytest.mark.parametrize("layout,stage", [("ring", "tile"), ("ring", "gather"),
                                           ("ring", "scatter"), ("pixel", "tile"),
                                           ("tile", "tile"), ("band", "tile"),
-                                          ("band", "fuse"), ("ring", "fuse"),
-                                          ("record", "fuse"), ("record", "gather")])
+                                          ("band", "fuse"), ("ring", "fuse")])
 def test_raw_pipeline_with_corrections(layout, stage, dev):
     say("raw pipeline with corrections", layout, stage)
     az = azint()
@@ -155,7 +154,7 @@ def test_raw_pipeline_with_corrections(layout, stage, dev):
     assert np.array_equal(xd.cpu().numpy(), x)
     out2 = plan.integrate(xd)
     torch.cuda.synchronize()
-    if layout in ("band", "record") and stage == "fuse":
+    if layout == "band" and stage == "fuse":
         # the fused gather multiplies by the reciprocal of norm: one rounding
         # per pixel away from the corrected image's quotient
         check(out2, m, x, TOL64, what="corrected image")
@@ -164,7 +163,7 @@ def test_raw_pipeline_with_corrections(layout, stage, dev):
             assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("layout", ["ring", "pixel", "tile", "band", "record"])
+@pytest.mark.parametrize("layout", ["ring", "pixel", "tile", "band"])
 @pytest.mark.parametrize("accum", ["f64", "kahan32"])
 @pytest.mark.parametrize("tiling", [(2048, 256, 2, 0, 1, 2), (64, 64, 0, 0, 16, 0),
                                     (512, 512, 3, 0, 16, 1), (1024, 128, 1, 256, 4, 2),
