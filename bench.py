@@ -90,9 +90,11 @@ def spmv_bytes(nnz, npix, npt, es):
 
 
 def bwd_bytes(nnz, npix, npt, es):
-    """Adjoint: CSC coefficients and bin ids, column pointers, the gradient
-    written, U and the upstream gradient read."""
-    return nnz * (es + 4) + (npix + 1) * 4 + npix * es + 2 * npt * es
+    """Adjoint of a one-dimensional plan: CSC coefficients, column pointers
+    and one first-bin word per pixel (a pixel's bins are consecutive, so no
+    per-entry bin ids are needed), the gradient written, U and the upstream
+    gradient read."""
+    return nnz * es + (npix + 1) * 4 + npix * 4 + npix * es + 2 * npt * es
 
 
 def build_plans(insts, dtype, az, threads=16):

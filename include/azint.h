@@ -314,8 +314,10 @@ int64_t azi_plan_device_bytes(const azi_plan* plan);
  * Per-pixel correction arrays of Section 6.4 (device pointers of the storage
  * type, npix values each, or NULL for "absent").  The plan keeps a copy of
  * dark and of norm = (flat * solid) * polar, formed once here, so the
- * per-frame map is x = (raw - dark) / norm.  Passing all NULL removes the
- * corrections.  Runs on `stream` and synchronises it.  Needs an uploaded plan.
+ * per-frame map is x = (raw - dark) / norm; with the band layout and
+ * AZI_STAGE_FUSE it also keeps the (dark, 1 / norm) pairs its gather reads.
+ * Passing all NULL removes the corrections.  Runs on `stream` and
+ * synchronises it.  Needs an uploaded plan.
  */
 int azi_plan_set_corrections(azi_plan* plan, const void* dark, const void* flat,
                              const void* solid, const void* polar, void* stream);

@@ -145,6 +145,32 @@ std::vector<char> to_storage(const double* src, int64_t n, int64_t n_alloc, int3
     return out;
 }
 
+// First bin of every pixel when each pixel's entries lie in consecutive
+// bins (every one-dimensional matrix the builder makes); empty otherwise.
+// The adjoint then reads one word per pixel instead of one per entry.
+std::vector<int32_t> consecutive_first(const azi::HostMatrix& m) {
+    std::vector<int32_t> first((size_t)m.npix, 0);
+    for (int64_t p = 0; p < m.npix; ++p) {
+        const int32_t k0 = m.colptr[p], k1 = m.colptr[p + 1];
+        if (k0 == k1) continue;
+        first[p] = m.rowidx[k0];
+        for (int32_t k = k0 + 1; k < k1; ++k)
+            if (m.rowidx[k] != m.rowidx[k0] + (k - k0)) return {};
+    }
+    return first;
+}
+
+// Uploads consecutive_first(m) to buf, or releases buf when the matrix has
+// a pixel with non-consecutive bins.
+int upload_first(const azi::HostMatrix& m, int device, DevBuf& buf) {
+    buf.release();
+    if (m.two_d) return AZI_OK;
+    std::vector<int32_t> first = consecutive_first(m);
+    if (first.empty() && m.npix > 0) return AZI_OK;
+    AZI_HIP(buf.upload(first.data(), first.size() * 4, device), "first bins");
+    return AZI_OK;
+}
+
 }  // namespace
 
 struct azi_plan {
@@ -158,7 +184,7 @@ struct azi_plan {
     DevBuf rowptr, indices, data, colptr, rowidx, cdata, tiles, splits, parts, dark, norm, xwork,
         vwork, order, dark_r, norm_r, pos, stiles, lidx, dest, btiles, brows, blp, bcoef, bin_ptr,
         bparts, npieces_buf, npacked, ncoef, bin_slot, bin_count, nparts_buf, ftiles, fslots,
-        fbin_ptr, fparts, corr;
+        fbin_ptr, fparts, corr, cfirst;
     int32_t nstiles = 0, nbtiles = 0, npieces = 0, band_rows = 8, nftiles = 0;
     int32_t ntiles = 0, nsplits = 0, nparts = 0;
     bool has_dark = false, has_norm = false;
@@ -175,7 +201,7 @@ struct azi_batch {
     int32_t ntiles = 0, nsplits = 0, nparts = 0;
     DevBuf rp, indices, data, colptr, rowidx, cdata, tiles, splits, parts, vwork, order, xwork, pos,
         stiles, lidx, dest, btiles, brows, blp, bcoef, bin_ptr, bparts, npieces_buf, npacked, ncoef,
-        bin_slot, bin_count, nparts_buf;
+        bin_slot, bin_count, nparts_buf, cfirst;
     int32_t nbtiles = 0, npieces = 0, band_rows = 8;
     std::vector<int64_t> cz_off;     // CSC entries of instance k
     std::vector<int64_t> piece_off;  // band pieces of instance k
@@ -740,6 +766,8 @@ int plan_build_device(azi_plan* p, int32_t npt, const double* range2, int device
             rc = download(m.data, p->dtype == AZI_F64 ? p->data.p : data64.p, nnz, s);
         if (rc != AZI_OK) return rc;
         AZI_HIP(hipStreamSynchronize(s), "download the matrix");
+        rc = upload_first(m, device, p->cfirst);
+        if (rc != AZI_OK) return rc;
     } catch (const std::bad_alloc&) {
         return fail(AZI_ENOMEM, "out of host memory for the matrix copy");
     }
@@ -966,6 +994,8 @@ int azi_plan_upload(azi_plan* p, int32_t device) {
             AZI_HIP(p->rowptr.upload(p->m.indptr.data(), p->m.indptr.size() * 4, device), "indptr");
             AZI_HIP(p->colptr.upload(p->m.colptr.data(), p->m.colptr.size() * 4, device), "colptr");
             AZI_HIP(p->rowidx.upload(p->m.rowidx.data(), (size_t)nnz * 4, device), "rowidx");
+            const int rcf = upload_first(p->m, device, p->cfirst);
+            if (rcf != AZI_OK) return rcf;
             std::vector<char> cd = to_storage(p->m.cdata.data(), nnz, nnz, p->dtype);
             AZI_HIP(p->cdata.upload(cd.data(), cd.size(), device), "cdata");
         } catch (const std::bad_alloc&) {
@@ -1003,7 +1033,7 @@ int azi_plan_upload(azi_plan* p, int32_t device) {
 
 int64_t azi_plan_device_bytes(const azi_plan* p) {
     if (!p) return 0;
-    const DevBuf* bufs[] = {&p->ftiles, &p->fslots, &p->fbin_ptr, &p->fparts, &p->corr,
+    const DevBuf* bufs[] = {&p->ftiles, &p->fslots, &p->fbin_ptr, &p->fparts, &p->corr, &p->cfirst,
                             &p->rowptr, &p->indices, &p->data, &p->colptr, &p->rowidx,
                             &p->cdata, &p->tiles, &p->splits, &p->parts, &p->dark,
                             &p->norm, &p->xwork, &p->vwork, &p->order, &p->dark_r,
@@ -1211,6 +1241,7 @@ int azi_integrate1d_backward(const azi_plan* p, const void* U, const void* gI, c
     azi::BackwardLaunch a;
     a.colptr = p->colptr.as<int32_t>();
     a.rowidx = p->rowidx.as<int32_t>();
+    a.first = p->cfirst.as<int32_t>();
     a.cdata = p->cdata.p;
     a.U = U;
     a.gI = gI;
@@ -1358,6 +1389,21 @@ int azi_batch_create(azi_plan* const* plans, int32_t n, int32_t device, azi_batc
         colptr[b->npix] = (int32_t)b->nnz;
         AZI_HIP(b->colptr.upload(colptr.data(), colptr.size() * 4, device), "colptr");
         AZI_HIP(b->rowidx.upload(rowidx.data(), rowidx.size() * 4, device), "rowidx");
+        // first bins (global) when every instance has consecutive bins per pixel
+        b->cfirst.release();
+        std::vector<int32_t> first;
+        for (int32_t k = 0; k < n; ++k) {
+            const azi::HostMatrix& m = plans[k]->m;
+            std::vector<int32_t> f = m.two_d ? std::vector<int32_t>() : consecutive_first(m);
+            if (f.empty() && m.npix > 0) {
+                first.clear();
+                break;
+            }
+            for (int32_t& v : f) v += (int32_t)b->bin_off[k];
+            first.insert(first.end(), f.begin(), f.end());
+        }
+        if ((int64_t)first.size() == b->npix)
+            AZI_HIP(b->cfirst.upload(first.data(), first.size() * 4, device), "first bins");
         AZI_HIP(b->cdata.upload(cdat.data(), (size_t)b->nnz * es, device), "cdata");
         AZI_HIP(b->vwork.alloc((size_t)b->npt * 8, device), "work vector");
         std::vector<std::vector<int32_t>> store;
@@ -1679,6 +1725,7 @@ int azi_batch_backward(azi_batch* b, const void* U, const void* gI, const void* 
     azi::BackwardLaunch a;
     a.colptr = b->colptr.as<int32_t>();
     a.rowidx = b->rowidx.as<int32_t>();
+    a.first = b->cfirst.as<int32_t>();
     a.cdata = b->cdata.p;
     a.U = U;
     a.gI = gI;

@@ -35,6 +35,8 @@ hipError_t launch_forward(const ForwardLaunch& a, hipStream_t s);
 struct BackwardLaunch {
     const int32_t* colptr = nullptr;   // npix + 1 (global nnz positions)
     const int32_t* rowidx = nullptr;   // global bin ids
+    const int32_t* first = nullptr;    // when set: each pixel's bins are consecutive from
+                                       // first[p] (rowidx then unused)
     const void* cdata = nullptr;       // storage type
     const void* U = nullptr;           // forward U, storage type
     const void* gI = nullptr;          // may be null

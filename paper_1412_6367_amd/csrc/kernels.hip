@@ -1,22 +1,30 @@
 // HIP kernels for gfx950 (CDNA4): the per-frame hot path of azimuthal
 // integration.
 //
-//   k_spmv     gather-form sparse product of Section 5.2: every output bin
-//              reads the pixels that feed it from the CSR (Section 5.2.1) and
-//              forms W = sum c*x and U = sum c in one pass, then I = W / U.
-//              Work is cut into tiles of bounded nonzero count (whole short
-//              rows, or pieces of a long row); the sums of a piece go to a
-//              partial slot and k_fixup adds the pieces of a row in order, so
-//              results are deterministic and need no floating-point atomics.
-//   k_fixup    finishes rows that were split over several tiles.
-//   k_correct  cast + correction map of Section 6.4.
-//   k_norm     (flat * solid) * polar, formed once per correction set.
+//   k_band     the default integration (band layout): bands of R bins whose
+//              entries are ordered by pixel, so a wavefront gathers nearly
+//              consecutive pixels of the row-major image; R lane-private
+//              accumulators per lane; the partial sums of each piece go to
+//              slots that k_band_reduce adds in piece order.  Its raw-frame
+//              form casts and corrects every pixel it gathers.
+//   k_spmv     gather-form sparse product of Section 5.2 on the CSR of
+//              Section 5.2.1 (pixel and ring layouts): every output bin
+//              reads the pixels that feed it and forms W = sum c*x and
+//              U = sum c in one pass, then I = W / U.  Work is cut into tiles
+//              of bounded nonzero count (whole short rows, or pieces of a
+//              long row); k_fixup adds the pieces of a row in order.
+//   k_block    the tile layout: image tiles staged in LDS, per-(tile, bin)
+//              partials added by k_block_reduce.
+//   k_correct  cast + correction map of Section 6.4; k_stage_* the same
+//              into ring order; k_norm (flat * solid) * polar and
+//              k_corr_pair (dark, 1 / norm), formed once per correction set.
 //   k_prep_v / k_csc_bwd   adjoint: gx_p = sum_b A_bp (gI_b / U_b + gW_b),
 //              one thread per pixel over its pixel-major (CSC) entries.
 //
-// Accumulation: double for either storage type (AZI_ACC_F64), or float with
-// Kahan compensation (AZI_ACC_KAHAN32, Section 5.2.2), whose per-lane
-// (sum, compensation) pairs are merged across lanes with Knuth's TwoSum.
+// Every sum has a fixed order (no floating-point atomics).  Accumulation:
+// double for either storage type (AZI_ACC_F64), or float with Kahan
+// compensation (AZI_ACC_KAHAN32, Section 5.2.2), whose per-lane (sum,
+// compensation) pairs are merged across lanes with Knuth's TwoSum.
 #include <hip/hip_runtime.h>
 
 #include "accum.h"
@@ -24,8 +32,6 @@
 
 namespace azi {
 namespace {
-
-
 
 // ---------------------------------------------------------------------------
 // Loads
@@ -557,21 +563,25 @@ __global__ void k_prep_v(const T* __restrict__ U, const T* __restrict__ gI,
 // pixel has a handful of entries (2.8 on average with bounding-box
 // splitting); the first four are loaded before any is used, so a lane keeps
 // its loads in flight instead of waiting entry by entry.  Consecutive lanes
-// read consecutive stretches of the entry arrays.
-template <class T>
+// read consecutive stretches of the entry arrays.  With kFirst the bins of
+// a pixel are consecutive and given by the pixel's first bin alone (one
+// word per pixel instead of one per entry).
+template <class T, bool kFirst>
 __global__ void k_csc_bwd(const int32_t* __restrict__ colptr, const int32_t* __restrict__ rowidx,
-                          const T* __restrict__ cdata, const double* __restrict__ v,
-                          const T* __restrict__ norm, T* __restrict__ gx, int64_t npix) {
+                          const int32_t* __restrict__ first, const T* __restrict__ cdata,
+                          const double* __restrict__ v, const T* __restrict__ norm,
+                          T* __restrict__ gx, int64_t npix) {
     const int64_t p = xcd_block(blockIdx.x, gridDim.x) * (int64_t)blockDim.x + threadIdx.x;
     if (p >= npix) return;
     const int32_t k0 = colptr[p], k1 = colptr[p + 1];
+    const int32_t b0 = kFirst ? first[p] : 0;
     T c[4];
     int32_t b[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         if (k0 + j < k1) {
             c[j] = cdata[k0 + j];
-            b[j] = rowidx[k0 + j];
+            b[j] = kFirst ? b0 + j : rowidx[k0 + j];
         }
     }
     double vb[4];
@@ -581,7 +591,8 @@ __global__ void k_csc_bwd(const int32_t* __restrict__ colptr, const int32_t* __r
 #pragma unroll
     for (int j = 0; j < 4; ++j)
         if (k0 + j < k1) acc = __fma_rn((double)c[j], vb[j], acc);
-    for (int32_t k = k0 + 4; k < k1; ++k) acc = __fma_rn((double)cdata[k], v[rowidx[k]], acc);
+    for (int32_t k = k0 + 4; k < k1; ++k)
+        acc = __fma_rn((double)cdata[k], v[kFirst ? b0 + (k - k0) : rowidx[k]], acc);
     if (norm) acc = acc / (double)norm[p];
     gx[p] = (T)acc;
 }
@@ -836,9 +847,14 @@ hipError_t backward_impl(const BackwardLaunch& a, hipStream_t s) {
     if (a.npix > 0) {
         const int64_t blocks = (a.npix + 255) / 256;
         if (blocks > INT32_MAX) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_csc_bwd<T>), dim3((unsigned)blocks), dim3(256), 0, s,
-                           a.colptr, a.rowidx, static_cast<const T*>(a.cdata), a.v,
-                           static_cast<const T*>(a.norm), static_cast<T*>(a.gx), a.npix);
+        if (a.first)
+            hipLaunchKernelGGL((k_csc_bwd<T, true>), dim3((unsigned)blocks), dim3(256), 0, s,
+                               a.colptr, a.rowidx, a.first, static_cast<const T*>(a.cdata), a.v,
+                               static_cast<const T*>(a.norm), static_cast<T*>(a.gx), a.npix);
+        else
+            hipLaunchKernelGGL((k_csc_bwd<T, false>), dim3((unsigned)blocks), dim3(256), 0, s,
+                               a.colptr, a.rowidx, a.first, static_cast<const T*>(a.cdata), a.v,
+                               static_cast<const T*>(a.norm), static_cast<T*>(a.gx), a.npix);
         return hipGetLastError();
     }
     return hipSuccess;
