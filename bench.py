@@ -105,11 +105,12 @@ def build_plans(insts, dtype, az, threads=16):
         return list(ex.map(mk, insts))
 
 
-def raw_bytes(nnz, npix, npt, es):
+def raw_bytes(nnz, npix, npt, es, cb):
     """Algorithmic bytes of one raw-frame integration with the correction
-    in the gather: the matrix, the raw int32 frame, dark and 1/norm (one
-    pair per pixel), row pointers, three outputs."""
-    return nnz * (es + 4) + npix * (4 + 2 * es) + (npt + 1) * 4 + 3 * npt * es
+    in the gather: the matrix, the raw int32 frame, dark and 1/norm (cb
+    bytes per pixel: a pair of the storage type, or 12 for float64 with
+    dark values that are floats), row pointers, three outputs."""
+    return nnz * (es + 4) + npix * (4 + cb) + (npt + 1) * 4 + 3 * npt * es
 
 
 def pipeline_line(az, torch, np, synth, dev, dtype, steps, warmup, frames_n=4):
@@ -151,7 +152,8 @@ def pipeline_line(az, torch, np, synth, dev, dtype, steps, warmup, frames_n=4):
     step_ms = mean_event_ms(ev)
     es = 8 if dtype == "f64" else 4
     nnz = plan.nnz
-    rb = raw_bytes(nnz, g.npix, inst.npt, es)
+    cb = plan.correction_bytes()
+    rb = raw_bytes(nnz, g.npix, inst.npt, es, cb)
     # two-pass breakdown: correction kernel, then integration of the image
     pairs = []
     for k in range(max(steps // 4, 10)):
@@ -171,6 +173,7 @@ def pipeline_line(az, torch, np, synth, dev, dtype, steps, warmup, frames_n=4):
     line = dict(npix=g.npix, npt=inst.npt, nnz=nnz, layout=plan.layout(),
                 tiling=plan.tiling(), ms_per_step=ms_step,
                 elements_per_s=g.npix / (ms_step * 1e-3),
+                correction_bytes_per_pixel=cb,
                 step_ms=step_ms, step_bytes=rb, step_gbs=rb / (step_ms * 1e6),
                 step_frac=rb / (step_ms * 1e6) / HBM_PEAK_GBS,
                 two_pass_correct_ms=corr_ms, two_pass_correct_gbs=corr_b / (corr_ms * 1e6),
@@ -194,7 +197,7 @@ def cold_line(torch, plan, outs, frame, npix, npt, nnz, es, reps=20):
         pairs.append((a, b))
     torch.cuda.synchronize()
     ms = mean_event_ms(pairs)
-    by = raw_bytes(nnz, npix, npt, es)
+    by = raw_bytes(nnz, npix, npt, es, plan.correction_bytes())
     return dict(step_ms=ms, step_gbs=by / (ms * 1e6),
                 step_frac=by / (ms * 1e6) / HBM_PEAK_GBS)
 

@@ -316,11 +316,20 @@ int64_t azi_plan_device_bytes(const azi_plan* plan);
  * dark and of norm = (flat * solid) * polar, formed once here, so the
  * per-frame map is x = (raw - dark) / norm; with the band layout and
  * AZI_STAGE_FUSE it also keeps the (dark, 1 / norm) pairs its gather reads.
+ * A float64 plan whose dark values are all exactly floats keeps them as
+ * 12-byte records (float dark, double 1 / norm) instead of 16-byte pairs:
+ * the results are the same bits, the gather reads 4 bytes less per pixel.
  * Passing all NULL removes the corrections.  Runs on `stream` and
  * synchronises it.  Needs an uploaded plan.
  */
 int azi_plan_set_corrections(azi_plan* plan, const void* dark, const void* flat,
                              const void* solid, const void* polar, void* stream);
+
+/* Bytes per pixel of the per-pixel correction the band gather reads (16 or
+ * 8 for pairs of float64 / float32, 12 for the records above), or 0 when the
+ * raw-frame path keeps no such array (no corrections, or another layout or
+ * stage).  0 for a NULL plan. */
+int32_t azi_plan_correction_bytes(const azi_plan* plan);
 
 /*
  * Cast and correction map (Section 6.4): x[p] = (T(raw[p]) - dark[p]) / norm[p]

@@ -99,6 +99,7 @@ _SIGS = {
     "azi_plan_get_layout": (ctypes.c_int, [_P, _P]),
     "azi_plan_upload": (ctypes.c_int, [_P, _I32]),
     "azi_plan_device_bytes": (_I64, [_P]),
+    "azi_plan_correction_bytes": (_I32, [_P]),
     "azi_plan_set_corrections": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "azi_correct": (ctypes.c_int, [_P, _P, _I32, _P, _P]),
     "azi_integrate1d": (ctypes.c_int, [_P, _P, _P, _P, _P, _D, _P]),
@@ -352,6 +353,11 @@ class Plan:
 
     def device_bytes(self):
         return int(lib().azi_plan_device_bytes(self._h))
+
+    def correction_bytes(self):
+        """Bytes per pixel of the correction the raw-frame band gather reads
+        (0 when there is none)."""
+        return int(lib().azi_plan_correction_bytes(self._h))
 
     def set_corrections(self, dark=None, flat=None, solid=None, polar=None, stream=None):
         for name, t in (("dark", dark), ("flat", flat), ("solid", solid), ("polar", polar)):

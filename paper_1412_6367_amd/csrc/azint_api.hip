@@ -186,6 +186,7 @@ struct azi_plan {
         bparts, npieces_buf, npacked, ncoef, bin_slot, bin_count, nparts_buf, ftiles, fslots,
         fbin_ptr, fparts, corr, cfirst;
     int32_t nstiles = 0, nbtiles = 0, npieces = 0, band_rows = 8, nftiles = 0;
+    int32_t corr_kind = azi::kCorrPair;
     int32_t ntiles = 0, nsplits = 0, nparts = 0;
     bool has_dark = false, has_norm = false;
 };
@@ -445,12 +446,35 @@ int plan_upload_fused(azi_plan* p) {
 }
 
 // (dark, 1 / norm) pairs for the band kernel's fused gather, formed when
-// the plan integrates raw frames with AZI_STAGE_FUSE and has corrections.
+// the plan integrates raw frames with AZI_STAGE_FUSE and has corrections;
+// 12-byte records instead when the plan is float64 and its dark values are
+// all floats.
 int plan_corr_pair(azi_plan* p, hipStream_t s) {
     p->corr.release();
+    p->corr_kind = azi::kCorrPair;
     if (p->layout != AZI_LAYOUT_BAND || p->tiling.stage != AZI_STAGE_FUSE ||
         !(p->has_dark || p->has_norm))
         return AZI_OK;
+    if (p->dtype == AZI_F64 && p->has_dark) {
+        // float64 dark values that are all floats: 12-byte records
+        DevBuf flag;
+        int32_t h = 1;
+        AZI_HIP(flag.alloc(4, p->device), "dark check");
+        AZI_HIP(azi::launch_dark_is_float(p->dark.as<double>(), p->m.npix, flag.as<int32_t>(), s),
+                "dark check");
+        AZI_HIP(hipMemcpyAsync(&h, flag.p, 4, hipMemcpyDeviceToHost, s), "dark check");
+        AZI_HIP(hipStreamSynchronize(s), "dark check");
+        if (h == 0) {
+            AZI_HIP(p->corr.alloc((size_t)p->m.npix * sizeof(azi::Corr12), p->device),
+                    "correction records");
+            AZI_HIP(azi::launch_corr_record12(p->dark.as<double>(),
+                                              p->has_norm ? p->norm.as<double>() : nullptr,
+                                              p->corr.p, p->m.npix, s), "correction records");
+            AZI_HIP(hipStreamSynchronize(s), "correction records");
+            p->corr_kind = azi::kCorrRecord12;
+            return AZI_OK;
+        }
+    }
     AZI_HIP(p->corr.alloc((size_t)p->m.npix * 2 * elem_size(p->dtype), p->device),
             "correction pairs");
     AZI_HIP(azi::launch_corr_pair(p->has_dark ? p->dark.p : nullptr,
@@ -1031,6 +1055,12 @@ int azi_plan_upload(azi_plan* p, int32_t device) {
     return rc;
 }
 
+int32_t azi_plan_correction_bytes(const azi_plan* p) {
+    if (!p || !p->corr.p) return 0;
+    if (p->corr_kind == azi::kCorrRecord12) return (int32_t)sizeof(azi::Corr12);
+    return (int32_t)(2 * elem_size(p->dtype));
+}
+
 int64_t azi_plan_device_bytes(const azi_plan* p) {
     if (!p) return 0;
     const DevBuf* bufs[] = {&p->ftiles, &p->fslots, &p->fbin_ptr, &p->fparts, &p->corr, &p->cfirst,
@@ -1222,6 +1252,7 @@ int azi_integrate1d_raw(const azi_plan* p, const void* raw, int32_t raw_dtype, v
         a.raw = raw;
         a.raw_dtype = raw_dtype;
         a.corr = (p->has_dark || p->has_norm) ? p->corr.p : nullptr;
+        a.corr_kind = p->corr_kind;
         AZI_HIP(azi::launch_band(a, static_cast<hipStream_t>(stream)), "band forward kernels");
         return AZI_OK;
     }

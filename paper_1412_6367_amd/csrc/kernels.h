@@ -58,6 +58,16 @@ hipError_t launch_correct(const void* raw, int32_t raw_dtype, const int32_t* ord
                           const void* dark, const void* norm, void* x, int32_t dtype,
                           int64_t n, hipStream_t s);
 
+// Per-pixel correction of the raw-frame band gather: (dark, 1 / norm) as a
+// pair of the storage type, or, for float64 plans whose dark values are all
+// floats, as a 12-byte record (4 bytes less per pixel, same results).
+constexpr int32_t kCorrPair = 0, kCorrRecord12 = 1;
+struct Corr12 {
+    float dark;
+    uint32_t inv_lo, inv_hi;  // the two halves of the double 1 / norm
+};
+static_assert(sizeof(Corr12) == 12, "12-byte correction record");
+
 // Band integration: k_band over pieces [0, npieces) fills the partial slots,
 // then k_band_reduce finishes bins [b0, b1).  x is the corrected image.
 struct BandLaunch {
@@ -76,6 +86,7 @@ struct BandLaunch {
     const void* raw = nullptr;
     int32_t raw_dtype = AZI_I32;
     const void* corr = nullptr;
+    int32_t corr_kind = kCorrPair;     // kCorrRecord12: Corr12 records (float64 only)
     void* parts = nullptr;
     void* I = nullptr;
     void* W = nullptr;
@@ -93,6 +104,12 @@ hipError_t launch_band(const BandLaunch& a, hipStream_t s);
 // array is null): the per-pixel correction of the fused band gather.
 hipError_t launch_corr_pair(const void* dark, const void* norm, void* pair, int32_t dtype,
                             int64_t n, hipStream_t s);
+// *flag (device int32) = 1 if some dark[i] is not exactly a float, else 0.
+hipError_t launch_dark_is_float(const double* dark, int64_t n, int32_t* flag, hipStream_t s);
+// rec[i] = Corr12{(float)dark[i], 1 / norm[i] or 1}; dark must be non-null
+// and hold floats only (launch_dark_is_float).
+hipError_t launch_corr_record12(const double* dark, const double* norm, void* rec, int64_t n,
+                                hipStream_t s);
 
 // Blocked (image-tile) integration: k_block over tiles [0, ntiles) fills the
 // partial slots, then k_block_reduce finishes bins [b0, b1).  `img` is the

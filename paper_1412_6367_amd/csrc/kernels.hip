@@ -27,6 +27,8 @@
 // compensation) pairs are merged across lanes with Knuth's TwoSum.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "accum.h"
 #include "kernels.h"
 
@@ -262,11 +264,22 @@ template <class T> struct Pair2;
 template <> struct Pair2<double> { using type = double2; };
 template <> struct Pair2<float> { using type = float2; };
 
+// (T(raw) - dark) * (1 / norm) from a pair of the storage type, or from a
+// 12-byte record (float dark, double 1 / norm) used when every dark value
+// is a float: the cast back to double is exact, so both give the same bits.
+__device__ inline double corr_apply(double v, const double2& c) { return (v - c.x) * c.y; }
+__device__ inline float corr_apply(float v, const float2& c) { return (v - c.x) * c.y; }
+__device__ inline double corr_apply(double v, const Corr12& c) {
+    const double inv = __hiloint2double((int)c.inv_hi, (int)c.inv_lo);
+    return (v - (double)c.dark) * inv;
+}
+
 // With kCorr the image is the raw frame: every gathered pixel is cast and
 // corrected on the way, (T(raw) - dark) * (1 / norm), dark and the
 // reciprocal of norm coming as one pair per pixel (one load), so the
 // corrected image is never written.
-template <class T, class Acc, int BLOCK, int R, class RawT = T, bool kCorr = false>
+template <class T, class Acc, int BLOCK, int R, class RawT = T, bool kCorr = false,
+          class CorrT = typename Pair2<T>::type>
 __global__ __launch_bounds__(BLOCK) void k_band(const BandPiece* __restrict__ pieces,
                                                 int32_t npieces,
                                                 const int32_t* __restrict__ packed,
@@ -274,8 +287,7 @@ __global__ __launch_bounds__(BLOCK) void k_band(const BandPiece* __restrict__ pi
                                                 const T* __restrict__ x,
                                                 Acc* __restrict__ parts,
                                                 const RawT* __restrict__ raw = nullptr,
-                                                const typename Pair2<T>::type* __restrict__ corr =
-                                                    nullptr) {
+                                                const CorrT* __restrict__ corr = nullptr) {
     constexpr int U = 4;
     constexpr int32_t kMask = (1 << kBandShift) - 1;
     __shared__ Acc red[BLOCK / kWave][R];
@@ -294,7 +306,7 @@ __global__ __launch_bounds__(BLOCK) void k_band(const BandPiece* __restrict__ pi
         const BandPiece pc = pieces[ti];
         const T* xb = kCorr ? nullptr : x + pc.pix_off;
         const RawT* rb = kCorr ? raw + pc.pix_off : nullptr;
-        const typename Pair2<T>::type* cb = (kCorr && corr) ? corr + pc.pix_off : nullptr;
+        const CorrT* cb = (kCorr && corr) ? corr + pc.pix_off : nullptr;
         Acc a[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) a[r].zero();
@@ -317,10 +329,7 @@ __global__ __launch_bounds__(BLOCK) void k_band(const BandPiece* __restrict__ pi
                     if (z + u * BLOCK < pc.z1) {
                         const int32_t pix = pk[u] & kMask;
                         v = (T)rb[pix];
-                        if (cb) {
-                            const auto c = cb[pix];
-                            v = (v - c.x) * c.y;
-                        }
+                        if (cb) v = corr_apply(v, cb[pix]);
                     }
                     xv[u] = v;
                 } else {
@@ -725,6 +734,16 @@ hipError_t band_launch(const BandLaunch& a, hipStream_t s) {
 template <class T, class Acc, int R, class RawT>
 hipError_t band_launch_raw(const BandLaunch& a, hipStream_t s) {
     const int grid = a.grid > 0 ? a.grid : a.npieces;
+    if constexpr (std::is_same<T, double>::value) {
+        if (a.corr && a.corr_kind == kCorrRecord12) {
+            hipLaunchKernelGGL((k_band<T, Acc, 256, R, RawT, true, Corr12>), dim3(grid), dim3(256),
+                               0, s, a.pieces, a.npieces, a.packed, static_cast<const T*>(a.coef),
+                               static_cast<const T*>(nullptr), static_cast<Acc*>(a.parts),
+                               static_cast<const RawT*>(a.raw), static_cast<const Corr12*>(a.corr));
+            return hipGetLastError();
+        }
+    }
+    if (a.corr_kind != kCorrPair) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_band<T, Acc, 256, R, RawT, true>), dim3(grid), dim3(256), 0, s,
                        a.pieces, a.npieces, a.packed, static_cast<const T*>(a.coef),
                        static_cast<const T*>(nullptr), static_cast<Acc*>(a.parts),
@@ -893,6 +912,47 @@ __global__ void k_corr_pair(const T* __restrict__ dark, const T* __restrict__ no
     pair[i] = v;
 }
 }  // namespace
+
+namespace {
+__global__ void k_dark_is_float(const double* __restrict__ dark, int64_t n,
+                                int32_t* __restrict__ flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double d = dark[i];
+    if (!((double)(float)d == d)) flag[0] = 1;
+}
+
+__global__ void k_corr_record12(const double* __restrict__ dark, const double* __restrict__ norm,
+                                Corr12* __restrict__ rec, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double inv = norm ? 1.0 / norm[i] : 1.0;
+    Corr12 r;
+    r.dark = (float)dark[i];
+    r.inv_lo = (uint32_t)__double2loint(inv);
+    r.inv_hi = (uint32_t)__double2hiint(inv);
+    rec[i] = r;
+}
+}  // namespace
+
+hipError_t launch_dark_is_float(const double* dark, int64_t n, int32_t* flag, hipStream_t s) {
+    hipError_t e = hipMemsetAsync(flag, 0, 4, s);
+    if (e != hipSuccess || n <= 0) return e;
+    const int64_t blocks = (n + 255) / 256;
+    if (blocks > INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_dark_is_float, dim3((unsigned)blocks), dim3(256), 0, s, dark, n, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_corr_record12(const double* dark, const double* norm, void* rec, int64_t n,
+                                hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    if (blocks > INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_corr_record12, dim3((unsigned)blocks), dim3(256), 0, s, dark, norm,
+                       static_cast<Corr12*>(rec), n);
+    return hipGetLastError();
+}
 
 hipError_t launch_corr_pair(const void* dark, const void* norm, void* pair, int32_t dtype,
                             int64_t n, hipStream_t s) {

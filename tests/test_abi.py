@@ -213,6 +213,15 @@ def test_upload_without_gpu_fails_cleanly():
     assert rc == -4 and "device" in msg
 
 
+def test_correction_bytes_without_device_arrays():
+    """A plan that holds no device correction records reports 0 bytes per
+    pixel (also for a NULL plan)."""
+    az = azint()
+    assert az.lib().azi_plan_correction_bytes(None) == 0
+    plan = az.Plan(12, 13, 6)
+    assert plan.correction_bytes() == 0
+
+
 def test_integration_on_cpu_via_exported_matrix_matches_oracle():
     """The exported CSR is what the kernels stream: scipy's product with it
     reproduces the oracle's W and U (Section 5.2.1 compatibility)."""

@@ -163,6 +163,43 @@ def test_raw_pipeline_with_corrections(layout, stage, dev):
             assert torch.equal(a, b)
 
 
+def test_fused_correction_record_and_pair_same_bits(dev):
+    """A float64 plan keeps (dark, 1/norm) as 12-byte records when every dark
+    value is a float and as 16-byte pairs otherwise.  Changing dark only on a
+    pixel that feeds no bin switches the form and must leave every bit of
+    the result unchanged; both results match the oracle."""
+    say("correction record vs pair")
+    az = azint()
+    inst = synth.instance_hw(151, 140, 8, npt=120, corrections=True)
+    g = inst.geom
+    rng_r = (4e-4, 6e-3)  # the inner disc of radius 4e-4 m feeds no bin
+    plan = az.Plan(g.h, g.w, inst.npt, center=(g.center_y, g.center_x), range=rng_r, device=dev)
+    colptr = plan.export_csc()[2]
+    empty_pix = np.flatnonzero(np.diff(colptr) == 0)
+    assert empty_pix.size > 0
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a).reshape(-1)).to(dev)
+    dark_f = inst.dark.reshape(-1).copy()          # integers: floats
+    dark_d = dark_f.copy()
+    dark_d[empty_pix[0]] = 0.1                      # not a float
+    outs, sizes, forms = [], [], []
+    for dark in (dark_f, dark_d):
+        plan.set_corrections(t(dark), t(inst.flat), t(inst.solid), t(inst.polar))
+        sizes.append(plan.device_bytes())
+        forms.append(plan.correction_bytes())
+        outs.append(plan.integrate_raw(t(inst.raw)))
+        torch.cuda.synchronize()
+    assert forms == [12, 16]
+    assert sizes[1] - sizes[0] == 4 * g.npix      # pairs are 4 bytes longer per pixel
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
+    m = oracle_matrix(g.h, g.w, g.center_y, g.center_x, inst.npt, 1e-4, 1e-4, "r_m", "bbox",
+                      rng_r)
+    for dark, out in zip((dark_f, dark_d), outs):
+        x = oracle.correct(inst.raw.reshape(-1), dark, inst.flat.reshape(-1),
+                           inst.solid.reshape(-1), inst.polar.reshape(-1))
+        check(out, m, x, TOL64, what="record/pair")
+
+
 @pytest.mark.parametrize("layout", ["ring", "pixel", "tile", "band"])
 @pytest.mark.parametrize("accum", ["f64", "kahan32"])
 @pytest.mark.parametrize("tiling", [(2048, 256, 2, 0, 1, 2), (64, 64, 0, 0, 16, 0),
