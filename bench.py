@@ -32,6 +32,8 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 
 KERNEL_OF_LAYOUT = {
     "band": "k_band (+k_band_reduce): band-ordered gather integration",
+    "run": "k_band_runs (+k_band_reduce): band-ordered gather integration, one word and one "
+           "gather per pixel run",
     "pixel": "k_spmv (+k_fixup): CSR gather integration",
     "ring": "k_spmv (+k_fixup): CSR gather integration, ring-ordered image",
     "tile": "k_block (+k_block_reduce): image-tile blocked integration",
@@ -113,6 +115,20 @@ def raw_bytes(nnz, npix, npt, es, cb):
     return nnz * (es + 4) + npix * (4 + cb) + (npt + 1) * 4 + 3 * npt * es
 
 
+def encoding_bytes(plan, np, npix, npt, es, cb):
+    """Bytes the run encoding itself streams per raw-frame step (a word per
+    pixel run within a band of 4 bins instead of an index per entry; the
+    step's roofline keeps the CSR figure of raw_bytes as its yardstick)."""
+    if plan.layout() != "run":
+        return raw_bytes(plan.nnz, npix, npt, es, cb)
+    _, bins, colptr = plan.export_csc()
+    full = np.diff(colptr) > 0
+    first = bins[colptr[:-1][full]] // 4
+    last = bins[colptr[1:][full] - 1] // 4
+    runs = int((last - first + 1).sum())
+    return runs * 4 + plan.nnz * es + npix * (4 + cb) + 3 * npt * es
+
+
 def pipeline_line(az, torch, np, synth, dev, dtype, steps, warmup, frames_n=4):
     """Step = one raw int32 frame -> I, W, U with the plan's corrections
     (azi_integrate1d_raw).  With the default tiling the band kernel casts and
@@ -154,6 +170,7 @@ def pipeline_line(az, torch, np, synth, dev, dtype, steps, warmup, frames_n=4):
     nnz = plan.nnz
     cb = plan.correction_bytes()
     rb = raw_bytes(nnz, g.npix, inst.npt, es, cb)
+    enc = encoding_bytes(plan, np, g.npix, inst.npt, es, cb)
     # two-pass breakdown: correction kernel, then integration of the image
     pairs = []
     for k in range(max(steps // 4, 10)):
@@ -175,6 +192,7 @@ def pipeline_line(az, torch, np, synth, dev, dtype, steps, warmup, frames_n=4):
                 elements_per_s=g.npix / (ms_step * 1e-3),
                 correction_bytes_per_pixel=cb,
                 step_ms=step_ms, step_bytes=rb, step_gbs=rb / (step_ms * 1e6),
+                step_encoding_bytes=enc, step_encoding_gbs=enc / (step_ms * 1e6),
                 step_frac=rb / (step_ms * 1e6) / HBM_PEAK_GBS,
                 two_pass_correct_ms=corr_ms, two_pass_correct_gbs=corr_b / (corr_ms * 1e6),
                 integrate_ms=spmv_ms, integrate_bytes=b,

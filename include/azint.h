@@ -223,7 +223,7 @@ int azi_plan_export_csc(const azi_plan* plan, void* data, int32_t* bins, int32_t
  *             AZI_STAGE_GATHER reads each ring position's pixel; _SCATTER
  *             reads row-major and writes each pixel's ring position;
  *             _TILE reads 32x128-pixel tiles row-major and writes them out in
- *             ring order through LDS.  AZI_STAGE_FUSE (band layout): the
+ *             ring order through LDS.  AZI_STAGE_FUSE (band and run layouts): the
  *             raw-frame calls (azi_integrate1d_raw, azi_batch_forward_raw)
  *             run one band kernel that casts and corrects every pixel it
  *             gathers as (raw - dark) * (1 / norm), dark and the reciprocal
@@ -260,9 +260,10 @@ int azi_plan_tile_schedule(const azi_plan* plan, const azi_tiling* tiling, int32
                            int32_t* tiles, int32_t* nsplits, int32_t* splits);
 
 /*
- * Device layout of the matrix (default AZI_LAYOUT_BAND; two-dimensional
- * plans default to AZI_LAYOUT_PIXEL with tile_nnz 4096, variant 3, band 1,
- * their rows being short).  AZI_LAYOUT_PIXEL: the gather kernels
+ * Device layout of the matrix (default AZI_LAYOUT_RUN; plans built on the
+ * device start in AZI_LAYOUT_BAND; two-dimensional plans default to
+ * AZI_LAYOUT_PIXEL with tile_nnz 4096, variant 3, band 1, their rows being
+ * short).  AZI_LAYOUT_PIXEL: the gather kernels
  * read the image in its row-major pixel order.  AZI_LAYOUT_RING:
  * the matrix columns are renumbered so that pixels are sorted by the first
  * bin they feed (ties in pixel order); every bin then reads its pixels from
@@ -292,6 +293,12 @@ int azi_plan_tile_schedule(const azi_plan* plan, const azi_tiling* tiling, int32
  * each bin's partials in tile order.  With azi_integrate1d_raw the cast and
  * correction happen in the same kernel.  Only the tiling's grid applies.
  * Batches do not take this layout.
+ * AZI_LAYOUT_RUN: the band layout with bands of 4 bins, stored per run: the
+ * entries of one pixel inside one band (consecutive bins) share one word
+ * (pixel, first row, count) and one gather of the pixel; the coefficients
+ * follow slot-major per group of 64 runs.  Pieces hold tile_nnz / 2 runs;
+ * the band value of the tiling is ignored.  A batch built from such plans
+ * uses AZI_LAYOUT_BAND.  Images up to 2^27 pixels.
  * Set before azi_plan_upload (a later call re-uploads).
  */
 #define AZI_LAYOUT_PIXEL 0
@@ -299,6 +306,7 @@ int azi_plan_tile_schedule(const azi_plan* plan, const azi_tiling* tiling, int32
 #define AZI_LAYOUT_TILE 2
 #define AZI_LAYOUT_BAND 3
 #define AZI_LAYOUT_FUSED 4
+#define AZI_LAYOUT_RUN 5
 int azi_plan_set_layout(azi_plan* plan, int32_t layout);
 int azi_plan_get_layout(const azi_plan* plan, int32_t* layout);
 
@@ -314,8 +322,9 @@ int64_t azi_plan_device_bytes(const azi_plan* plan);
  * Per-pixel correction arrays of Section 6.4 (device pointers of the storage
  * type, npix values each, or NULL for "absent").  The plan keeps a copy of
  * dark and of norm = (flat * solid) * polar, formed once here, so the
- * per-frame map is x = (raw - dark) / norm; with the band layout and
- * AZI_STAGE_FUSE it also keeps the (dark, 1 / norm) pairs its gather reads.
+ * per-frame map is x = (raw - dark) / norm; with the band or run layout
+ * and AZI_STAGE_FUSE it also keeps the (dark, 1 / norm) pairs its gather
+ * reads.
  * A float64 plan whose dark values are all exactly floats keeps them as
  * 12-byte records (float dark, double 1 / norm) instead of 16-byte pairs:
  * the results are the same bits, the gather reads 4 bytes less per pixel.

@@ -26,7 +26,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libazint.so")
 
 UNITS = {"r_m": 0, "r_mm": 1, "2th_rad": 2, "2th_deg": 3, "q_nm": 4}
-LAYOUTS = {"pixel": 0, "ring": 1, "tile": 2, "band": 3, "fused": 4}
+LAYOUTS = {"pixel": 0, "ring": 1, "tile": 2, "band": 3, "fused": 4, "run": 5}
 SPLITS = {"none": 0, "bbox": 1, "full": 2}
 _DT = {torch.int16: 0, torch.int32: 2, torch.float32: 4, torch.float64: 5}
 for _name, _code in (("uint16", 1), ("uint32", 3)):
@@ -224,7 +224,8 @@ class Plan:
                   wavelength=1e-10, unit="r_m", split="bbox", range=None, dtype=torch.float64,
                   accum="f64", stream=None):
         """A one-dimensional plan built by the device plan builder on
-        ``device`` (returned uploaded there, band layout)."""
+        ``device`` (returned uploaded there, band layout; set_layout("run")
+        switches to the run encoding, built from the plan's host copy)."""
         dev = torch.device(device) if not isinstance(device, torch.device) else device
         idx = dev.index if dev.index is not None else torch.cuda.current_device()
         py, px = (pixel, pixel) if np.isscalar(pixel) else pixel

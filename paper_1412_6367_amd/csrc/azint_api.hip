@@ -184,7 +184,7 @@ struct azi_plan {
     DevBuf rowptr, indices, data, colptr, rowidx, cdata, tiles, splits, parts, dark, norm, xwork,
         vwork, order, dark_r, norm_r, pos, stiles, lidx, dest, btiles, brows, blp, bcoef, bin_ptr,
         bparts, npieces_buf, npacked, ncoef, bin_slot, bin_count, nparts_buf, ftiles, fslots,
-        fbin_ptr, fparts, corr, cfirst;
+        fbin_ptr, fparts, corr, cfirst, rgbase;
     int32_t nstiles = 0, nbtiles = 0, npieces = 0, band_rows = 8, nftiles = 0;
     int32_t corr_kind = azi::kCorrPair;
     int32_t ntiles = 0, nsplits = 0, nparts = 0;
@@ -306,6 +306,9 @@ int upload_blocks(const azi::BlockMatrix& bm, int32_t dtype, int device, DevBuf&
     return AZI_OK;
 }
 
+// The band layout in either encoding (per entry, or per run).
+bool is_band(int32_t layout) { return layout == AZI_LAYOUT_BAND || layout == AZI_LAYOUT_RUN; }
+
 int32_t band_rows_of(const azi_tiling& t) {
     return (t.band == 4 || t.band == 8 || t.band == 16) ? t.band : 8;
 }
@@ -330,6 +333,32 @@ int upload_bands(const azi::BandMatrix& bm, int32_t dtype, int device, DevBuf& p
 }
 
 int plan_upload_bands(azi_plan* p) {
+    p->rgbase.release();
+    if (p->layout == AZI_LAYOUT_RUN) {
+        try {
+            azi::RunMatrix rm;
+            if (!azi::build_runs(p->m, std::max(64, p->tiling.tile_nnz / 2), rm))
+                return fail(AZI_EOVERFLOW,
+                            "the run layout takes images below 2^27 pixels and 2^31 entries");
+            azi::BandMatrix bm;
+            bm.pieces.swap(rm.pieces);
+            bm.packed.swap(rm.runs);
+            bm.coef.swap(rm.coef);
+            bm.bin_slot.swap(rm.bin_slot);
+            bm.bin_count.swap(rm.bin_count);
+            bm.nslots = rm.nslots;
+            p->band_rows = azi::kRunRows;
+            int rc = upload_bands(bm, p->dtype, p->device, p->npieces_buf, p->npacked, p->ncoef,
+                                  p->bin_slot, p->bin_count, p->nparts_buf);
+            if (rc != AZI_OK) return rc;
+            AZI_HIP(p->rgbase.upload(rm.gbase.data(), rm.gbase.size() * 4, p->device),
+                    "run groups");
+            p->npieces = (int32_t)bm.pieces.size();
+        } catch (const std::bad_alloc&) {
+            return fail(AZI_ENOMEM, "out of host memory building the run matrix");
+        }
+        return AZI_OK;
+    }
     try {
         azi::BandMatrix bm;
         p->band_rows = band_rows_of(p->tiling);
@@ -351,6 +380,7 @@ azi::BandLaunch plan_band_args(const azi_plan* p, const void* x, void* I, void* 
     a.pieces = p->npieces_buf.as<azi::BandPiece>();
     a.npieces = p->npieces;
     a.packed = p->npacked.as<int32_t>();
+    a.gbase = p->layout == AZI_LAYOUT_RUN ? p->rgbase.as<int32_t>() : nullptr;
     a.coef = p->ncoef.p;
     a.bin_slot = p->bin_slot.as<int32_t>();
     a.bin_count = p->bin_count.as<int32_t>();
@@ -452,7 +482,7 @@ int plan_upload_fused(azi_plan* p) {
 int plan_corr_pair(azi_plan* p, hipStream_t s) {
     p->corr.release();
     p->corr_kind = azi::kCorrPair;
-    if (p->layout != AZI_LAYOUT_BAND || p->tiling.stage != AZI_STAGE_FUSE ||
+    if (!is_band(p->layout) || p->tiling.stage != AZI_STAGE_FUSE ||
         !(p->has_dark || p->has_norm))
         return AZI_OK;
     if (p->dtype == AZI_F64 && p->has_dark) {
@@ -616,6 +646,7 @@ int plan_create(const azi_geom* geom, int32_t npt, int32_t npt_azim, int32_t uni
     }
     if (rc != AZI_OK) return fail(rc, err);
     size_default_tiling(p.get());
+    p->layout = AZI_LAYOUT_RUN;
     if (p->m.two_d) {
         // short rows (tens of entries): the plain CSR with whole rows per
         // tile beats the band order, whose per-band pieces would be tiny
@@ -914,7 +945,7 @@ int azi_plan_set_tiling(azi_plan* p, const azi_tiling* t) {
         DeviceGuard g(p->device);
         if (g.err != hipSuccess) return hip_fail(g.err, "set device");
         AZI_HIP(hipDeviceSynchronize(), "synchronise before retiling");
-        if (p->layout == AZI_LAYOUT_BAND) {
+        if (is_band(p->layout)) {
             int rc = plan_upload_bands(p);
             if (rc != AZI_OK) return rc;
         }
@@ -947,8 +978,8 @@ int azi_plan_tile_schedule(const azi_plan* p, const azi_tiling* tl, int32_t* nti
 
 int azi_plan_set_layout(azi_plan* p, int32_t layout) {
     if (!p) return fail(AZI_EINVAL, "plan is NULL");
-    if (layout < AZI_LAYOUT_PIXEL || layout > AZI_LAYOUT_FUSED)
-        return fail(AZI_EINVAL, "layout must be one of AZI_LAYOUT_PIXEL/RING/TILE/BAND/FUSED");
+    if (layout < AZI_LAYOUT_PIXEL || layout > AZI_LAYOUT_RUN)
+        return fail(AZI_EINVAL, "layout must be one of AZI_LAYOUT_PIXEL/RING/TILE/BAND/FUSED/RUN");
     if (layout == AZI_LAYOUT_FUSED && (p->m.two_d || p->split == AZI_SPLIT_FULL))
         return fail(AZI_EINVAL,
                     "the fused layout takes one-dimensional plans without full splitting");
@@ -1027,7 +1058,7 @@ int azi_plan_upload(azi_plan* p, int32_t device) {
         }
         AZI_HIP(p->xwork.alloc((size_t)p->m.npix * es, device), "work image");
         AZI_HIP(p->vwork.alloc((size_t)p->m.npt * 8, device), "work vector");
-        if (p->layout == AZI_LAYOUT_BAND) {
+        if (is_band(p->layout)) {
             int rc2 = plan_upload_bands(p);
             if (rc2 != AZI_OK) return rc2;
         }
@@ -1153,7 +1184,7 @@ int azi_integrate1d(const azi_plan* p, const void* x, void* I, void* W, void* U,
                 "blocked forward kernels");
         return AZI_OK;
     }
-    if (p->layout == AZI_LAYOUT_BAND) {
+    if (is_band(p->layout)) {
         AZI_HIP(azi::launch_band(plan_band_args(p, x, I, W, U, empty), s), "band forward kernels");
         return AZI_OK;
     }
@@ -1204,7 +1235,7 @@ int azi_integrate1d_staged(const azi_plan* p, void* I, void* W, void* U, double 
                 "blocked forward kernels");
         return AZI_OK;
     }
-    if (p->layout == AZI_LAYOUT_BAND) {
+    if (is_band(p->layout)) {
         AZI_HIP(azi::launch_band(plan_band_args(p, p->xwork.p, I, W, U, empty),
                                  static_cast<hipStream_t>(stream)),
                 "band forward kernels");
@@ -1241,7 +1272,7 @@ int azi_integrate1d_raw(const azi_plan* p, const void* raw, int32_t raw_dtype, v
                 "blocked forward kernels");
         return AZI_OK;
     }
-    if (p && p->layout == AZI_LAYOUT_BAND && p->tiling.stage == AZI_STAGE_FUSE &&
+    if (p && is_band(p->layout) && p->tiling.stage == AZI_STAGE_FUSE &&
         p->device >= 0) {
         // cast and correction in the band kernel's gather
         if (!raw) return fail(AZI_EINVAL, "raw must not be NULL");
@@ -1292,8 +1323,11 @@ int azi_batch_create(azi_plan* const* plans, int32_t n, int32_t device, azi_batc
     *out = nullptr;
     for (int32_t k = 0; k < n; ++k) {
         if (!plans[k]) return fail(AZI_EINVAL, "plan is NULL");
+        const auto batch_layout = [](const azi_plan* q) {
+            return q->layout == AZI_LAYOUT_RUN ? AZI_LAYOUT_BAND : q->layout;
+        };
         if (plans[k]->dtype != plans[0]->dtype || plans[k]->accum != plans[0]->accum ||
-            plans[k]->layout != plans[0]->layout)
+            batch_layout(plans[k]) != batch_layout(plans[0]))
             return fail(AZI_EINVAL, "plans of a batch must share dtype, accumulation and layout");
     if (plans[0]->layout == AZI_LAYOUT_FUSED)
         return fail(AZI_EINVAL, "batches take the pixel, ring, tile or band layout");
@@ -1309,7 +1343,8 @@ int azi_batch_create(azi_plan* const* plans, int32_t n, int32_t device, azi_batc
     b->accum = plans[0]->accum;
     b->device = device;
     b->tiling = plans[0]->tiling;
-    b->layout = plans[0]->layout;
+    // batches keep the band layout's per-entry encoding
+    b->layout = plans[0]->layout == AZI_LAYOUT_RUN ? AZI_LAYOUT_BAND : plans[0]->layout;
     b->pix_off.assign(n + 1, 0);
     b->bin_off.assign(n + 1, 0);
     b->nz_off.assign(n + 1, 0);

@@ -173,6 +173,30 @@ bool build_bands(const HostMatrix& m, int32_t R, int32_t piece_nnz, int64_t pix_
 void band_pieces(const int64_t* start, int32_t nbands, int32_t npt, int32_t R, int32_t piece_nnz,
                  int64_t base, int64_t pix_off, int64_t bin_off, BandMatrix& bm);
 
+// Run encoding of the band layout (bands of kRunRows bins).  A run is the
+// stretch of one pixel's entries inside one band (consecutive bins): one
+// word pix | first row << kBandShift | (count - 1) << kRunCountShift.  Runs
+// of a band are in pixel order; every band, and so every piece, starts on a
+// multiple of 64 runs.  The coefficients of the 64 runs of group g start at
+// gbase[g], slot-major: the first coefficient of each run in run order,
+// then the second of the runs that have one, and so on.  A wavefront takes
+// one group and finds every lane's coefficients from the counts alone.
+// Pieces (z0, z1 in runs) and slots are as in the band layout.
+constexpr int32_t kRunRows = 4;
+constexpr int32_t kRunCountShift = 29;
+struct RunMatrix {
+    std::vector<BandPiece> pieces;
+    std::vector<int32_t> runs;
+    std::vector<int32_t> gbase;
+    std::vector<double> coef;
+    std::vector<int32_t> bin_slot, bin_count;
+    int32_t nslots = 0;
+};
+// Builds the run encoding of `m` with pieces of at most piece_runs runs (a
+// multiple of 64).  Returns false if the image has 2^27 pixels or more or
+// the coefficients do not fit int32 offsets.
+bool build_runs(const HostMatrix& m, int32_t piece_runs, RunMatrix& rm);
+
 // Matrix-free ("fused") schedule: the image cut into kFusedH x kFusedW
 // tiles; tile t feeds the bin window [wlo, wlo + nwin) and writes the partial
 // sums of bin wlo + k to slot slots[slot_off + k]; bin b owns slots

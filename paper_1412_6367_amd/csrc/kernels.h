@@ -73,7 +73,8 @@ static_assert(sizeof(Corr12) == 12, "12-byte correction record");
 struct BandLaunch {
     const BandPiece* pieces = nullptr;
     int32_t npieces = 0;
-    const int32_t* packed = nullptr;
+    const int32_t* packed = nullptr;   // entries, or the runs when gbase is set
+    const int32_t* gbase = nullptr;    // run encoding (R = kRunRows): group coefficient bases
     const void* coef = nullptr;
     const int32_t* bin_slot = nullptr;
     const int32_t* bin_count = nullptr;

@@ -362,6 +362,114 @@ __global__ __launch_bounds__(BLOCK) void k_band(const BandPiece* __restrict__ pi
     }
 }
 
+// Run encoding of the band layout: a wavefront takes a group of 64 runs
+// (lane = run), reads each run's word, finds where its 1..4 coefficients
+// sit from the group's counts (ballots and lane ranks: no table), gathers
+// the pixel once for the whole run and adds each coefficient's product to
+// the accumulator of its row.  U groups per wavefront are in flight at a
+// time.  The partial sums are reduced and written as in k_band.
+template <class T, class Acc, int U, class RawT = T, bool kCorr = false,
+          class CorrT = typename Pair2<T>::type>
+__global__ __launch_bounds__(256) void k_band_runs(const BandPiece* __restrict__ pieces,
+                                                   int32_t npieces,
+                                                   const int32_t* __restrict__ runs,
+                                                   const int32_t* __restrict__ gbase,
+                                                   const T* __restrict__ coef,
+                                                   const T* __restrict__ x,
+                                                   Acc* __restrict__ parts,
+                                                   const RawT* __restrict__ raw = nullptr,
+                                                   const CorrT* __restrict__ corr = nullptr) {
+    constexpr int BLOCK = 256, R = kRunRows;
+    constexpr int32_t kMask = (1 << kBandShift) - 1;
+    __shared__ Acc red[BLOCK / kWave][R];
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave), lane = tid & (kWave - 1);
+    const int32_t g = blockIdx.x, Gd = gridDim.x;
+    int32_t t_begin, t_end, t_step;
+    if (Gd < 8) {
+        t_begin = g; t_end = npieces; t_step = Gd;
+    } else {
+        const int32_t xcd = g & 7, q = g >> 3, nq = (Gd - xcd + 7) >> 3;
+        const int32_t per = npieces >> 3, rem = npieces & 7;
+        const int32_t t0 = xcd * per + min(xcd, rem);
+        t_begin = t0 + q; t_end = t0 + per + (xcd < rem ? 1 : 0); t_step = nq;
+    }
+    for (int32_t ti = t_begin; ti < t_end; ti += t_step) {
+        const BandPiece pc = pieces[ti];
+        Acc a[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) a[r].zero();
+        for (int32_t z0 = pc.z0 + wave * kWave; z0 < pc.z1; z0 += BLOCK * U) {
+            int32_t rw[U], base[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int32_t zg = z0 + u * BLOCK;       // uniform over the wavefront
+                rw[u] = -1;
+                base[u] = 0;
+                if (zg < pc.z1) {
+                    base[u] = gbase[zg >> 6];
+                    if (zg + lane < pc.z1) rw[u] = __builtin_nontemporal_load(runs + zg + lane);
+                }
+            }
+            T c[U][R];
+            int n[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                n[u] = rw[u] < 0 ? 0 : ((rw[u] >> kRunCountShift) & 3) + 1;
+                int32_t off = base[u];
+#pragma unroll
+                for (int j = 0; j < R; ++j) {
+                    const uint64_t m = __ballot(n[u] > j);
+                    const int32_t rank = (int32_t)__builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                    c[u][j] = n[u] > j ? __builtin_nontemporal_load(coef + off + rank) : T(0);
+                    off += (int32_t)__popcll(m);
+                }
+            }
+            T xv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                T v = T(0);
+                if (n[u] > 0) {
+                    const int32_t pix = rw[u] & kMask;
+                    if constexpr (kCorr) {
+                        v = (T)raw[pc.pix_off + pix];
+                        if (corr) v = corr_apply(v, corr[pc.pix_off + pix]);
+                    } else {
+                        v = x[pc.pix_off + pix];
+                    }
+                }
+                xv[u] = v;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int r0 = (rw[u] >> kBandShift) & 3;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int j = r - r0;
+                    if (j >= 0 && j < n[u]) {
+                        const T cv = j == 0 ? c[u][0] : j == 1 ? c[u][1] : j == 2 ? c[u][2] : c[u][3];
+                        a[r].add(cv, xv[u]);
+                    }
+                }
+            }
+        }
+        const int lanew = tid & (kWave - 1);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            group_reduce(a[r], kWave);
+            if (lanew == 0) red[wave][r] = a[r];
+        }
+        __syncthreads();
+        if (tid < R) {
+            Acc sacc = red[0][tid];
+            for (int k = 1; k < BLOCK / kWave; ++k) sacc.merge(red[k][tid]);
+            parts[pc.slot0 + tid] = sacc;
+        }
+        __syncthreads();
+    }
+}
+
 // One wavefront per bin adds the partial sums of its band's pieces (slots
 // first, first + R, ...) in a fixed order and writes W, U and I.
 template <class T, class Acc>
@@ -777,9 +885,59 @@ hipError_t band_block(const BandLaunch& a, hipStream_t s) {
     }
 }
 
+// Groups in flight per wavefront (measured at 1e7 pixels: 2 for float64,
+// 4 for float32, whose registers are half the size).
+template <class T> constexpr int kRunGroups = sizeof(T) == 8 ? 2 : 4;
+
+template <class T, class Acc, class RawT, class CorrT>
+hipError_t runs_launch_raw(const BandLaunch& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_band_runs<T, Acc, kRunGroups<T>, RawT, true, CorrT>), dim3(grid),
+                       dim3(256), 0, s, a.pieces, a.npieces, a.packed, a.gbase,
+                       static_cast<const T*>(a.coef), static_cast<const T*>(nullptr),
+                       static_cast<Acc*>(a.parts), static_cast<const RawT*>(a.raw),
+                       static_cast<const CorrT*>(a.corr));
+    return hipGetLastError();
+}
+
+template <class T, class Acc, class RawT>
+hipError_t runs_raw_corr(const BandLaunch& a, int grid, hipStream_t s) {
+    if constexpr (std::is_same<T, double>::value) {
+        if (a.corr && a.corr_kind == kCorrRecord12)
+            return runs_launch_raw<T, Acc, RawT, Corr12>(a, grid, s);
+    }
+    if (a.corr_kind != kCorrPair) return hipErrorInvalidValue;
+    return runs_launch_raw<T, Acc, RawT, typename Pair2<T>::type>(a, grid, s);
+}
+
+template <class T, class Acc>
+hipError_t runs_launch(const BandLaunch& a, hipStream_t s) {
+    const int grid = a.grid > 0 ? a.grid : a.npieces;
+    if (!a.raw) {
+        hipLaunchKernelGGL((k_band_runs<T, Acc, kRunGroups<T>>), dim3(grid), dim3(256), 0, s,
+                           a.pieces, a.npieces, a.packed, a.gbase, static_cast<const T*>(a.coef),
+                           static_cast<const T*>(a.x), static_cast<Acc*>(a.parts),
+                           static_cast<const T*>(nullptr),
+                           static_cast<const typename Pair2<T>::type*>(nullptr));
+        return hipGetLastError();
+    }
+    switch (a.raw_dtype) {
+        case AZI_I16: return runs_raw_corr<T, Acc, int16_t>(a, grid, s);
+        case AZI_U16: return runs_raw_corr<T, Acc, uint16_t>(a, grid, s);
+        case AZI_I32: return runs_raw_corr<T, Acc, int32_t>(a, grid, s);
+        case AZI_U32: return runs_raw_corr<T, Acc, uint32_t>(a, grid, s);
+        case AZI_F32: return runs_raw_corr<T, Acc, float>(a, grid, s);
+        case AZI_F64: return runs_raw_corr<T, Acc, double>(a, grid, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <class T, class Acc>
 hipError_t band_impl(const BandLaunch& a, hipStream_t s) {
-    if (a.npieces > 0) {
+    if (a.npieces > 0 && a.gbase) {
+        if (a.R != kRunRows) return hipErrorInvalidValue;
+        const hipError_t e = runs_launch<T, Acc>(a, s);
+        if (e != hipSuccess) return e;
+    } else if (a.npieces > 0) {
         hipError_t e;
         switch (a.R) {
             case 4: e = band_block<T, Acc, 4>(a, s); break;

@@ -70,7 +70,7 @@ TILINGS = [dict(), dict(tile_nnz=256, block=64, variant=0, band=1),
            dict(tile_nnz=4096, block=512, variant=6, grid=128, band=8)]
 
 
-@pytest.mark.parametrize("layout", ["band", "tile", "ring", "pixel"])
+@pytest.mark.parametrize("layout", ["band", "tile", "ring", "pixel", "run"])
 @pytest.mark.parametrize("tiling", range(len(TILINGS)))
 @pytest.mark.parametrize("g", GEOMS, ids=lambda g: f"{g[0]}x{g[1]}-{g[7]}-{g[6]}-{g[5]}")
 def test_forward2d_f64(g, tiling, layout, dev):

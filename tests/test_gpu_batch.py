@@ -306,3 +306,27 @@ def test_band_fused_correction(dtype, dev):
         graph.launch()
         torch.cuda.synchronize()
         assert torch.equal(I, I0) and torch.equal(W, W0) and torch.equal(U, U0)
+
+
+def test_batch_of_run_plans_uses_band_entries(dev):
+    """Plans in the run layout (alone or mixed with band plans) make a batch
+    in the band layout's per-entry encoding: the same bits as a batch of
+    band plans."""
+    say("batch of run plans")
+    insts = small_batch(12, 33)
+    x = torch.from_numpy(flat_images(insts, np.float64)).to(dev)
+    _, bb = make_batch(insts, torch.float64, dev, layout="band")
+    _, br = make_batch(insts, torch.float64, dev, layout="run")
+    az = azint()
+    mixed = []
+    for k, inst in enumerate(insts):
+        g = inst.geom
+        mixed.append(az.Plan(g.h, g.w, inst.npt, center=(g.center_y, g.center_x),
+                             layout="run" if k % 2 else "band"))
+    bm = az.Batch(mixed, device=dev)
+    ref = bb.forward(x)
+    for b in (br, bm):
+        out = b.forward(x)
+        torch.cuda.synchronize()
+        for u, v in zip(out, ref):
+            assert torch.equal(u, v)

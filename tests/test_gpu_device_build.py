@@ -56,7 +56,7 @@ def test_device_plan_equals_host_plan(g, dev):
     az = azint()
     dtype = torch.float64 if dt == "f64" else torch.float32
     kw = dict(center=(cy, cx), unit=unit, split=split, range=rng, dtype=dtype)
-    hp = az.Plan(h, w, npt, **kw)
+    hp = az.Plan(h, w, npt, layout="band", **kw)   # the device builder's layout
     dp = az.Plan.on_device(h, w, npt, device=dev, **kw)
     ih, idv = hp.info(), dp.info()
     assert idv["npt"] == npt and idv["npix"] == h * w
@@ -95,7 +95,7 @@ def test_device_plan_layout_switch_and_backward(dev):
     dp = az.Plan.on_device(h, w, npt, device=dev)
     hp = az.Plan(h, w, npt, device=dev)
     x = torch.from_numpy(np.random.default_rng(5).uniform(0, 10, size=h * w)).to(dev)
-    for layout in ("pixel", "ring", "tile", "band"):
+    for layout in ("pixel", "ring", "tile", "band", "run"):
         dp.set_layout(layout)
         hp.set_layout(layout)
         a, b = dp.integrate(x), hp.integrate(x)

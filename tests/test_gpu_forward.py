@@ -71,7 +71,7 @@ def tiling_kw(t):
     return dict(zip(("tile_nnz", "block", "variant", "grid", "band", "stage"), t))
 
 
-@pytest.mark.parametrize("layout", ["ring", "pixel", "tile", "band"])
+@pytest.mark.parametrize("layout", ["ring", "pixel", "tile", "band", "run"])
 @pytest.mark.parametrize("tiling", TILINGS, ids=lambda t: "t{}b{}v{}g{}n{}s{}".format(*t))
 @pytest.mark.parametrize("g", GEOMS, ids=lambda g: f"{g[0]}x{g[1]}-{g[5]}-{g[6]}-{g[4]}")
 def test_forward_f64(g, tiling, layout, dev):
@@ -133,7 +133,8 @@ def test_correction_map_bit_exact(raw_dtype, dev):
 @pytest.mark.parametrize("layout,stage", [("ring", "tile"), ("ring", "gather"),
                                           ("ring", "scatter"), ("pixel", "tile"),
                                           ("tile", "tile"), ("band", "tile"),
-                                          ("band", "fuse"), ("ring", "fuse")])
+                                          ("band", "fuse"), ("ring", "fuse"),
+                                          ("run", "fuse"), ("run", "gather")])
 def test_raw_pipeline_with_corrections(layout, stage, dev):
     say("raw pipeline with corrections", layout, stage)
     az = azint()
@@ -154,7 +155,7 @@ def test_raw_pipeline_with_corrections(layout, stage, dev):
     assert np.array_equal(xd.cpu().numpy(), x)
     out2 = plan.integrate(xd)
     torch.cuda.synchronize()
-    if layout == "band" and stage == "fuse":
+    if layout in ("band", "run") and stage == "fuse":
         # the fused gather multiplies by the reciprocal of norm: one rounding
         # per pixel away from the corrected image's quotient
         check(out2, m, x, TOL64, what="corrected image")
@@ -163,7 +164,8 @@ def test_raw_pipeline_with_corrections(layout, stage, dev):
             assert torch.equal(a, b)
 
 
-def test_fused_correction_record_and_pair_same_bits(dev):
+@pytest.mark.parametrize("layout", ["band", "run"])
+def test_fused_correction_record_and_pair_same_bits(layout, dev):
     """A float64 plan keeps (dark, 1/norm) as 12-byte records when every dark
     value is a float and as 16-byte pairs otherwise.  Changing dark only on a
     pixel that feeds no bin switches the form and must leave every bit of
@@ -173,7 +175,8 @@ def test_fused_correction_record_and_pair_same_bits(dev):
     inst = synth.instance_hw(151, 140, 8, npt=120, corrections=True)
     g = inst.geom
     rng_r = (4e-4, 6e-3)  # the inner disc of radius 4e-4 m feeds no bin
-    plan = az.Plan(g.h, g.w, inst.npt, center=(g.center_y, g.center_x), range=rng_r, device=dev)
+    plan = az.Plan(g.h, g.w, inst.npt, center=(g.center_y, g.center_x), range=rng_r,
+                   layout=layout, device=dev)
     colptr = plan.export_csc()[2]
     empty_pix = np.flatnonzero(np.diff(colptr) == 0)
     assert empty_pix.size > 0
@@ -200,7 +203,7 @@ def test_fused_correction_record_and_pair_same_bits(dev):
         check(out, m, x, TOL64, what="record/pair")
 
 
-@pytest.mark.parametrize("layout", ["ring", "pixel", "tile", "band"])
+@pytest.mark.parametrize("layout", ["ring", "pixel", "tile", "band", "run"])
 @pytest.mark.parametrize("accum", ["f64", "kahan32"])
 @pytest.mark.parametrize("tiling", [(2048, 256, 2, 0, 1, 2), (64, 64, 0, 0, 16, 0),
                                     (512, 512, 3, 0, 16, 1), (1024, 128, 1, 256, 4, 2),
@@ -377,3 +380,71 @@ def test_band_layout_shapes(R, piece, block, grid, dev):
     x = np.random.default_rng(R + piece).uniform(-1, 50, 300 * 280)
     check(plan.integrate(torch.from_numpy(x).to(dev), empty=7.0), m, x, TOL64, empty=7.0,
           what="band")
+
+
+@pytest.mark.parametrize("piece,grid", [(4096, 0), (64, 0), (128, 8), (16384, 2048), (1024, 64)])
+@pytest.mark.parametrize("g", [(300, 280, 150.2, 139.7, 250, "r_m", "bbox"),
+                               (1, 17, 0.5, 8.5, 5, "r_m", "bbox"),
+                               (64, 48, -5.0, 70.0, 40, "r_m", "bbox"),
+                               (120, 130, 60.2, 64.9, 140, "r_m", "full"),
+                               (50, 60, 25.3, 30.7, 37, "r_m", "none"),
+                               (20, 20, 10.0, 10.0, 1, "r_m", "bbox"),
+                               (90, 70, -10.0, 35.0, 80, "q_nm", "full")],
+                         ids=lambda g: f"{g[0]}x{g[1]}-{g[5]}-{g[6]}-{g[4]}")
+def test_run_layout_shapes(g, piece, grid, dev):
+    """The run encoding of the band layout (a word per pixel run within a
+    band, coefficients slot-major per 64 runs) against the oracle, for
+    pieces from one group of 64 runs to 8192 runs and persistent grids, and
+    within FP64 rounding of the per-entry band encoding."""
+    h, w, cy, cx, npt, unit, split = g
+    say("run shapes", g, piece, grid)
+    az = azint()
+    plan = az.Plan(h, w, npt, center=(cy, cx), unit=unit, split=split, layout="run", device=dev,
+                   tile_nnz=piece, grid=grid)
+    band = az.Plan(h, w, npt, center=(cy, cx), unit=unit, split=split, layout="band", device=dev)
+    m = oracle_matrix(h, w, cy, cx, npt, 1e-4, 1e-4, unit, split)
+    x = np.random.default_rng(h + piece).uniform(-1, 50, h * w)
+    xt = torch.from_numpy(x).to(dev)
+    out = plan.integrate(xt, empty=7.0)
+    again = plan.integrate(xt, empty=7.0)
+    ref = band.integrate(xt, empty=7.0)
+    torch.cuda.synchronize()
+    check(out, m, x, TOL64, empty=7.0, what="run")
+    for a, b in zip(out, again):
+        assert torch.equal(a, b)
+    _, Wabs, Uo = oracle.integrate(m, np.abs(x))
+    assert norm_err(out[1].cpu().numpy(), ref[1].cpu().numpy(), Wabs) <= 2 * TOL64
+    assert norm_err(out[2].cpu().numpy(), ref[2].cpu().numpy(), Uo) <= 2 * TOL64
+
+
+def test_run_layout_c2_full_size(dev):
+    """The 10-Mpixel float64 workload in the run layout, raw frame with
+    corrections as the benchmark runs it: sampled bins against the oracle
+    one by one, every bin against the per-entry band encoding, and
+    conservation."""
+    say("run c2")
+    az = azint()
+    inst = synth.instance(synth.C2["n"], synth.C2["seed"], corrections=True)
+    g = inst.geom
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a).reshape(-1)).to(dev)
+    plans = {}
+    for layout in ("run", "band"):
+        p = az.Plan(g.h, g.w, inst.npt, center=(g.center_y, g.center_x), layout=layout,
+                    device=dev)
+        p.set_corrections(t(inst.dark), t(inst.flat), t(inst.solid), t(inst.polar))
+        plans[layout] = p
+    raw = t(inst.raw)
+    I, W, U = (a.cpu().numpy() for a in plans["run"].integrate_raw(raw))
+    Ib, Wb, Ub = (a.cpu().numpy() for a in plans["band"].integrate_raw(raw))
+    x = oracle.correct(inst.raw.reshape(-1), inst.dark.reshape(-1), inst.flat.reshape(-1),
+                       inst.solid.reshape(-1), inst.polar.reshape(-1))
+    assert np.all(np.abs(U - Ub) <= 2 * TOL64 * Ub)
+    assert np.all(np.abs(W - Wb) <= 2 * TOL64 * np.abs(Wb))
+    assert abs(U.sum() - g.npix) <= 1e-12 * g.npix
+    assert abs(W.sum() - x.sum()) <= 1e-12 * np.abs(x).sum()
+    bins = np.unique(np.r_[0, 1, inst.npt - 1, np.random.default_rng(2).choice(inst.npt, 13,
+                                                                                  replace=False)])
+    for b, ((Io, Wo, Uo), (_, Wa, _)) in _sampled_bins_oracle(g, inst.npt, x, bins).items():
+        assert abs(W[b] - Wo[0]) <= TOL64 * Wa[0], (b, W[b], Wo[0])
+        assert abs(U[b] - Uo[0]) <= TOL64 * Uo[0], (b, U[b], Uo[0])
+        assert abs(I[b] - Io[0]) <= TOL64 * Wa[0] / Uo[0], (b, I[b], Io[0])
