@@ -297,8 +297,10 @@ int azi_plan_tile_schedule(const azi_plan* plan, const azi_tiling* tiling, int32
  * entries of one pixel inside one band (consecutive bins) share one word
  * (pixel, first row, count) and one gather of the pixel; the coefficients
  * follow slot-major per group of 64 runs.  Pieces hold tile_nnz / 2 runs;
- * the band value of the tiling is ignored.  A batch built from such plans
- * uses AZI_LAYOUT_BAND.  Images up to 2^27 pixels.
+ * the band value of the tiling is ignored (bands of 4 bins); block 128
+ * gives 128-thread workgroups (for batches of small images), any other
+ * value 256.  Images up to 2^27 pixels; a batch up to 2^31 runs and
+ * entries.
  * Set before azi_plan_upload (a later call re-uploads).
  */
 #define AZI_LAYOUT_PIXEL 0

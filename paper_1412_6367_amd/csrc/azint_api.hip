@@ -202,7 +202,7 @@ struct azi_batch {
     int32_t ntiles = 0, nsplits = 0, nparts = 0;
     DevBuf rp, indices, data, colptr, rowidx, cdata, tiles, splits, parts, vwork, order, xwork, pos,
         stiles, lidx, dest, btiles, brows, blp, bcoef, bin_ptr, bparts, npieces_buf, npacked, ncoef,
-        bin_slot, bin_count, nparts_buf, cfirst;
+        bin_slot, bin_count, nparts_buf, cfirst, rgbase;
     int32_t nbtiles = 0, npieces = 0, band_rows = 8;
     std::vector<int64_t> cz_off;     // CSC entries of instance k
     std::vector<int64_t> piece_off;  // band pieces of instance k
@@ -337,7 +337,7 @@ int plan_upload_bands(azi_plan* p) {
     if (p->layout == AZI_LAYOUT_RUN) {
         try {
             azi::RunMatrix rm;
-            if (!azi::build_runs(p->m, std::max(64, p->tiling.tile_nnz / 2), rm))
+            if (!azi::build_runs(p->m, std::max(64, p->tiling.tile_nnz / 2), 0, 0, rm))
                 return fail(AZI_EOVERFLOW,
                             "the run layout takes images below 2^27 pixels and 2^31 entries");
             azi::BandMatrix bm;
@@ -1323,14 +1323,11 @@ int azi_batch_create(azi_plan* const* plans, int32_t n, int32_t device, azi_batc
     *out = nullptr;
     for (int32_t k = 0; k < n; ++k) {
         if (!plans[k]) return fail(AZI_EINVAL, "plan is NULL");
-        const auto batch_layout = [](const azi_plan* q) {
-            return q->layout == AZI_LAYOUT_RUN ? AZI_LAYOUT_BAND : q->layout;
-        };
         if (plans[k]->dtype != plans[0]->dtype || plans[k]->accum != plans[0]->accum ||
-            batch_layout(plans[k]) != batch_layout(plans[0]))
+            plans[k]->layout != plans[0]->layout)
             return fail(AZI_EINVAL, "plans of a batch must share dtype, accumulation and layout");
     if (plans[0]->layout == AZI_LAYOUT_FUSED)
-        return fail(AZI_EINVAL, "batches take the pixel, ring, tile or band layout");
+        return fail(AZI_EINVAL, "batches take the pixel, ring, tile, band or run layout");
     }
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || count < 1)
@@ -1343,8 +1340,7 @@ int azi_batch_create(azi_plan* const* plans, int32_t n, int32_t device, azi_batc
     b->accum = plans[0]->accum;
     b->device = device;
     b->tiling = plans[0]->tiling;
-    // batches keep the band layout's per-entry encoding
-    b->layout = plans[0]->layout == AZI_LAYOUT_RUN ? AZI_LAYOUT_BAND : plans[0]->layout;
+    b->layout = plans[0]->layout;
     b->pix_off.assign(n + 1, 0);
     b->bin_off.assign(n + 1, 0);
     b->nz_off.assign(n + 1, 0);
@@ -1405,7 +1401,7 @@ int azi_batch_create(azi_plan* const* plans, int32_t n, int32_t device, azi_batc
                 b->rp_host[b->ip_off[k] + r] = m.indptr[r] + (int32_t)z0;
         }
         b->cz_off = cz_off;
-        if (b->layout == AZI_LAYOUT_BAND) {
+        if (is_band(b->layout)) {
             std::vector<const azi::HostMatrix*> ms(n);
             for (int32_t k = 0; k < n; ++k) ms[k] = &plans[k]->m;
             int rc2 = batch_build_bands(b.get(), ms);
@@ -1512,7 +1508,7 @@ int azi_batch_set_tiling(azi_batch* b, const azi_tiling* t) {
     b->tiling = *t;
     if (retile) {
         AZI_HIP(hipDeviceSynchronize(), "synchronise before retiling");
-        if (b->layout == AZI_LAYOUT_BAND && b->npieces_buf.p) {
+        if (is_band(b->layout) && b->npieces_buf.p) {
             int rc = batch_rebuild_bands(b);
             if (rc != AZI_OK) return rc;
         }
@@ -1539,6 +1535,34 @@ namespace {
 // Brings a batch's images into its work image (ring positions, or a cast
 // copy), instance range [k0, k1) only.
 int batch_build_bands(azi_batch* b, const std::vector<const azi::HostMatrix*>& ms) {
+    b->rgbase.release();
+    if (b->layout == AZI_LAYOUT_RUN) {
+        azi::RunMatrix rm;
+        b->band_rows = azi::kRunRows;
+        b->piece_off.assign(b->n + 1, 0);
+        for (int32_t k = 0; k < b->n; ++k) {
+            b->piece_off[k] = (int64_t)rm.pieces.size();
+            if (!azi::build_runs(*ms[k], std::max(64, b->tiling.tile_nnz / 2), b->pix_off[k],
+                                 b->bin_off[k], rm))
+                return fail(AZI_EOVERFLOW,
+                            "the run layout takes images below 2^27 pixels and 2^31 runs and "
+                            "entries per batch");
+        }
+        b->piece_off[b->n] = (int64_t)rm.pieces.size();
+        azi::BandMatrix bm;
+        bm.pieces.swap(rm.pieces);
+        bm.packed.swap(rm.runs);
+        bm.coef.swap(rm.coef);
+        bm.bin_slot.swap(rm.bin_slot);
+        bm.bin_count.swap(rm.bin_count);
+        bm.nslots = rm.nslots;
+        int rc = upload_bands(bm, b->dtype, b->device, b->npieces_buf, b->npacked, b->ncoef,
+                              b->bin_slot, b->bin_count, b->nparts_buf);
+        if (rc != AZI_OK) return rc;
+        AZI_HIP(b->rgbase.upload(rm.gbase.data(), rm.gbase.size() * 4, b->device), "run groups");
+        b->npieces = (int32_t)bm.pieces.size();
+        return AZI_OK;
+    }
     azi::BandMatrix bm;
     b->band_rows = band_rows_of(b->tiling);
     b->piece_off.assign(b->n + 1, 0);
@@ -1598,6 +1622,7 @@ azi::BandLaunch batch_band_args(const azi_batch* b, const void* x, int32_t k0, i
     a.pieces = b->npieces_buf.as<azi::BandPiece>() + b->piece_off[k0];
     a.npieces = (int32_t)(b->piece_off[k1] - b->piece_off[k0]);
     a.packed = b->npacked.as<int32_t>();
+    a.gbase = b->layout == AZI_LAYOUT_RUN ? b->rgbase.as<int32_t>() : nullptr;
     a.coef = b->ncoef.p;
     a.bin_slot = b->bin_slot.as<int32_t>();
     a.bin_count = b->bin_count.as<int32_t>();
@@ -1697,7 +1722,7 @@ int azi_batch_forward(azi_batch* b, const void* x, void* I, void* W, void* U, do
                 "batched blocked kernels");
         return AZI_OK;
     }
-    if (b->layout == AZI_LAYOUT_BAND) {
+    if (is_band(b->layout)) {
         AZI_HIP(azi::launch_band(batch_band_args(b, x, 0, b->n, I, W, U, empty), s),
                 "batched band kernels");
         return AZI_OK;
@@ -1726,7 +1751,7 @@ int azi_batch_forward_raw(azi_batch* b, const void* raw, int32_t raw_dtype, void
                 "batched blocked kernels");
         return AZI_OK;
     }
-    if (b->layout == AZI_LAYOUT_BAND && b->tiling.stage == AZI_STAGE_FUSE) {
+    if (is_band(b->layout) && b->tiling.stage == AZI_STAGE_FUSE) {
         azi::BandLaunch a = batch_band_args(b, nullptr, 0, b->n, I, W, U, empty);
         a.raw = raw;
         a.raw_dtype = raw_dtype;
@@ -1735,7 +1760,7 @@ int azi_batch_forward_raw(azi_batch* b, const void* raw, int32_t raw_dtype, void
     }
     int rc = batch_stage(b, raw, raw_dtype, 0, b->n, s);
     if (rc != AZI_OK) return rc;
-    if (b->layout == AZI_LAYOUT_BAND) {
+    if (is_band(b->layout)) {
         AZI_HIP(azi::launch_band(batch_band_args(b, b->xwork.p, 0, b->n, I, W, U, empty), s),
                 "batched band kernels");
         return AZI_OK;
@@ -1758,7 +1783,7 @@ int azi_batch_forward_loop(azi_batch* b, const void* x, void* I, void* W, void* 
                     "per-instance blocked kernels");
         return AZI_OK;
     }
-    if (b->layout == AZI_LAYOUT_BAND) {
+    if (is_band(b->layout)) {
         for (int32_t k = 0; k < b->n; ++k)
             AZI_HIP(azi::launch_band(batch_band_args(b, x, k, k + 1, I, W, U, empty), s),
                     "per-instance band kernels");
@@ -1821,7 +1846,12 @@ int azi_batch_autotune(azi_batch* b, const void* x, void* I, void* W, void* U, v
     // candidate tilings: the knobs that matter for the batch's layout
     std::vector<azi_tiling> cands;
     const int32_t st = b->tiling.stage;
-    if (b->layout == AZI_LAYOUT_BAND) {
+    if (b->layout == AZI_LAYOUT_RUN) {
+        // bands of 4 bins are fixed for runs; workgroups of 128 or 256 threads
+        for (int32_t tn : {1024, 2048, 4096, 8192, 16384})
+            for (int32_t bl : {128, 256})
+                for (int32_t gm : {0, 8}) cands.push_back(azi_tiling{tn, bl, 5, gm * ncu, 4, st});
+    } else if (b->layout == AZI_LAYOUT_BAND) {
         for (int32_t tn : {1024, 2048, 4096, 8192})
             for (int32_t band : {4, 8})
                 for (int32_t bl : {128, 256, 512})
@@ -1849,7 +1879,7 @@ int azi_batch_autotune(azi_batch* b, const void* x, void* I, void* W, void* U, v
 
         rc = azi_batch_set_tiling(b, &cand);
         if (rc != AZI_OK) break;
-        const int32_t units = b->layout == AZI_LAYOUT_BAND   ? b->npieces
+        const int32_t units = is_band(b->layout)             ? b->npieces
                               : b->layout == AZI_LAYOUT_TILE ? b->nbtiles
                                                              : b->ntiles;
         if (cand.grid > 0 && cand.grid >= units) continue;  // same as one per unit

@@ -192,10 +192,13 @@ struct RunMatrix {
     std::vector<int32_t> bin_slot, bin_count;
     int32_t nslots = 0;
 };
-// Builds the run encoding of `m` with pieces of at most piece_runs runs (a
-// multiple of 64).  Returns false if the image has 2^27 pixels or more or
-// the coefficients do not fit int32 offsets.
-bool build_runs(const HostMatrix& m, int32_t piece_runs, RunMatrix& rm);
+// Appends the run encoding of one instance (CSC `m`; its pixels start at
+// pix_off, its bins at bin_off of the batch) to `rm`, with pieces of at most
+// piece_runs runs (rounded down to a multiple of 64).  Returns false if the
+// image has 2^27 pixels or more or the runs or coefficients would not fit
+// int32 positions.
+bool build_runs(const HostMatrix& m, int32_t piece_runs, int64_t pix_off, int64_t bin_off,
+                RunMatrix& rm);
 
 // Matrix-free ("fused") schedule: the image cut into kFusedH x kFusedW
 // tiles; tile t feeds the bin window [wlo, wlo + nwin) and writes the partial

@@ -368,9 +368,9 @@ __global__ __launch_bounds__(BLOCK) void k_band(const BandPiece* __restrict__ pi
 // the pixel once for the whole run and adds each coefficient's product to
 // the accumulator of its row.  U groups per wavefront are in flight at a
 // time.  The partial sums are reduced and written as in k_band.
-template <class T, class Acc, int U, class RawT = T, bool kCorr = false,
+template <class T, class Acc, int U, int BLOCK, class RawT = T, bool kCorr = false,
           class CorrT = typename Pair2<T>::type>
-__global__ __launch_bounds__(256) void k_band_runs(const BandPiece* __restrict__ pieces,
+__global__ __launch_bounds__(BLOCK) void k_band_runs(const BandPiece* __restrict__ pieces,
                                                    int32_t npieces,
                                                    const int32_t* __restrict__ runs,
                                                    const int32_t* __restrict__ gbase,
@@ -379,7 +379,7 @@ __global__ __launch_bounds__(256) void k_band_runs(const BandPiece* __restrict__
                                                    Acc* __restrict__ parts,
                                                    const RawT* __restrict__ raw = nullptr,
                                                    const CorrT* __restrict__ corr = nullptr) {
-    constexpr int BLOCK = 256, R = kRunRows;
+    constexpr int R = kRunRows;
     constexpr int32_t kMask = (1 << kBandShift) - 1;
     __shared__ Acc red[BLOCK / kWave][R];
     const int tid = threadIdx.x;
@@ -891,11 +891,18 @@ template <class T> constexpr int kRunGroups = sizeof(T) == 8 ? 2 : 4;
 
 template <class T, class Acc, class RawT, class CorrT>
 hipError_t runs_launch_raw(const BandLaunch& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_band_runs<T, Acc, kRunGroups<T>, RawT, true, CorrT>), dim3(grid),
-                       dim3(256), 0, s, a.pieces, a.npieces, a.packed, a.gbase,
-                       static_cast<const T*>(a.coef), static_cast<const T*>(nullptr),
-                       static_cast<Acc*>(a.parts), static_cast<const RawT*>(a.raw),
-                       static_cast<const CorrT*>(a.corr));
+    if (a.block == 128)
+        hipLaunchKernelGGL((k_band_runs<T, Acc, kRunGroups<T>, 128, RawT, true, CorrT>),
+                           dim3(grid), dim3(128), 0, s, a.pieces, a.npieces, a.packed, a.gbase,
+                           static_cast<const T*>(a.coef), static_cast<const T*>(nullptr),
+                           static_cast<Acc*>(a.parts), static_cast<const RawT*>(a.raw),
+                           static_cast<const CorrT*>(a.corr));
+    else
+        hipLaunchKernelGGL((k_band_runs<T, Acc, kRunGroups<T>, 256, RawT, true, CorrT>),
+                           dim3(grid), dim3(256), 0, s, a.pieces, a.npieces, a.packed, a.gbase,
+                           static_cast<const T*>(a.coef), static_cast<const T*>(nullptr),
+                           static_cast<Acc*>(a.parts), static_cast<const RawT*>(a.raw),
+                           static_cast<const CorrT*>(a.corr));
     return hipGetLastError();
 }
 
@@ -913,11 +920,18 @@ template <class T, class Acc>
 hipError_t runs_launch(const BandLaunch& a, hipStream_t s) {
     const int grid = a.grid > 0 ? a.grid : a.npieces;
     if (!a.raw) {
-        hipLaunchKernelGGL((k_band_runs<T, Acc, kRunGroups<T>>), dim3(grid), dim3(256), 0, s,
-                           a.pieces, a.npieces, a.packed, a.gbase, static_cast<const T*>(a.coef),
-                           static_cast<const T*>(a.x), static_cast<Acc*>(a.parts),
-                           static_cast<const T*>(nullptr),
-                           static_cast<const typename Pair2<T>::type*>(nullptr));
+        if (a.block == 128)
+            hipLaunchKernelGGL((k_band_runs<T, Acc, kRunGroups<T>, 128>), dim3(grid), dim3(128),
+                               0, s, a.pieces, a.npieces, a.packed, a.gbase,
+                               static_cast<const T*>(a.coef), static_cast<const T*>(a.x),
+                               static_cast<Acc*>(a.parts), static_cast<const T*>(nullptr),
+                               static_cast<const typename Pair2<T>::type*>(nullptr));
+        else
+            hipLaunchKernelGGL((k_band_runs<T, Acc, kRunGroups<T>, 256>), dim3(grid), dim3(256),
+                               0, s, a.pieces, a.npieces, a.packed, a.gbase,
+                               static_cast<const T*>(a.coef), static_cast<const T*>(a.x),
+                               static_cast<Acc*>(a.parts), static_cast<const T*>(nullptr),
+                               static_cast<const typename Pair2<T>::type*>(nullptr));
         return hipGetLastError();
     }
     switch (a.raw_dtype) {

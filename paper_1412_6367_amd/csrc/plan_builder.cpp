@@ -474,9 +474,10 @@ void band_pieces(const int64_t* start, int32_t nbands, int32_t npt, int32_t R, i
     }
 }
 
-bool build_runs(const HostMatrix& m, int32_t piece_runs, RunMatrix& rm) {
+bool build_runs(const HostMatrix& m, int32_t piece_runs, int64_t pix_off, int64_t bin_off,
+                RunMatrix& rm) {
     constexpr int32_t R = kRunRows;
-    if (m.npix >= ((int64_t)1 << kBandShift) || m.nnz() >= (int64_t)INT32_MAX) return false;
+    if (m.npix >= ((int64_t)1 << kBandShift)) return false;
     const int32_t npt = m.npt;
     const int32_t nbands = (npt + R - 1) / R;
     // runs: maximal stretches of a pixel's entries in one band with
@@ -497,23 +498,26 @@ bool build_runs(const HostMatrix& m, int32_t piece_runs, RunMatrix& rm) {
     };
     std::vector<int64_t> cnt(nbands, 0);
     for_runs([&](int64_t, int32_t k, int32_t) { cnt[m.rowidx[k] / R]++; });
-    std::vector<int64_t> start(nbands + 1, 0);
+    // this instance's runs begin at the (64-aligned) end of rm.runs
+    const int64_t base = (int64_t)rm.runs.size();
+    std::vector<int64_t> start(nbands + 1, base);
     for (int32_t b = 0; b < nbands; ++b) start[b + 1] = start[b] + (cnt[b] + 63) / 64 * 64;
-    if (start[nbands] >= (int64_t)INT32_MAX) return false;
-    rm.runs.assign(start[nbands], 0);
-    std::vector<int32_t> first_k(start[nbands], 0);  // CSC position of each run's first entry
+    if (start[nbands] >= (int64_t)INT32_MAX ||
+        (int64_t)rm.coef.size() + m.nnz() >= (int64_t)INT32_MAX)
+        return false;
+    rm.runs.resize(start[nbands], 0);
+    std::vector<int32_t> first_k(start[nbands] - base, 0);  // CSC position of a run's first entry
     std::vector<int64_t> cur(start.begin(), start.end() - 1);
     for_runs([&](int64_t p, int32_t k, int32_t e) {
         const int32_t b = m.rowidx[k];
         const int64_t z = cur[b / R]++;
         rm.runs[z] = (int32_t)p | ((b % R) << kBandShift) | ((e - k - 1) << kRunCountShift);
-        first_k[z] = k;
+        first_k[z - base] = k;
     });
-    // coefficients, slot-major per group of 64 runs
-    const int64_t ngroups = start[nbands] / 64;
-    rm.gbase.assign(ngroups, 0);
-    rm.coef.assign(m.nnz(), 0.0);
-    int64_t pos = 0;
+    // coefficients, slot-major per group of 64 runs (group = run index / 64)
+    rm.gbase.resize(start[nbands] / 64, 0);
+    int64_t pos = (int64_t)rm.coef.size();
+    rm.coef.resize(pos + m.nnz(), 0.0);
     for (int32_t b = 0; b < nbands; ++b) {
         for (int64_t g = start[b] / 64; g < start[b + 1] / 64; ++g) {
             rm.gbase[g] = (int32_t)pos;
@@ -521,14 +525,14 @@ bool build_runs(const HostMatrix& m, int32_t piece_runs, RunMatrix& rm) {
             for (int32_t j = 0; j < R; ++j)
                 for (int64_t z = z0; z < z1; ++z)
                     if ((rm.runs[z] >> kRunCountShift) + 1 > j)
-                        rm.coef[pos++] = m.cdata[first_k[z] + j];
+                        rm.coef[pos++] = m.cdata[first_k[z - base] + j];
         }
     }
     // pieces: each band cut into near-equal parts on multiples of 64 runs
-    rm.pieces.clear();
-    rm.bin_slot.assign(npt, 0);
-    rm.bin_count.assign(npt, 0);
-    rm.nslots = 0;
+    if (rm.bin_slot.size() < (size_t)(bin_off + npt)) {
+        rm.bin_slot.resize(bin_off + npt, 0);
+        rm.bin_count.resize(bin_off + npt, 0);
+    }
     const int64_t chunk = std::max<int64_t>(64, piece_runs / 64 * 64);
     for (int32_t band = 0; band < nbands; ++band) {
         const int32_t bin0 = band * R;
@@ -536,15 +540,15 @@ bool build_runs(const HostMatrix& m, int32_t piece_runs, RunMatrix& rm) {
         const int64_t z0 = start[band], len = cnt[band];
         const int32_t pieces = len > 0 ? (int32_t)((len + chunk - 1) / chunk) : 1;
         for (int32_t r = 0; r < nrows; ++r) {
-            rm.bin_slot[bin0 + r] = rm.nslots + r;
-            rm.bin_count[bin0 + r] = pieces;
+            rm.bin_slot[bin_off + bin0 + r] = rm.nslots + r;
+            rm.bin_count[bin_off + bin0 + r] = pieces;
         }
         const int64_t groups = (len + 63) / 64;
         int64_t prev = z0;
         for (int32_t k = 0; k < pieces; ++k) {
             const int64_t next = k + 1 < pieces ? z0 + groups * (k + 1) / pieces * 64 : z0 + len;
-            rm.pieces.push_back(BandPiece{(int32_t)prev, (int32_t)next, bin0, nrows, rm.nslots, 0,
-                                          0});
+            rm.pieces.push_back(BandPiece{(int32_t)prev, (int32_t)next, (int32_t)(bin_off + bin0),
+                                          nrows, rm.nslots, 0, pix_off});
             rm.nslots += R;
             prev = next;
         }

@@ -41,7 +41,8 @@ def small_batch(n=40, seed=21):
 
 @pytest.mark.parametrize("layout,stage", [("ring", "tile"), ("ring", "gather"),
                                           ("ring", "scatter"), ("pixel", "tile"),
-                                          ("tile", "tile"), ("band", "tile")])
+                                          ("tile", "tile"), ("band", "tile"),
+                                          ("run", "tile"), ("run", "fuse")])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_batch_equals_per_instance_and_oracle(dtype, layout, stage, dev):
     say("batch vs per instance", dtype, layout, stage)
@@ -129,7 +130,7 @@ def test_batch_backward(dtype, dev):
         assert norm_err(gx[po[k]:po[k + 1]].double().cpu().numpy(), ref, scale) <= tol, k
 
 
-@pytest.mark.parametrize("layout", ["ring", "tile", "band"])
+@pytest.mark.parametrize("layout", ["ring", "tile", "band", "run"])
 def test_graph_replays_match_eager(layout, dev):
     """A captured forward+backward replays the same bits every time, with
     eager work and synchronisations in between."""
@@ -182,7 +183,7 @@ def test_autotune_picks_valid_config(dev, tmp_path):
     rep = az.autotune(batch, x, cache_path=str(cache))
     best = rep["best"]
     assert batch.tiling()["tile_nnz"] == best["tile_nnz"]
-    assert len(rep["candidates"]) >= 10
+    assert len(rep["candidates"]) >= 5
     got = batch.forward(x)
     torch.cuda.synchronize()
     for a, b in zip(ref, got):
@@ -194,7 +195,7 @@ def test_autotune_picks_valid_config(dev, tmp_path):
     assert json.loads(cache.read_text())
 
 
-@pytest.mark.parametrize("layout", ["band", "tile", "ring"])
+@pytest.mark.parametrize("layout", ["run", "band", "tile", "ring"])
 def test_c3_full_batch_sampled(layout, dev):
     """The 4096-instance workload at full size, in the benchmark's launch
     configuration: batched forward == per-instance loop bit for bit, 12
@@ -308,25 +309,38 @@ def test_band_fused_correction(dtype, dev):
         assert torch.equal(I, I0) and torch.equal(W, W0) and torch.equal(U, U0)
 
 
-def test_batch_of_run_plans_uses_band_entries(dev):
-    """Plans in the run layout (alone or mixed with band plans) make a batch
-    in the band layout's per-entry encoding: the same bits as a batch of
-    band plans."""
+def test_batch_of_run_plans(dev):
+    """A batch of run-layout plans keeps the run encoding: bit for bit the
+    plan-by-plan results, within the FP64 tolerance of the oracle, and the
+    raw-frame form equals the corrected-image form for uncorrected frames.
+    Plans of the band and run layouts do not mix in one batch."""
+    import oracle
+    from tests.test_gpu_forward import TOL64, check
     say("batch of run plans")
-    insts = small_batch(12, 33)
-    x = torch.from_numpy(flat_images(insts, np.float64)).to(dev)
-    _, bb = make_batch(insts, torch.float64, dev, layout="band")
-    _, br = make_batch(insts, torch.float64, dev, layout="run")
-    az = azint()
-    mixed = []
-    for k, inst in enumerate(insts):
+    insts = small_batch(24, 33)
+    plans, br = make_batch(insts, torch.float64, dev, layout="run")
+    x = flat_images(insts, np.float64)
+    I, W, U = br.forward(torch.from_numpy(x).to(dev))
+    raw = torch.from_numpy(np.concatenate([i.raw.reshape(-1) for i in insts])).to(dev)
+    Ir, Wr, Ur = br.forward_raw(raw)
+    torch.cuda.synchronize()
+    assert torch.equal(I, Ir) and torch.equal(W, Wr) and torch.equal(U, Ur)
+    po = bo = 0
+    for plan, inst in zip(plans, insts):
         g = inst.geom
-        mixed.append(az.Plan(g.h, g.w, inst.npt, center=(g.center_y, g.center_x),
-                             layout="run" if k % 2 else "band"))
-    bm = az.Batch(mixed, device=dev)
-    ref = bb.forward(x)
-    for b in (br, bm):
-        out = b.forward(x)
-        torch.cuda.synchronize()
-        for u, v in zip(out, ref):
-            assert torch.equal(u, v)
+        plan.upload(dev)
+        xk = inst.raw.reshape(-1).astype(np.float64)
+        out = plan.integrate(torch.from_numpy(xk).to(dev))
+        n = inst.npt
+        for a, b in zip((I, W, U), out):
+            assert torch.equal(a[bo:bo + n], b)
+        m = oracle.build_matrix(h=g.h, w=g.w, pixel_y=g.pixel_y, pixel_x=g.pixel_x,
+                                center_y=g.center_y, center_x=g.center_x, dist=g.dist,
+                                wavelength=g.wavelength, npt=n)
+        check(out, m, xk, TOL64, what=f"instance {g.h}x{g.w}")
+        bo += n
+        po += g.npix
+    az = azint()
+    mixed = [az.Plan(10, 12, 6, layout="run"), az.Plan(10, 12, 6, layout="band")]
+    with pytest.raises(az.AzintError):
+        az.Batch(mixed, device=dev)
