@@ -334,7 +334,8 @@ class Plan:
         return tiles, splits
 
     def set_layout(self, layout):
-        """"pixel", "ring", "tile" or "band" layout of the device matrix."""
+        """"pixel", "ring", "tile", "band", "fused" or "run" layout of the
+        device matrix."""
         _check(lib().azi_plan_set_layout(self._h, LAYOUTS[layout]))
 
     def layout(self):
@@ -356,7 +357,7 @@ class Plan:
         return int(lib().azi_plan_device_bytes(self._h))
 
     def correction_bytes(self):
-        """Bytes per pixel of the correction the raw-frame band gather reads
+        """Bytes per pixel of the correction the raw-frame band / run gather reads
         (0 when there is none)."""
         return int(lib().azi_plan_correction_bytes(self._h))
 

@@ -1,12 +1,14 @@
 // HIP kernels for gfx950 (CDNA4): the per-frame hot path of azimuthal
 // integration.
 //
-//   k_band     the default integration (band layout): bands of R bins whose
-//              entries are ordered by pixel, so a wavefront gathers nearly
-//              consecutive pixels of the row-major image; R lane-private
-//              accumulators per lane; the partial sums of each piece go to
-//              slots that k_band_reduce adds in piece order.  Its raw-frame
-//              form casts and corrects every pixel it gathers.
+//   k_band_runs  the default integration (run layout): bands of 4 bins
+//              whose entries are ordered by pixel, stored as one word per
+//              run of a pixel's entries in the band, so a wavefront gathers
+//              nearly consecutive pixels of the row-major image once per run;
+//              lane-private accumulators per band row; the partial sums of
+//              each piece go to slots that k_band_reduce adds in piece order.
+//              Its raw-frame form casts and corrects every pixel it gathers.
+//   k_band     the same over one word per entry (band layout, R = 4, 8, 16).
 //   k_spmv     gather-form sparse product of Section 5.2 on the CSR of
 //              Section 5.2.1 (pixel and ring layouts): every output bin
 //              reads the pixels that feed it and forms W = sum c*x and
@@ -17,7 +19,8 @@
 //              partials added by k_block_reduce.
 //   k_correct  cast + correction map of Section 6.4; k_stage_* the same
 //              into ring order; k_norm (flat * solid) * polar and
-//              k_corr_pair (dark, 1 / norm), formed once per correction set.
+//              k_corr_pair (dark, 1 / norm) or k_corr_record12, formed once
+//              per correction set.
 //   k_prep_v / k_csc_bwd   adjoint: gx_p = sum_b A_bp (gI_b / U_b + gW_b),
 //              one thread per pixel over its pixel-major (CSC) entries.
 //
@@ -1086,6 +1089,8 @@ __global__ void k_corr_pair(const T* __restrict__ dark, const T* __restrict__ no
 }  // namespace
 
 namespace {
+// flag[0] = 1 when some dark[i] does not survive the round trip through
+// float (every writer stores the same 1, so their order does not matter).
 __global__ void k_dark_is_float(const double* __restrict__ dark, int64_t n,
                                 int32_t* __restrict__ flag) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
