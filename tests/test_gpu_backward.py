@@ -156,3 +156,40 @@ def test_backward_f32(dev):
     U32 = U.cpu().numpy().astype(np.float64)
     ref = oracle.integrate_vjp(m32, U32, gI.astype(np.float64))
     assert norm_err(gx, ref, grad_scale(m32, U32, gI.astype(np.float64), None)) <= 2.0 ** -22
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_first_bin_adjoint_bits_equal_per_entry_adjoint(dtype, dev):
+    """One-dimensional plans run the adjoint from each pixel's first bin (its
+    bins are consecutive); a batch that also holds a 2-D plan reads the
+    per-entry bin ids of the CSC for all its pixels.  The products are added
+    in the same order either way, so the 1-D instances' gradients must agree
+    bit for bit."""
+    say("first-bin vs per-entry adjoint", dtype)
+    az = azint()
+    shapes = [(90, 100, 44.6, 50.2, 40), (31, 29, 15.5, 14.5, 300), (1, 17, 0.5, 8.5, 5),
+              (257, 263, 128.5, 131.5, 256)]
+    plans = [az.Plan(h, w, n, center=(cy, cx), dtype=dtype, layout="pixel")
+             for (h, w, cy, cx, n) in shapes]
+    two = az.Plan(40, 50, 20, npt_azim=8, dtype=dtype, layout="pixel")
+    batch = az.Batch(plans[:2] + [two] + plans[2:], device=dev)
+    npd = np.float64 if dtype == torch.float64 else np.float32
+    rng = np.random.default_rng(31)
+    xs = [rng.uniform(0, 1, size=p.npix).astype(npd) for p in plans[:2] + [two] + plans[2:]]
+    x = torch.from_numpy(np.concatenate(xs)).to(dev)
+    I, W, U = batch.forward(x)
+    gI = torch.from_numpy(rng.standard_normal(batch.npt).astype(npd)).to(dev)
+    gW = torch.from_numpy(rng.standard_normal(batch.npt).astype(npd)).to(dev)
+    gx = batch.backward(U, gI, gW)
+    torch.cuda.synchronize()
+    po, bo = batch.pix_off, batch.bin_off
+    order = [0, 1, None, 2, 3]
+    for k, j in enumerate(order):
+        if j is None:
+            continue
+        p = plans[j]
+        p.upload(dev)
+        gk = p.backward(U[bo[k]:bo[k + 1]].contiguous(), gI[bo[k]:bo[k + 1]].contiguous(),
+                        gW[bo[k]:bo[k + 1]].contiguous())
+        torch.cuda.synchronize()
+        assert torch.equal(gk, gx[po[k]:po[k + 1]]), shapes[j]
