@@ -3,8 +3,8 @@
 Python binding of ``include/azint.h``: argument marshalling only.  Every step
 of the per-frame path runs in the library's HIP kernels; PyTorch provides
 device memory and streams.  Importing the package does not need a GPU; the
-library itself must have been built (``__graft_entry__.build()`` or
-``python paper_1412_6367_amd/build.py``), otherwise the first call raises.
+library itself must have been built (``python paper_1412_6367_amd/build.py``),
+otherwise the first call raises.
 
 Method: Kieffer & Ashiotis, "PyFAI: a Python library for high performance
 azimuthal integration on GPU" (EuroSciPy 2014) -- bounding-box pixel
@@ -134,7 +134,7 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise AzintError(f"{LIB_PATH} is missing: build it first "
-                             "(python -c 'import __graft_entry__ as g; g.build()')")
+                             "(python paper_1412_6367_amd/build.py)")
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             f = getattr(L, name)
