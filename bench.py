@@ -15,7 +15,8 @@ a cold-cache timing of the integration kernel, the 4096-instance batch (one
 persistent graph launch vs a per-instance loop), the 1e6-pixel adjoint, the
 1024-instance float32 forward+adjoint batch with autotuned tiles, the
 matrix-free (fused) kernel on the same frame, two-dimensional integration of
-the frame (1000 x 360 bins), and host- vs device-built plans.
+the frame (1000 x 360 bins), host- vs device-built plans, and full pixel
+splitting of the frame.
 """
 import argparse
 import json
@@ -439,6 +440,43 @@ def plan_build_line(az, torch, np, synth, dev):
     return line
 
 
+def full_split_line(az, torch, np, synth, dev, reps=50):
+    """Full pixel splitting (Section 4.2) of the c2 frame: host and device
+    plan builds, and the raw-frame step with the four corrections in the
+    default layout (the same kernels as the bounding-box step, over the
+    full-split coefficients)."""
+    c = synth.C2
+    inst = synth.instance(c["n"], c["seed"], corrections=True)
+    g = inst.geom
+    t0 = time.perf_counter()
+    plan = az.Plan(g.h, g.w, inst.npt, center=(g.center_y, g.center_x), split="full", device=dev)
+    torch.cuda.synchronize()
+    host_s = time.perf_counter() - t0
+    az.Plan.on_device(g.h, g.w, inst.npt, center=(g.center_y, g.center_x), split="full",
+                      device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dp = az.Plan.on_device(g.h, g.w, inst.npt, center=(g.center_y, g.center_x), split="full",
+                           device=dev)
+    torch.cuda.synchronize()
+    dev_s = time.perf_counter() - t0
+    del dp
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a).reshape(-1)).to(dev)
+    plan.set_corrections(t(inst.dark), t(inst.flat), t(inst.solid), t(inst.polar))
+    raw = t(inst.raw)
+    outs = tuple(torch.empty(inst.npt, dtype=torch.float64, device=dev) for _ in range(3))
+    ms = _timed(torch, lambda: plan.integrate_raw(raw, out=outs), reps)
+    nnz = plan.nnz
+    by = raw_bytes(nnz, g.npix, inst.npt, 8, plan.correction_bytes())
+    line = dict(npix=g.npix, npt=inst.npt, nnz=nnz, layout=plan.layout(),
+                host_build_upload_s=host_s, device_build_s=dev_s, step_ms=ms,
+                step_bytes=by, step_gbs=by / (ms * 1e6), step_frac=by / (ms * 1e6) / HBM_PEAK_GBS,
+                elements_per_s=g.npix / (ms * 1e-3))
+    del plan
+    torch.cuda.empty_cache()
+    return line
+
+
 def cpu_baseline(np, synth):
     """The FP64 oracle on the host: one full ~1e7-pixel frame per repetition
     (correction + integration; the matrix is built beforehand, untimed, as
@@ -549,7 +587,8 @@ def main():
                                            True, True)
         log(f"[c5] {json.dumps(result['lines']['c5'])}")
     for name, fn in (("c2_fuse_stage", fuse_stage_line), ("c2_fused", fused_line),
-                     ("c2_2d", two_d_line), ("c2_plan_build", plan_build_line)):
+                     ("c2_2d", two_d_line), ("c2_plan_build", plan_build_line),
+                     ("c2_full_split", full_split_line)):
         if run(name):
             result["lines"][name] = fn(az, torch, np, synth, dev)
             log(f"[{name}] {json.dumps(result['lines'][name])}")

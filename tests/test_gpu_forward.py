@@ -448,3 +448,35 @@ def test_run_layout_c2_full_size(dev):
         assert abs(W[b] - Wo[0]) <= TOL64 * Wa[0], (b, W[b], Wo[0])
         assert abs(U[b] - Uo[0]) <= TOL64 * Uo[0], (b, U[b], Uo[0])
         assert abs(I[b] - Io[0]) <= TOL64 * Wa[0] / Uo[0], (b, I[b], Io[0])
+
+
+def test_c2_full_split_full_size(dev):
+    """Full pixel splitting (Section 4.2) of the 10-Mpixel frame in the
+    default layout, as the benchmark times it: conservation over all bins,
+    and three sampled bins against the oracle's polygon clipping of the
+    pixels whose radial box reaches them."""
+    say("c2 full split")
+    az = azint()
+    inst = synth.instance(synth.C2["n"], synth.C2["seed"])
+    g = inst.geom
+    plan = az.Plan(g.h, g.w, inst.npt, center=(g.center_y, g.center_x), split="full", device=dev)
+    x = inst.raw.reshape(-1).astype(np.float64)
+    I, W, U = (a.cpu().numpy() for a in plan.integrate(torch.from_numpy(x).to(dev)))
+    assert abs(U.sum() - g.npix) <= 1e-9 * g.npix
+    assert abs(W.sum() - x.sum()) <= 1e-9 * x.sum()
+    geo = (g.h, g.w, g.pixel_y, g.pixel_x, g.center_y, g.center_x, g.dist, g.wavelength)
+    lo, hi, rc = oracle.pixel_extents(*geo, "r_m")
+    pmin, pmax = oracle.default_range(lo, hi, rc, "full")
+    corners = oracle.pixel_corners(*geo, "r_m")
+    delta = (pmax - pmin) / inst.npt
+    for b in (1, 700, 2900):
+        say("  bin", b)
+        sel = np.nonzero((hi >= pmin + (b - 1) * delta) & (lo <= pmin + (b + 2) * delta))[0]
+        pix, bins, coef = oracle.full_entries(corners[sel], lo[sel], hi[sel], inst.npt, pmin,
+                                              pmax)
+        keep = bins == b
+        xs = x[sel[pix[keep]]]
+        Wo, Uo, Wa = (coef[keep] * xs).sum(), coef[keep].sum(), (coef[keep] * np.abs(xs)).sum()
+        assert abs(W[b] - Wo) <= TOL64 * Wa, (b, W[b], Wo)
+        assert abs(U[b] - Uo) <= TOL64 * Uo, (b, U[b], Uo)
+        assert abs(I[b] - Wo / Uo) <= TOL64 * Wa / Uo, (b, I[b], Wo / Uo)
