@@ -344,3 +344,60 @@ def test_batch_of_run_plans(dev):
     mixed = [az.Plan(10, 12, 6, layout="run"), az.Plan(10, 12, 6, layout="band")]
     with pytest.raises(az.AzintError):
         az.Batch(mixed, device=dev)
+
+
+def test_c5_full_batch_sampled(dev):
+    """The 1024-instance float32 workload at full size (1.4e8 pixels) in the
+    benchmark's launch configuration (default layout, autotuned tiling):
+    the batched forward equals the per-instance loop bit for bit and
+    conserves every instance; sampled instances' forward and adjoint match
+    the FP64 oracle to the float32 tolerance."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+    from tests.test_gpu_forward import TOL32_F64
+    say("c5 full")
+    az = azint()
+    c = synth.C5
+    insts = synth.batch(c["count"], c["lo"], c["hi"], c["seed"], grad=True)
+
+    def mk(inst):
+        g = inst.geom
+        return az.Plan(g.h, g.w, inst.npt, center=(g.center_y, g.center_x),
+                       dtype=torch.float32)
+
+    with ThreadPoolExecutor(16) as ex:
+        plans = list(ex.map(mk, insts))
+    batch = az.Batch(plans, device=dev)
+    x = torch.from_numpy(flat_images(insts, np.float32)).to(dev)
+    az.autotune(batch, x)
+    say("  tiling", batch.tiling())
+    I, W, U = batch.forward(x)
+    Il, Wl, Ul = batch.forward(x, loop=True)
+    gI = torch.from_numpy(np.concatenate([i.grad for i in insts]).astype(np.float32)).to(dev)
+    gx = batch.backward(U, gI)
+    torch.cuda.synchronize()
+    assert torch.equal(I, Il) and torch.equal(W, Wl) and torch.equal(U, Ul)
+    Wh, Uh, gh = W.double().cpu().numpy(), U.double().cpu().numpy(), gx.double().cpu().numpy()
+    xh = x.double().cpu().numpy()
+    po, bo = batch.pix_off, batch.bin_off
+    for k in range(len(insts)):
+        n = po[k + 1] - po[k]
+        assert abs(Uh[bo[k]:bo[k + 1]].sum() - n) <= 1e-5 * n, k
+        xs = xh[po[k]:po[k + 1]].sum()
+        assert abs(Wh[bo[k]:bo[k + 1]].sum() - xs) <= 1e-5 * xs, k
+    sizes = np.diff(po)
+    picks = list(np.random.default_rng(5).choice(len(insts), 6, replace=False))
+    picks.append(int(np.argmax(sizes)))
+    for k in picks:
+        inst = insts[k]
+        g = inst.geom
+        m = oracle_matrix(g.h, g.w, g.center_y, g.center_x, inst.npt)
+        xv = xh[po[k]:po[k + 1]]
+        Io, Wo, Uo = oracle.integrate(m, xv)
+        assert norm_err(Wh[bo[k]:bo[k + 1]], Wo, Wo) <= TOL32_F64, k
+        assert norm_err(Uh[bo[k]:bo[k + 1]], Uo, Uo) <= TOL32_F64, k
+        gk = inst.grad.astype(np.float32).astype(np.float64)
+        ref = oracle.integrate_vjp(m, Uo, gk)
+        scale = oracle.integrate_vjp(m, Uo, np.abs(gk))
+        assert norm_err(gh[po[k]:po[k + 1]], ref, scale) <= TOL32_F64, k
