@@ -132,10 +132,11 @@ def encoding_bytes(plan, np, npix, npt, es, cb):
 
 def pipeline_line(az, torch, np, synth, dev, dtype, steps, warmup, frames_n=4):
     """Step = one raw int32 frame -> I, W, U with the plan's corrections
-    (azi_integrate1d_raw).  With the default tiling the band kernel casts and
-    corrects each pixel it gathers, so the step is that kernel plus the
-    per-bin reduction.  The two-pass form (correction kernel, then the band
-    kernel on the corrected image) is timed beside it."""
+    (azi_integrate1d_raw).  With the default layout and tiling the run
+    kernel casts and corrects each pixel it gathers, so the step is that
+    kernel plus the per-bin reduction.  The two-pass form (correction
+    kernel, then the run kernel on the corrected image) and the step
+    replayed from HIP graphs are timed beside it."""
     c = synth.C2
     inst = synth.instance(c["n"], c["seed"], corrections=True)
     g = inst.geom
@@ -185,6 +186,19 @@ def pipeline_line(az, torch, np, synth, dev, dtype, steps, warmup, frames_n=4):
     torch.cuda.synchronize()
     corr_ms = mean_event_ms([(e[0], e[1]) for e in pairs])
     spmv_ms = mean_event_ms([(e[1], e[2]) for e in pairs])
+    # the same step replayed from HIP graphs (one per rotating frame buffer)
+    graphs = [plan.graph(f, *outs) for f in frames]
+    for k in range(warmup):
+        graphs[k % frames_n].launch()
+    gev = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(2)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    for k in range(steps):
+        gev[k][0].record()
+        graphs[k % frames_n].launch()
+        gev[k][1].record()
+    torch.cuda.synchronize()
+    graph_ms = mean_event_ms(gev)
+    del graphs
     b = spmv_bytes(nnz, g.npix, inst.npt, es)
     # raw + dark + norm read, corrected image written
     corr_b = g.npix * (4 + 3 * es)
@@ -195,6 +209,7 @@ def pipeline_line(az, torch, np, synth, dev, dtype, steps, warmup, frames_n=4):
                 step_ms=step_ms, step_bytes=rb, step_gbs=rb / (step_ms * 1e6),
                 step_encoding_bytes=enc, step_encoding_gbs=enc / (step_ms * 1e6),
                 step_frac=rb / (step_ms * 1e6) / HBM_PEAK_GBS,
+                graph_step_ms=graph_ms, graph_elements_per_s=g.npix / (graph_ms * 1e-3),
                 two_pass_correct_ms=corr_ms, two_pass_correct_gbs=corr_b / (corr_ms * 1e6),
                 integrate_ms=spmv_ms, integrate_bytes=b,
                 integrate_gbs=b / (spmv_ms * 1e6),
