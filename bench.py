@@ -15,8 +15,9 @@ a cold-cache timing of the integration kernel, the 4096-instance batch (one
 persistent graph launch vs a per-instance loop), the 1e6-pixel adjoint, the
 1024-instance float32 forward+adjoint batch with autotuned tiles, the
 matrix-free (fused) kernel on the same frame, two-dimensional integration of
-the frame (1000 x 360 bins), host- vs device-built plans, and full pixel
-splitting of the frame.
+the frame (1000 x 360 bins), host- vs device-built plans, full pixel
+splitting of the frame, and a plain 1 GiB device copy (the measured
+streaming ceiling).
 """
 import argparse
 import json
@@ -492,6 +493,18 @@ def full_split_line(az, torch, np, synth, dev, reps=50):
     return line
 
 
+def stream_copy_line(torch, dev, reps=20):
+    """The measured streaming ceiling: a plain device-to-device copy of 1 GiB
+    (read + write counted), beside the 8 TB/s HBM specification."""
+    src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    ms = _timed(torch, lambda: dst.copy_(src), reps)
+    by = 2 * src.numel() * 8
+    del src, dst
+    torch.cuda.empty_cache()
+    return dict(bytes=by, ms=ms, gbs=by / (ms * 1e6), frac=by / (ms * 1e6) / HBM_PEAK_GBS)
+
+
 def cpu_baseline(np, synth):
     """The FP64 oracle on the host: one full ~1e7-pixel frame per repetition
     (correction + integration; the matrix is built beforehand, untimed, as
@@ -601,6 +614,9 @@ def main():
         result["lines"]["c5"] = batch_line(az, torch, np, synth, dev, synth.C5, "f32",
                                            True, True)
         log(f"[c5] {json.dumps(result['lines']['c5'])}")
+    if run("stream_copy"):
+        result["lines"]["stream_copy"] = stream_copy_line(torch, dev)
+        log(f"[stream_copy] {json.dumps(result['lines']['stream_copy'])}")
     for name, fn in (("c2_fuse_stage", fuse_stage_line), ("c2_fused", fused_line),
                      ("c2_2d", two_d_line), ("c2_plan_build", plan_build_line),
                      ("c2_full_split", full_split_line)):

@@ -274,6 +274,10 @@ def test_band_fused_correction(dtype, dev):
                     device=dev, stage=stage)
         p.set_corrections(t(inst.dark), t(inst.flat), t(inst.solid), t(inst.polar))
         plans.append(p)
+    # correction bytes per pixel: none kept by the two-pass stage; 12-byte
+    # records for float64 with an integer dark, 8-byte float pairs for float32
+    assert plans[0].correction_bytes() == 0
+    assert plans[1].correction_bytes() == (12 if dtype == torch.float64 else 8)
     raw = torch.from_numpy(inst.raw.reshape(-1)).to(dev)
     a = plans[0].integrate_raw(raw)
     b = plans[1].integrate_raw(raw)
@@ -289,6 +293,7 @@ def test_band_fused_correction(dtype, dev):
     check(a, m, x, tol, what="two pass")
     # switching the stage after the corrections builds the pairs then
     plans[0].set_tiling(stage="fuse")
+    assert plans[0].correction_bytes() == plans[1].correction_bytes()
     c = plans[0].integrate_raw(raw)
     torch.cuda.synchronize()
     for u, v in zip(b, c):
