@@ -260,10 +260,10 @@ int azi_plan_tile_schedule(const azi_plan* plan, const azi_tiling* tiling, int32
                            int32_t* tiles, int32_t* nsplits, int32_t* splits);
 
 /*
- * Device layout of the matrix (default AZI_LAYOUT_RUN; plans built on the
- * device start in AZI_LAYOUT_BAND; two-dimensional plans default to
- * AZI_LAYOUT_PIXEL with tile_nnz 4096, variant 3, band 1, their rows being
- * short).  AZI_LAYOUT_PIXEL: the gather kernels
+ * Device layout of the matrix (default AZI_LAYOUT_RUN, or AZI_LAYOUT_PIXEL
+ * for images of 2^27 pixels or more; plans built on the device start in
+ * AZI_LAYOUT_BAND; two-dimensional plans default to AZI_LAYOUT_PIXEL with
+ * tile_nnz 4096, variant 3, band 1, their rows being short).  AZI_LAYOUT_PIXEL: the gather kernels
  * read the image in its row-major pixel order.  AZI_LAYOUT_RING:
  * the matrix columns are renumbered so that pixels are sorted by the first
  * bin they feed (ties in pixel order); every bin then reads its pixels from

@@ -646,7 +646,8 @@ int plan_create(const azi_geom* geom, int32_t npt, int32_t npt_azim, int32_t uni
     }
     if (rc != AZI_OK) return fail(rc, err);
     size_default_tiling(p.get());
-    p->layout = AZI_LAYOUT_RUN;
+    // the run layout numbers pixels in 27 bits; larger images take the CSR
+    p->layout = p->m.npix < ((int64_t)1 << azi::kBandShift) ? AZI_LAYOUT_RUN : AZI_LAYOUT_PIXEL;
     if (p->m.two_d) {
         // short rows (tens of entries): the plain CSR with whole rows per
         // tile beats the band order, whose per-band pieces would be tiny
