@@ -480,3 +480,53 @@ def test_c2_full_split_full_size(dev):
         assert abs(W[b] - Wo) <= TOL64 * Wa, (b, W[b], Wo)
         assert abs(U[b] - Uo) <= TOL64 * Uo, (b, U[b], Uo)
         assert abs(I[b] - Wo / Uo) <= TOL64 * Wa / Uo, (b, I[b], Wo / Uo)
+
+
+def _random_geometries(n, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        h, w = int(rng.integers(1, 260)), int(rng.integers(1, 260))
+        # beam on the detector, on a pixel corner, or outside it
+        kind = rng.integers(0, 3)
+        if kind == 0:
+            cy, cx = rng.uniform(0, h), rng.uniform(0, w)
+        elif kind == 1:
+            cy, cx = float(rng.integers(0, h + 1)), float(rng.integers(0, w + 1))
+        else:
+            cy, cx = rng.uniform(-h, 2 * h), rng.uniform(-w, 2 * w)
+        npt = int(rng.integers(1, 400))
+        split = ["bbox", "bbox", "full", "none"][int(rng.integers(0, 4))]
+        unit = ["r_m", "r_m", "r_mm"][int(rng.integers(0, 3))]
+        tile = int(rng.choice([64, 512, 4096, 16384]))
+        block = int(rng.choice([128, 256]))
+        out.append((h, w, cy, cx, npt, split, unit, tile, block))
+    return out
+
+
+@pytest.mark.parametrize("g", _random_geometries(24, 2024),
+                         ids=lambda g: f"{g[0]}x{g[1]}-{g[5]}-{g[4]}-t{g[7]}b{g[8]}")
+def test_run_layout_random_geometries(g, dev):
+    """Seeded random detectors (sizes 1-259, the beam on, at a corner of or
+    away from the detector, 1-399 bins, every split, radial units, several
+    tilings) in the default run layout against the oracle, for a corrected
+    image and for the raw pipeline with corrections."""
+    h, w, cy, cx, npt, split, unit, tile, block = g
+    say("random", g)
+    az = azint()
+    plan = az.Plan(h, w, npt, center=(cy, cx), split=split, unit=unit, device=dev,
+                   tile_nnz=tile, block=block)
+    assert plan.layout() == "run"
+    m = oracle_matrix(h, w, cy, cx, npt, 1e-4, 1e-4, unit, split)
+    rng = np.random.default_rng(h * 1000 + w)
+    x = rng.uniform(-5.0, 100.0, size=h * w)
+    check(plan.integrate(torch.from_numpy(x).to(dev), empty=-2.0), m, x, TOL64, empty=-2.0,
+          what=str(g))
+    raw = rng.integers(0, 1 << 16, size=h * w).astype(np.int32)
+    dark = rng.integers(0, 50, size=h * w).astype(np.float64)
+    flat = rng.uniform(0.9, 1.1, size=h * w)
+    t = lambda a: torch.from_numpy(a).to(dev)
+    plan.set_corrections(dark=t(dark), flat=t(flat))
+    out = plan.integrate_raw(t(raw))
+    torch.cuda.synchronize()
+    check(out, m, oracle.correct(raw.astype(np.float64), dark, flat), TOL64, what=f"raw {g}")
