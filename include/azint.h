@@ -204,7 +204,7 @@ int azi_plan_export_csc(const azi_plan* plan, void* data, int32_t* bins, int32_t
  * the stage, by the one rounding of the fused correction).  A new plan
  * starts at tile_nnz 4096, block 256, variant 5, grid 0, band 4, stage
  * AZI_STAGE_FUSE; below 2^22 nonzeros at tile_nnz 2048
- * (two-dimensional plans: 4096, 256, 3, 0, 1, AZI_STAGE_GATHER).
+ * (two-dimensional plans: 4096, 256, 2, 0, 1, AZI_STAGE_GATHER).
  *   tile_nnz  most nonzeros one workgroup sums per tile (64..16384, a
  *             multiple of 64); rows longer than that are cut into pieces
  *             whose sums are added in order by a small fix-up kernel.
@@ -263,7 +263,7 @@ int azi_plan_tile_schedule(const azi_plan* plan, const azi_tiling* tiling, int32
  * Device layout of the matrix (default AZI_LAYOUT_RUN, or AZI_LAYOUT_PIXEL
  * for images of 2^27 pixels or more; plans built on the device start in
  * AZI_LAYOUT_BAND; two-dimensional plans default to AZI_LAYOUT_PIXEL with
- * tile_nnz 4096, variant 3, band 1, their rows being short).  AZI_LAYOUT_PIXEL: the gather kernels
+ * tile_nnz 4096, variant 2, band 1, their rows being short).  AZI_LAYOUT_PIXEL: the gather kernels
  * read the image in its row-major pixel order.  AZI_LAYOUT_RING:
  * the matrix columns are renumbered so that pixels are sorted by the first
  * bin they feed (ties in pixel order); every bin then reads its pixels from
