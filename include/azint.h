@@ -259,6 +259,27 @@ int azi_plan_get_tiling(const azi_plan* plan, azi_tiling* tiling, int32_t* ntile
 int azi_plan_tile_schedule(const azi_plan* plan, const azi_tiling* tiling, int32_t* ntiles,
                            int32_t* tiles, int32_t* nsplits, int32_t* splits);
 
+/* Host-side view of the run encoding (AZI_LAYOUT_RUN) of a one-dimensional
+ * or 2-D plan's matrix with pieces of tile_nnz / 2 runs (no device needed;
+ * for inspection and tests).  Host buffers, any of them NULL to skip:
+ *   runs[nruns]      pixel | first row in the band << 27 | (count - 1) << 29
+ *                    per run, -1 for the padding that starts every band on a
+ *                    multiple of 64 runs;
+ *   gbase[nruns/64]  first coefficient of each group of 64 runs;
+ *   coef[nnz]        the coefficients (double), slot-major per group: the
+ *                    first coefficient of each run in run order, then the
+ *                    second of the runs that have one, and so on;
+ *   pieces[8 * npieces] int32 {run_begin, run_end, first bin of the band,
+ *                    rows of the band, first partial slot, 0, 0, 0};
+ *   bin_slot[npt], bin_count[npt]  each bin's first partial slot and count
+ *                    (slots first, first + 4, ...).
+ * nruns / npieces (may be NULL) receive the counts.  AZI_EOVERFLOW for
+ * images of 2^27 pixels or more, AZI_EINVAL for a tile_nnz outside
+ * [64, 16384]. */
+int azi_plan_run_schedule(const azi_plan* plan, int32_t tile_nnz, int64_t* nruns, int32_t* runs,
+                          int32_t* gbase, double* coef, int32_t* npieces, int32_t* pieces,
+                          int32_t* bin_slot, int32_t* bin_count);
+
 /*
  * Device layout of the matrix (default AZI_LAYOUT_RUN, or AZI_LAYOUT_PIXEL
  * for images of 2^27 pixels or more; plans built on the device start in

@@ -95,6 +95,7 @@ _SIGS = {
     "azi_plan_set_tiling": (ctypes.c_int, [_P, _P]),
     "azi_plan_get_tiling": (ctypes.c_int, [_P, _P, _P]),
     "azi_plan_tile_schedule": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "azi_plan_run_schedule": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _P, _P, _P, _P]),
     "azi_plan_set_layout": (ctypes.c_int, [_P, _I32]),
     "azi_plan_get_layout": (ctypes.c_int, [_P, _P]),
     "azi_plan_upload": (ctypes.c_int, [_P, _I32]),
@@ -332,6 +333,26 @@ class Plan:
                                             tiles.ctypes.data, ctypes.byref(ns),
                                             splits.ctypes.data))
         return tiles, splits
+
+    def run_schedule(self, tile_nnz=None):
+        """Host-built run encoding of the matrix (the run layout's arrays:
+        runs, gbase, coef, pieces (n, 8), bin_slot, bin_count)."""
+        tn = self.tiling()["tile_nnz"] if tile_nnz is None else int(tile_nnz)
+        nr, npc = _I64(), _I32()
+        _check(lib().azi_plan_run_schedule(self._h, tn, ctypes.byref(nr), None, None, None,
+                                           ctypes.byref(npc), None, None, None))
+        runs = np.empty(nr.value, dtype=np.int32)
+        gbase = np.empty(nr.value // 64, dtype=np.int32)
+        coef = np.empty(self.nnz, dtype=np.float64)
+        pieces = np.empty((npc.value, 8), dtype=np.int32)
+        slot = np.empty(self.npt, dtype=np.int32)
+        count = np.empty(self.npt, dtype=np.int32)
+        _check(lib().azi_plan_run_schedule(self._h, tn, None, runs.ctypes.data,
+                                           gbase.ctypes.data, coef.ctypes.data, None,
+                                           pieces.ctypes.data, slot.ctypes.data,
+                                           count.ctypes.data))
+        return dict(runs=runs, gbase=gbase, coef=coef, pieces=pieces, bin_slot=slot,
+                    bin_count=count)
 
     def set_layout(self, layout):
         """"pixel", "ring", "tile", "band", "fused" or "run" layout of the

@@ -980,6 +980,35 @@ int azi_plan_tile_schedule(const azi_plan* p, const azi_tiling* tl, int32_t* nti
     return AZI_OK;
 }
 
+int azi_plan_run_schedule(const azi_plan* p, int32_t tile_nnz, int64_t* nruns, int32_t* runs,
+                          int32_t* gbase, double* coef, int32_t* npieces, int32_t* pieces,
+                          int32_t* bin_slot, int32_t* bin_count) {
+    if (!p) return fail(AZI_EINVAL, "plan is NULL");
+    if (tile_nnz < 64 || tile_nnz > 16384) return fail(AZI_EINVAL, "tile_nnz must be in [64, 16384]");
+    try {
+        azi::RunMatrix rm;
+        if (!azi::build_runs(p->m, std::max(64, tile_nnz / 2), 0, 0, rm))
+            return fail(AZI_EOVERFLOW,
+                        "the run layout takes images below 2^27 pixels and 2^31 entries");
+        if (nruns) *nruns = (int64_t)rm.runs.size();
+        if (npieces) *npieces = (int32_t)rm.pieces.size();
+        if (runs) std::copy(rm.runs.begin(), rm.runs.end(), runs);
+        if (gbase) std::copy(rm.gbase.begin(), rm.gbase.end(), gbase);
+        if (coef) std::copy(rm.coef.begin(), rm.coef.end(), coef);
+        if (pieces)
+            for (size_t k = 0; k < rm.pieces.size(); ++k) {
+                const azi::BandPiece& pc = rm.pieces[k];
+                const int32_t v[8] = {pc.z0, pc.z1, pc.bin0, pc.nrows, pc.slot0, 0, 0, 0};
+                std::copy(v, v + 8, pieces + 8 * k);
+            }
+        if (bin_slot) std::copy(rm.bin_slot.begin(), rm.bin_slot.end(), bin_slot);
+        if (bin_count) std::copy(rm.bin_count.begin(), rm.bin_count.end(), bin_count);
+    } catch (const std::bad_alloc&) {
+        return fail(AZI_ENOMEM, "out of host memory building the run matrix");
+    }
+    return AZI_OK;
+}
+
 int azi_plan_set_layout(azi_plan* p, int32_t layout) {
     if (!p) return fail(AZI_EINVAL, "plan is NULL");
     if (layout < AZI_LAYOUT_PIXEL || layout > AZI_LAYOUT_RUN)

@@ -177,7 +177,7 @@ void band_pieces(const int64_t* start, int32_t nbands, int32_t npt, int32_t R, i
 // stretch of one pixel's entries inside one band (consecutive bins): one
 // word pix | first row << kBandShift | (count - 1) << kRunCountShift.  Runs
 // of a band are in pixel order; every band, and so every piece, starts on a
-// multiple of 64 runs.  The coefficients of the 64 runs of group g start at
+// multiple of 64 runs (the padding words are -1).  The coefficients of the 64 runs of group g start at
 // gbase[g], slot-major: the first coefficient of each run in run order,
 // then the second of the runs that have one, and so on.  A wavefront takes
 // one group and finds every lane's coefficients from the counts alone.

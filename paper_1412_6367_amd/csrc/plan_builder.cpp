@@ -505,7 +505,7 @@ bool build_runs(const HostMatrix& m, int32_t piece_runs, int64_t pix_off, int64_
     if (start[nbands] >= (int64_t)INT32_MAX ||
         (int64_t)rm.coef.size() + m.nnz() >= (int64_t)INT32_MAX)
         return false;
-    rm.runs.resize(start[nbands], 0);
+    rm.runs.resize(start[nbands], -1);  // padding to the next band: no run
     std::vector<int32_t> first_k(start[nbands] - base, 0);  // CSC position of a run's first entry
     std::vector<int64_t> cur(start.begin(), start.end() - 1);
     for_runs([&](int64_t p, int32_t k, int32_t e) {

@@ -368,3 +368,69 @@ def test_device_plan_builder_without_gpu_fails_cleanly():
     rc = L.azi_plan_create_device(ctypes.byref(g), 8, 0, 1, None, 5, 0, -1, None,
                                   ctypes.byref(out))
     assert rc == -4
+
+
+def _decode_runs(s, npt):
+    """(pixel, bin, coefficient) of every entry of a run encoding, read the
+    way the run kernel reads it: per group of 64 runs, the j-th coefficient
+    of lane l sits after the groups' earlier slots, at the rank of l among
+    the lanes whose runs have more than j entries."""
+    runs, gbase, coef, pieces = s["runs"], s["gbase"], s["coef"], s["pieces"]
+    band_bin0 = np.full(len(runs), -1, dtype=np.int64)
+    for z0, z1, bin0, nrows, slot, *_ in pieces:
+        assert z0 % 64 == 0 and z1 >= z0
+        band_bin0[z0:z1] = bin0
+    pix, bins, cs = [], [], []
+    for g in range(len(runs) // 64):
+        w = runs[64 * g:64 * g + 64]
+        live = (w >= 0) & (band_bin0[64 * g:64 * g + 64] >= 0)
+        n = np.where(live, ((w >> 29) & 3) + 1, 0)
+        r0 = (w >> 27) & 3
+        p = w & ((1 << 27) - 1)
+        off = int(gbase[g])
+        for j in range(4):
+            lanes = np.nonzero(n > j)[0]
+            for rank, lane in enumerate(lanes):
+                pix.append(int(p[lane]))
+                bins.append(int(band_bin0[64 * g + lane] + r0[lane] + j))
+                cs.append(coef[off + rank])
+            off += len(lanes)
+    return np.array(pix), np.array(bins), np.array(cs)
+
+
+@pytest.mark.parametrize("g", [(90, 100, 44.6, 50.2, 40, "bbox", 0), (31, 29, 15.5, 14.5, 300, "bbox", 0),
+                               (64, 48, -5.0, 70.0, 40, "bbox", 0), (1, 17, 0.5, 8.5, 5, "bbox", 0),
+                               (120, 130, 60.2, 64.9, 140, "full", 0),
+                               (50, 60, 25.3, 30.7, 37, "none", 0),
+                               (40, 50, 20.1, 24.7, 20, "bbox", 36)],
+                         ids=lambda g: f"{g[0]}x{g[1]}-{g[5]}-{g[4]}-az{g[6]}")
+@pytest.mark.parametrize("tile", [64, 4096])
+def test_run_encoding_holds_every_entry_once(g, tile):
+    """The run layout's host builder: decoded as the kernel reads it, the
+    runs give back exactly the plan's entries (pixel, bin, coefficient bits);
+    pieces start on multiples of 64 runs and cover each band's runs; every
+    bin's slots are its band's pieces."""
+    h, w, cy, cx, npt, split, na = g
+    az = azint()
+    plan = az.Plan(h, w, npt, npt_azim=na or None, center=(cy, cx), split=split)
+    s = plan.run_schedule(tile_nnz=tile)
+    pix, bins, cs = _decode_runs(s, plan.npt)
+    data, cbins, colptr = plan.export_csc()
+    cpix = np.repeat(np.arange(plan.npix), np.diff(colptr))
+    a = np.lexsort((bins, pix))
+    b = np.lexsort((cbins, cpix))
+    assert len(pix) == plan.nnz
+    assert np.array_equal(pix[a], cpix[b]) and np.array_equal(bins[a], cbins[b])
+    assert np.array_equal(cs[a].view(np.int64), data[b].astype(np.float64).view(np.int64))
+    # pieces: per band consecutive, each bin's slots are those of its band's pieces
+    for z0, z1, bin0, nrows, slot, *_ in s["pieces"]:
+        assert 1 <= nrows <= 4 and slot % 4 == 0
+    firsts = {}
+    for z0, z1, bin0, nrows, slot, *_ in s["pieces"]:
+        firsts.setdefault(int(bin0), []).append(int(slot))
+    for bin0, slots in firsts.items():
+        assert slots == list(range(slots[0], slots[0] + 4 * len(slots), 4))
+        for r in range(4):
+            if bin0 + r < plan.npt:
+                assert s["bin_slot"][bin0 + r] == slots[0] + r
+                assert s["bin_count"][bin0 + r] == len(slots)
