@@ -469,6 +469,20 @@ int azi_batch_autotune(azi_batch* batch, const void* x, void* out_I, void* out_W
                        void* out_U, void* stream, char* report, int32_t report_len);
 
 /*
+ * Autotuner for one plan: times candidate layouts and tilings (run, band
+ * and pixel layouts for one-dimensional plans, the pixel layout's load
+ * variants and tiles and the run layout for 2-D plans) on the plan's own
+ * corrected image x with HIP events on `stream` (azi_integrate1d), keeps the
+ * fastest (azi_plan_set_layout / azi_plan_set_tiling) and writes a JSON
+ * report into report (host, report_len bytes, may be NULL).  While the plan
+ * has corrections, only tilings of its current layout are tried.  x, out_*
+ * are device buffers as for azi_integrate1d (their contents are
+ * overwritten).  Synchronous; needs an uploaded plan.
+ */
+int azi_plan_autotune(azi_plan* plan, const void* x, void* out_I, void* out_W, void* out_U,
+                      void* stream, char* report, int32_t report_len);
+
+/*
  * Capture a batch's forward (and, when grad_I or grad_W is non-NULL, its
  * backward right after, reading the U written by the forward) into a HIP
  * graph bound to these device buffers.  Replays with azi_graph_launch.

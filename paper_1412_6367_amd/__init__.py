@@ -96,6 +96,7 @@ _SIGS = {
     "azi_plan_get_tiling": (ctypes.c_int, [_P, _P, _P]),
     "azi_plan_tile_schedule": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "azi_plan_run_schedule": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "azi_plan_autotune": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _I32]),
     "azi_plan_set_layout": (ctypes.c_int, [_P, _I32]),
     "azi_plan_get_layout": (ctypes.c_int, [_P, _P]),
     "azi_plan_upload": (ctypes.c_int, [_P, _I32]),
@@ -333,6 +334,17 @@ class Plan:
                                             tiles.ctypes.data, ctypes.byref(ns),
                                             splits.ctypes.data))
         return tiles, splits
+
+    def autotune(self, x, *, stream=None):
+        """Time candidate layouts and tilings on the corrected image ``x``,
+        keep the fastest and return the library's JSON report as a dict
+        (layouts change only while the plan has no corrections)."""
+        _need(x, self.dtype, self.npix, self.device, "x")
+        I, W, U = self._outs(None)
+        buf = ctypes.create_string_buffer(1 << 16)
+        _check(lib().azi_plan_autotune(self._h, _ptr(x), _ptr(I), _ptr(W), _ptr(U),
+                                       _stream(stream), buf, len(buf)))
+        return json.loads(buf.value.decode())
 
     def run_schedule(self, tile_nnz=None):
         """Host-built run encoding of the matrix (the run layout's arrays:

@@ -1966,6 +1966,104 @@ int azi_batch_autotune(azi_batch* b, const void* x, void* I, void* W, void* U, v
     return AZI_OK;
 }
 
+int azi_plan_autotune(azi_plan* p, const void* x, void* I, void* W, void* U, void* stream,
+                      char* report, int32_t report_len) {
+    int rc = check_plan_ready(p);
+    if (rc != AZI_OK) return rc;
+    if (!x || !I) return fail(AZI_EINVAL, "x and out_I must not be NULL");
+    DeviceGuard g(p->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "set device");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    struct Cand {
+        int32_t layout;
+        azi_tiling t;
+    };
+    const int32_t st = p->tiling.stage;
+    // layouts change only while the plan has no corrections (they are tied
+    // to the layout's pixel order)
+    const bool relayout = !(p->has_dark || p->has_norm);
+    std::vector<Cand> cands;
+    auto add = [&](int32_t layout, int32_t tn, int32_t bl, int32_t var, int32_t band) {
+        if (relayout || layout == p->layout) cands.push_back(Cand{layout, {tn, bl, var, 0, band, st}});
+    };
+    if (p->m.two_d) {
+        for (int32_t var : {2, 3, 5})
+            for (int32_t tn : {2048, 4096, 8192})
+                for (int32_t bl : {128, 256}) add(AZI_LAYOUT_PIXEL, tn, bl, var, 1);
+        add(AZI_LAYOUT_RUN, 4096, 128, 5, 4);
+    } else {
+        const bool runs_ok = p->m.npix < ((int64_t)1 << azi::kBandShift);
+        if (runs_ok) {
+            for (int32_t tn : {2048, 4096, 8192})
+                for (int32_t bl : {128, 256}) add(AZI_LAYOUT_RUN, tn, bl, 5, 4);
+            for (int32_t tn : {2048, 4096})
+                for (int32_t band : {4, 8}) add(AZI_LAYOUT_BAND, tn, 256, 5, band);
+        }
+        for (int32_t var : {2, 3, 5}) add(AZI_LAYOUT_PIXEL, 4096, 256, var, 1);
+    }
+    if (cands.empty()) cands.push_back(Cand{p->layout, p->tiling});
+    static const char* const kNames[] = {"pixel", "ring", "tile", "band", "fused", "run"};
+    hipEvent_t e0, e1;
+    AZI_HIP(hipEventCreate(&e0), "event");
+    AZI_HIP(hipEventCreate(&e1), "event");
+    std::string rep = "{\"candidates\": [";
+    float best_ms = 1e30f;
+    Cand best = cands.front();
+    for (size_t k = 0; k < cands.size() && rc == AZI_OK; ++k) {
+        const Cand& c = cands[k];
+        rc = azi_plan_set_layout(p, c.layout);
+        if (rc == AZI_OK) rc = azi_plan_set_tiling(p, &c.t);
+        if (rc != AZI_OK) break;
+        hipError_t e = hipSuccess;
+        if (azi_integrate1d(p, x, I, W, U, 0.0, s) != AZI_OK) e = hipErrorLaunchFailure;
+        float ms_best = 1e30f;
+        for (int rep_i = 0; rep_i < 5 && e == hipSuccess; ++rep_i) {
+            e = hipEventRecord(e0, s);
+            if (e == hipSuccess && azi_integrate1d(p, x, I, W, U, 0.0, s) != AZI_OK)
+                e = hipErrorLaunchFailure;
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            ms_best = std::min(ms_best, ms);
+        }
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "autotune launch");
+            break;
+        }
+        char buf[256];
+        std::snprintf(buf, sizeof buf,
+                      "%s{\"layout\": \"%s\", \"tile_nnz\": %d, \"block\": %d, "
+                      "\"variant\": %d, \"band\": %d, \"ms\": %.5f}",
+                      k ? ", " : "", kNames[c.layout], c.t.tile_nnz, c.t.block, c.t.variant,
+                      c.t.band, ms_best);
+        rep += buf;
+        if (ms_best < best_ms) {
+            best_ms = ms_best;
+            best = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != AZI_OK) return rc;
+    rc = azi_plan_set_layout(p, best.layout);
+    if (rc == AZI_OK) rc = azi_plan_set_tiling(p, &best.t);
+    if (rc != AZI_OK) return rc;
+    char buf[256];
+    std::snprintf(buf, sizeof buf,
+                  "], \"best\": {\"layout\": \"%s\", \"tile_nnz\": %d, \"block\": %d, "
+                  "\"variant\": %d, \"band\": %d, \"ms\": %.5f}}",
+                  kNames[best.layout], best.t.tile_nnz, best.t.block, best.t.variant, best.t.band,
+                  best_ms);
+    rep += buf;
+    if (report && report_len > 0) {
+        const size_t n = std::min((size_t)report_len - 1, rep.size());
+        std::memcpy(report, rep.data(), n);
+        report[n] = '\0';
+    }
+    return AZI_OK;
+}
+
 }  // extern "C"
 
 namespace {

@@ -530,3 +530,41 @@ def test_run_layout_random_geometries(g, dev):
     out = plan.integrate_raw(t(raw))
     torch.cuda.synchronize()
     check(out, m, oracle.correct(raw.astype(np.float64), dark, flat), TOL64, what=f"raw {g}")
+
+
+@pytest.mark.parametrize("kind", ["1d", "2d", "1d-corrected"])
+def test_plan_autotune(kind, dev):
+    """The plan autotuner tries layouts and tilings on the plan's own image,
+    keeps the fastest, reports every candidate, and the tuned plan still
+    matches the oracle.  With corrections set, only tilings of the current
+    layout are tried."""
+    say("plan autotune", kind)
+    az = azint()
+    h, w, cy, cx = 200, 190, 95.2, 100.6
+    na = 36 if kind == "2d" else None
+    plan = az.Plan(h, w, 60 if na else 150, npt_azim=na, center=(cy, cx), device=dev)
+    rng = np.random.default_rng(21)
+    x = rng.uniform(0.0, 100.0, size=h * w)
+    xt = torch.from_numpy(x).to(dev)
+    start = plan.layout()
+    if kind == "1d-corrected":
+        plan.set_corrections(dark=torch.zeros(h * w, dtype=torch.float64, device=dev))
+    rep = plan.autotune(xt)
+    layouts = {c["layout"] for c in rep["candidates"]}
+    assert len(rep["candidates"]) >= 3
+    assert rep["best"]["ms"] == min(c["ms"] for c in rep["candidates"])
+    assert plan.layout() == rep["best"]["layout"]
+    assert plan.tiling()["tile_nnz"] == rep["best"]["tile_nnz"]
+    if kind == "1d-corrected":
+        assert layouts == {start}
+    else:
+        assert len(layouts) >= 2
+    if na:
+        m = oracle.build_matrix2d(h=h, w=w, pixel_y=1e-4, pixel_x=1e-4, center_y=cy,
+                                  center_x=cx, dist=0.1, wavelength=1e-10, npt_rad=60,
+                                  npt_azim=na, unit="r_m", split="bbox")
+    else:
+        m = oracle_matrix(h, w, cy, cx, 150)
+    out = plan.integrate(xt, empty=-1.0)
+    torch.cuda.synchronize()
+    check(out, m, x, TOL64, empty=-1.0, what=f"tuned {kind}")
