@@ -290,7 +290,8 @@ def batch_line(az, torch, np, synth, dev, cfg, dtype, with_bwd, tune, reps=20):
         line.update(backward_ms=bwd_ms, backward_gbs=bb / (bwd_ms * 1e6),
                     backward_frac=bb / (bwd_ms * 1e6) / HBM_PEAK_GBS,
                     graph_fwd_bwd_ms=graph_ms,
-                    graph_elements_per_s=batch.npix / (graph_ms * 1e-3))
+                    graph_elements_per_s=batch.npix / (graph_ms * 1e-3),
+                    graph_fwd_bwd_frac=(fb + bb) / (graph_ms * 1e6) / HBM_PEAK_GBS)
     else:
         line.update(graph_forward_ms=graph_ms,
                     graph_elements_per_s=batch.npix / (graph_ms * 1e-3),
