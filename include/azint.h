@@ -497,6 +497,16 @@ int azi_graph_create_plan(const azi_plan* plan, const void* raw, int32_t raw_dty
                           void* out_I, void* out_W, void* out_U, double empty,
                           void* stream, azi_graph** out);
 
+/*
+ * Replay a captured graph on `stream` (no allocation, no synchronisation),
+ * and free one.  A graph records the device addresses of its plan's or
+ * batch's matrices and work buffers and of the caller's buffers: it stays
+ * valid while all of them do, i.e. until the plan or batch is destroyed,
+ * re-uploaded, given another layout, tiling or corrections, or the
+ * caller's buffers are freed.  Destroy and capture again after any of
+ * these.  azi_graph_launch: AZI_EINVAL for a NULL graph; azi_graph_destroy(NULL)
+ * does nothing.
+ */
 int azi_graph_launch(azi_graph* graph, void* stream);
 int azi_graph_destroy(azi_graph* graph);
 
