@@ -212,8 +212,9 @@ int azi_plan_export_csc(const azi_plan* plan, void* data, int32_t* bins, int32_t
  *   variant   load scheme, 0..AZI_NUM_VARIANTS-1: 0 four consecutive
  *             nonzeros per lane, 2 loads in flight; 4 the same with 4 in
  *             flight; 1, 2, 6 lane-strided (one gather instruction reads
- *             consecutive nonzeros of a row) with 4, 8, 16 in flight;
- *             3 and 5 as 2 and 6 with non-temporal loads of the matrix.
+ *             consecutive nonzeros of a row) with 4, 8, 16 in flight,
+ *             2 loading the coefficients non-temporally; 3 and 5 as 2
+ *             and 6 with non-temporal loads of the whole matrix.
  *   grid      0: one workgroup per tile; > 0: that many persistent
  *             workgroups walk the tiles.
  *   band      > 1: pieces of up to `band` consecutive long rows are

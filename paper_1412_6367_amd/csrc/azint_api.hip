@@ -132,8 +132,10 @@ constexpr int64_t kSmallNnz = (int64_t)1 << 22;
 
 void size_default_tiling(azi_plan* p);
 // Two-dimensional plans (short rows, CSR layout): lane-strided loads of
-// whole rows, 8 deep, through the caches (68 us against 79 us with
-// non-temporal matrix loads for 1000 x 360 bins of a ~1e7-pixel frame).
+// whole rows, 8 deep, pixel ids through the caches and coefficients
+// non-temporal (71 us warm, 108 us cold for 1000 x 360 bins of a ~1e7-pixel
+// frame; 79 / 103 us with the whole matrix non-temporal, 70 / 124 us with
+// all of it cached).
 constexpr azi_tiling kDefaultTiling2d = {4096, 256, 2, 0, 1, AZI_STAGE_GATHER};
 
 // Converts double coefficients to the storage type into a padded buffer.

@@ -109,9 +109,9 @@ __device__ inline T ld(const T* p) {
 // Lane-strided form: lane j of the group takes nonzeros zlo + j, + lanes, ...
 // so one gather instruction reads `lanes` consecutive nonzeros of a row --
 // pixels that sit next to each other on the detector -- and touches few
-// cache lines.  NT streams the matrix with non-temporal loads, leaving the
-// caches to the image being gathered.
-template <int UNROLL, bool NT, class T, class Acc>
+// cache lines.  NT_IDX / NT_DAT stream the pixel ids / coefficients with
+// non-temporal loads, leaving the caches to the image being gathered.
+template <int UNROLL, bool NT_IDX, bool NT_DAT, class T, class Acc>
 __device__ inline void accumulate_strided(Acc& a, int32_t zlo, int32_t zhi, int lane, int lanes,
                                           const int32_t* __restrict__ idx,
                                           const T* __restrict__ dat, const T* __restrict__ x) {
@@ -122,8 +122,8 @@ __device__ inline void accumulate_strided(Acc& a, int32_t zlo, int32_t zhi, int 
         for (int u = 0; u < UNROLL; ++u) {
             const int32_t e = z + u * lanes;
             if (e < zhi) {
-                iv[u] = ld<NT>(idx + e);
-                dv[u] = ld<NT>(dat + e);
+                iv[u] = ld<NT_IDX>(idx + e);
+                dv[u] = ld<NT_DAT>(dat + e);
             }
         }
         T xv[UNROLL];
@@ -135,15 +135,19 @@ __device__ inline void accumulate_strided(Acc& a, int32_t zlo, int32_t zhi, int 
     }
 }
 
-// Kernel variants (load layout, unroll depth, non-temporal matrix stream).
+// Kernel variants (load layout, unroll depth, non-temporal pixel ids /
+// coefficients).  Variant 2 keeps the pixel ids cached and streams the
+// coefficients: for the short rows of 2-D plans the ids stay in the
+// last-level cache from frame to frame while the coefficients would evict
+// the gathered pixels.
 template <int VAR> struct Variant;
-template <> struct Variant<0> { static constexpr bool x4 = true;  static constexpr int unroll = 2; static constexpr bool nt = false; };
-template <> struct Variant<1> { static constexpr bool x4 = false; static constexpr int unroll = 4; static constexpr bool nt = false; };
-template <> struct Variant<2> { static constexpr bool x4 = false; static constexpr int unroll = 8; static constexpr bool nt = false; };
-template <> struct Variant<3> { static constexpr bool x4 = false; static constexpr int unroll = 8; static constexpr bool nt = true; };
-template <> struct Variant<4> { static constexpr bool x4 = true;  static constexpr int unroll = 4; static constexpr bool nt = false; };
-template <> struct Variant<5> { static constexpr bool x4 = false; static constexpr int unroll = 16; static constexpr bool nt = true; };
-template <> struct Variant<6> { static constexpr bool x4 = false; static constexpr int unroll = 16; static constexpr bool nt = false; };
+template <> struct Variant<0> { static constexpr bool x4 = true;  static constexpr int unroll = 2; static constexpr bool nt_idx = false, nt_dat = false; };
+template <> struct Variant<1> { static constexpr bool x4 = false; static constexpr int unroll = 4; static constexpr bool nt_idx = false, nt_dat = false; };
+template <> struct Variant<2> { static constexpr bool x4 = false; static constexpr int unroll = 8; static constexpr bool nt_idx = false, nt_dat = true; };
+template <> struct Variant<3> { static constexpr bool x4 = false; static constexpr int unroll = 8; static constexpr bool nt_idx = true, nt_dat = true; };
+template <> struct Variant<4> { static constexpr bool x4 = true;  static constexpr int unroll = 4; static constexpr bool nt_idx = false, nt_dat = false; };
+template <> struct Variant<5> { static constexpr bool x4 = false; static constexpr int unroll = 16; static constexpr bool nt_idx = true, nt_dat = true; };
+template <> struct Variant<6> { static constexpr bool x4 = false; static constexpr int unroll = 16; static constexpr bool nt_idx = false, nt_dat = false; };
 constexpr int kVariants = 7;
 
 template <int VAR, class T, class Acc>
@@ -152,7 +156,7 @@ __device__ inline void accumulate_var(Acc& a, int32_t zlo, int32_t zhi, int lane
                                       const T* __restrict__ x) {
     using V = Variant<VAR>;
     if constexpr (V::x4) accumulate<V::unroll>(a, zlo, zhi, lane, lanes, idx, dat, x);
-    else accumulate_strided<V::unroll, V::nt>(a, zlo, zhi, lane, lanes, idx, dat, x);
+    else accumulate_strided<V::unroll, V::nt_idx, V::nt_dat>(a, zlo, zhi, lane, lanes, idx, dat, x);
 }
 
 template <class T, class Acc, int BLOCK, int VAR>
