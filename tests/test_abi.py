@@ -434,3 +434,25 @@ def test_run_encoding_holds_every_entry_once(g, tile):
             if bin0 + r < plan.npt:
                 assert s["bin_slot"][bin0 + r] == slots[0] + r
                 assert s["bin_count"][bin0 + r] == len(slots)
+
+
+def test_new_entry_points_reject_bad_arguments():
+    """Argument errors of the run-schedule export, the plan autotuner and the
+    correction-bytes query, without a GPU."""
+    az = azint()
+    L = az.lib()
+    plan = az.Plan(12, 13, 6)
+    n = ctypes.c_int64()
+    for tn in (0, 63, 16385):
+        rc, msg = _err(L.azi_plan_run_schedule(plan.handle, tn, ctypes.byref(n), None, None,
+                                               None, None, None, None, None))
+        assert rc == -1 and "tile_nnz" in msg
+    assert _err(L.azi_plan_run_schedule(None, 4096, ctypes.byref(n), None, None, None, None,
+                                        None, None, None))[0] == -1
+    assert L.azi_plan_run_schedule(plan.handle, 64, ctypes.byref(n), None, None, None, None,
+                                   None, None, None) == 0 and n.value % 64 == 0
+    # the autotuner needs an uploaded plan
+    rc, msg = _err(L.azi_plan_autotune(plan.handle, None, None, None, None, None, None, 0))
+    assert rc < 0
+    assert L.azi_plan_autotune(None, None, None, None, None, None, None, 0) < 0
+    assert L.azi_plan_correction_bytes(plan.handle) == 0
