@@ -191,6 +191,7 @@ struct azi_plan {
         bparts, npieces_buf, npacked, ncoef, bin_slot, bin_count, nparts_buf, ftiles, fslots,
         fbin_ptr, fparts, corr, cfirst, rgbase;
     int32_t nstiles = 0, nbtiles = 0, npieces = 0, band_rows = 8, nftiles = 0;
+    int32_t max_count = INT32_MAX;  // largest number of band partials of a bin
     int32_t corr_kind = azi::kCorrPair;
     int32_t ntiles = 0, nsplits = 0, nparts = 0;
     bool has_dark = false, has_norm = false;
@@ -209,6 +210,7 @@ struct azi_batch {
         stiles, lidx, dest, btiles, brows, blp, bcoef, bin_ptr, bparts, npieces_buf, npacked, ncoef,
         bin_slot, bin_count, nparts_buf, cfirst, rgbase;
     int32_t nbtiles = 0, npieces = 0, band_rows = 8;
+    int32_t max_count = INT32_MAX;  // largest number of band partials of a bin
     std::vector<int64_t> cz_off;     // CSC entries of instance k
     std::vector<int64_t> piece_off;  // band pieces of instance k
     std::vector<int64_t> btile_off;  // blocked tiles of instance k
@@ -318,9 +320,16 @@ int32_t band_rows_of(const azi_tiling& t) {
     return (t.band == 4 || t.band == 8 || t.band == 16) ? t.band : 8;
 }
 
+int32_t max_count_of(const std::vector<int32_t>& bin_count) {
+    int32_t m = 0;
+    for (int32_t c : bin_count) m = std::max(m, c);
+    return m;
+}
+
 int upload_bands(const azi::BandMatrix& bm, int32_t dtype, int device, DevBuf& pieces,
                  DevBuf& packed, DevBuf& coef, DevBuf& bin_slot, DevBuf& bin_count,
-                 DevBuf& parts) {
+                 DevBuf& parts, int32_t& max_count) {
+    max_count = INT32_MAX;
     if (bm.packed.size() + kPad >= (size_t)INT32_MAX || bm.pieces.size() >= (size_t)INT32_MAX)
         return fail(AZI_EOVERFLOW, "band matrix exceeds 2^31 entries or pieces");
     AZI_HIP(pieces.upload(bm.pieces.data(), bm.pieces.size() * sizeof(azi::BandPiece), device),
@@ -334,6 +343,7 @@ int upload_bands(const azi::BandMatrix& bm, int32_t dtype, int device, DevBuf& p
     AZI_HIP(bin_slot.upload(bm.bin_slot.data(), bm.bin_slot.size() * 4, device), "bin slots");
     AZI_HIP(bin_count.upload(bm.bin_count.data(), bm.bin_count.size() * 4, device), "bin counts");
     AZI_HIP(parts.alloc((size_t)std::max(bm.nslots, 1) * 16, device), "band partials");
+    max_count = max_count_of(bm.bin_count);
     return AZI_OK;
 }
 
@@ -354,7 +364,7 @@ int plan_upload_bands(azi_plan* p) {
             bm.nslots = rm.nslots;
             p->band_rows = azi::kRunRows;
             int rc = upload_bands(bm, p->dtype, p->device, p->npieces_buf, p->npacked, p->ncoef,
-                                  p->bin_slot, p->bin_count, p->nparts_buf);
+                                  p->bin_slot, p->bin_count, p->nparts_buf, p->max_count);
             if (rc != AZI_OK) return rc;
             AZI_HIP(p->rgbase.upload(rm.gbase.data(), rm.gbase.size() * 4, p->device),
                     "run groups");
@@ -370,7 +380,7 @@ int plan_upload_bands(azi_plan* p) {
         if (!azi::build_bands(p->m, p->band_rows, p->tiling.tile_nnz, 0, 0, bm))
             return fail(AZI_EOVERFLOW, "the band layout takes images below 2^27 pixels");
         int rc = upload_bands(bm, p->dtype, p->device, p->npieces_buf, p->npacked, p->ncoef,
-                              p->bin_slot, p->bin_count, p->nparts_buf);
+                              p->bin_slot, p->bin_count, p->nparts_buf, p->max_count);
         if (rc != AZI_OK) return rc;
         p->npieces = (int32_t)bm.pieces.size();
     } catch (const std::bad_alloc&) {
@@ -389,6 +399,7 @@ azi::BandLaunch plan_band_args(const azi_plan* p, const void* x, void* I, void* 
     a.coef = p->ncoef.p;
     a.bin_slot = p->bin_slot.as<int32_t>();
     a.bin_count = p->bin_count.as<int32_t>();
+    a.max_count = p->max_count;
     a.R = p->band_rows;
     a.b0 = 0;
     a.b1 = p->m.npt;
@@ -721,8 +732,10 @@ int plan_device_bands(azi_plan* p, const int32_t* rowidx, const int32_t* pix, co
         AZI_HIP(p->npieces_buf.upload(bm.pieces.data(), bm.pieces.size() * sizeof(azi::BandPiece),
                                       dev), "band pieces");
         AZI_HIP(p->bin_slot.upload(bm.bin_slot.data(), bm.bin_slot.size() * 4, dev), "bin slots");
+        p->max_count = INT32_MAX;
         AZI_HIP(p->bin_count.upload(bm.bin_count.data(), bm.bin_count.size() * 4, dev),
                 "bin counts");
+        p->max_count = max_count_of(bm.bin_count);
         AZI_HIP(p->nparts_buf.alloc((size_t)std::max(bm.nslots, 1) * 16, dev), "band partials");
         p->npieces = (int32_t)bm.pieces.size();
     } catch (const std::bad_alloc&) {
@@ -1592,7 +1605,7 @@ int batch_build_bands(azi_batch* b, const std::vector<const azi::HostMatrix*>& m
         bm.bin_count.swap(rm.bin_count);
         bm.nslots = rm.nslots;
         int rc = upload_bands(bm, b->dtype, b->device, b->npieces_buf, b->npacked, b->ncoef,
-                              b->bin_slot, b->bin_count, b->nparts_buf);
+                              b->bin_slot, b->bin_count, b->nparts_buf, b->max_count);
         if (rc != AZI_OK) return rc;
         AZI_HIP(b->rgbase.upload(rm.gbase.data(), rm.gbase.size() * 4, b->device), "run groups");
         b->npieces = (int32_t)bm.pieces.size();
@@ -1609,7 +1622,7 @@ int batch_build_bands(azi_batch* b, const std::vector<const azi::HostMatrix*>& m
     }
     b->piece_off[b->n] = (int64_t)bm.pieces.size();
     int rc = upload_bands(bm, b->dtype, b->device, b->npieces_buf, b->npacked, b->ncoef,
-                          b->bin_slot, b->bin_count, b->nparts_buf);
+                          b->bin_slot, b->bin_count, b->nparts_buf, b->max_count);
     if (rc != AZI_OK) return rc;
     b->npieces = (int32_t)bm.pieces.size();
     return AZI_OK;
@@ -1661,6 +1674,7 @@ azi::BandLaunch batch_band_args(const azi_batch* b, const void* x, int32_t k0, i
     a.coef = b->ncoef.p;
     a.bin_slot = b->bin_slot.as<int32_t>();
     a.bin_count = b->bin_count.as<int32_t>();
+    a.max_count = b->max_count;
     a.R = b->band_rows;
     a.b0 = b->bin_off[k0];
     a.b1 = b->bin_off[k1];

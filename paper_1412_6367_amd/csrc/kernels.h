@@ -78,6 +78,7 @@ struct BandLaunch {
     const void* coef = nullptr;
     const int32_t* bin_slot = nullptr;
     const int32_t* bin_count = nullptr;
+    int32_t max_count = INT32_MAX;     // largest bin_count (selects the reduction form)
     int32_t R = 8;
     int64_t b0 = 0, b1 = 0;
     const void* x = nullptr;

@@ -495,6 +495,36 @@ __global__ void k_band_reduce(const int32_t* __restrict__ bin_slot,
     if (lane == 0) write_row((int32_t)b, a, I, W, U, empty);
 }
 
+// One lane per bin, for matrices whose bins have at most kLaneParts
+// partials.  The lane combines them as lane 0 of k_band_reduce's xor tree
+// does (partial k with k + 4, then k + 2, then k + 1; the tree's wider steps
+// only add zeros, which leave the sums unchanged), so both forms write the
+// same bits.  It launches 64 times fewer wavefronts, which matters for
+// batches of many small images, where most bins have one or two partials.
+constexpr int kLaneParts = 8;
+
+template <class T, class Acc>
+__global__ void k_band_reduce_lane(const int32_t* __restrict__ bin_slot,
+                                   const int32_t* __restrict__ bin_count, int32_t R, int64_t b0,
+                                   int64_t b1, const Acc* __restrict__ parts, T* __restrict__ I,
+                                   T* __restrict__ W, T* __restrict__ U, double empty) {
+    const int64_t b = b0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= b1) return;
+    const int32_t first = bin_slot[b], cnt = bin_count[b];
+    Acc v[kLaneParts];
+#pragma unroll
+    for (int k = 0; k < kLaneParts; ++k) {
+        v[k].zero();
+        if (k < cnt) v[k].merge(parts[first + (int64_t)k * R]);
+    }
+#pragma unroll
+    for (int m = kLaneParts / 2; m > 0; m >>= 1) {
+#pragma unroll
+        for (int k = 0; k < m; ++k) v[k].merge(v[k + m]);
+    }
+    write_row((int32_t)b, v[0], I, W, U, empty);
+}
+
 // ---------------------------------------------------------------------------
 // Blocked form: one workgroup per image tile
 // ---------------------------------------------------------------------------
@@ -969,6 +999,13 @@ hipError_t band_impl(const BandLaunch& a, hipStream_t s) {
         if (e != hipSuccess) return e;
     }
     const int64_t nb = a.b1 - a.b0;
+    if (nb > 0 && a.max_count <= kLaneParts) {
+        hipLaunchKernelGGL((k_band_reduce_lane<T, Acc>), dim3((unsigned)((nb + 255) / 256)),
+                           dim3(256), 0, s, a.bin_slot, a.bin_count, a.R, a.b0, a.b1,
+                           static_cast<const Acc*>(a.parts), static_cast<T*>(a.I),
+                           static_cast<T*>(a.W), static_cast<T*>(a.U), a.empty);
+        return hipGetLastError();
+    }
     if (nb > 0) {
         hipLaunchKernelGGL((k_band_reduce<T, Acc>), dim3((unsigned)((nb + 3) / 4)), dim3(256), 0,
                            s, a.bin_slot, a.bin_count, a.R, a.b0, a.b1,

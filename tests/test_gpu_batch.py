@@ -406,3 +406,42 @@ def test_c5_full_batch_sampled(dev):
         ref = oracle.integrate_vjp(m, Uo, gk)
         scale = oracle.integrate_vjp(m, Uo, np.abs(gk))
         assert norm_err(gh[po[k]:po[k + 1]], ref, scale) <= TOL32_F64, k
+
+
+@pytest.mark.parametrize("dtype,accum", [(torch.float64, "f64"), (torch.float32, "kahan32")])
+def test_lane_and_wavefront_reductions_agree(dtype, accum, dev):
+    """A launch whose bins all have at most 8 band partials finishes them one
+    lane per bin; otherwise one wavefront per bin.  Both combine a bin's
+    partials in the same order, so a batch holding an image with long bands
+    (more than 8 partials per bin: the wavefront form for the whole batch)
+    equals, bit for bit, each of the other images integrated alone (the lane
+    form), over bins with 1 to 8 partials."""
+    say("lane vs wavefront reduction", dtype, accum)
+    az = azint()
+    geoms = [(300, 300, 20), (100, 100, 50), (64, 64, 40), (70, 50, 45)]
+    tile = 512
+    plans = []
+    for h, w, n in geoms:
+        p = az.Plan(h, w, n, center=(h / 2 + 0.3, w / 2 - 0.7), dtype=dtype, accum=accum,
+                    layout="run")
+        p.set_tiling(tile_nnz=tile)
+        plans.append(p)
+    counts = [p.run_schedule(tile)["bin_count"] for p in plans]
+    assert counts[0].max() > 8
+    assert all(c.max() <= 8 for c in counts[1:])
+    assert set(np.concatenate(counts[1:]).tolist()) == set(range(1, 9))
+    batch = az.Batch(plans, device=dev)
+    batch.set_tiling(tile_nnz=tile)
+    assert batch.tiling()["tile_nnz"] == tile
+    rng = np.random.default_rng(41)
+    npd = np.float64 if dtype == torch.float64 else np.float32
+    xs = [rng.uniform(-5.0, 1000.0, size=h * w).astype(npd) for h, w, _ in geoms]
+    I, W, U = batch.forward(torch.from_numpy(np.concatenate(xs)).to(dev), empty=-2.0)
+    torch.cuda.synchronize()
+    bo = batch.bin_off
+    for k, (plan, x) in enumerate(zip(plans, xs)):
+        plan.upload(dev)
+        assert plan.tiling()["tile_nnz"] == tile
+        out = plan.integrate(torch.from_numpy(x).to(dev), empty=-2.0)
+        for a, b in zip((I, W, U), out):
+            assert torch.equal(a[bo[k]:bo[k + 1]], b), (k, geoms[k])
