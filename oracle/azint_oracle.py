@@ -80,7 +80,7 @@ __all__ = [
     "pixel_corners", "full_entries", "polygon_area", "clip_slab",
     "entries_to_csr", "build_matrix", "correct", "corner_azimuth", "azimuth_extents",
     "azimuth_entries_loop", "bbox2d_entries", "full2d_entries", "nosplit2d_entries", "build_matrix2d", "integrate", "integrate_loop",
-    "integrate_vjp", "kahan_sum_f32", "positions",
+    "integrate_vjp", "kahan_sum_f32", "positions", "correction_norm",
 ]
 
 
@@ -602,6 +602,19 @@ def build_matrix(h, w, pixel_y, pixel_x, center_y, center_x, dist, wavelength,
 # Per-frame computation
 # ----------------------------------------------------------------------------
 
+def correction_norm(flat=None, solid=None, polar=None):
+    """The divisor of the correction map of Section 6.4, (flat * solid) *
+    polar, formed left to right; absent arrays drop out, and None is
+    returned when all three are absent."""
+    norm = None
+    for arr in (flat, solid, polar):
+        if arr is None:
+            continue
+        a = np.asarray(arr, dtype=np.float64).reshape(-1)
+        norm = a if norm is None else norm * a
+    return norm
+
+
 def correct(raw, dark=None, flat=None, solid=None, polar=None):
     """Correction map of Section 6.4: x = (raw - dark) / ((flat*solid)*polar).
 
@@ -610,25 +623,10 @@ def correct(raw, dark=None, flat=None, solid=None, polar=None):
     x = np.asarray(raw).astype(np.float64).reshape(-1)
     if dark is not None:
         x = x - np.asarray(dark, dtype=np.float64).reshape(-1)
-    norm = None
-    for arr in (flat, solid, polar):
-        if arr is None:
-            continue
-        a = np.asarray(arr, dtype=np.float64).reshape(-1)
-        norm = a if norm is None else norm * a
+    norm = correction_norm(flat, solid, polar)
     if norm is not None:
         x = x / norm
     return x
-
-
-def correction_norm(flat=None, solid=None, polar=None):
-    norm = None
-    for arr in (flat, solid, polar):
-        if arr is None:
-            continue
-        a = np.asarray(arr, dtype=np.float64).reshape(-1)
-        norm = a if norm is None else norm * a
-    return norm
 
 
 def integrate(m, x, empty=0.0):

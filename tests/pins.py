@@ -69,6 +69,51 @@ def exact_bbox_matrix(lo, hi, npt, pmin, pmax):
     return A
 
 
+def exact_rect_area(poly, a, b, c=None, d=None):
+    """Signed area of polygon `poly` (list of (x, y) Fractions, any order of
+    traversal, simple or not) inside the rectangle [a, b] x [c, d]; c / d
+    None leave y unbounded (a vertical slab).
+
+    Green's theorem edge by edge, with no polygon clipping: the area is
+    -(closed integral of y dx) over the boundary of the clipped region; the
+    parts of that boundary on x = a or x = b have dx = 0, and those on y = c
+    or y = d are accounted for by clamping y into [c, d].  So every edge
+    contributes -integral of clamp(y(x), c, d) dx over its x-span within
+    [a, b], integrated exactly: the span is cut where y(x) meets c or d, and
+    on each piece the integrand is a constant or y(x) itself (trapezoid).
+    Counter-clockwise traversal gives a positive area."""
+    def clamp(v):
+        if c is not None and v < c:
+            return c
+        if d is not None and v > d:
+            return d
+        return v
+
+    total = F(0)
+    n = len(poly)
+    for k in range(n):
+        (x0, y0), (x1, y1) = poly[k], poly[(k + 1) % n]
+        if x0 == x1:
+            continue
+        lo_, hi_ = max(min(x0, x1), a), min(max(x0, x1), b)
+        if hi_ <= lo_:
+            continue
+        slope = (y1 - y0) / (x1 - x0)
+        yat = lambda x: y0 + slope * (x - x0)
+        cuts = {lo_, hi_}
+        for level in (c, d):
+            if level is not None and slope != 0:
+                xc = x0 + (level - y0) / slope
+                if lo_ < xc < hi_:
+                    cuts.add(xc)
+        cuts = sorted(cuts)
+        part = F(0)
+        for u, v in zip(cuts[:-1], cuts[1:]):
+            part += (v - u) * (clamp(yat(u)) + clamp(yat(v))) / 2
+        total += -part if x1 > x0 else part
+    return total
+
+
 def pin_extents_exact(O):
     """P1a: lo and hi are the correctly rounded true radial extent (R2)."""
     for case in TINY_CASES:
@@ -367,6 +412,97 @@ def pin_correction(O):
     assert np.array_equal(O.correct(raw, solid=solid, polar=polar), [5.0, 7.0, 1.5, 4000.0])
 
 
+
+def pin_correction_norm(O):
+    """The normalisation of Section 6.4, norm = (flat * solid) * polar, on
+    hand-computed products; absent arrays drop out of the product."""
+    flat = np.array([2.0, 0.5, 1.0, 4.0])
+    solid = np.array([0.5, 1.0, 0.25, 0.5])
+    polar = np.array([4.0, 2.0, 1.0, 0.125])
+    assert np.array_equal(O.correction_norm(flat, solid, polar), [4.0, 1.0, 0.25, 0.25])
+    assert np.array_equal(O.correction_norm(flat, None, polar), [8.0, 1.0, 1.0, 0.5])
+    assert np.array_equal(O.correction_norm(None, solid, None), solid)
+    assert O.correction_norm() is None
+    raw = np.array([9, 3, 1, 2])
+    assert np.array_equal(O.correct(raw, None, flat, solid, polar), [2.25, 3.0, 4.0, 8.0])
+
+
+def _exact_centre_sq(h, w, py, px, cy, cx):
+    py, px, cy, cx = F(py), F(px), F(cy), F(cx)
+    return [((F(2 * j + 1, 2) - cx) * px) ** 2 + ((F(2 * i + 1, 2) - cy) * py) ** 2
+            for i in range(h) for j in range(w)]
+
+
+def _near(got, ref, ulps):
+    if ref == 0.0:
+        return got == 0.0
+    return abs(got - ref) <= ulps * math.ulp(ref)
+
+
+def pin_default_range(O):
+    """Reading R3: without an explicit range the bins span [min lo, max hi]
+    of the pixels' radial boxes when pixels are split (so that every box
+    lies inside and pixels are conserved), and [min, max] of the pixel-centre
+    values without splitting, as numpy's histogram of Section 3.3 takes it.
+    Checked against the exact extents (square roots of exact rationals),
+    including detectors whose beam lies outside them, where the range does
+    not start at 0, and through the monotone unit maps of Section 3."""
+    for case in TINY_CASES:
+        h, w, cy, cx, npt, py, px = case
+        args = _geom_args(case)
+        lo2, hi2 = exact_extent_sq(h, w, py, px, cy, cx)
+        c2 = _exact_centre_sq(h, w, py, px, cy, cx)
+        rlo, rhi = math.sqrt(float(min(lo2))), math.sqrt(float(max(hi2)))
+        for split in ("bbox", "full"):
+            m = O.build_matrix(npt=npt, split=split, **args)
+            assert _near(m["pmin"], rlo, 4) and _near(m["pmax"], rhi, 4), (case, split)
+        m = O.build_matrix(npt=npt, split="none", **args)
+        clo, chi = math.sqrt(float(min(c2))), math.sqrt(float(max(c2)))
+        assert _near(m["pmin"], clo, 4) and _near(m["pmax"], chi, 4), (case, "none")
+        edges = np.histogram(m["centre"], npt)[1]
+        assert edges[0] == m["pmin"] and edges[-1] == m["pmax"]
+        m2 = O.build_matrix2d(npt_rad=npt, npt_azim=4, split="bbox", **args)
+        assert _near(m2["pmin"], rlo, 4) and _near(m2["pmax"], rhi, 4), (case, "2d")
+        # 2theta in degrees: atan(r / d) * 180 / pi of the same extremes
+        m = O.build_matrix(npt=npt, split="bbox", unit="2th_deg", **args)
+        for got, r in ((m["pmin"], rlo), (m["pmax"], rhi)):
+            ref = math.degrees(math.atan(r / DIST))
+            assert _near(got, ref, 16), (case, got, ref)
+    # the beam outside the detector: the box range starts well above 0
+    h, w, cy, cx, npt, py, px = TINY_CASES[4]
+    m = O.build_matrix(npt=npt, split="bbox", **_geom_args(TINY_CASES[4]))
+    assert m["pmin"] > 0.2e-4
+
+
+def pin_positions(O):
+    """The abscissa returned with the profile (the tth of the usage example
+    in Section 3) is each bin's centre pmin + (b + 1/2) (pmax - pmin) / npt:
+    exact rationals, the midpoints of numpy's histogram edges (Section 3.3),
+    and the positions stored with a built matrix are those of its range."""
+    for npt, pmin, pmax in ((4, 0.0, 1.0), (7, 0.25, 3.5), (13, 1.0e-4, 2.7e-3),
+                            (1, -1.0, 1.0), (1000, 0.0, 0.2)):
+        got = O.positions(npt, pmin, pmax)
+        assert len(got) == npt
+        d = (F(pmax) - F(pmin)) / npt
+        for b in range(npt):
+            ref = float(F(pmin) + (b + F(1, 2)) * d)
+            assert _near(got[b], ref, 4), (npt, pmin, pmax, b, got[b], ref)
+        edges = np.linspace(pmin, pmax, npt + 1)
+        assert np.allclose(got, (edges[:-1] + edges[1:]) / 2, rtol=1e-14, atol=0)
+    for case in TINY_CASES[:3]:
+        h, w, cy, cx, npt, py, px = case
+        m = O.build_matrix(npt=npt, split="none", **_geom_args(case))
+        edges = np.histogram(m["centre"], npt)[1]
+        assert np.allclose(m["positions"], (edges[:-1] + edges[1:]) / 2, rtol=1e-14, atol=0)
+        m2 = O.build_matrix2d(npt_rad=npt, npt_azim=6, split="bbox", **_geom_args(case))
+        d = (F(m2["pmax"]) - F(m2["pmin"])) / npt
+        for b in range(npt):
+            assert _near(m2["positions"][b], float(F(m2["pmin"]) + (b + F(1, 2)) * d), 4)
+        dc = 2 * F(math.pi) / 6
+        for k in range(6):
+            assert abs(m2["azimuths"][k] - float(-F(math.pi) + (k + F(1, 2)) * dc)) <= 1e-15
+
+
 FULL_CASES = [
     # (h, w, center_y, center_x, npt, pixel_y, pixel_x)
     (5, 6, 2.5, 3.0, 9, 1e-4, 1e-4),
@@ -378,8 +514,10 @@ FULL_CASES = [
 
 def pin_full_exact(O):
     """P12: full-splitting coefficients equal the exact area fractions of the
-    corner quadrilaterals (clipped exactly in rational arithmetic from the
-    float64 corner coordinates), bbox where the pixel holds the centre."""
+    corner quadrilaterals (Section 4.2, reading R13), each bin's share
+    integrated exactly in rational arithmetic from the float64 corner
+    coordinates by Green's theorem (``exact_rect_area``: no polygon
+    clipping, unlike the oracle), bbox where the pixel holds the centre."""
     for case in FULL_CASES:
         h, w, cy, cx, npt, py, px = case
         args = _geom_args(case)
@@ -394,10 +532,10 @@ def pin_full_exact(O):
             if m["lo"][p] == 0.0:
                 continue
             quad = [(F(float(a)), F(float(b))) for a, b in corners[p]]
-            area = O.polygon_area(quad)
+            area = exact_rect_area(quad, min(q[0] for q in quad), max(q[0] for q in quad))
             for b in range(npt):
-                a_b = O.polygon_area(O.clip_slab(quad, pmin + b * d, pmin + (b + 1) * d))
-                if a_b > 0:
+                a_b = exact_rect_area(quad, pmin + b * d, pmin + (b + 1) * d)
+                if a_b != 0:
                     exact[(b, p)] = a_b / area
         for key, ref in exact.items():
             assert abs(got.get(key, 0.0) - float(ref)) <= 1e-12, (case, key)
@@ -601,6 +739,46 @@ def pin_2d_physical_area(O):
             assert np.abs(got - frac).max() < 5e-3, (cy, cx, p)
 
 
+def pin_2d_full_exact(O):
+    """P19b: two-dimensional full splitting (readings R13, R14) equals the
+    exact area of each corner quadrilateral inside every (radial bin, wedge)
+    rectangle over its whole area, wedges repeated every 2 pi, integrated in
+    rational arithmetic by Green's theorem (``exact_rect_area``), pi taken as
+    its float64 value; bbox-shaped rows of pixels holding the beam are left
+    to the other 2-D pins."""
+    pi = F(math.pi)
+    for (h, w, cy, cx, nr, na) in CASES_2D:
+        m = O.build_matrix2d(npt_rad=nr, npt_azim=na, split="full", **_args2d(h, w, cy, cx))
+        corners = O.pixel_corners(h, w, 1e-4, 1e-4, cy, cx, DIST, WL, "r_m")
+        pmin, pmax = F(m["pmin"]), F(m["pmax"])
+        dr = (pmax - pmin) / nr
+        dc = 2 * pi / na
+        got = {}
+        for b, p, c in zip(m["bins"].tolist(), m["pix"].tolist(), m["coef"].tolist()):
+            got[(b, p)] = got.get((b, p), 0.0) + c
+        for p in range(h * w):
+            if m["lo"][p] == 0.0:
+                continue
+            quad = [(F(float(a)), F(float(b))) for a, b in corners[p]]
+            xs = [q[0] for q in quad]
+            ys = [q[1] for q in quad]
+            area = exact_rect_area(quad, min(xs), max(xs))
+            exact = {}
+            k0 = math.floor((min(ys) + pi) / dc) - 1
+            k1 = math.ceil((max(ys) + pi) / dc) + 1
+            for a in range(nr):
+                for k in range(k0, k1 + 1):
+                    s = exact_rect_area(quad, pmin + a * dr, pmin + (a + 1) * dr,
+                                        -pi + k * dc, -pi + (k + 1) * dc)
+                    if s != 0:
+                        row = (k % na) * nr + a
+                        exact[row] = exact.get(row, F(0)) + s / area
+            rows = set(exact) | {b for (b, q) in got if q == p}
+            for row in rows:
+                ref = float(exact.get(row, 0))
+                assert abs(got.get((row, p), 0.0) - ref) <= 1e-12, (h, w, cy, cx, p, row)
+
+
 def pin_2d_conservation(O):
     """P20: two-dimensional splits conserve pixels and signal (Section 4),
     and a constant image integrates to that constant in every bin with
@@ -670,8 +848,9 @@ def pin_2d_histogram(O):
 ALL_PINS = [pin_extents_exact, pin_bbox_bruteforce, pin_results_exact,
             pin_nosplit_histogram, pin_naive_mean, pin_conservation, pin_unit_weights,
             pin_constant_image, pin_symmetry, pin_scipy_csr, pin_adjoint, pin_kahan,
-            pin_closed_forms, pin_bbox_clipped, pin_correction,
+            pin_closed_forms, pin_bbox_clipped, pin_correction, pin_correction_norm,
+            pin_default_range, pin_positions,
             pin_full_exact, pin_full_physical_area, pin_full_conservation,
             pin_full_rotation, pin_2d_marginal, pin_2d_azimuth_extent,
-            pin_2d_bbox_bruteforce, pin_2d_physical_area, pin_2d_conservation,
+            pin_2d_bbox_bruteforce, pin_2d_physical_area, pin_2d_full_exact, pin_2d_conservation,
             pin_2d_rotation, pin_2d_histogram]

@@ -18,7 +18,8 @@ _orig = {name: getattr(O, name) for name in
           "integrate_vjp", "kahan_sum_f32", "unit_of_radius", "correct",
           "pixel_corners", "full_entries", "polygon_area", "corner_azimuth",
           "azimuth_entries_loop", "bbox2d_entries", "full2d_entries", "azimuth_extents",
-          "nosplit2d_entries")}
+          "nosplit2d_entries", "default_range", "positions", "correction_norm",
+          "clip_slab")}
 
 
 def _corners_no_unwrap(h, w, pixel_y, pixel_x, center_y, center_x, dist, wavelength,
@@ -233,6 +234,26 @@ def _extents_never_whole(h, w, pixel_y, pixel_x, center_y, center_x, lo):
     return chi_lo, chi_hi, np.zeros_like(whole)
 
 
+
+def _range_from_zero(lo, hi, centre, split):
+    # the naive loop's [0, max] taken as the default range
+    pmin, pmax = _orig["default_range"](lo, hi, centre, split)
+    return 0.0, pmax
+
+
+def _positions_left_edges(npt, pmin, pmax):
+    return pmin + np.arange(npt) * ((pmax - pmin) / npt)
+
+
+def _norm_without_polar(flat=None, solid=None, polar=None):
+    return _orig["correction_norm"](flat, solid, None)
+
+
+def _clip_slab_too_wide(poly, x0, x1):
+    # the right edge of the slab put one slab width too far
+    return _orig["clip_slab"](poly, x0, x1 + (x1 - x0))
+
+
 MUTANTS = {
     "bbox_drop_inner": ("bbox_entries", _bbox_drop_inner),
     "bbox_b1_plus_one": ("bbox_entries", _bbox_b1_plus_one),
@@ -260,6 +281,10 @@ MUTANTS = {
     "2d_full_wedge_offset": ("full2d_entries", _full2d_wedge_offset),
     "2d_beam_pixel_not_whole": ("azimuth_extents", _extents_never_whole),
     "2d_nosplit_rows_swapped": ("nosplit2d_entries", _nosplit2d_rows_swapped),
+    "range_from_zero": ("default_range", _range_from_zero),
+    "positions_left_edges": ("positions", _positions_left_edges),
+    "norm_without_polar": ("correction_norm", _norm_without_polar),
+    "clip_slab_too_wide": ("clip_slab", _clip_slab_too_wide),
 }
 
 
