@@ -323,7 +323,11 @@ int azi_plan_run_schedule(const azi_plan* plan, int32_t tile_nnz, int64_t* nruns
  * gives 128-thread workgroups (for batches of small images), any other
  * value 256.  Images up to 2^27 pixels; a batch up to 2^31 runs and
  * entries.
- * Set before azi_plan_upload (a later call re-uploads).
+ * Set before azi_plan_upload (a later call re-uploads).  AZI_ESTATE once
+ * corrections are set on an uploaded plan.  A refused or failed call leaves
+ * the plan in its previous layout (if the re-upload of the new layout fails,
+ * the previous layout is uploaded again; should that fail too, the plan is
+ * left off the device, as after a failed azi_plan_upload).
  */
 #define AZI_LAYOUT_PIXEL 0
 #define AZI_LAYOUT_RING 1

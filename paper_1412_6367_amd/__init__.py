@@ -464,7 +464,9 @@ class Plan:
         _check(lib().azi_graph_create_plan(self._h, _ptr(raw), self._raw_code(raw), _ptr(I),
                                            _ptr(W), _ptr(U), float(empty), _stream(stream),
                                            ctypes.byref(out)))
-        return Graph(out, keep=(raw, I, W, U))
+        # the graph holds this plan's matrix and work-buffer addresses: keep
+        # the plan alive for as long as the graph
+        return Graph(out, keep=(self, raw, I, W, U))
 
 
 class Integrate1d(torch.autograd.Function):
@@ -478,6 +480,7 @@ class Integrate1d(torch.autograd.Function):
     def forward(ctx, x, plan, empty=0.0):
         I, W, U = plan.integrate(x.contiguous(), empty=empty)
         ctx.plan = plan
+        ctx.shape = x.shape
         ctx.save_for_backward(U)
         ctx.mark_non_differentiable(U)
         return I, W, U
@@ -488,7 +491,7 @@ class Integrate1d(torch.autograd.Function):
         gI = None if gI is None else gI.contiguous()
         gW = None if gW is None else gW.contiguous()
         gx = ctx.plan.backward(U, gI, gW)
-        return gx, None, None
+        return gx.view(ctx.shape), None, None
 
 
 def integrate1d(image, plan, *, empty=0.0):
@@ -612,7 +615,9 @@ class Batch:
         _check(lib().azi_graph_create_batch(self._h, _ptr(x), _ptr(I), _ptr(W), _ptr(U),
                                             float(empty), _ptr(grad_I), _ptr(grad_W),
                                             _ptr(grad_x), _stream(stream), ctypes.byref(out)))
-        return Graph(out, keep=(x, I, W, U, grad_I, grad_W, grad_x))
+        # the graph holds this batch's matrices and work buffers: keep the
+        # batch alive for as long as the graph
+        return Graph(out, keep=(self, x, I, W, U, grad_I, grad_W, grad_x))
 
     def autotune(self, x, *, stream=None):
         I, W, U = self._outs(None)

@@ -10,6 +10,7 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -20,6 +21,7 @@ ARCH = os.environ.get("AZINT_OFFLOAD_ARCH", "gfx950")
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wno-unused-command-line-argument"]
+HIP_SOURCES = ("kernels.hip", "azint_api.hip", "plan_device.hip", "fused.hip")
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math",
               "-Wall", "-Wextra"]
 
@@ -44,18 +46,21 @@ def _run(cmd, verbose):
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     hipcc = _hipcc()
-    objs = []
     host = os.path.join(BUILD, "plan_builder.o")
-    _run(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, "plan_builder.cpp"), "-o", host], verbose)
-    objs.append(host)
-    for name in ("kernels.hip", "azint_api.hip", "plan_device.hip", "fused.hip"):
+    steps = [(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, "plan_builder.cpp"), "-o", host],
+              host)]
+    for name in HIP_SOURCES:
         obj = os.path.join(BUILD, name.replace(".hip", ".o"))
         # the device plan builder and the matrix-free kernel decide bin
         # indices: no contraction, as on the host
         extra = (["-ffp-contract=off", "-fno-fast-math"]
                  if name in ("plan_device.hip", "fused.hip") else [])
-        _run([hipcc, *HIP_FLAGS, *extra, "-c", os.path.join(CSRC, name), "-o", obj], verbose)
-        objs.append(obj)
+        steps.append(([hipcc, *HIP_FLAGS, *extra, "-c", os.path.join(CSRC, name), "-o", obj],
+                      obj))
+    # the translation units are independent: compile them side by side
+    with ThreadPoolExecutor(max_workers=min(len(steps), os.cpu_count() or 1)) as ex:
+        list(ex.map(lambda st: _run(st[0], verbose), steps))
+    objs = [obj for _, obj in steps]
     tmp = LIB + ".tmp"
     _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp], verbose)
     os.replace(tmp, LIB)

@@ -1032,18 +1032,36 @@ int azi_plan_set_layout(azi_plan* p, int32_t layout) {
         return fail(AZI_EINVAL,
                     "the fused layout takes one-dimensional plans without full splitting");
     if (layout == p->layout) return AZI_OK;
+    // every check comes before the layout changes, so a refused call leaves
+    // the plan as it was
+    if (p->device >= 0 && (p->has_dark || p->has_norm))
+        return fail(AZI_ESTATE, "set the layout before the corrections");
+    const int32_t old = p->layout;
     p->layout = layout;
-    if (p->device >= 0) {
-        if (p->has_dark || p->has_norm)
-            return fail(AZI_ESTATE, "set the layout before the corrections");
-        {
-            DeviceGuard g(p->device);
-            if (g.err != hipSuccess) return hip_fail(g.err, "set device");
-            AZI_HIP(hipDeviceSynchronize(), "synchronise before re-upload");
+    if (p->device < 0) return AZI_OK;
+    {
+        DeviceGuard g(p->device);
+        if (g.err != hipSuccess) {
+            p->layout = old;
+            return hip_fail(g.err, "set device");
         }
-        return azi_plan_upload(p, p->device);
+        const hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) {
+            p->layout = old;
+            return hip_fail(e, "synchronise before re-upload");
+        }
     }
-    return AZI_OK;
+    const int32_t dev = p->device;
+    const int rc = azi_plan_upload(p, dev);
+    if (rc == AZI_OK) return AZI_OK;
+    // the new layout could not be placed: put the old one back
+    const std::string why = azi_last_error();
+    p->layout = old;
+    const int rc2 = azi_plan_upload(p, dev);
+    return fail(rc, why + (rc2 == AZI_OK
+                               ? " (the plan keeps its previous layout)"
+                               : " (the previous layout could not be restored either: the plan "
+                                 "is no longer on a device)"));
 }
 
 int azi_plan_get_layout(const azi_plan* p, int32_t* layout) {

@@ -233,9 +233,30 @@ int build_matrix(const azi_geom& g, int32_t npt, int32_t npt_azim, int32_t unit,
     m.colptr.assign(npix + 1, 0);
     m.rowidx.clear();
     m.cdata.clear();
-    m.rowidx.reserve(boxes ? npix * 3 : npix);
-    m.cdata.reserve(m.rowidx.capacity());
     const int64_t limit = std::numeric_limits<int32_t>::max();
+    int64_t reserve = boxes ? npix * 3 : npix;
+    if (!two_d && split != AZI_SPLIT_FULL) {
+        // one-dimensional bounding box or no split: a pixel's entries are
+        // exactly the bins b0 .. b1 of its box (never a zero coefficient),
+        // so the count is known before anything is stored
+        int64_t nnz = 0;
+        for (int64_t p = 0; p < npix; ++p) {
+            if (split == AZI_SPLIT_BBOX) {
+                const BoxTerms t = bbox_terms(lo[p], hi[p], pmin, delta, npt);
+                if (t.b0 <= t.b1) nnz += (int64_t)t.b1 - t.b0 + 1;
+            } else {
+                const double fc = (lo[p] - pmin) / delta;
+                if (fc >= 0.0 && fc <= (double)npt) ++nnz;
+            }
+        }
+        if (nnz >= limit) {
+            err = "matrix has 2^31 nonzeros or more";
+            return AZI_EOVERFLOW;
+        }
+        reserve = nnz;
+    }
+    m.rowidx.reserve(reserve);
+    m.cdata.reserve(m.rowidx.capacity());
     auto push = [&](int32_t b, double c) {
         m.rowidx.push_back(b);
         m.cdata.push_back(c);

@@ -456,3 +456,44 @@ def test_new_entry_points_reject_bad_arguments():
     assert rc < 0
     assert L.azi_plan_autotune(None, None, None, None, None, None, None, 0) < 0
     assert L.azi_plan_correction_bytes(plan.handle) == 0
+
+
+def test_overflow_limits_are_reported():
+    """Counts that do not fit int32 give AZI_EOVERFLOW (-3) before anything
+    large is allocated: 2^31 pixels, 2^31 bins of a 2-D plan, and a 1-D
+    matrix of 2^31 nonzeros or more (a 3 x 3 detector whose boxes each span
+    ~2^28 of 2^30 bins)."""
+    az = azint()
+    with pytest.raises(az.AzintError, match="azint error -3: image has 2\\^31 pixels"):
+        az.Plan(46341, 46341, 10)
+    with pytest.raises(az.AzintError, match="azint error -3: .*2\\^31"):
+        az.Plan(4, 4, 1 << 16, npt_azim=1 << 15)
+    with pytest.raises(az.AzintError, match="azint error -3: matrix has 2\\^31 nonzeros"):
+        az.Plan(3, 3, 1 << 30)
+    # just below: the same detector with 2^20 bins builds, ~3e6 nonzeros
+    p = az.Plan(3, 3, 1 << 20)
+    assert 2_000_000 < p.nnz < 1 << 31
+
+
+def test_images_of_2_27_pixels_default_to_the_csr_layout():
+    """The run and band layouts number pixels in 27 bits: an image of 2^27
+    pixels or more (here 11586^2, with a narrow radial range so that the
+    matrix stays small) starts in the pixel (CSR) layout, and the run
+    schedule of it is refused with AZI_EOVERFLOW."""
+    az = azint()
+    n = 11586
+    assert n * n >= 1 << 27
+    p = az.Plan(n, n, 16, center=(n / 2 + 0.3, n / 2 - 0.2), range=(2e-4, 6e-4))
+    assert p.layout() == "pixel"
+    assert 0 < p.nnz < 10_000
+    cnt = ctypes.c_int64()
+    rc = az.lib().azi_plan_run_schedule(p._h, 4096, ctypes.byref(cnt), None, None, None, None,
+                                        None, None, None)
+    assert rc == -3
+    assert b"2^27" in az.lib().azi_last_error()
+    # the matrix itself is right: each row against the oracle's, via the
+    # pixels that can reach the range
+    data, indices, indptr = p.export_csr()
+    ii, jj = np.divmod(indices, n)
+    assert np.all(np.abs(ii - n / 2) < 8) and np.all(np.abs(jj - n / 2) < 8)
+    del p

@@ -108,11 +108,14 @@ def test_dot_product_identity(dev):
     assert abs(lhs - rhs) <= 1e-13 * scale
 
 
-def test_autograd_function_gradcheck(dev):
-    say("gradcheck")
+@pytest.mark.parametrize("shape", [(256,), (16, 16)])
+def test_autograd_function_gradcheck(shape, dev):
+    """gradcheck of the autograd function on a flat image and on an (h, w)
+    image, whose gradient must come back in the image's own shape."""
+    say("gradcheck", shape)
     az = azint()
     plan = az.Plan(16, 16, 12, center=(8.3, 7.9), device=dev)
-    x = torch.rand(256, dtype=torch.float64, device=dev, requires_grad=True)
+    x = torch.rand(shape, dtype=torch.float64, device=dev, requires_grad=True)
 
     def f(x):
         I, W, _ = az.Integrate1d.apply(x, plan, 0.0)
@@ -120,6 +123,9 @@ def test_autograd_function_gradcheck(dev):
 
     # W ~ 30 here: its rounding (~4e-15) over 2*eps gives ~2e-9 of FD noise
     assert torch.autograd.gradcheck(f, (x,), eps=1e-6, atol=2e-8, rtol=1e-7)
+    I, W, _ = az.Integrate1d.apply(x, plan, 0.0)
+    (g,) = torch.autograd.grad(I.sum() + W.sum(), x)
+    assert g.shape == x.shape
 
 
 def test_backward_wrt_raw_with_corrections(dev):

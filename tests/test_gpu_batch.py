@@ -172,6 +172,42 @@ def test_plan_graph(dev):
         assert torch.equal(I, I0) and torch.equal(W, W0) and torch.equal(U, U0)
 
 
+def test_graph_keeps_its_owner_alive(dev):
+    """A graph records its plan's (or batch's) device matrices and work
+    buffers: dropping the caller's last reference to the owner must not free
+    them while the graph lives."""
+    say("graph owner")
+    import gc
+    az = azint()
+    inst = synth.instance(20000, 5)
+    g = inst.geom
+    plan = az.Plan(g.h, g.w, inst.npt, device=dev)
+    raw = torch.from_numpy(inst.raw.reshape(-1)).to(dev)
+    I0, W0, U0 = plan.integrate_raw(raw)
+    I, W, U = (torch.empty_like(I0) for _ in range(3))
+    graph = plan.graph(raw, I, W, U)
+    assert any(k is plan for k in graph._keep)
+    del plan
+    insts = small_batch(12, 19)
+    _, batch = make_batch(insts, torch.float64, dev)
+    x = torch.from_numpy(flat_images(insts, np.float64)).to(dev)
+    Ib0, Wb0, Ub0 = batch.forward(x)
+    Ib, Wb, Ub = (torch.empty_like(Ib0) for _ in range(3))
+    bgraph = batch.graph(x, Ib, Wb, Ub)
+    assert any(k is batch for k in bgraph._keep)
+    del batch, _
+    gc.collect()
+    # other allocations that could reuse freed memory
+    junk = [torch.full((1 << 20,), 7.0, dtype=torch.float64, device=dev) for _ in range(8)]
+    for _ in range(2):
+        graph.launch()
+        bgraph.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(I, I0) and torch.equal(W, W0) and torch.equal(U, U0)
+        assert torch.equal(Ib, Ib0) and torch.equal(Wb, Wb0) and torch.equal(Ub, Ub0)
+    del junk
+
+
 def test_autotune_picks_valid_config(dev, tmp_path):
     say("autotune")
     az = azint()
@@ -210,21 +246,28 @@ def test_c3_full_batch_sampled(layout, dev):
     Il, Wl, Ul = batch.forward(x, loop=True)
     torch.cuda.synchronize()
     assert torch.equal(I, Il) and torch.equal(W, Wl) and torch.equal(U, Ul)
+    Ih = I.cpu().numpy()
     Uh = U.cpu().numpy()
     Wh = W.cpu().numpy()
     po, bo = batch.pix_off, batch.bin_off
     xh = x.cpu().numpy()
     for k in range(len(insts)):
         assert abs(Uh[bo[k]:bo[k + 1]].sum() - (po[k + 1] - po[k])) <= 1e-9 * (po[k + 1] - po[k])
-        assert abs(Wh[bo[k]:bo[k + 1]].sum() - xh[po[k]:po[k + 1]].sum()) <= 1e-12 * xh[po[k]:po[k + 1]].sum()
+        xs = np.abs(xh[po[k]:po[k + 1]]).sum()
+        assert abs(Wh[bo[k]:bo[k + 1]].sum() - xh[po[k]:po[k + 1]].sum()) <= 1e-12 * xs
     for k in np.random.default_rng(0).choice(len(insts), 12, replace=False):
         inst = insts[k]
         g = inst.geom
         m = oracle_matrix(g.h, g.w, g.center_y, g.center_x, inst.npt)
         xv = inst.raw.reshape(-1).astype(np.float64)
         Io, Wo, Uo = oracle.integrate(m, xv)
-        _, Wa, _ = oracle.integrate(m, xv)
-        assert norm_err(Wh[bo[k]:bo[k + 1]], Wo, Wa) <= 1e-12, k
+        _, Wa, _ = oracle.integrate(m, np.abs(xv))
+        sI = np.where(Uo > 0, Wa / np.where(Uo > 0, Uo, 1.0), 0.0)
+        sl = slice(bo[k], bo[k + 1])
+        assert norm_err(Wh[sl], Wo, Wa) <= 1e-12, k
+        assert norm_err(Uh[sl], Uo, Uo) <= 1e-12, k
+        assert norm_err(Ih[sl], Io, sI) <= 1e-12, k
+        assert np.all(Ih[sl][Uo == 0] == 0.0) and np.all(Wh[sl][Uo == 0] == 0.0), k
 
 
 @pytest.mark.parametrize("R,piece", [(4, 512), (8, 2048), (16, 256), (8, 64)])
