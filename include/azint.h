@@ -396,6 +396,32 @@ int azi_integrate1d_raw(const azi_plan* plan, const void* raw, int32_t raw_dtype
                         void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * azi_integrate1d_raw with the same kernels, the same order of sums and so
+ * the same bits, but the partial sums go to a static device array of
+ * azi_noalloc_scratch_bytes() bytes (8 MiB) instead of the plan's own work
+ * buffer.  Every device the library runs on holds one such array until the
+ * process ends; its address is looked up on the first call on each device.
+ * The call allocates nothing and does not synchronise.
+ *   Layouts: run and band (stage AZI_STAGE_FUSE, the defaults), tile and
+ *   fused; the pixel and ring layouts (which also need the plan's work
+ *   image) give AZI_EINVAL.
+ *   Limit: a plan whose partial sums exceed the array (16 bytes per slot:
+ *   4 slots per band piece, one per (tile, bin) of the tile and fused
+ *   layouts) gives AZI_EINVAL; at the default tiling a ~1e7-pixel frame
+ *   with 3162 bins needs about 0.5 MB.
+ *   Sharing: all calls on one device share its array and every call
+ *   overwrites what it needs before reading it, so sequential calls, on one
+ *   stream or ordered by events, are safe; calls that overlap in time on
+ *   one device (different streams or threads) race on it.
+ */
+int azi_integrate1d_raw_noalloc(const azi_plan* plan, const void* raw, int32_t raw_dtype,
+                                void* out_I, void* out_W, void* out_U, double empty,
+                                void* stream);
+int64_t azi_noalloc_scratch_bytes(void);
+
+/*
  * The two stages of azi_integrate1d_raw as separate calls (for callers that
  * time or overlap them): azi_plan_stage runs the cast and correction of a
  * raw image into the plan's work image, in the plan's layout;

@@ -106,6 +106,8 @@ _SIGS = {
     "azi_correct": (ctypes.c_int, [_P, _P, _I32, _P, _P]),
     "azi_integrate1d": (ctypes.c_int, [_P, _P, _P, _P, _P, _D, _P]),
     "azi_integrate1d_raw": (ctypes.c_int, [_P, _P, _I32, _P, _P, _P, _D, _P]),
+    "azi_integrate1d_raw_noalloc": (ctypes.c_int, [_P, _P, _I32, _P, _P, _P, _D, _P]),
+    "azi_noalloc_scratch_bytes": (_I64, []),
     "azi_integrate1d_backward": (ctypes.c_int, [_P, _P, _P, _P, _P, _I32, _P]),
     "azi_plan_stage": (ctypes.c_int, [_P, _P, _I32, _P]),
     "azi_integrate1d_staged": (ctypes.c_int, [_P, _P, _P, _P, _D, _P]),
@@ -436,6 +438,16 @@ class Plan:
         I, W, U = self._outs(out)
         _check(lib().azi_integrate1d_raw(self._h, _ptr(raw), self._raw_code(raw), _ptr(I),
                                          _ptr(W), _ptr(U), float(empty), _stream(stream)))
+        return I, W, U
+
+    def integrate_raw_noalloc(self, raw, *, empty=0.0, out=None, stream=None):
+        """integrate_raw with its partial sums in the library's static device
+        array: given `out`, neither this call nor the library allocates."""
+        _need(raw, None, self.npix, self.device, "raw")
+        I, W, U = self._outs(out)
+        _check(lib().azi_integrate1d_raw_noalloc(self._h, _ptr(raw), self._raw_code(raw),
+                                                 _ptr(I), _ptr(W), _ptr(U), float(empty),
+                                                 _stream(stream)))
         return I, W, U
 
     def stage(self, raw, *, stream=None):

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1356,6 +1357,87 @@ int azi_integrate1d_raw(const azi_plan* p, const void* raw, int32_t raw_dtype, v
     int rc = azi_plan_stage(p, raw, raw_dtype, stream);
     if (rc != AZI_OK) return rc;
     return azi_integrate1d_staged(p, I, W, U, empty, stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Partial sums of azi_integrate1d_raw_noalloc.  Each device that loads the
+// library holds its own copy until the process ends; host code reaches it
+// only through the address hipGetSymbolAddress returns for that device.
+constexpr size_t kScratchBytes = (size_t)8 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on `device`, which must be current; looked up
+// on the first call for each device and kept.
+int scratch_address(int device, void** out) {
+    if (device < 0 || device >= kMaxScratchDevices)
+        return fail(AZI_EDEVICE, "device ordinal beyond the static scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* ptr = nullptr;
+        AZI_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "static scratch address");
+        if (!ptr) return fail(AZI_EDEVICE, "static scratch address is NULL");
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return AZI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t azi_noalloc_scratch_bytes(void) { return (int64_t)kScratchBytes; }
+
+int azi_integrate1d_raw_noalloc(const azi_plan* p, const void* raw, int32_t raw_dtype, void* I,
+                                void* W, void* U, double empty, void* stream) {
+    int rc = check_plan_ready(p);
+    if (rc != AZI_OK) return rc;
+    if (!raw || !I) return fail(AZI_EINVAL, "raw and out_I must not be NULL");
+    if (!valid_raw_dtype(raw_dtype)) return fail(AZI_EINVAL, "unknown raw dtype");
+    // the layouts whose raw-frame path needs partial sums and nothing else
+    size_t need = 0;
+    if (is_band(p->layout) && p->tiling.stage == AZI_STAGE_FUSE) need = p->nparts_buf.bytes;
+    else if (p->layout == AZI_LAYOUT_TILE) need = p->bparts.bytes;
+    else if (p->layout == AZI_LAYOUT_FUSED) need = p->fparts.bytes;
+    else
+        return fail(AZI_EINVAL,
+                    "the allocation-free call takes the run and band layouts (stage "
+                    "AZI_STAGE_FUSE), the tile layout and the fused layout");
+    if (need > kScratchBytes)
+        return fail(AZI_EINVAL, "plan needs " + std::to_string(need) +
+                                    " bytes of partial sums, more than the " +
+                                    std::to_string(kScratchBytes) + "-byte static scratch");
+    DeviceGuard g(p->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "set device");
+    void* parts = nullptr;
+    rc = scratch_address(p->device, &parts);
+    if (rc != AZI_OK) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (p->layout == AZI_LAYOUT_FUSED) {
+        azi::FusedLaunch a = plan_fused_args(p, raw, raw_dtype, true, I, W, U, empty);
+        a.parts = parts;
+        AZI_HIP(azi::launch_fused(a, s), "fused forward kernels");
+    } else if (p->layout == AZI_LAYOUT_TILE) {
+        azi::BlockLaunch a = plan_block_args(p, raw, raw_dtype, true, I, W, U, empty);
+        a.parts = parts;
+        AZI_HIP(azi::launch_block(a, s), "blocked forward kernels");
+    } else {
+        azi::BandLaunch a = plan_band_args(p, nullptr, I, W, U, empty);
+        a.raw = raw;
+        a.raw_dtype = raw_dtype;
+        a.corr = (p->has_dark || p->has_norm) ? p->corr.p : nullptr;
+        a.corr_kind = p->corr_kind;
+        a.parts = parts;
+        AZI_HIP(azi::launch_band(a, s), "band forward kernels");
+    }
+    return AZI_OK;
 }
 
 int azi_integrate1d_backward(const azi_plan* p, const void* U, const void* gI, const void* gW,
