@@ -42,6 +42,20 @@ KERNEL_OF_LAYOUT = {
 }
 
 
+def kernel_of(line):
+    """The step's dominant kernel, from the plan's layout and tiling."""
+    t = line["tiling"]
+    if line["layout"] == "run" and t["band"] in (16, 32):
+        k = (f"k_runs_grouped (+k_band_reduce): run-encoded gather integration, "
+             f"{t['band'] // 4} neighbouring bands of 4 bins per workgroup")
+    else:
+        k = KERNEL_OF_LAYOUT[line["layout"]]
+    if t["stage"] == 4:
+        return k + ", 1/norm folded into the coefficients and dark stored per run: the raw " \
+                   "count is the only gathered value"
+    return k + ", reading the raw frame and correcting in the gather"
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -120,7 +134,9 @@ def raw_bytes(nnz, npix, npt, es, cb):
 def encoding_bytes(plan, np, npix, npt, es, cb):
     """Bytes the run encoding itself streams per raw-frame step (a word per
     pixel run within a band of 4 bins instead of an index per entry; the
-    step's roofline keeps the CSR figure of raw_bytes as its yardstick)."""
+    step's roofline keeps the CSR figure of raw_bytes as its yardstick).
+    With 1/norm folded into the coefficients the dark value (cb bytes) is
+    stored per run beside the run word instead of gathered per pixel."""
     if plan.layout() != "run":
         return raw_bytes(plan.nnz, npix, npt, es, cb)
     _, bins, colptr = plan.export_csc()
@@ -128,10 +144,13 @@ def encoding_bytes(plan, np, npix, npt, es, cb):
     first = bins[colptr[:-1][full]] // 4
     last = bins[colptr[1:][full] - 1] // 4
     runs = int((last - first + 1).sum())
+    if plan.tiling()["stage"] == 4:
+        return runs * (4 + cb) + plan.nnz * es + npix * 4 + 3 * npt * es
     return runs * 4 + plan.nnz * es + npix * (4 + cb) + 3 * npt * es
 
 
-def pipeline_line(az, torch, np, synth, dev, dtype, steps, warmup, frames_n=4):
+def pipeline_line(az, torch, np, synth, dev, dtype, steps, warmup, frames_n=4, accum="f64",
+                  stage=None):
     """Step = one raw int32 frame -> I, W, U with the plan's corrections
     (azi_integrate1d_raw).  With the default layout and tiling the run
     kernel casts and corrects each pixel it gathers, so the step is that
@@ -144,8 +163,9 @@ def pipeline_line(az, torch, np, synth, dev, dtype, steps, warmup, frames_n=4):
     tdt = torch.float64 if dtype == "f64" else torch.float32
     npd = np.float64 if dtype == "f64" else np.float32
     t0 = time.perf_counter()
-    plan = az.Plan(g.h, g.w, inst.npt, center=(g.center_y, g.center_x), dtype=tdt, device=dev)
-    log(f"[{dtype}] plan {g.h}x{g.w} npt={inst.npt} nnz={plan.nnz} built+uploaded in "
+    plan = az.Plan(g.h, g.w, inst.npt, center=(g.center_y, g.center_x), dtype=tdt, accum=accum,
+                   device=dev, **({"stage": stage} if stage else {}))
+    log(f"[{dtype}/{accum}] plan {g.h}x{g.w} npt={inst.npt} nnz={plan.nnz} built+uploaded in "
         f"{time.perf_counter() - t0:.1f}s")
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a).reshape(-1).astype(npd)).to(dev)
     plan.set_corrections(t(inst.dark), t(inst.flat), t(inst.solid), t(inst.polar))
@@ -175,6 +195,9 @@ def pipeline_line(az, torch, np, synth, dev, dtype, steps, warmup, frames_n=4):
     rb = raw_bytes(nnz, g.npix, inst.npt, es, cb)
     enc = encoding_bytes(plan, np, g.npix, inst.npt, es, cb)
     # two-pass breakdown: correction kernel, then integration of the image
+    # (its kernels' first launches untimed)
+    plan.stage(frames[0])
+    plan.integrate_staged(out=outs)
     pairs = []
     for k in range(max(steps // 4, 10)):
         e = tuple(torch.cuda.Event(enable_timing=True) for _ in range(3))
@@ -203,7 +226,7 @@ def pipeline_line(az, torch, np, synth, dev, dtype, steps, warmup, frames_n=4):
     b = spmv_bytes(nnz, g.npix, inst.npt, es)
     # raw + dark + norm read, corrected image written
     corr_b = g.npix * (4 + 3 * es)
-    line = dict(npix=g.npix, npt=inst.npt, nnz=nnz, layout=plan.layout(),
+    line = dict(npix=g.npix, npt=inst.npt, nnz=nnz, layout=plan.layout(), accum=accum,
                 tiling=plan.tiling(), ms_per_step=ms_step,
                 elements_per_s=g.npix / (ms_step * 1e-3),
                 correction_bytes_per_pixel=cb,
@@ -218,23 +241,49 @@ def pipeline_line(az, torch, np, synth, dev, dtype, steps, warmup, frames_n=4):
     return line, plan, outs, frames[0]
 
 
-def cold_line(torch, plan, outs, frame, npix, npt, nnz, es, reps=20):
-    """The step's kernel (raw frame, corrections in the gather) after
-    streaming 1 GiB, which flushes L2 and MALL."""
-    flush = torch.empty(1 << 28, dtype=torch.float32, device=plan.device)
-    pairs = []
-    for _ in range(reps):
-        flush.fill_(1.0)
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        plan.integrate_raw(frame, out=outs)
-        b.record()
-        pairs.append((a, b))
-    torch.cuda.synchronize()
-    ms = mean_event_ms(pairs)
+class Flush:
+    """Reads 1 GiB (a sum into one scalar) to push the step's data out of the
+    L2 caches and the 256 MB MALL.  Reading leaves no dirty lines behind, so
+    the timed launch after it writes nothing back on the flush's account."""
+
+    def __init__(self, torch, dev):
+        self.torch = torch
+        self.buf = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        self.out = torch.empty((), dtype=torch.float64, device=dev)
+
+    def __call__(self):
+        self.torch.sum(self.buf, dim=0, out=self.out)
+
+
+def flushed_ms(torch, fn, flush, sets=3, reps=10):
+    """The timing protocol of the paper's benchmarks (Section 6: best of 3
+    sets of 10), each launch preceded by a cache flush: the median of each
+    set, the best of the sets.  Returns (best, the three medians)."""
+    fn()
+    meds = []
+    for _ in range(sets):
+        pairs = []
+        for _ in range(reps):
+            flush()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            pairs.append((a, b))
+        torch.cuda.synchronize()
+        ts = sorted(a.elapsed_time(b) for a, b in pairs)
+        meds.append(0.5 * (ts[(reps - 1) // 2] + ts[reps // 2]))
+    return min(meds), meds
+
+
+def cold_line(torch, plan, outs, frame, npix, npt, nnz, es, flush):
+    """The step (raw frame, corrections in the gather) with the caches
+    flushed before every launch."""
+    ms, meds = flushed_ms(torch, lambda: plan.integrate_raw(frame, out=outs), flush)
     by = raw_bytes(nnz, npix, npt, es, plan.correction_bytes())
-    return dict(step_ms=ms, step_gbs=by / (ms * 1e6),
-                step_frac=by / (ms * 1e6) / HBM_PEAK_GBS)
+    return dict(step_ms=ms, set_medians_ms=meds, step_bytes=by, step_gbs=by / (ms * 1e6),
+                step_frac=by / (ms * 1e6) / HBM_PEAK_GBS,
+                protocol="1 GiB read before each launch; median of 10, best of 3 sets")
 
 
 def batch_line(az, torch, np, synth, dev, cfg, dtype, with_bwd, tune, reps=20):
@@ -277,6 +326,26 @@ def batch_line(az, torch, np, synth, dev, cfg, dtype, with_bwd, tune, reps=20):
     loop_ms = timed(lambda: batch.forward(x, out=(I, W, U), loop=True))
     graph = batch.graph(x, I, W, U, grad_I=gI, grad_x=gx)
     graph_ms = timed(graph.launch)
+    persistent = None
+    if report:
+        # the fastest persistent grid of the sweep (a fixed number of
+        # workgroups walking the static piece schedule), timed beside the
+        # chosen tiling, eagerly and captured in a graph
+        pc = [c for c in report["candidates"] if c["grid"] > 0]
+        if pc:
+            bp = min(pc, key=lambda c: c["ms"])
+            batch.set_tiling(tile_nnz=bp["tile_nnz"], block=bp["block"], grid=bp["grid"])
+            p_fwd = timed(lambda: batch.forward(x, out=(I, W, U)))
+            pgraph = batch.graph(x, I, W, U)
+            p_graph = timed(pgraph.launch)
+            del pgraph
+            fb0 = spmv_bytes(batch.nnz, batch.npix, batch.npt, es)
+            persistent = dict(tiling=batch.tiling(), forward_ms=p_fwd,
+                              forward_frac=fb0 / (p_fwd * 1e6) / HBM_PEAK_GBS,
+                              graph_forward_ms=p_graph,
+                              graph_forward_frac=fb0 / (p_graph * 1e6) / HBM_PEAK_GBS)
+            batch.set_tiling(**{k: tiling[k] for k in ("tile_nnz", "block", "variant", "grid",
+                                                       "band", "stage")})
     fb = spmv_bytes(batch.nnz, batch.npix, batch.npt, es)
     line = dict(instances=batch.n, npix=batch.npix, npt=batch.npt, nnz=batch.nnz,
                 tiling=tiling, forward_ms=fwd_ms, forward_gbs=fb / (fwd_ms * 1e6),
@@ -298,6 +367,8 @@ def batch_line(az, torch, np, synth, dev, cfg, dtype, with_bwd, tune, reps=20):
                     graph_frac=fb / (graph_ms * 1e6) / HBM_PEAK_GBS)
     if report:
         line["autotune_candidates"] = len(report["candidates"])
+    if persistent:
+        line["persistent"] = persistent
     del graph, batch
     torch.cuda.empty_cache()
     return line
@@ -329,12 +400,10 @@ def adjoint_line(az, torch, np, synth, dev, reps=50):
                 backward_gbs=bwd_bytes(nnz, g.npix, inst.npt, 8) / (b * 1e6))
 
 
-def _timed(torch, fn, reps=20, flush=None):
+def _timed(torch, fn, reps=20):
     fn()
     pairs = []
     for _ in range(reps):
-        if flush is not None:
-            flush.fill_(1.0)
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()
         fn()
@@ -359,9 +428,10 @@ def fused_line(az, torch, np, synth, dev, reps=50):
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a).reshape(-1).astype(np.float64)).to(dev)
     x = t(inst.raw)
     outs = tuple(torch.empty(inst.npt, dtype=torch.float64, device=dev) for _ in range(3))
-    flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    flush = Flush(torch, dev)
     warm = _timed(torch, lambda: plan.integrate(x, out=outs), reps)
-    cold = _timed(torch, lambda: plan.integrate(x, out=outs), reps, flush)
+    cold, _ = flushed_ms(torch, lambda: plan.integrate(x, out=outs), flush)
+    del flush
     plan.set_corrections(t(inst.dark), t(inst.flat), t(inst.solid), t(inst.polar))
     raw = torch.from_numpy(inst.raw.reshape(-1)).to(dev)
     pipe = _timed(torch, lambda: plan.integrate_raw(raw, out=outs), reps)
@@ -417,9 +487,10 @@ def two_d_line(az, torch, np, synth, dev, nr=1000, na=360, reps=30):
     build_s = time.perf_counter() - t0
     x = torch.from_numpy(inst.raw.reshape(-1).astype(np.float64)).to(dev)
     outs = tuple(torch.empty(plan.npt, dtype=torch.float64, device=dev) for _ in range(3))
-    flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    flush = Flush(torch, dev)
     warm = _timed(torch, lambda: plan.integrate(x, out=outs), reps)
-    cold = _timed(torch, lambda: plan.integrate(x, out=outs), reps, flush)
+    cold, _ = flushed_ms(torch, lambda: plan.integrate(x, out=outs), flush)
+    del flush
     nnz = plan.nnz
     by = spmv_bytes(nnz, g.npix, plan.npt, 8)
     line = dict(npix=g.npix, npt_rad=nr, npt_azim=na, nnz=nnz, layout=plan.layout(),
@@ -533,7 +604,22 @@ def cpu_baseline(np, synth):
     return dict(value=g.npix / best, unit="elements/s", cores=1, kind="oracle",
                 sample=f"full 3162x3163 frame, correction + integration, best of {reps} "
                        f"({best:.2f} s each; matrix built beforehand, untimed); "
-                       f"single-threaded NumPy")
+                       f"single-threaded NumPy",
+                host_cpu=host_cpu_model(), host_cpu_count=os.cpu_count(),
+                host_cpus_usable=len(os.sched_getaffinity(0)))
+
+
+def host_cpu_model():
+    """The host CPU's model name (first entry of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
 
 def main():
@@ -550,9 +636,16 @@ def main():
 
     dev = torch.device("cuda:0")
     az.lib()
+    flush = Flush(torch, dev)
     line64, plan, outs, frame = pipeline_line(az, torch, np, synth, dev, "f64", args.steps,
                                               args.warmup)
     log(f"[f64] {json.dumps(line64)}")
+    es64 = 8
+    cold64 = cold_line(torch, plan, outs, frame, line64["npix"], line64["npt"], line64["nnz"],
+                       es64, flush)
+    log(f"[f64 flushed] {json.dumps(cold64)}")
+    del plan, outs, frame
+    torch.cuda.empty_cache()
     result = {
         "metric": "elements/s and fraction of HBM roofline, plain vs batched+adjoint",
         "value": line64["elements_per_s"],
@@ -574,34 +667,45 @@ def main():
                         "applied in the integration kernel's gather",
             "npix": line64["npix"], "npt": line64["npt"], "nnz": line64["nnz"],
         },
+        # headline: the step with L2 and MALL flushed before every launch (the
+        # benchmark protocol); the steady-state figure of the timed region,
+        # where frames follow each other and the caches keep what the
+        # previous frame left, is under "warm"
         "roofline": {
             "bound": "hbm",
-            "kernel": KERNEL_OF_LAYOUT[line64["layout"]] + ", reading the raw frame and "
-                      "correcting in the gather",
-            "achieved": line64["step_gbs"],
+            "kernel": kernel_of(line64),
+            "achieved": cold64["step_gbs"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": line64["step_frac"],
-            "traffic": measured_traffic("c2_f64"),
+            "frac": cold64["step_frac"],
+            "traffic": measured_traffic("c2_f64_flushed"),
             "bytes_per_launch": line64["step_bytes"],
-            "avg_launch_ms": line64["step_ms"],
+            "avg_launch_ms": cold64["step_ms"],
+            "cache": "flushed: " + cold64["protocol"],
+            "warm": {
+                "achieved": line64["step_gbs"],
+                "frac": line64["step_frac"],
+                "avg_launch_ms": line64["step_ms"],
+                "traffic": measured_traffic("c2_f64"),
+                "cache": "warm: back-to-back steps of the timed region, 4 frames rotating",
+            },
         },
-        "lines": {"c2_f64": line64},
+        "lines": {"c2_f64": line64, "c2_f64_cold": cold64},
     }
-    es64 = 8
     want = set(args.only.split(",")) if args.only else None
     run = lambda name: (not args.main_only) and (want is None or name in want)
-    if run("c2_f64_cold"):
-        result["lines"]["c2_f64_cold"] = cold_line(torch, plan, outs, frame, line64["npix"],
-                                                   line64["npt"], line64["nnz"], es64)
-        log(f"[cold] {json.dumps(result['lines']['c2_f64_cold'])}")
-    del plan, outs, frame
-    torch.cuda.empty_cache()
-    if run("c2_f32"):
-        l32, p32, o32, f32 = pipeline_line(az, torch, np, synth, dev, "f32", args.steps,
-                                           args.warmup)
-        result["lines"]["c2_f32"] = l32
-        log(f"[f32] {json.dumps(l32)}")
+    for name, dt, accum, stage in (("c2_f32", "f32", "f64", None),
+                                   ("c2_f32_kahan", "f32", "kahan32", None),
+                                   ("c2_f64_fold", "f64", "f64", "fold"),
+                                   ("c2_f32_fold", "f32", "f64", "fold")):
+        if not run(name):
+            continue
+        l32, p32, o32, f32 = pipeline_line(az, torch, np, synth, dev, dt, args.steps,
+                                           args.warmup, accum=accum, stage=stage)
+        l32["cold"] = cold_line(torch, p32, o32, f32, l32["npix"], l32["npt"], l32["nnz"],
+                                8 if dt == "f64" else 4, flush)
+        result["lines"][name] = l32
+        log(f"[{name}] {json.dumps(l32)}")
         del p32, o32, f32
         torch.cuda.empty_cache()
     if run("c3"):

@@ -201,10 +201,11 @@ int azi_plan_export_csc(const azi_plan* plan, void* data, int32_t* bins, int32_t
 /*
  * Launch and tile schedule of the forward kernel (tuning only: results
  * change at most in the order of the floating-point additions, and, for
- * the stage, by the one rounding of the fused correction).  A new plan
- * starts at tile_nnz 4096, block 256, variant 5, grid 0, band 4, stage
- * AZI_STAGE_FUSE; below 2^22 nonzeros at tile_nnz 2048
- * (two-dimensional plans: 4096, 256, 2, 0, 1, AZI_STAGE_GATHER).
+ * the stage, by the one rounding of the fused or folded correction).  A
+ * new plan starts at tile_nnz 4096, block 256, variant 5, grid 0, band 16,
+ * stage AZI_STAGE_FOLD; below 2^22 nonzeros at tile_nnz 2048 (plans built
+ * on the device, which start in the band layout: band 4;
+ * two-dimensional plans: 4096, 256, 2, 0, 1, AZI_STAGE_GATHER).
  *   tile_nnz  most nonzeros one workgroup sums per tile (64..16384, a
  *             multiple of 64); rows longer than that are cut into pieces
  *             whose sums are added in order by a small fix-up kernel.
@@ -219,7 +220,13 @@ int azi_plan_export_csc(const azi_plan* plan, void* data, int32_t* bins, int32_t
  *             workgroups walk the tiles.
  *   band      > 1: pieces of up to `band` consecutive long rows are
  *             interleaved, so tiles that run together read the same part of
- *             neighbouring rings; 0 or 1: rows one after the other.
+ *             neighbouring rings; 0 or 1: rows one after the other.  Band
+ *             layout: bins per band (4, 8 or 16).  Run layout: 16 or 32
+ *             puts 4 or 8 neighbouring bands of 4 bins in one workgroup (one
+ *             wavefront per band, over common stretches of image rows, so
+ *             that they share the gathered image lines in the CU's cache;
+ *             the workgroup then has 256 or 512 threads whatever `block`
+ *             says); other values, one band per workgroup of `block`.
  *   stage     how an image is brought into ring positions (ring layout only):
  *             AZI_STAGE_GATHER reads each ring position's pixel; _SCATTER
  *             reads row-major and writes each pixel's ring position;
@@ -234,12 +241,25 @@ int azi_plan_export_csc(const azi_plan* plan, void* data, int32_t* bins, int32_t
  *             the rounded reciprocal differs from the quotient of
  *             azi_correct by at most one rounding per pixel.  azi_plan_stage
  *             and the staged call keep the two passes.
+ *             AZI_STAGE_FOLD (run layout; the band layout takes it as
+ *             AZI_STAGE_FUSE): as AZI_STAGE_FUSE, but 1 / norm is folded
+ *             into the coefficients when the corrections are set (a second
+ *             copy of the coefficients, each multiplied by its pixel's
+ *             1 / norm and rounded once) and each run of the run encoding
+ *             keeps its pixel's dark value beside its word, so the raw
+ *             count is the only gathered value: the kernel forms
+ *             A_bp * (raw - dark) with A_bp carrying 1 / norm, the same sum
+ *             in another order, one rounding per product away from the
+ *             quotient of azi_correct.  U, which does not depend on the
+ *             image, is summed once from the unfolded coefficients at that
+ *             point and written with every frame.
  */
 #define AZI_NUM_VARIANTS 7
 #define AZI_STAGE_GATHER 0
 #define AZI_STAGE_SCATTER 1
 #define AZI_STAGE_TILE 2
 #define AZI_STAGE_FUSE 3
+#define AZI_STAGE_FOLD 4
 typedef struct azi_tiling {
     int32_t tile_nnz, block, variant, grid, band, stage;
 } azi_tiling;
@@ -271,7 +291,10 @@ int azi_plan_tile_schedule(const azi_plan* plan, const azi_tiling* tiling, int32
  *                    first coefficient of each run in run order, then the
  *                    second of the runs that have one, and so on;
  *   pieces[8 * npieces] int32 {run_begin, run_end, first bin of the band,
- *                    rows of the band, first partial slot, 0, 0, 0};
+ *                    rows of the band, first partial slot, 0, 0, 0}; with
+ *                    the plan's tiling band 16 or 32, the workgroups' entries
+ *                    (4 or 8 per workgroup, one per band, slot -1 past the
+ *                    last band);
  *   bin_slot[npt], bin_count[npt]  each bin's first partial slot and count
  *                    (slots first, first + 4, ...).
  * nruns / npieces (may be NULL) receive the counts.  AZI_EOVERFLOW for
@@ -363,9 +386,11 @@ int azi_plan_set_corrections(azi_plan* plan, const void* dark, const void* flat,
                              const void* solid, const void* polar, void* stream);
 
 /* Bytes per pixel of the per-pixel correction the band gather reads (16 or
- * 8 for pairs of float64 / float32, 12 for the records above), or 0 when the
- * raw-frame path keeps no such array (no corrections, or another layout or
- * stage).  0 for a NULL plan. */
+ * 8 for pairs of float64 / float32, 12 for the records above; with
+ * AZI_STAGE_FOLD the dark value alone, stored per run rather than per
+ * pixel: 4 as a float, else the storage size), or 0 when the raw-frame
+ * path keeps no such array (no corrections or no dark with
+ * AZI_STAGE_FOLD, or another layout or stage).  0 for a NULL plan. */
 int32_t azi_plan_correction_bytes(const azi_plan* plan);
 
 /*
@@ -404,7 +429,7 @@ int azi_integrate1d_raw(const azi_plan* plan, const void* raw, int32_t raw_dtype
  * buffer.  Every device the library runs on holds one such array until the
  * process ends; its address is looked up on the first call on each device.
  * The call allocates nothing and does not synchronise.
- *   Layouts: run and band (stage AZI_STAGE_FUSE, the defaults), tile and
+ *   Layouts: run and band (stage AZI_STAGE_FUSE or _FOLD), tile and
  *   fused; the pixel and ring layouts (which also need the plan's work
  *   image) give AZI_EINVAL.
  *   Limit: a plan whose partial sums exceed the array (16 bytes per slot:

@@ -97,6 +97,29 @@ __device__ inline void write_row(int32_t r, const Acc& a, T* __restrict__ I, T* 
     I[r] = (u != 0) ? (T)(w / u) : (T)empty;
 }
 
+// write_row with U taken from outside the partial sums (ufix_in, the plan's
+// U in double), or only U stored (ufix_out): see BandLaunch.
+template <class T, class Acc>
+__device__ inline void write_row_u(int32_t r, const Acc& a, T* __restrict__ I,
+                                   T* __restrict__ W, T* __restrict__ U, double empty,
+                                   const double* __restrict__ ufix_in,
+                                   double* __restrict__ ufix_out) {
+    if (ufix_out) {
+        ufix_out[r] = (double)a.U();
+        return;
+    }
+    if (!ufix_in) {
+        write_row(r, a, I, W, U, empty);
+        return;
+    }
+    using V = decltype(a.U());
+    const V u = (V)ufix_in[r];
+    const auto w = a.W();
+    if (W) W[r] = (T)w;
+    if (U) U[r] = (T)u;
+    I[r] = (u != 0) ? (T)(w / u) : (T)empty;
+}
+
 // Workgroup g runs on XCD g % 8; this maps it to a block index so that each
 // XCD walks one contiguous eighth of the blocks (a bijection on [0, n)).
 __device__ inline int64_t xcd_block(int64_t g, int64_t n) {

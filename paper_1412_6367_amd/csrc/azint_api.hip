@@ -118,13 +118,22 @@ bool valid_tiling(const azi_tiling& t) {
     return t.tile_nnz >= 64 && t.tile_nnz <= 16384 && t.tile_nnz % 64 == 0 &&
            (t.block == 64 || t.block == 128 || t.block == 256 || t.block == 512) &&
            t.variant >= 0 && t.variant < azi::kNumVariants && t.grid >= 0 && t.band >= 0 &&
-           t.stage >= AZI_STAGE_GATHER && t.stage <= AZI_STAGE_FUSE;
+           t.stage >= AZI_STAGE_GATHER && t.stage <= AZI_STAGE_FOLD;
 }
 
-// Fastest measured on the ~1e7-pixel, 3162-bin workload: bands of 4 bins,
-// pieces of 4096 entries, raw frames corrected in the band gather.
-constexpr azi_tiling kDefaultTiling = {4096, 256, 5, 0, 4, AZI_STAGE_FUSE};
-constexpr azi_tiling kDefaultTiling32 = {4096, 256, 5, 0, 4, AZI_STAGE_FUSE};
+// Stages whose raw-frame path corrects each pixel in the band gather.
+bool gather_corrects(int32_t stage) {
+    return stage == AZI_STAGE_FUSE || stage == AZI_STAGE_FOLD;
+}
+
+// Fastest measured on the ~1e7-pixel, 3162-bin workload: run layout with
+// four neighbouring bands of 4 bins per workgroup, pieces of 2048 runs
+// (tile_nnz 4096), raw frames corrected in the gather with 1 / norm folded
+// into the coefficients and dark stored per run (float64: 90 us warm and
+// cold against 106 / 116 us with one band per workgroup and the (dark,
+// 1 / norm) pair gathered per pixel).
+constexpr azi_tiling kDefaultTiling = {4096, 256, 5, 0, 16, AZI_STAGE_FOLD};
+constexpr azi_tiling kDefaultTiling32 = {4096, 256, 5, 0, 16, AZI_STAGE_FOLD};
 // Below ~4e6 nonzeros (a ~1e6-pixel frame) there are too few 4096-entry
 // pieces to fill 256 CUs: 2048 entries (18 us against 21 us at 1e6 pixels).
 // The workgroup stays at 256 threads, the raw-frame band kernel's, so the
@@ -190,8 +199,9 @@ struct azi_plan {
     DevBuf rowptr, indices, data, colptr, rowidx, cdata, tiles, splits, parts, dark, norm, xwork,
         vwork, order, dark_r, norm_r, pos, stiles, lidx, dest, btiles, brows, blp, bcoef, bin_ptr,
         bparts, npieces_buf, npacked, ncoef, bin_slot, bin_count, nparts_buf, ftiles, fslots,
-        fbin_ptr, fparts, corr, cfirst, rgbase;
+        fbin_ptr, fparts, corr, cfirst, rgbase, fcoef, ufix;
     int32_t nstiles = 0, nbtiles = 0, npieces = 0, band_rows = 8, nftiles = 0;
+    bool folded = false;  // run layout, AZI_STAGE_FOLD, corrections set
     int32_t max_count = INT32_MAX;  // largest number of band partials of a bin
     int32_t corr_kind = azi::kCorrPair;
     int32_t ntiles = 0, nsplits = 0, nparts = 0;
@@ -317,6 +327,10 @@ int upload_blocks(const azi::BlockMatrix& bm, int32_t dtype, int device, DevBuf&
 // The band layout in either encoding (per entry, or per run).
 bool is_band(int32_t layout) { return layout == AZI_LAYOUT_BAND || layout == AZI_LAYOUT_RUN; }
 
+// Run layout: neighbouring bands co-scheduled per workgroup (tiling band
+// 16 or 32 = 4 or 8 bands of 4 bins), else one band per workgroup.
+int32_t run_waves(const azi_tiling& t) { return t.band == 16 ? 4 : t.band == 32 ? 8 : 1; }
+
 int32_t band_rows_of(const azi_tiling& t) {
     return (t.band == 4 || t.band == 8 || t.band == 16) ? t.band : 8;
 }
@@ -353,7 +367,8 @@ int plan_upload_bands(azi_plan* p) {
     if (p->layout == AZI_LAYOUT_RUN) {
         try {
             azi::RunMatrix rm;
-            if (!azi::build_runs(p->m, std::max(64, p->tiling.tile_nnz / 2), 0, 0, rm))
+            if (!azi::build_runs(p->m, std::max(64, p->tiling.tile_nnz / 2), 0, 0, rm, nullptr,
+                                 run_waves(p->tiling)))
                 return fail(AZI_EOVERFLOW,
                             "the run layout takes images below 2^27 pixels and 2^31 entries");
             azi::BandMatrix bm;
@@ -397,6 +412,7 @@ azi::BandLaunch plan_band_args(const azi_plan* p, const void* x, void* I, void* 
     a.npieces = p->npieces;
     a.packed = p->npacked.as<int32_t>();
     a.gbase = p->layout == AZI_LAYOUT_RUN ? p->rgbase.as<int32_t>() : nullptr;
+    a.waves = p->layout == AZI_LAYOUT_RUN ? run_waves(p->tiling) : 1;
     a.coef = p->ncoef.p;
     a.bin_slot = p->bin_slot.as<int32_t>();
     a.bin_count = p->bin_count.as<int32_t>();
@@ -414,6 +430,23 @@ azi::BandLaunch plan_band_args(const azi_plan* p, const void* x, void* I, void* 
     a.grid = p->tiling.grid;
     a.dtype = p->dtype;
     a.accum = p->accum;
+    return a;
+}
+
+// Raw-frame band launch: cast and correction in the gather; with the
+// normalisation folded (AZI_STAGE_FOLD) the folded coefficients, dark alone
+// and the plan's U.
+azi::BandLaunch plan_band_raw_args(const azi_plan* p, const void* raw, int32_t raw_dtype,
+                                   void* I, void* W, void* U, double empty) {
+    azi::BandLaunch a = plan_band_args(p, nullptr, I, W, U, empty);
+    a.raw = raw;
+    a.raw_dtype = raw_dtype;
+    a.corr = (p->has_dark || p->has_norm) ? p->corr.p : nullptr;
+    a.corr_kind = p->corr_kind;
+    if (p->folded) {
+        if (p->fcoef.p) a.coef = p->fcoef.p;
+        a.ufix_in = p->ufix.as<double>();
+    }
     return a;
 }
 
@@ -496,12 +529,101 @@ int plan_upload_fused(azi_plan* p) {
 // the plan integrates raw frames with AZI_STAGE_FUSE and has corrections;
 // 12-byte records instead when the plan is float64 and its dark values are
 // all floats.
+// AZI_STAGE_FOLD on the run layout: every coefficient multiplied by its
+// pixel's 1 / norm (on the host, from the plan's double coefficients,
+// rounded once to the storage type), each run's dark value stored beside
+// the run words, and the U of every bin summed once from the unfolded
+// coefficients in the per-frame order (the kernels over any image, the
+// reduction keeping U only).
+template <class S>
+int download_as_double(const DevBuf& src, int64_t n, std::vector<double>& out, hipStream_t s) {
+    std::vector<S> tmp((size_t)n);
+    AZI_HIP(hipMemcpyAsync(tmp.data(), src.p, (size_t)n * sizeof(S), hipMemcpyDeviceToHost, s),
+            "download corrections");
+    AZI_HIP(hipStreamSynchronize(s), "download corrections");
+    out.assign(tmp.begin(), tmp.end());
+    return AZI_OK;
+}
+
+int plan_fold(azi_plan* p, hipStream_t s) {
+    const int64_t npix = p->m.npix;
+    try {
+        std::vector<double> inv, dark;
+        int rc = AZI_OK;
+        if (p->has_norm) {
+            rc = p->dtype == AZI_F64 ? download_as_double<double>(p->norm, npix, inv, s)
+                                     : download_as_double<float>(p->norm, npix, inv, s);
+            if (rc != AZI_OK) return rc;
+            for (double& v : inv) v = 1.0 / v;
+        }
+        if (p->has_dark) {
+            rc = p->dtype == AZI_F64 ? download_as_double<double>(p->dark, npix, dark, s)
+                                     : download_as_double<float>(p->dark, npix, dark, s);
+            if (rc != AZI_OK) return rc;
+        }
+        azi::RunMatrix rm;
+        if (!azi::build_runs(p->m, std::max(64, p->tiling.tile_nnz / 2), 0, 0, rm,
+                             p->has_norm ? inv.data() : nullptr, run_waves(p->tiling)))
+            return fail(AZI_EOVERFLOW,
+                        "the run layout takes images below 2^27 pixels and 2^31 entries");
+        if (p->has_norm) {
+            std::vector<char> c = to_storage(rm.coef.data(), (int64_t)rm.coef.size(),
+                                             (int64_t)rm.coef.size() + kPad, p->dtype);
+            AZI_HIP(p->fcoef.upload(c.data(), c.size(), p->device), "folded coefficients");
+        }
+        if (p->has_dark) {
+            // float when every dark value is one (always for float32 plans)
+            bool as_float = true;
+            for (double d : dark)
+                if ((double)(float)d != d) {
+                    as_float = false;
+                    break;
+                }
+            constexpr int32_t kPixMask = (1 << azi::kBandShift) - 1;
+            const size_t nr = rm.runs.size() + kPad;
+            std::vector<double> rd(nr, 0.0);
+            for (size_t z = 0; z < rm.runs.size(); ++z)
+                if (rm.runs[z] >= 0) rd[z] = dark[(size_t)(rm.runs[z] & kPixMask)];
+            std::vector<char> c = to_storage(rd.data(), (int64_t)nr, (int64_t)nr,
+                                             as_float ? AZI_F32 : p->dtype);
+            AZI_HIP(p->corr.upload(c.data(), c.size(), p->device), "run dark values");
+            p->corr_kind = as_float && p->dtype == AZI_F64 ? azi::kCorrRunDarkF32
+                                                           : azi::kCorrRunDark;
+        } else {
+            p->corr_kind = azi::kCorrRunDark;
+        }
+    } catch (const std::bad_alloc&) {
+        return fail(AZI_ENOMEM, "out of host memory folding the corrections");
+    }
+    AZI_HIP(p->ufix.alloc((size_t)p->m.npt * 8, p->device), "fixed U");
+    azi::BandLaunch a = plan_band_args(p, p->xwork.p, nullptr, nullptr, nullptr, 0.0);
+    a.ufix_out = p->ufix.as<double>();
+    AZI_HIP(azi::launch_band(a, s), "fixed U");
+    AZI_HIP(hipStreamSynchronize(s), "folded corrections");
+    return AZI_OK;
+}
+
 int plan_corr_pair(azi_plan* p, hipStream_t s) {
     p->corr.release();
+    p->fcoef.release();
+    p->ufix.release();
+    p->folded = false;
     p->corr_kind = azi::kCorrPair;
-    if (!is_band(p->layout) || p->tiling.stage != AZI_STAGE_FUSE ||
+    if (!is_band(p->layout) || !gather_corrects(p->tiling.stage) ||
         !(p->has_dark || p->has_norm))
         return AZI_OK;
+    if (p->layout == AZI_LAYOUT_RUN && p->tiling.stage == AZI_STAGE_FOLD) {
+        const int rc = plan_fold(p, s);
+        if (rc != AZI_OK) {
+            p->corr.release();
+            p->fcoef.release();
+            p->ufix.release();
+            p->corr_kind = azi::kCorrPair;
+            return rc;
+        }
+        p->folded = true;
+        return AZI_OK;
+    }
     if (p->dtype == AZI_F64 && p->has_dark) {
         // float64 dark values that are all floats: 12-byte records
         DevBuf flag;
@@ -536,8 +658,8 @@ int plan_corr_pair(azi_plan* p, hipStream_t s) {
 azi::StageLaunch plan_stage_args(const azi_plan* p, const void* img, int32_t img_dtype,
                                  bool correct) {
     azi::StageLaunch a;
-    // AZI_STAGE_FUSE concerns the band layout; the ring staging then gathers
-    a.mode = p->tiling.stage == AZI_STAGE_FUSE ? AZI_STAGE_GATHER : p->tiling.stage;
+    // AZI_STAGE_FUSE / _FOLD concern the band layouts; the ring staging then gathers
+    a.mode = gather_corrects(p->tiling.stage) ? AZI_STAGE_GATHER : p->tiling.stage;
     a.raw = img;
     a.raw_dtype = img_dtype;
     a.order = p->order.as<int32_t>();
@@ -851,7 +973,10 @@ int plan_build_device(azi_plan* p, int32_t npt, const double* range2, int device
     p->used = npix;
     AZI_HIP(p->xwork.alloc((size_t)npix * es, device), "work image");
     AZI_HIP(p->vwork.alloc((size_t)npt * 8, device), "work vector");
+    // the band layout's own bands of 4 bins (band 16 means four neighbouring
+    // bands per workgroup only in the run layout)
     p->layout = AZI_LAYOUT_BAND;
+    p->tiling.band = 4;
     int rc = plan_device_bands(p, p->rowidx.as<int32_t>(), pix.as<int32_t>(), cdata64.as<double>(),
                                nnz, work, skeys, perm, s);
     if (rc != AZI_OK) return rc;
@@ -953,14 +1078,8 @@ int azi_plan_set_tiling(azi_plan* p, const azi_tiling* t) {
     if (!valid_tiling(*t)) return fail(AZI_EINVAL, kTilingRule);
     const bool retile = t->tile_nnz != p->tiling.tile_nnz || t->band != p->tiling.band;
     const bool restage = t->stage != p->tiling.stage;
+    const bool reblock = t->block != p->tiling.block;
     p->tiling = *t;
-    if (p->device >= 0 && restage) {
-        DeviceGuard g(p->device);
-        if (g.err != hipSuccess) return hip_fail(g.err, "set device");
-        AZI_HIP(hipDeviceSynchronize(), "synchronise before changing the stage");
-        const int rc = plan_corr_pair(p, nullptr);
-        if (rc != AZI_OK) return rc;
-    }
     if (p->device >= 0 && retile) {
         DeviceGuard g(p->device);
         if (g.err != hipSuccess) return hip_fail(g.err, "set device");
@@ -969,7 +1088,16 @@ int azi_plan_set_tiling(azi_plan* p, const azi_tiling* t) {
             int rc = plan_upload_bands(p);
             if (rc != AZI_OK) return rc;
         }
-        return plan_upload_tiles(p);
+        const int rc = plan_upload_tiles(p);
+        if (rc != AZI_OK) return rc;
+    }
+    // the folded form's U follows the pieces and the workgroup size
+    if (p->device >= 0 && (restage || (p->folded && (retile || reblock)))) {
+        DeviceGuard g(p->device);
+        if (g.err != hipSuccess) return hip_fail(g.err, "set device");
+        AZI_HIP(hipDeviceSynchronize(), "synchronise before changing the stage");
+        const int rc = plan_corr_pair(p, nullptr);
+        if (rc != AZI_OK) return rc;
     }
     return AZI_OK;
 }
@@ -1003,7 +1131,8 @@ int azi_plan_run_schedule(const azi_plan* p, int32_t tile_nnz, int64_t* nruns, i
     if (tile_nnz < 64 || tile_nnz > 16384) return fail(AZI_EINVAL, "tile_nnz must be in [64, 16384]");
     try {
         azi::RunMatrix rm;
-        if (!azi::build_runs(p->m, std::max(64, tile_nnz / 2), 0, 0, rm))
+        if (!azi::build_runs(p->m, std::max(64, tile_nnz / 2), 0, 0, rm, nullptr,
+                             run_waves(p->tiling)))
             return fail(AZI_EOVERFLOW,
                         "the run layout takes images below 2^27 pixels and 2^31 entries");
         if (nruns) *nruns = (int64_t)rm.runs.size();
@@ -1156,12 +1285,15 @@ int azi_plan_upload(azi_plan* p, int32_t device) {
 int32_t azi_plan_correction_bytes(const azi_plan* p) {
     if (!p || !p->corr.p) return 0;
     if (p->corr_kind == azi::kCorrRecord12) return (int32_t)sizeof(azi::Corr12);
+    if (p->corr_kind == azi::kCorrRunDarkF32) return 4;
+    if (p->corr_kind == azi::kCorrRunDark) return (int32_t)elem_size(p->dtype);
     return (int32_t)(2 * elem_size(p->dtype));
 }
 
 int64_t azi_plan_device_bytes(const azi_plan* p) {
     if (!p) return 0;
     const DevBuf* bufs[] = {&p->ftiles, &p->fslots, &p->fbin_ptr, &p->fparts, &p->corr, &p->cfirst,
+                            &p->fcoef, &p->ufix,
                             &p->rowptr, &p->indices, &p->data, &p->colptr, &p->rowidx,
                             &p->cdata, &p->tiles, &p->splits, &p->parts, &p->dark,
                             &p->norm, &p->xwork, &p->vwork, &p->order, &p->dark_r,
@@ -1339,19 +1471,15 @@ int azi_integrate1d_raw(const azi_plan* p, const void* raw, int32_t raw_dtype, v
                 "blocked forward kernels");
         return AZI_OK;
     }
-    if (p && is_band(p->layout) && p->tiling.stage == AZI_STAGE_FUSE &&
-        p->device >= 0) {
+    if (p && is_band(p->layout) && gather_corrects(p->tiling.stage) && p->device >= 0) {
         // cast and correction in the band kernel's gather
         if (!raw) return fail(AZI_EINVAL, "raw must not be NULL");
         if (!valid_raw_dtype(raw_dtype)) return fail(AZI_EINVAL, "unknown raw dtype");
         DeviceGuard g(p->device);
         if (g.err != hipSuccess) return hip_fail(g.err, "set device");
-        azi::BandLaunch a = plan_band_args(p, nullptr, I, W, U, empty);
-        a.raw = raw;
-        a.raw_dtype = raw_dtype;
-        a.corr = (p->has_dark || p->has_norm) ? p->corr.p : nullptr;
-        a.corr_kind = p->corr_kind;
-        AZI_HIP(azi::launch_band(a, static_cast<hipStream_t>(stream)), "band forward kernels");
+        AZI_HIP(azi::launch_band(plan_band_raw_args(p, raw, raw_dtype, I, W, U, empty),
+                                 static_cast<hipStream_t>(stream)),
+                "band forward kernels");
         return AZI_OK;
     }
     int rc = azi_plan_stage(p, raw, raw_dtype, stream);
@@ -1403,13 +1531,13 @@ int azi_integrate1d_raw_noalloc(const azi_plan* p, const void* raw, int32_t raw_
     if (!valid_raw_dtype(raw_dtype)) return fail(AZI_EINVAL, "unknown raw dtype");
     // the layouts whose raw-frame path needs partial sums and nothing else
     size_t need = 0;
-    if (is_band(p->layout) && p->tiling.stage == AZI_STAGE_FUSE) need = p->nparts_buf.bytes;
+    if (is_band(p->layout) && gather_corrects(p->tiling.stage)) need = p->nparts_buf.bytes;
     else if (p->layout == AZI_LAYOUT_TILE) need = p->bparts.bytes;
     else if (p->layout == AZI_LAYOUT_FUSED) need = p->fparts.bytes;
     else
         return fail(AZI_EINVAL,
                     "the allocation-free call takes the run and band layouts (stage "
-                    "AZI_STAGE_FUSE), the tile layout and the fused layout");
+                    "AZI_STAGE_FUSE or AZI_STAGE_FOLD), the tile layout and the fused layout");
     if (need > kScratchBytes)
         return fail(AZI_EINVAL, "plan needs " + std::to_string(need) +
                                     " bytes of partial sums, more than the " +
@@ -1429,11 +1557,7 @@ int azi_integrate1d_raw_noalloc(const azi_plan* p, const void* raw, int32_t raw_
         a.parts = parts;
         AZI_HIP(azi::launch_block(a, s), "blocked forward kernels");
     } else {
-        azi::BandLaunch a = plan_band_args(p, nullptr, I, W, U, empty);
-        a.raw = raw;
-        a.raw_dtype = raw_dtype;
-        a.corr = (p->has_dark || p->has_norm) ? p->corr.p : nullptr;
-        a.corr_kind = p->corr_kind;
+        azi::BandLaunch a = plan_band_raw_args(p, raw, raw_dtype, I, W, U, empty);
         a.parts = parts;
         AZI_HIP(azi::launch_band(a, s), "band forward kernels");
     }
@@ -1691,7 +1815,7 @@ int batch_build_bands(azi_batch* b, const std::vector<const azi::HostMatrix*>& m
         for (int32_t k = 0; k < b->n; ++k) {
             b->piece_off[k] = (int64_t)rm.pieces.size();
             if (!azi::build_runs(*ms[k], std::max(64, b->tiling.tile_nnz / 2), b->pix_off[k],
-                                 b->bin_off[k], rm))
+                                 b->bin_off[k], rm, nullptr, run_waves(b->tiling)))
                 return fail(AZI_EOVERFLOW,
                             "the run layout takes images below 2^27 pixels and 2^31 runs and "
                             "entries per batch");
@@ -1771,6 +1895,7 @@ azi::BandLaunch batch_band_args(const azi_batch* b, const void* x, int32_t k0, i
     a.npieces = (int32_t)(b->piece_off[k1] - b->piece_off[k0]);
     a.packed = b->npacked.as<int32_t>();
     a.gbase = b->layout == AZI_LAYOUT_RUN ? b->rgbase.as<int32_t>() : nullptr;
+    a.waves = b->layout == AZI_LAYOUT_RUN ? run_waves(b->tiling) : 1;
     a.coef = b->ncoef.p;
     a.bin_slot = b->bin_slot.as<int32_t>();
     a.bin_count = b->bin_count.as<int32_t>();
@@ -1831,7 +1956,7 @@ int batch_stage(azi_batch* b, const void* img, int32_t img_dtype, int32_t k0, in
         return AZI_OK;
     }
     azi::StageLaunch a;
-    a.mode = b->tiling.stage == AZI_STAGE_FUSE ? AZI_STAGE_GATHER : b->tiling.stage;
+    a.mode = gather_corrects(b->tiling.stage) ? AZI_STAGE_GATHER : b->tiling.stage;
     a.raw = img;
     a.raw_dtype = img_dtype;
     a.dtype = b->dtype;
@@ -1900,7 +2025,7 @@ int azi_batch_forward_raw(azi_batch* b, const void* raw, int32_t raw_dtype, void
                 "batched blocked kernels");
         return AZI_OK;
     }
-    if (is_band(b->layout) && b->tiling.stage == AZI_STAGE_FUSE) {
+    if (is_band(b->layout) && gather_corrects(b->tiling.stage)) {
         azi::BandLaunch a = batch_band_args(b, nullptr, 0, b->n, I, W, U, empty);
         a.raw = raw;
         a.raw_dtype = raw_dtype;
@@ -1996,10 +2121,14 @@ int azi_batch_autotune(azi_batch* b, const void* x, void* I, void* W, void* U, v
     std::vector<azi_tiling> cands;
     const int32_t st = b->tiling.stage;
     if (b->layout == AZI_LAYOUT_RUN) {
-        // bands of 4 bins are fixed for runs; workgroups of 128 or 256 threads
-        for (int32_t tn : {1024, 2048, 4096, 8192, 16384})
+        // bands of 4 bins are fixed for runs; one band per workgroup of 128
+        // or 256 threads, or four neighbouring bands per workgroup (band 16)
+        for (int32_t tn : {1024, 2048, 4096, 8192, 16384}) {
             for (int32_t bl : {128, 256})
-                for (int32_t gm : {0, 8}) cands.push_back(azi_tiling{tn, bl, 5, gm * ncu, 4, st});
+                for (int32_t gm : {0, 4, 8, 16})
+                    cands.push_back(azi_tiling{tn, bl, 5, gm * ncu, 4, st});
+            for (int32_t gm : {0, 8}) cands.push_back(azi_tiling{tn, 256, 5, gm * ncu, 16, st});
+        }
     } else if (b->layout == AZI_LAYOUT_BAND) {
         for (int32_t tn : {1024, 2048, 4096, 8192})
             for (int32_t band : {4, 8})
@@ -2112,6 +2241,8 @@ int azi_plan_autotune(azi_plan* p, const void* x, void* I, void* W, void* U, voi
         if (runs_ok) {
             for (int32_t tn : {2048, 4096, 8192})
                 for (int32_t bl : {128, 256}) add(AZI_LAYOUT_RUN, tn, bl, 5, 4);
+            for (int32_t tn : {2048, 4096, 8192})
+                for (int32_t band : {16, 32}) add(AZI_LAYOUT_RUN, tn, 256, 5, band);
             for (int32_t tn : {2048, 4096})
                 for (int32_t band : {4, 8}) add(AZI_LAYOUT_BAND, tn, 256, 5, band);
         }

@@ -197,8 +197,17 @@ struct RunMatrix {
 // piece_runs runs (rounded down to a multiple of 64).  Returns false if the
 // image has 2^27 pixels or more or the runs or coefficients would not fit
 // int32 positions.
+// With `scale` (npix values), every coefficient of pixel p is multiplied by
+// scale[p] (rounded once) as it is stored.
+// waves > 1: the pieces are instead cut for workgroups of `waves`
+// neighbouring bands over common stretches of image rows: entry
+// t * waves + w of rm.pieces is band w of workgroup t (z0 == z1 and slot0 ==
+// -1 past the last band).  The rows of a stretch end where the group's
+// longest band has a piece boundary (pieces of at most piece_runs runs);
+// every band's runs are cut on multiples of 64 at the first group of 64 runs
+// whose first pixel lies in the next stretch.
 bool build_runs(const HostMatrix& m, int32_t piece_runs, int64_t pix_off, int64_t bin_off,
-                RunMatrix& rm);
+                RunMatrix& rm, const double* scale = nullptr, int32_t waves = 1);
 
 // Matrix-free ("fused") schedule: the image cut into kFusedH x kFusedW
 // tiles; tile t feeds the bin window [wlo, wlo + nwin) and writes the partial

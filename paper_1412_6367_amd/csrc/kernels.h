@@ -60,8 +60,19 @@ hipError_t launch_correct(const void* raw, int32_t raw_dtype, const int32_t* ord
 
 // Per-pixel correction of the raw-frame band gather: (dark, 1 / norm) as a
 // pair of the storage type, or, for float64 plans whose dark values are all
-// floats, as a 12-byte record (4 bytes less per pixel, same results).
-constexpr int32_t kCorrPair = 0, kCorrRecord12 = 1;
+// floats, as a 12-byte record (4 bytes less per pixel, same results).  With
+// the normalisation folded into the coefficients (AZI_STAGE_FOLD, run
+// layout) dark alone is subtracted, stored once per run beside the run
+// words and read with them (run z's value is the dark of its pixel), which
+// leaves the raw count as the only gather: as float for float64 plans whose
+// dark values are all floats (kCorrRunDarkF32), else in the storage type
+// (kCorrRunDark).
+constexpr int32_t kCorrPair = 0, kCorrRecord12 = 1, kCorrRunDarkF32 = 2, kCorrRunDark = 3;
+// Element type of a run-indexed dark array.
+template <class V>
+struct RunDark {
+    V v;
+};
 struct Corr12 {
     float dark;
     uint32_t inv_lo, inv_hi;  // the two halves of the double 1 / norm
@@ -80,6 +91,10 @@ struct BandLaunch {
     const int32_t* bin_count = nullptr;
     int32_t max_count = INT32_MAX;     // largest bin_count (selects the reduction form)
     int32_t R = 8;
+    // run encoding: 1 = one band per workgroup (the pieces are BandPiece
+    // per piece); 4 or 8 = that many neighbouring bands per workgroup (the
+    // pieces hold `waves` entries per workgroup, see k_runs_grouped)
+    int32_t waves = 1;
     int64_t b0 = 0, b1 = 0;
     const void* x = nullptr;
     // raw-frame form: when `raw` is set, x is ignored and each gathered pixel
@@ -98,6 +113,13 @@ struct BandLaunch {
     int32_t grid = 0;
     int32_t dtype = AZI_F64;
     int32_t accum = AZI_ACC_F64;
+    // U of a plan does not depend on the image.  ufix_out: the reduction
+    // writes each bin's U (as the accumulator holds it, in double) there and
+    // nothing else; ufix_in: the reduction takes U from it instead of from
+    // the partial sums (used when the coefficients carry the normalisation,
+    // whose sums are then not U).
+    double* ufix_out = nullptr;
+    const double* ufix_in = nullptr;
 };
 
 hipError_t launch_band(const BandLaunch& a, hipStream_t s);

@@ -280,6 +280,15 @@ __device__ inline double corr_apply(double v, const Corr12& c) {
     const double inv = __hiloint2double((int)c.inv_hi, (int)c.inv_lo);
     return (v - (double)c.dark) * inv;
 }
+// Dark alone, when the coefficients carry 1 / norm (AZI_STAGE_FOLD): the
+// difference of an integer count and a float dark is exact in double.
+__device__ inline double corr_apply(double v, float d) { return v - (double)d; }
+__device__ inline double corr_apply(double v, double d) { return v - d; }
+__device__ inline float corr_apply(float v, float d) { return v - d; }
+template <class T, class V>
+__device__ inline T corr_apply(T v, RunDark<V> d) { return corr_apply(v, d.v); }
+template <class C> struct IsRunDark { static constexpr bool value = false; };
+template <class V> struct IsRunDark<RunDark<V>> { static constexpr bool value = true; };
 
 // With kCorr the image is the raw frame: every gathered pixel is cast and
 // corrected on the way, (T(raw) - dark) * (1 / norm), dark and the
@@ -373,8 +382,103 @@ __global__ __launch_bounds__(BLOCK) void k_band(const BandPiece* __restrict__ pi
 // (lane = run), reads each run's word, finds where its 1..4 coefficients
 // sit from the group's counts (ballots and lane ranks: no table), gathers
 // the pixel once for the whole run and adds each coefficient's product to
-// the accumulator of its row.  U groups per wavefront are in flight at a
-// time.  The partial sums are reduced and written as in k_band.
+// the accumulator of its row.  run_groups handles U such groups at once,
+// the u-th starting at run z + u * stride (none at or beyond z1).
+template <class T, class Acc, int U, class RawT, bool kCorr, class CorrT>
+__device__ __forceinline__ void run_groups(int32_t z, int32_t stride, int32_t z1, int lane,
+                                           const int32_t* __restrict__ runs,
+                                           const int32_t* __restrict__ gbase,
+                                           const T* __restrict__ coef, const T* __restrict__ x,
+                                           const RawT* __restrict__ raw,
+                                           const CorrT* __restrict__ corr, int64_t pix_off,
+                                           Acc (&a)[kRunRows]) {
+    constexpr int R = kRunRows;
+    constexpr int32_t kMask = (1 << kBandShift) - 1;
+    constexpr bool kRunCorr = kCorr && IsRunDark<CorrT>::value;
+    int32_t rw[U], base[U];
+    CorrT dv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int32_t zg = z + u * stride;       // uniform over the wavefront
+        rw[u] = -1;
+        base[u] = 0;
+        if (zg < z1) {
+            base[u] = gbase[zg >> 6];
+            if (zg + lane < z1) {
+                rw[u] = __builtin_nontemporal_load(runs + zg + lane);
+                if constexpr (kRunCorr) {
+                    if (corr)
+                        dv[u].v = __builtin_nontemporal_load(
+                            reinterpret_cast<const decltype(dv[u].v)*>(corr) + zg + lane);
+                }
+            }
+        }
+    }
+    T c[U][R];
+    int n[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        n[u] = rw[u] < 0 ? 0 : ((rw[u] >> kRunCountShift) & 3) + 1;
+        int32_t off = base[u];
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const uint64_t m = __ballot(n[u] > j);
+            const int32_t rank = (int32_t)__builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            c[u][j] = n[u] > j ? __builtin_nontemporal_load(coef + off + rank) : T(0);
+            off += (int32_t)__popcll(m);
+        }
+    }
+    T xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        T v = T(0);
+        if (n[u] > 0) {
+            const int32_t pix = rw[u] & kMask;
+            if constexpr (kRunCorr) {
+                v = (T)raw[pix_off + pix];
+                if (corr) v = corr_apply(v, dv[u]);
+            } else if constexpr (kCorr) {
+                v = (T)raw[pix_off + pix];
+                if (corr) v = corr_apply(v, corr[pix_off + pix]);
+            } else {
+                v = x[pix_off + pix];
+            }
+        }
+        xv[u] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int r0 = (rw[u] >> kBandShift) & 3;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int j = r - r0;
+            if (j >= 0 && j < n[u]) {
+                const T cv = j == 0 ? c[u][0] : j == 1 ? c[u][1] : j == 2 ? c[u][2] : c[u][3];
+                a[r].add(cv, xv[u]);
+            }
+        }
+    }
+}
+
+// Maps workgroup g of Gd onto its pieces: one per workgroup when Gd covers
+// them, otherwise each XCD (g % 8) walks one contiguous eighth.
+__device__ __forceinline__ void piece_range(int32_t g, int32_t Gd, int32_t npieces,
+                                            int32_t& t_begin, int32_t& t_end,
+                                            int32_t& t_step) {
+    if (Gd < 8) {
+        t_begin = g; t_end = npieces; t_step = Gd;
+    } else {
+        const int32_t xcd = g & 7, q = g >> 3, nq = (Gd - xcd + 7) >> 3;
+        const int32_t per = npieces >> 3, rem = npieces & 7;
+        const int32_t t0 = xcd * per + min(xcd, rem);
+        t_begin = t0 + q; t_end = t0 + per + (xcd < rem ? 1 : 0); t_step = nq;
+    }
+}
+
+// One workgroup per piece of one band: the wavefronts take the piece's
+// groups in turn, U in flight each; the R row sums are reduced over the
+// workgroup in a fixed tree and written to the piece's partial slots.
 template <class T, class Acc, int U, int BLOCK, class RawT = T, bool kCorr = false,
           class CorrT = typename Pair2<T>::type>
 __global__ __launch_bounds__(BLOCK) void k_band_runs(const BandPiece* __restrict__ pieces,
@@ -387,85 +491,23 @@ __global__ __launch_bounds__(BLOCK) void k_band_runs(const BandPiece* __restrict
                                                    const RawT* __restrict__ raw = nullptr,
                                                    const CorrT* __restrict__ corr = nullptr) {
     constexpr int R = kRunRows;
-    constexpr int32_t kMask = (1 << kBandShift) - 1;
     __shared__ Acc red[BLOCK / kWave][R];
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid / kWave), lane = tid & (kWave - 1);
-    const int32_t g = blockIdx.x, Gd = gridDim.x;
     int32_t t_begin, t_end, t_step;
-    if (Gd < 8) {
-        t_begin = g; t_end = npieces; t_step = Gd;
-    } else {
-        const int32_t xcd = g & 7, q = g >> 3, nq = (Gd - xcd + 7) >> 3;
-        const int32_t per = npieces >> 3, rem = npieces & 7;
-        const int32_t t0 = xcd * per + min(xcd, rem);
-        t_begin = t0 + q; t_end = t0 + per + (xcd < rem ? 1 : 0); t_step = nq;
-    }
+    piece_range(blockIdx.x, gridDim.x, npieces, t_begin, t_end, t_step);
     for (int32_t ti = t_begin; ti < t_end; ti += t_step) {
         const BandPiece pc = pieces[ti];
         Acc a[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) a[r].zero();
-        for (int32_t z0 = pc.z0 + wave * kWave; z0 < pc.z1; z0 += BLOCK * U) {
-            int32_t rw[U], base[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int32_t zg = z0 + u * BLOCK;       // uniform over the wavefront
-                rw[u] = -1;
-                base[u] = 0;
-                if (zg < pc.z1) {
-                    base[u] = gbase[zg >> 6];
-                    if (zg + lane < pc.z1) rw[u] = __builtin_nontemporal_load(runs + zg + lane);
-                }
-            }
-            T c[U][R];
-            int n[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                n[u] = rw[u] < 0 ? 0 : ((rw[u] >> kRunCountShift) & 3) + 1;
-                int32_t off = base[u];
-#pragma unroll
-                for (int j = 0; j < R; ++j) {
-                    const uint64_t m = __ballot(n[u] > j);
-                    const int32_t rank = (int32_t)__builtin_amdgcn_mbcnt_hi(
-                        (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                    c[u][j] = n[u] > j ? __builtin_nontemporal_load(coef + off + rank) : T(0);
-                    off += (int32_t)__popcll(m);
-                }
-            }
-            T xv[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                T v = T(0);
-                if (n[u] > 0) {
-                    const int32_t pix = rw[u] & kMask;
-                    if constexpr (kCorr) {
-                        v = (T)raw[pc.pix_off + pix];
-                        if (corr) v = corr_apply(v, corr[pc.pix_off + pix]);
-                    } else {
-                        v = x[pc.pix_off + pix];
-                    }
-                }
-                xv[u] = v;
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int r0 = (rw[u] >> kBandShift) & 3;
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const int j = r - r0;
-                    if (j >= 0 && j < n[u]) {
-                        const T cv = j == 0 ? c[u][0] : j == 1 ? c[u][1] : j == 2 ? c[u][2] : c[u][3];
-                        a[r].add(cv, xv[u]);
-                    }
-                }
-            }
-        }
-        const int lanew = tid & (kWave - 1);
+        for (int32_t z0 = pc.z0 + wave * kWave; z0 < pc.z1; z0 += BLOCK * U)
+            run_groups<T, Acc, U, RawT, kCorr, CorrT>(z0, BLOCK, pc.z1, lane, runs, gbase, coef,
+                                                      x, raw, corr, pc.pix_off, a);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             group_reduce(a[r], kWave);
-            if (lanew == 0) red[wave][r] = a[r];
+            if (lane == 0) red[wave][r] = a[r];
         }
         __syncthreads();
         if (tid < R) {
@@ -477,13 +519,50 @@ __global__ __launch_bounds__(BLOCK) void k_band_runs(const BandPiece* __restrict
     }
 }
 
+// Co-scheduled bands: a workgroup of WAVES wavefronts takes WAVES
+// neighbouring bands over one stretch of image rows, wavefront w walking
+// band w's runs of those rows (entry ti * WAVES + w of the schedule).
+// Neighbouring bands are neighbouring rings, so the wavefronts of a
+// workgroup gather from the same image lines at about the same time and
+// share them in the CU's L1 cache.  Each wavefront reduces its own band's
+// R row sums and writes them to its partial slots: no LDS, no barrier.
+template <class T, class Acc, int U, int WAVES, class RawT = T, bool kCorr = false,
+          class CorrT = typename Pair2<T>::type>
+__global__ __launch_bounds__(WAVES * kWave) void k_runs_grouped(
+    const BandPiece* __restrict__ pieces, int32_t ntiles, const int32_t* __restrict__ runs,
+    const int32_t* __restrict__ gbase, const T* __restrict__ coef, const T* __restrict__ x,
+    Acc* __restrict__ parts, const RawT* __restrict__ raw = nullptr,
+    const CorrT* __restrict__ corr = nullptr) {
+    constexpr int R = kRunRows;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = threadIdx.x & (kWave - 1);
+    int32_t t_begin, t_end, t_step;
+    piece_range(blockIdx.x, gridDim.x, ntiles, t_begin, t_end, t_step);
+    for (int32_t ti = t_begin; ti < t_end; ti += t_step) {
+        const BandPiece pc = pieces[(int64_t)ti * WAVES + wave];
+        Acc a[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) a[r].zero();
+        for (int32_t z0 = pc.z0; z0 < pc.z1; z0 += kWave * U)
+            run_groups<T, Acc, U, RawT, kCorr, CorrT>(z0, kWave, pc.z1, lane, runs, gbase, coef,
+                                                      x, raw, corr, pc.pix_off, a);
+#pragma unroll
+        for (int r = 0; r < R; ++r) group_reduce(a[r], kWave);
+        if (lane == 0 && pc.slot0 >= 0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) parts[pc.slot0 + r] = a[r];
+        }
+    }
+}
+
 // One wavefront per bin adds the partial sums of its band's pieces (slots
 // first, first + R, ...) in a fixed order and writes W, U and I.
 template <class T, class Acc>
 __global__ void k_band_reduce(const int32_t* __restrict__ bin_slot,
                               const int32_t* __restrict__ bin_count, int32_t R, int64_t b0,
                               int64_t b1, const Acc* __restrict__ parts, T* __restrict__ I,
-                              T* __restrict__ W, T* __restrict__ U, double empty) {
+                              T* __restrict__ W, T* __restrict__ U, double empty,
+                              const double* __restrict__ ufix_in, double* __restrict__ ufix_out) {
     const int64_t b = b0 + (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (b >= b1) return;
     const int lane = threadIdx.x & (kWave - 1);
@@ -492,7 +571,7 @@ __global__ void k_band_reduce(const int32_t* __restrict__ bin_slot,
     const int32_t first = bin_slot[b], cnt = bin_count[b];
     for (int32_t k = lane; k < cnt; k += kWave) a.merge(parts[first + (int64_t)k * R]);
     group_reduce(a, kWave);
-    if (lane == 0) write_row((int32_t)b, a, I, W, U, empty);
+    if (lane == 0) write_row_u((int32_t)b, a, I, W, U, empty, ufix_in, ufix_out);
 }
 
 // One lane per bin, for matrices whose bins have at most kLaneParts
@@ -507,7 +586,9 @@ template <class T, class Acc>
 __global__ void k_band_reduce_lane(const int32_t* __restrict__ bin_slot,
                                    const int32_t* __restrict__ bin_count, int32_t R, int64_t b0,
                                    int64_t b1, const Acc* __restrict__ parts, T* __restrict__ I,
-                                   T* __restrict__ W, T* __restrict__ U, double empty) {
+                                   T* __restrict__ W, T* __restrict__ U, double empty,
+                                   const double* __restrict__ ufix_in,
+                                   double* __restrict__ ufix_out) {
     const int64_t b = b0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= b1) return;
     const int32_t first = bin_slot[b], cnt = bin_count[b];
@@ -522,7 +603,7 @@ __global__ void k_band_reduce_lane(const int32_t* __restrict__ bin_slot,
 #pragma unroll
         for (int k = 0; k < m; ++k) v[k].merge(v[k + m]);
     }
-    write_row((int32_t)b, v[0], I, W, U, empty);
+    write_row_u((int32_t)b, v[0], I, W, U, empty, ufix_in, ufix_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -926,21 +1007,47 @@ hipError_t band_block(const BandLaunch& a, hipStream_t s) {
 // 4 for float32, whose registers are half the size).
 template <class T> constexpr int kRunGroups = sizeof(T) == 8 ? 2 : 4;
 
-template <class T, class Acc, class RawT, class CorrT>
-hipError_t runs_launch_raw(const BandLaunch& a, int grid, hipStream_t s) {
+// Launches the run-layout kernel of the launch's form: one band per
+// workgroup of a.block threads (a.waves == 1), or a.waves co-scheduled
+// bands per workgroup.
+template <class T, class Acc, class RawT, bool kCorr, class CorrT>
+hipError_t runs_kernel(const BandLaunch& a, const T* x, hipStream_t s) {
+    constexpr int G = kRunGroups<T>;
+    const T* coef = static_cast<const T*>(a.coef);
+    Acc* parts = static_cast<Acc*>(a.parts);
+    const RawT* raw = static_cast<const RawT*>(a.raw);
+    const CorrT* corr = static_cast<const CorrT*>(a.corr);
+    if (a.waves > 1) {
+        const int32_t ntiles = a.npieces / a.waves;
+        const int grid = a.grid > 0 ? a.grid : ntiles;
+        if (ntiles <= 0) return hipSuccess;
+        if (a.waves == 4)
+            hipLaunchKernelGGL((k_runs_grouped<T, Acc, G, 4, RawT, kCorr, CorrT>), dim3(grid),
+                               dim3(4 * kWave), 0, s, a.pieces, ntiles, a.packed, a.gbase, coef,
+                               x, parts, raw, corr);
+        else if (a.waves == 8)
+            hipLaunchKernelGGL((k_runs_grouped<T, Acc, G, 8, RawT, kCorr, CorrT>), dim3(grid),
+                               dim3(8 * kWave), 0, s, a.pieces, ntiles, a.packed, a.gbase, coef,
+                               x, parts, raw, corr);
+        else
+            return hipErrorInvalidValue;
+        return hipGetLastError();
+    }
+    const int grid = a.grid > 0 ? a.grid : a.npieces;
     if (a.block == 128)
-        hipLaunchKernelGGL((k_band_runs<T, Acc, kRunGroups<T>, 128, RawT, true, CorrT>),
-                           dim3(grid), dim3(128), 0, s, a.pieces, a.npieces, a.packed, a.gbase,
-                           static_cast<const T*>(a.coef), static_cast<const T*>(nullptr),
-                           static_cast<Acc*>(a.parts), static_cast<const RawT*>(a.raw),
-                           static_cast<const CorrT*>(a.corr));
+        hipLaunchKernelGGL((k_band_runs<T, Acc, G, 128, RawT, kCorr, CorrT>), dim3(grid),
+                           dim3(128), 0, s, a.pieces, a.npieces, a.packed, a.gbase, coef, x, parts,
+                           raw, corr);
     else
-        hipLaunchKernelGGL((k_band_runs<T, Acc, kRunGroups<T>, 256, RawT, true, CorrT>),
-                           dim3(grid), dim3(256), 0, s, a.pieces, a.npieces, a.packed, a.gbase,
-                           static_cast<const T*>(a.coef), static_cast<const T*>(nullptr),
-                           static_cast<Acc*>(a.parts), static_cast<const RawT*>(a.raw),
-                           static_cast<const CorrT*>(a.corr));
+        hipLaunchKernelGGL((k_band_runs<T, Acc, G, 256, RawT, kCorr, CorrT>), dim3(grid),
+                           dim3(256), 0, s, a.pieces, a.npieces, a.packed, a.gbase, coef, x, parts,
+                           raw, corr);
     return hipGetLastError();
+}
+
+template <class T, class Acc, class RawT, class CorrT>
+hipError_t runs_launch_raw(const BandLaunch& a, int, hipStream_t s) {
+    return runs_kernel<T, Acc, RawT, true, CorrT>(a, nullptr, s);
 }
 
 template <class T, class Acc, class RawT>
@@ -948,29 +1055,21 @@ hipError_t runs_raw_corr(const BandLaunch& a, int grid, hipStream_t s) {
     if constexpr (std::is_same<T, double>::value) {
         if (a.corr && a.corr_kind == kCorrRecord12)
             return runs_launch_raw<T, Acc, RawT, Corr12>(a, grid, s);
+        if (a.corr && a.corr_kind == kCorrRunDarkF32)
+            return runs_launch_raw<T, Acc, RawT, RunDark<float>>(a, grid, s);
     }
-    if (a.corr_kind != kCorrPair) return hipErrorInvalidValue;
+    if (a.corr && a.corr_kind == kCorrRunDark)
+        return runs_launch_raw<T, Acc, RawT, RunDark<T>>(a, grid, s);
+    if (a.corr_kind != kCorrPair && a.corr) return hipErrorInvalidValue;
     return runs_launch_raw<T, Acc, RawT, typename Pair2<T>::type>(a, grid, s);
 }
 
 template <class T, class Acc>
 hipError_t runs_launch(const BandLaunch& a, hipStream_t s) {
     const int grid = a.grid > 0 ? a.grid : a.npieces;
-    if (!a.raw) {
-        if (a.block == 128)
-            hipLaunchKernelGGL((k_band_runs<T, Acc, kRunGroups<T>, 128>), dim3(grid), dim3(128),
-                               0, s, a.pieces, a.npieces, a.packed, a.gbase,
-                               static_cast<const T*>(a.coef), static_cast<const T*>(a.x),
-                               static_cast<Acc*>(a.parts), static_cast<const T*>(nullptr),
-                               static_cast<const typename Pair2<T>::type*>(nullptr));
-        else
-            hipLaunchKernelGGL((k_band_runs<T, Acc, kRunGroups<T>, 256>), dim3(grid), dim3(256),
-                               0, s, a.pieces, a.npieces, a.packed, a.gbase,
-                               static_cast<const T*>(a.coef), static_cast<const T*>(a.x),
-                               static_cast<Acc*>(a.parts), static_cast<const T*>(nullptr),
-                               static_cast<const typename Pair2<T>::type*>(nullptr));
-        return hipGetLastError();
-    }
+    if (!a.raw)
+        return runs_kernel<T, Acc, T, false, typename Pair2<T>::type>(
+            a, static_cast<const T*>(a.x), s);
     switch (a.raw_dtype) {
         case AZI_I16: return runs_raw_corr<T, Acc, int16_t>(a, grid, s);
         case AZI_U16: return runs_raw_corr<T, Acc, uint16_t>(a, grid, s);
@@ -1003,14 +1102,16 @@ hipError_t band_impl(const BandLaunch& a, hipStream_t s) {
         hipLaunchKernelGGL((k_band_reduce_lane<T, Acc>), dim3((unsigned)((nb + 255) / 256)),
                            dim3(256), 0, s, a.bin_slot, a.bin_count, a.R, a.b0, a.b1,
                            static_cast<const Acc*>(a.parts), static_cast<T*>(a.I),
-                           static_cast<T*>(a.W), static_cast<T*>(a.U), a.empty);
+                           static_cast<T*>(a.W), static_cast<T*>(a.U), a.empty, a.ufix_in,
+                           a.ufix_out);
         return hipGetLastError();
     }
     if (nb > 0) {
         hipLaunchKernelGGL((k_band_reduce<T, Acc>), dim3((unsigned)((nb + 3) / 4)), dim3(256), 0,
                            s, a.bin_slot, a.bin_count, a.R, a.b0, a.b1,
                            static_cast<const Acc*>(a.parts), static_cast<T*>(a.I),
-                           static_cast<T*>(a.W), static_cast<T*>(a.U), a.empty);
+                           static_cast<T*>(a.W), static_cast<T*>(a.U), a.empty, a.ufix_in,
+                           a.ufix_out);
         return hipGetLastError();
     }
     return hipSuccess;

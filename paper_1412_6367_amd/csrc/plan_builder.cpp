@@ -496,7 +496,7 @@ void band_pieces(const int64_t* start, int32_t nbands, int32_t npt, int32_t R, i
 }
 
 bool build_runs(const HostMatrix& m, int32_t piece_runs, int64_t pix_off, int64_t bin_off,
-                RunMatrix& rm) {
+                RunMatrix& rm, const double* scale, int32_t waves) {
     constexpr int32_t R = kRunRows;
     if (m.npix >= ((int64_t)1 << kBandShift)) return false;
     const int32_t npt = m.npt;
@@ -545,8 +545,11 @@ bool build_runs(const HostMatrix& m, int32_t piece_runs, int64_t pix_off, int64_
             const int64_t z0 = g * 64, z1 = std::min(z0 + 64, start[b] + cnt[b]);
             for (int32_t j = 0; j < R; ++j)
                 for (int64_t z = z0; z < z1; ++z)
-                    if ((rm.runs[z] >> kRunCountShift) + 1 > j)
-                        rm.coef[pos++] = m.cdata[first_k[z - base] + j];
+                    if ((rm.runs[z] >> kRunCountShift) + 1 > j) {
+                        const double c = m.cdata[first_k[z - base] + j];
+                        rm.coef[pos++] =
+                            scale ? c * scale[rm.runs[z] & ((1 << kBandShift) - 1)] : c;
+                    }
         }
     }
     // pieces: each band cut into near-equal parts on multiples of 64 runs
@@ -555,6 +558,59 @@ bool build_runs(const HostMatrix& m, int32_t piece_runs, int64_t pix_off, int64_
         rm.bin_count.resize(bin_off + npt, 0);
     }
     const int64_t chunk = std::max<int64_t>(64, piece_runs / 64 * 64);
+    if (waves > 1) {
+        constexpr int32_t kPixMask = (1 << kBandShift) - 1;
+        for (int32_t g0 = 0; g0 < nbands; g0 += waves) {
+            const int32_t gn = std::min(waves, nbands - g0);
+            int32_t bmax = g0;
+            for (int32_t b = g0; b < g0 + gn; ++b)
+                if (cnt[b] > cnt[bmax]) bmax = b;
+            const int64_t maxlen = cnt[bmax];
+            const int32_t K = maxlen > 0 ? (int32_t)((maxlen + chunk - 1) / chunk) : 1;
+            // first pixel of each stretch but the first, from the longest band
+            std::vector<int64_t> cut((size_t)K + 1, 0);
+            const int64_t gmax = (maxlen + 63) / 64;
+            for (int32_t k = 1; k < K; ++k)
+                cut[k] = rm.runs[start[bmax] + 64 * (gmax * k / K)] & kPixMask;
+            cut[K] = std::numeric_limits<int64_t>::max();
+            // per band: group boundaries of the stretches
+            std::vector<int64_t> zc((size_t)gn * (K + 1));
+            for (int32_t w = 0; w < gn; ++w) {
+                const int32_t b = g0 + w;
+                const int64_t ng = (cnt[b] + 63) / 64;
+                int64_t j = 0;
+                zc[(size_t)w * (K + 1)] = start[b];
+                for (int32_t k = 1; k <= K; ++k) {
+                    while (j < ng && (k == K || (rm.runs[start[b] + 64 * j] & kPixMask) < cut[k]))
+                        ++j;
+                    zc[(size_t)w * (K + 1) + k] = start[b] + 64 * j;
+                }
+                const int32_t bin0 = b * R;
+                const int32_t nrows = std::min(R, npt - bin0);
+                for (int32_t r = 0; r < nrows; ++r) {
+                    rm.bin_slot[bin_off + bin0 + r] = rm.nslots + w * K * R + r;
+                    rm.bin_count[bin_off + bin0 + r] = K;
+                }
+            }
+            for (int32_t k = 0; k < K; ++k) {
+                for (int32_t w = 0; w < waves; ++w) {
+                    if (w >= gn) {
+                        rm.pieces.push_back(BandPiece{0, 0, 0, 0, -1, 0, pix_off});
+                        continue;
+                    }
+                    const int32_t b = g0 + w;
+                    const int32_t bin0 = b * R;
+                    rm.pieces.push_back(BandPiece{(int32_t)zc[(size_t)w * (K + 1) + k],
+                                                  (int32_t)zc[(size_t)w * (K + 1) + k + 1],
+                                                  (int32_t)(bin_off + bin0),
+                                                  std::min(R, npt - bin0),
+                                                  rm.nslots + (w * K + k) * R, 0, pix_off});
+                }
+            }
+            rm.nslots += gn * K * R;
+        }
+        return true;
+    }
     for (int32_t band = 0; band < nbands; ++band) {
         const int32_t bin0 = band * R;
         const int32_t nrows = std::min(R, npt - bin0);

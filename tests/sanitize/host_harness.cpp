@@ -94,6 +94,19 @@ int main() {
                 }
             expect(entries == nnz && (int64_t)rm.coef.size() >= nnz, "run entries", line);
         }
+        // neighbouring bands per workgroup, coefficients scaled per pixel
+        std::vector<double> scale((size_t)m.npix, 0.5);
+        for (int32_t waves : {4, 8}) {
+            azi::RunMatrix rg;
+            if (azi::build_runs(m, 256, 0, 0, rg, scale.data(), waves)) {
+                expect(rg.pieces.size() % (size_t)waves == 0, "grouped entries", line);
+                expect(rg.runs == rm.runs, "grouped runs", line);
+                bool halves = rg.coef.size() == rm.coef.size();
+                for (size_t k = 0; halves && k < rg.coef.size(); ++k)
+                    halves = rg.coef[k] == 0.5 * rm.coef[k];
+                expect(halves, "scaled coefficients", line);
+            }
+        }
         if (!m.two_d) {
             std::vector<azi::FusedTile> ft;
             std::vector<int32_t> slots, bin_ptr;

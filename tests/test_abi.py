@@ -197,7 +197,7 @@ def test_argument_errors():
     assert _err(L.azi_plan_set_tiling(plan.handle, T(1024, 128, 7, 0, 0, 0)))[0] == -1
     assert _err(L.azi_plan_set_tiling(plan.handle, T(1024, 128, -1, 0, 0, 0)))[0] == -1
     assert _err(L.azi_plan_set_tiling(plan.handle, T(1024, 128, 1, -8, 0, 0)))[0] == -1
-    assert _err(L.azi_plan_set_tiling(plan.handle, T(1024, 128, 1, 0, 0, 4)))[0] == -1
+    assert _err(L.azi_plan_set_tiling(plan.handle, T(1024, 128, 1, 0, 0, 5)))[0] == -1
     assert _err(L.azi_plan_set_tiling(plan.handle, None))[0] == -1
     assert L.azi_plan_set_tiling(plan.handle, T(1024, 128, 6, 512, 4, 1)) == 0
     assert plan.tiling() == dict(tile_nnz=1024, block=128, variant=6, grid=512, band=4, stage=1)
@@ -412,7 +412,7 @@ def test_run_encoding_holds_every_entry_once(g, tile):
     bin's slots are its band's pieces."""
     h, w, cy, cx, npt, split, na = g
     az = azint()
-    plan = az.Plan(h, w, npt, npt_azim=na or None, center=(cy, cx), split=split)
+    plan = az.Plan(h, w, npt, npt_azim=na or None, center=(cy, cx), split=split, band=4)
     s = plan.run_schedule(tile_nnz=tile)
     pix, bins, cs = _decode_runs(s, plan.npt)
     data, cbins, colptr = plan.export_csc()
@@ -497,3 +497,68 @@ def test_images_of_2_27_pixels_default_to_the_csr_layout():
     ii, jj = np.divmod(indices, n)
     assert np.all(np.abs(ii - n / 2) < 8) and np.all(np.abs(jj - n / 2) < 8)
     del p
+
+
+@pytest.mark.parametrize("g", [(300, 280, 150.2, 140.7, 260), (90, 100, 44.6, 50.2, 41),
+                               (64, 48, -5.0, 70.0, 40), (1, 17, 0.5, 8.5, 5),
+                               (257, 263, 10.0, 250.0, 333)],
+                         ids=lambda g: f"{g[0]}x{g[1]}-{g[4]}")
+@pytest.mark.parametrize("band", [16, 32])
+@pytest.mark.parametrize("tile", [128, 1024, 4096])
+def test_grouped_run_schedule_covers_every_run_once(g, band, tile):
+    """Workgroups of 4 or 8 neighbouring bands: entry t * waves + w is band
+    w of the workgroup's group; each band's entries tile its runs on
+    multiples of 64 in order, the entries of a workgroup cover one common
+    stretch of image rows (no band's entry starts before the stretch's first
+    pixel nor holds a group starting past its end), and each bin's slots are
+    its band's entries in order."""
+    h, w, cy, cx, npt = g
+    waves = band // 4
+    az = azint()
+    plan = az.Plan(h, w, npt, center=(cy, cx), tile_nnz=tile, band=band)
+    s = plan.run_schedule(tile_nnz=tile)
+    runs, pieces = s["runs"], s["pieces"]
+    nbands = (npt + 3) // 4
+    assert len(pieces) % waves == 0
+    ntiles = len(pieces) // waves
+    mask = (1 << 27) - 1
+    per_band = {}
+    for t in range(ntiles):
+        ents = pieces[t * waves:(t + 1) * waves]
+        bands = [int(e[2]) // 4 for e in ents if e[4] >= 0]
+        assert bands == list(range(bands[0], bands[0] + len(bands)))
+        assert bands[0] % waves == 0
+        for e in ents:
+            z0, z1, bin0, nrows, slot = (int(v) for v in e[:5])
+            if slot < 0:
+                assert z0 == z1 == 0
+                continue
+            assert z0 % 64 == 0 and z1 % 64 == 0 and z0 <= z1
+            assert nrows == min(4, npt - bin0) and slot % 4 == 0
+            per_band.setdefault(bin0 // 4, []).append((t, z0, z1, slot))
+    assert sorted(per_band) == list(range(nbands))
+    # every band: entries consecutive, covering [band start, band end)
+    starts = [0]
+    for b in range(nbands):
+        ent = per_band[b]
+        assert ent[0][1] == starts[-1]
+        for (_, _, z1, s0), (_, z0n, _, s1) in zip(ent, ent[1:]):
+            assert z0n == z1 and s1 == s0 + 4
+        end = ent[-1][2]
+        valid = runs[ent[0][1]:end] >= 0
+        assert end % 64 == 0 and (end - ent[0][1]) >= valid.sum()
+        starts.append(end)
+        for r in range(min(4, npt - 4 * b)):
+            assert s["bin_slot"][4 * b + r] == ent[0][3] + r
+            assert s["bin_count"][4 * b + r] == len(ent)
+    assert starts[-1] == len(runs)
+    # one stretch of rows per workgroup: a band's entry starts at the first
+    # group whose first pixel is not before the stretch (taken from the
+    # neighbours' entries of the same workgroup)
+    for t in range(ntiles):
+        ents = [e for e in pieces[t * waves:(t + 1) * waves] if e[4] >= 0]
+        firsts = [int(runs[e[0]]) & mask for e in ents if e[1] > e[0] and runs[e[0]] >= 0]
+        lasts = [int(runs[e[1] - 64]) & mask for e in ents if e[1] > e[0] and runs[e[1] - 64] >= 0]
+        if firsts and lasts and len(ents) > 1:
+            # groups of one workgroup start within the same stretch of pixels
+            assert max(firsts) <= max(lasts) + w * 64

@@ -44,11 +44,15 @@ def test_encoding_bytes_count_the_runs():
     """The run encoding's bytes use one word per pixel run within a band of
     4 bins: the count from the CSC equals the runs of the exported schedule."""
     az = azint()
-    plan = az.Plan(150, 140, 90, center=(70.3, 75.8))
+    plan = az.Plan(150, 140, 90, center=(70.3, 75.8), stage="fuse")
     s = plan.run_schedule()
     runs = int((s["runs"] >= 0).sum())
     got = bench.encoding_bytes(plan, np, plan.npix, plan.npt, 8, 12)
     assert got == runs * 4 + plan.nnz * 8 + plan.npix * (4 + 12) + 3 * plan.npt * 8
+    # folded normalisation: the dark value (4 bytes) is stored per run
+    plan.set_tiling(stage="fold")
+    got = bench.encoding_bytes(plan, np, plan.npix, plan.npt, 8, 4)
+    assert got == runs * (4 + 4) + plan.nnz * 8 + plan.npix * 4 + 3 * plan.npt * 8
     plan.set_layout("band")
     assert bench.encoding_bytes(plan, np, plan.npix, plan.npt, 8, 12) == \
         bench.raw_bytes(plan.nnz, plan.npix, plan.npt, 8, 12)

@@ -451,8 +451,9 @@ def test_c5_full_batch_sampled(dev):
         assert norm_err(gh[po[k]:po[k + 1]], ref, scale) <= TOL32_F64, k
 
 
+@pytest.mark.parametrize("band", [4, 16])
 @pytest.mark.parametrize("dtype,accum", [(torch.float64, "f64"), (torch.float32, "kahan32")])
-def test_lane_and_wavefront_reductions_agree(dtype, accum, dev):
+def test_lane_and_wavefront_reductions_agree(dtype, accum, band, dev):
     """A launch whose bins all have at most 8 band partials finishes them one
     lane per bin; otherwise one wavefront per bin.  Both combine a bin's
     partials in the same order, so a batch holding an image with long bands
@@ -467,12 +468,13 @@ def test_lane_and_wavefront_reductions_agree(dtype, accum, dev):
     for h, w, n in geoms:
         p = az.Plan(h, w, n, center=(h / 2 + 0.3, w / 2 - 0.7), dtype=dtype, accum=accum,
                     layout="run")
-        p.set_tiling(tile_nnz=tile)
+        p.set_tiling(tile_nnz=tile, band=band)
         plans.append(p)
     counts = [p.run_schedule(tile)["bin_count"] for p in plans]
     assert counts[0].max() > 8
     assert all(c.max() <= 8 for c in counts[1:])
-    assert set(np.concatenate(counts[1:]).tolist()) == set(range(1, 9))
+    if band == 4:
+        assert set(np.concatenate(counts[1:]).tolist()) == set(range(1, 9))
     batch = az.Batch(plans, device=dev)
     batch.set_tiling(tile_nnz=tile)
     assert batch.tiling()["tile_nnz"] == tile

@@ -56,7 +56,7 @@ def test_device_plan_equals_host_plan(g, dev):
     az = azint()
     dtype = torch.float64 if dt == "f64" else torch.float32
     kw = dict(center=(cy, cx), unit=unit, split=split, range=rng, dtype=dtype)
-    hp = az.Plan(h, w, npt, layout="band", **kw)   # the device builder's layout
+    hp = az.Plan(h, w, npt, layout="band", band=4, **kw)   # the device builder's layout
     dp = az.Plan.on_device(h, w, npt, device=dev, **kw)
     ih, idv = hp.info(), dp.info()
     assert idv["npt"] == npt and idv["npix"] == h * w
@@ -93,7 +93,7 @@ def test_device_plan_layout_switch_and_backward(dev):
     az = azint()
     h, w, npt = 150, 170, 120
     dp = az.Plan.on_device(h, w, npt, device=dev)
-    hp = az.Plan(h, w, npt, device=dev)
+    hp = az.Plan(h, w, npt, band=4, device=dev)   # the device-built plan's tiling
     x = torch.from_numpy(np.random.default_rng(5).uniform(0, 10, size=h * w)).to(dev)
     for layout in ("pixel", "ring", "tile", "band", "run"):
         dp.set_layout(layout)

@@ -1,0 +1,169 @@
+"""The raw-frame path with 1/norm folded into the coefficients
+(AZI_STAGE_FOLD, run layout) against the FP64 oracle, and against the
+unfolded path (AZI_STAGE_FUSE) on the same plan: W and I within the stated
+tolerance, U bit for bit (it is summed once from the unfolded coefficients
+in the per-frame order)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.helpers import azint, oracle_matrix
+from tests.test_gpu_forward import TOL32_F64, TOL64, check
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+RAW_TYPES = [np.int32, np.uint16, np.float32, np.float64]
+COMBOS = [(1, 1, 1, 1), (1, 0, 0, 0), (0, 1, 1, 0), (0, 0, 0, 1), (0, 0, 0, 0)]
+
+
+def _setup(az, dev, inst, dtype, accum, stage, **kw):
+    g = inst.geom
+    return az.Plan(g.h, g.w, inst.npt, center=(g.center_y, g.center_x), dtype=dtype,
+                   accum=accum, layout="run", stage=stage, device=dev, **kw)
+
+
+def _tensor(a, dev, npd=None):
+    a = np.ascontiguousarray(a).reshape(-1)
+    return torch.from_numpy(a if npd is None else a.astype(npd)).to(dev)
+
+
+@pytest.mark.parametrize("band", [4, 16])
+@pytest.mark.parametrize("raw_dtype", RAW_TYPES, ids=lambda t: np.dtype(t).name)
+@pytest.mark.parametrize("combo", COMBOS, ids=lambda c: "".join(map(str, c)))
+@pytest.mark.parametrize("dtype,accum", [(torch.float64, "f64"), (torch.float32, "f64"),
+                                         (torch.float32, "kahan32")],
+                         ids=["f64", "f32", "k32"])
+def test_fold_matches_oracle(dtype, accum, combo, raw_dtype, band, dev):
+    say("fold", dtype, accum, combo, raw_dtype)
+    az = azint()
+    inst = synth.instance_hw(173, 181, 9, npt=150, corrections=True)
+    g = inst.geom
+    npd = np.float64 if dtype == torch.float64 else np.float32
+    arrs = [a if on else None for a, on in zip((inst.dark, inst.flat, inst.solid, inst.polar),
+                                               combo)]
+    raw_np = inst.raw.reshape(-1).astype(raw_dtype)
+    raw = _tensor(raw_np, dev)
+    outs = {}
+    for stage in ("fold", "fuse"):
+        plan = _setup(az, dev, inst, dtype, accum, stage, band=band)
+        plan.set_corrections(*(None if a is None else _tensor(a, dev, npd) for a in arrs))
+        outs[stage] = plan.integrate_raw(raw, empty=-3.0)
+        torch.cuda.synchronize()
+    # U does not depend on the image: the folded path's U is the unfolded one's
+    assert torch.equal(outs["fold"][2], outs["fuse"][2])
+    m = oracle_matrix(g.h, g.w, g.center_y, g.center_x, inst.npt)
+    # the oracle corrects the same storage-type corrections as the plan holds
+    x = oracle.correct(raw_np, *(None if a is None else a.astype(npd).astype(np.float64)
+                                 for a in arrs))
+    tol = TOL64 if dtype == torch.float64 else TOL32_F64
+    check(outs["fold"], m, x, tol, empty=-3.0, what=f"fold {combo}")
+
+
+@pytest.mark.parametrize("band", [4, 16, 32])
+def test_fold_follows_tiling_changes(band, dev):
+    """Pieces, workgroup size and persistent grids change the order of the
+    sums: U is summed again, and the results stay within tolerance."""
+    say("fold retile")
+    az = azint()
+    inst = synth.instance_hw(260, 240, 10, npt=200, corrections=True)
+    g = inst.geom
+    t = lambda a: _tensor(a, dev)
+    m = oracle_matrix(g.h, g.w, g.center_y, g.center_x, inst.npt)
+    x = oracle.correct(inst.raw, inst.dark, inst.flat, inst.solid, inst.polar)
+    fold = _setup(az, dev, inst, torch.float64, "f64", "fold", band=band)
+    fuse = _setup(az, dev, inst, torch.float64, "f64", "fuse", band=band)
+    for p in (fold, fuse):
+        p.set_corrections(t(inst.dark), t(inst.flat), t(inst.solid), t(inst.polar))
+    for kw in (dict(tile_nnz=1024), dict(block=128), dict(grid=64), dict(tile_nnz=8192, grid=0),
+               dict(block=256, tile_nnz=4096)):
+        for p in (fold, fuse):
+            p.set_tiling(**kw)
+        a = fold.integrate_raw(t(inst.raw))
+        b = fuse.integrate_raw(t(inst.raw))
+        torch.cuda.synchronize()
+        assert torch.equal(a[2], b[2]), kw
+        check(a, m, x, TOL64, what=str(kw))
+
+
+def test_fold_stage_switch_and_recorrect(dev):
+    """Switching the stage of a corrected plan, and setting new corrections
+    on a folded plan, keep the results right."""
+    say("fold switch")
+    az = azint()
+    inst = synth.instance_hw(150, 170, 11, npt=120, corrections=True)
+    g = inst.geom
+    t = lambda a: _tensor(a, dev)
+    m = oracle_matrix(g.h, g.w, g.center_y, g.center_x, inst.npt)
+    plan = _setup(az, dev, inst, torch.float64, "f64", "fuse")
+    plan.set_corrections(t(inst.dark), t(inst.flat), t(inst.solid), t(inst.polar))
+    x = oracle.correct(inst.raw, inst.dark, inst.flat, inst.solid, inst.polar)
+    for stage in ("fold", "fuse", "fold"):
+        plan.set_tiling(stage=stage)
+        check(plan.integrate_raw(t(inst.raw)), m, x, TOL64, what=stage)
+    assert plan.correction_bytes() == 4         # integer dark: a float per run
+    flat2 = inst.flat[::-1].copy()
+    plan.set_corrections(None, t(flat2), None, t(inst.polar))
+    x2 = oracle.correct(inst.raw, None, flat2, None, inst.polar)
+    check(plan.integrate_raw(t(inst.raw)), m, x2, TOL64, what="new corrections")
+    # a float64 dark that is not a float keeps its double form
+    dark = inst.dark.reshape(-1).astype(np.float64) + 0.1
+    plan.set_corrections(t(dark), t(inst.flat), t(inst.solid), t(inst.polar))
+    assert plan.correction_bytes() == 8
+    x3 = oracle.correct(inst.raw, dark, inst.flat, inst.solid, inst.polar)
+    check(plan.integrate_raw(t(inst.raw)), m, x3, TOL64, what="double dark")
+
+
+def test_fold_graph_and_noalloc(dev):
+    """The folded step captured in a graph and through the allocation-free
+    entry point gives the eager call's bits, replay after replay."""
+    say("fold graph")
+    az = azint()
+    inst = synth.instance_hw(300, 280, 12, npt=250, corrections=True)
+    g = inst.geom
+    t = lambda a: _tensor(a, dev)
+    plan = _setup(az, dev, inst, torch.float64, "f64", "fold")
+    plan.set_corrections(t(inst.dark), t(inst.flat), t(inst.solid), t(inst.polar))
+    raw = t(inst.raw)
+    ref = [o.clone() for o in plan.integrate_raw(raw)]
+    outs = tuple(torch.full((plan.npt,), float("nan"), dtype=torch.float64, device=dev)
+                 for _ in range(3))
+    gr = plan.graph(raw, *outs)
+    for _ in range(3):
+        for o in outs:
+            o.fill_(float("nan"))
+        gr.launch()
+        torch.cuda.synchronize()
+        for a, b in zip(outs, ref):
+            assert torch.equal(a, b)
+        plan.integrate_raw(raw)  # eager work between replays
+    na = plan.integrate_raw_noalloc(raw)
+    torch.cuda.synchronize()
+    for a, b in zip(na, ref):
+        assert torch.equal(a, b)
+
+
+def test_fold_band_layout_is_fuse(dev):
+    """The band layout takes AZI_STAGE_FOLD as AZI_STAGE_FUSE."""
+    az = azint()
+    inst = synth.instance_hw(120, 110, 13, npt=90, corrections=True)
+    g = inst.geom
+    t = lambda a: _tensor(a, dev)
+    res = []
+    for stage in ("fold", "fuse"):
+        p = az.Plan(g.h, g.w, inst.npt, center=(g.center_y, g.center_x), layout="band",
+                    stage=stage, device=dev)
+        p.set_corrections(t(inst.dark), t(inst.flat), t(inst.solid), t(inst.polar))
+        res.append(p.integrate_raw(t(inst.raw)))
+        torch.cuda.synchronize()
+    for a, b in zip(*res):
+        assert torch.equal(a, b)

@@ -176,7 +176,7 @@ def test_fused_correction_record_and_pair_same_bits(layout, dev):
     g = inst.geom
     rng_r = (4e-4, 6e-3)  # the inner disc of radius 4e-4 m feeds no bin
     plan = az.Plan(g.h, g.w, inst.npt, center=(g.center_y, g.center_x), range=rng_r,
-                   layout=layout, device=dev)
+                   layout=layout, stage="fuse", device=dev)
     colptr = plan.export_csc()[2]
     empty_pix = np.flatnonzero(np.diff(colptr) == 0)
     assert empty_pix.size > 0
