@@ -97,6 +97,10 @@ struct DeviceGuard {
 };
 
 constexpr int64_t kPad = 64;  // nonzero arrays: instance starts on 64, 64 spare at the end
+// The adjoint reads each pixel's first four coefficients and bin values
+// with two vector loads whatever the pixel's count: its coefficient array
+// and bin-value vector keep this many spare elements at the end.
+constexpr int64_t kAdjPad = 4;
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
@@ -950,7 +954,7 @@ int plan_build_device(azi_plan* p, int32_t npt, const double* range2, int device
                                cdata64.as<double>(), p->indices.as<int32_t>(), p->data.p,
                                p->dtype, p->dtype != AZI_F64 ? data64.as<double>() : nullptr, s),
             "gather");
-    AZI_HIP(p->cdata.alloc(n1 * es, device), "cdata");
+    AZI_HIP(p->cdata.alloc((n1 + kAdjPad) * es, device), "cdata");
     AZI_HIP(azi::launch_to_storage(cdata64.as<double>(), nnz, p->cdata.p, p->dtype, s), "cdata");
     // host copy of the matrix, for export and for the host-side layouts
     try {
@@ -972,7 +976,7 @@ int plan_build_device(azi_plan* p, int32_t npt, const double* range2, int device
     p->order.release();
     p->used = npix;
     AZI_HIP(p->xwork.alloc((size_t)npix * es, device), "work image");
-    AZI_HIP(p->vwork.alloc((size_t)npt * 8, device), "work vector");
+    AZI_HIP(p->vwork.alloc((size_t)(npt + kAdjPad) * 8, device), "work vector");
     // the band layout's own bands of 4 bins (band 16 means four neighbouring
     // bands per workgroup only in the run layout)
     p->layout = AZI_LAYOUT_BAND;
@@ -1247,13 +1251,13 @@ int azi_plan_upload(azi_plan* p, int32_t device) {
             AZI_HIP(p->rowidx.upload(p->m.rowidx.data(), (size_t)nnz * 4, device), "rowidx");
             const int rcf = upload_first(p->m, device, p->cfirst);
             if (rcf != AZI_OK) return rcf;
-            std::vector<char> cd = to_storage(p->m.cdata.data(), nnz, nnz, p->dtype);
+            std::vector<char> cd = to_storage(p->m.cdata.data(), nnz, nnz + kAdjPad, p->dtype);
             AZI_HIP(p->cdata.upload(cd.data(), cd.size(), device), "cdata");
         } catch (const std::bad_alloc&) {
             return fail(AZI_ENOMEM, "out of host memory staging the upload");
         }
         AZI_HIP(p->xwork.alloc((size_t)p->m.npix * es, device), "work image");
-        AZI_HIP(p->vwork.alloc((size_t)p->m.npt * 8, device), "work vector");
+        AZI_HIP(p->vwork.alloc((size_t)(p->m.npt + kAdjPad) * 8, device), "work vector");
         if (is_band(p->layout)) {
             int rc2 = plan_upload_bands(p);
             if (rc2 != AZI_OK) return rc2;
@@ -1709,7 +1713,7 @@ int azi_batch_create(azi_plan* const* plans, int32_t n, int32_t device, azi_batc
         std::vector<int32_t>().swap(idx);
         std::vector<char>().swap(dat);
         std::vector<int32_t> colptr((size_t)b->npix + 1, 0), rowidx((size_t)b->nnz, 0);
-        std::vector<char> cdat((size_t)std::max<int64_t>(b->nnz, 1) * es, 0);
+        std::vector<char> cdat((size_t)(std::max<int64_t>(b->nnz, 1) + kAdjPad) * es, 0);
         for (int32_t k = 0; k < n; ++k) {
             const azi::HostMatrix& m = plans[k]->m;
             for (int64_t p = 0; p < m.npix; ++p)
@@ -1738,8 +1742,8 @@ int azi_batch_create(azi_plan* const* plans, int32_t n, int32_t device, azi_batc
         }
         if ((int64_t)first.size() == b->npix)
             AZI_HIP(b->cfirst.upload(first.data(), first.size() * 4, device), "first bins");
-        AZI_HIP(b->cdata.upload(cdat.data(), (size_t)b->nnz * es, device), "cdata");
-        AZI_HIP(b->vwork.alloc((size_t)b->npt * 8, device), "work vector");
+        AZI_HIP(b->cdata.upload(cdat.data(), cdat.size(), device), "cdata");
+        AZI_HIP(b->vwork.alloc((size_t)(b->npt + kAdjPad) * 8, device), "work vector");
         std::vector<std::vector<int32_t>> store;
         std::vector<const int32_t*> ptrs;
         std::vector<int32_t> npts;

@@ -36,13 +36,14 @@ struct BackwardLaunch {
     const int32_t* colptr = nullptr;   // npix + 1 (global nnz positions)
     const int32_t* rowidx = nullptr;   // global bin ids
     const int32_t* first = nullptr;    // when set: each pixel's bins are consecutive from
-                                       // first[p] (rowidx then unused)
+                                       // first[p] (rowidx then unused); cdata and v
+                                       // then hold 4 spare elements past their end
     const void* cdata = nullptr;       // storage type
     const void* U = nullptr;           // forward U, storage type
     const void* gI = nullptr;          // may be null
     const void* gW = nullptr;          // may be null
     const void* norm = nullptr;        // divide the result by it when non-null
-    double* v = nullptr;               // work buffer, npt doubles
+    double* v = nullptr;               // work buffer, npt (+ 4 spare) doubles
     void* gx = nullptr;                // npix, storage type
     int64_t npix = 0;
     int64_t npt = 0;

@@ -801,6 +801,20 @@ __global__ void k_prep_v(const T* __restrict__ U, const T* __restrict__ gI,
 // read consecutive stretches of the entry arrays.  With kFirst the bins of
 // a pixel are consecutive and given by the pixel's first bin alone (one
 // word per pixel instead of one per entry).
+// Four consecutive values from a 4-byte (float) or 8-byte (double)
+// aligned address, as one or two vector loads.
+typedef float F4u __attribute__((ext_vector_type(4), aligned(4)));
+typedef double D2u __attribute__((ext_vector_type(2), aligned(8)));
+__device__ inline void load4u(const float* p, float v[4]) {
+    const F4u a = *reinterpret_cast<const F4u*>(p);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+}
+__device__ inline void load4u(const double* p, double v[4]) {
+    const D2u a = *reinterpret_cast<const D2u*>(p);
+    const D2u b = *reinterpret_cast<const D2u*>(p + 2);
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+
 template <class T, bool kFirst>
 __global__ void k_csc_bwd(const int32_t* __restrict__ colptr, const int32_t* __restrict__ rowidx,
                           const int32_t* __restrict__ first, const T* __restrict__ cdata,
@@ -809,19 +823,29 @@ __global__ void k_csc_bwd(const int32_t* __restrict__ colptr, const int32_t* __r
     const int64_t p = xcd_block(blockIdx.x, gridDim.x) * (int64_t)blockDim.x + threadIdx.x;
     if (p >= npix) return;
     const int32_t k0 = colptr[p], k1 = colptr[p + 1];
-    const int32_t b0 = kFirst ? first[p] : 0;
     T c[4];
-    int32_t b[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        if (k0 + j < k1) {
-            c[j] = cdata[k0 + j];
-            b[j] = kFirst ? b0 + j : rowidx[k0 + j];
-        }
-    }
     double vb[4];
+    int32_t b0 = 0;
+    if constexpr (kFirst) {
+        // the pixel's first four coefficients and the values of its first
+        // four bins (consecutive) in two vector loads each; entries past
+        // the pixel's count are read (the arrays keep spare elements) and
+        // not used
+        b0 = first[p];
+        load4u(cdata + k0, c);
+        load4u(v + b0, vb);
+    } else {
+        int32_t b[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) vb[j] = (k0 + j < k1) ? v[b[j]] : 0.0;
+        for (int j = 0; j < 4; ++j) {
+            if (k0 + j < k1) {
+                c[j] = cdata[k0 + j];
+                b[j] = rowidx[k0 + j];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) vb[j] = (k0 + j < k1) ? v[b[j]] : 0.0;
+    }
     double acc = 0.0;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
