@@ -484,7 +484,18 @@ def two_d_line(az, torch, np, synth, dev, nr=1000, na=360, reps=30):
     g = inst.geom
     t0 = time.perf_counter()
     plan = az.Plan(g.h, g.w, nr, npt_azim=na, center=(g.center_y, g.center_x), device=dev)
+    torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
+    # the same plan from the device builder (its first call untimed)
+    az.Plan.on_device(g.h, g.w, nr, npt_azim=na, center=(g.center_y, g.center_x), device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dplan = az.Plan.on_device(g.h, g.w, nr, npt_azim=na, center=(g.center_y, g.center_x),
+                              device=dev)
+    torch.cuda.synchronize()
+    device_build_s = time.perf_counter() - t0
+    del dplan
+    torch.cuda.empty_cache()
     x = torch.from_numpy(inst.raw.reshape(-1).astype(np.float64)).to(dev)
     outs = tuple(torch.empty(plan.npt, dtype=torch.float64, device=dev) for _ in range(3))
     flush = Flush(torch, dev)
@@ -494,7 +505,8 @@ def two_d_line(az, torch, np, synth, dev, nr=1000, na=360, reps=30):
     nnz = plan.nnz
     by = spmv_bytes(nnz, g.npix, plan.npt, 8)
     line = dict(npix=g.npix, npt_rad=nr, npt_azim=na, nnz=nnz, layout=plan.layout(),
-                build_s=build_s, integrate_ms=warm, integrate_cold_ms=cold,
+                build_s=build_s, device_build_s=device_build_s,
+                integrate_ms=warm, integrate_cold_ms=cold,
                 integrate_bytes=by, integrate_gbs=by / (warm * 1e6),
                 integrate_frac=by / (warm * 1e6) / HBM_PEAK_GBS,
                 integrate_cold_frac=by / (cold * 1e6) / HBM_PEAK_GBS,

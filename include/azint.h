@@ -167,6 +167,23 @@ int azi_plan_create_device(const azi_geom* geom, int32_t npt, int32_t unit, int3
                            const double* range2, int32_t dtype, int32_t accum, int32_t device,
                            void* stream, azi_plan** out);
 
+/*
+ * The two-dimensional plan of azi_plan_create2d (Section 4, radius x
+ * azimuth) built on a device by the same kernels as azi_plan_create_device:
+ * per-pixel entries from the operations of the host builder (the radial
+ * shares bit for bit with AZI_UNIT_R_M / _R_MM; the azimuths from the
+ * device's atan2, which may differ from the C library's by an ulp, so a
+ * coefficient at a wedge edge can differ by rounding and a sliver entry of
+ * a few ulps can appear or vanish), the row-major (CSR) order from the
+ * stable radix sort by row.  The plan comes back uploaded to `device` in
+ * the pixel layout with the two-dimensional default tiling, with a host
+ * copy of its matrix.  Errors as azi_plan_create2d and
+ * azi_plan_create_device.
+ */
+int azi_plan_create2d_device(const azi_geom* geom, int32_t npt_rad, int32_t npt_azim,
+                             int32_t unit, int32_t split, const double* range2, int32_t dtype,
+                             int32_t accum, int32_t device, void* stream, azi_plan** out);
+
 /* Free a plan and its device memory.  NULL is accepted (no-op). */
 int azi_plan_destroy(azi_plan* plan);
 

@@ -85,6 +85,8 @@ _SIGS = {
                                          _I32, ctypes.POINTER(_P)]),
     "azi_plan_create_device": (ctypes.c_int, [ctypes.POINTER(_Geom), _I32, _I32, _I32, _P, _I32,
                                               _I32, _I32, _P, ctypes.POINTER(_P)]),
+    "azi_plan_create2d_device": (ctypes.c_int, [ctypes.POINTER(_Geom), _I32, _I32, _I32, _I32, _P,
+                                                _I32, _I32, _I32, _P, ctypes.POINTER(_P)]),
     "azi_plan_shape": (ctypes.c_int, [_P, _P, _P]),
     "azi_plan_azimuths": (ctypes.c_int, [_P, _P]),
     "azi_plan_destroy": (ctypes.c_int, [_P]),
@@ -224,30 +226,37 @@ class Plan:
             self.upload(device)
 
     @classmethod
-    def on_device(cls, h, w, npt, *, device, pixel=1e-4, center=None, dist=0.1,
+    def on_device(cls, h, w, npt, *, device, npt_azim=None, pixel=1e-4, center=None, dist=0.1,
                   wavelength=1e-10, unit="r_m", split="bbox", range=None, dtype=torch.float64,
                   accum="f64", stream=None):
-        """A one-dimensional plan built by the device plan builder on
-        ``device`` (returned uploaded there, band layout; set_layout("run")
-        switches to the run encoding, built from the plan's host copy)."""
+        """A plan built by the device plan builder on ``device``: one-
+        dimensional (returned uploaded there, band layout; set_layout("run")
+        switches to the run encoding, built from the plan's host copy), or
+        with ``npt_azim`` two-dimensional (pixel layout)."""
         dev = torch.device(device) if not isinstance(device, torch.device) else device
         idx = dev.index if dev.index is not None else torch.cuda.current_device()
         py, px = (pixel, pixel) if np.isscalar(pixel) else pixel
         cy, cx = (h / 2.0, w / 2.0) if center is None else center
         self = cls.__new__(cls)
-        self.npt_rad, self.npt_azim = int(npt), 0
-        self.h, self.w, self.npt = int(h), int(w), int(npt)
+        self.npt_rad, self.npt_azim = int(npt), int(npt_azim) if npt_azim else 0
+        self.h, self.w = int(h), int(w)
+        self.npt = self.npt_rad * max(self.npt_azim, 1)
         self.dtype, self.accum = dtype, accum
         self._h = None
         g = _Geom(int(h), int(w), float(py), float(px), float(cy), float(cx), float(dist),
                   float(wavelength))
         rng = None if range is None else (ctypes.c_double * 2)(float(range[0]), float(range[1]))
         out = ctypes.c_void_p()
+        rng_p = ctypes.cast(rng, ctypes.c_void_p) if rng else None
         with torch.cuda.device(idx):
-            _check(lib().azi_plan_create_device(
-                ctypes.byref(g), int(npt), UNITS[unit], SPLITS[split],
-                ctypes.cast(rng, ctypes.c_void_p) if rng else None, _STORAGE[dtype],
-                _ACCUM[accum], idx, _stream(stream), ctypes.byref(out)))
+            if self.npt_azim:
+                _check(lib().azi_plan_create2d_device(
+                    ctypes.byref(g), int(npt), self.npt_azim, UNITS[unit], SPLITS[split], rng_p,
+                    _STORAGE[dtype], _ACCUM[accum], idx, _stream(stream), ctypes.byref(out)))
+            else:
+                _check(lib().azi_plan_create_device(
+                    ctypes.byref(g), int(npt), UNITS[unit], SPLITS[split], rng_p,
+                    _STORAGE[dtype], _ACCUM[accum], idx, _stream(stream), ctypes.byref(out)))
         self._h = out
         self.device = torch.device("cuda", idx)
         return self

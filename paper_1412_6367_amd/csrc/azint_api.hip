@@ -741,10 +741,11 @@ int32_t azi_version(void) { return AZI_ABI_VERSION; }
 const char* azi_last_error(void) { return g_err.c_str(); }
 
 namespace {
-int plan_build_device(azi_plan* p, int32_t npt, const double* range2, int device, hipStream_t s);
+int plan_build_device(azi_plan* p, int32_t npt, int32_t npt_azim, const double* range2,
+                      int device, hipStream_t s);
 
-// device < 0: the host builder; otherwise the device builder on that device
-// (one-dimensional plans), leaving the plan uploaded there.
+// device < 0: the host builder; otherwise the device builder on that device,
+// leaving the plan uploaded there.
 int plan_create(const azi_geom* geom, int32_t npt, int32_t npt_azim, int32_t unit, int32_t split,
                 const double* range2, int32_t dtype, int32_t accum, azi_plan** out,
                 int32_t device = -1, hipStream_t stream = nullptr) {
@@ -775,7 +776,7 @@ int plan_create(const azi_geom* geom, int32_t npt, int32_t npt_azim, int32_t uni
     p->unit = unit;
     p->split = split;
     if (device >= 0) {
-        const int rc = plan_build_device(p.get(), npt, range2, device, stream);
+        const int rc = plan_build_device(p.get(), npt, npt_azim, range2, device, stream);
         if (rc != AZI_OK) return rc;
         *out = p.release();
         return AZI_OK;
@@ -872,7 +873,8 @@ int plan_device_bands(azi_plan* p, const int32_t* rowidx, const int32_t* pix, co
     return AZI_OK;
 }
 
-int plan_build_device(azi_plan* p, int32_t npt, const double* range2, int device, hipStream_t s) {
+int plan_build_device(azi_plan* p, int32_t npt, int32_t npt_azim, const double* range2,
+                      int device, hipStream_t s) {
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || count < 1)
         return fail(AZI_EDEVICE, "no HIP device available");
@@ -882,11 +884,15 @@ int plan_build_device(azi_plan* p, int32_t npt, const double* range2, int device
     const azi_geom& g = p->geom;
     const int64_t npix = (int64_t)g.h * g.w;
     if (npix >= (int64_t)INT32_MAX) return fail(AZI_EOVERFLOW, "image has 2^31 pixels or more");
+    const bool two_d = npt_azim > 0;
+    if (two_d && (int64_t)npt * npt_azim >= (int64_t)INT32_MAX)
+        return fail(AZI_EOVERFLOW, "npt_rad * npt_azim is 2^31 or more");
     p->device = device;
     azi::HostMatrix& m = p->m;
-    m.npt = m.npt_rad = npt;
-    m.npt_azim = 1;
-    m.two_d = false;
+    m.npt_rad = npt;
+    m.npt = two_d ? npt * npt_azim : npt;
+    m.npt_azim = two_d ? npt_azim : 1;
+    m.two_d = two_d;
     m.npix = npix;
     const bool boxes = p->split != AZI_SPLIT_NONE;
     const int64_t nblk = (npix + azi::kBuildBlock - 1) / azi::kBuildBlock;
@@ -914,8 +920,9 @@ int plan_build_device(azi_plan* p, int32_t npt, const double* range2, int device
     m.pmax = pr[1];
     const double delta = (m.pmax - m.pmin) / npt;
     AZI_HIP(cnt.alloc((size_t)npix * 4, device), "entry counts");
+    const int32_t nazim = two_d ? npt_azim : 0;
     AZI_HIP(azi::launch_count(g, p->unit, p->split, lo.as<double>(), hi.as<double>(), m.pmin, delta,
-                              npt, cnt.as<int32_t>(), s), "entry counts");
+                              npt, nazim, cnt.as<int32_t>(), s), "entry counts");
     AZI_HIP(p->colptr.alloc((size_t)(npix + 1) * 4, device), "colptr");
     AZI_HIP(scanw.alloc(azi::scan_work_bytes(npix), device), "scan work");
     AZI_HIP(tot.alloc(8, device), "scan total");
@@ -936,16 +943,16 @@ int plan_build_device(azi_plan* p, int32_t npt, const double* range2, int device
     AZI_HIP(cdata64.alloc(n1 * 8, device), "coefficients");
     AZI_HIP(pix.alloc(n1 * 4, device), "pixel ids");
     AZI_HIP(azi::launch_fill(g, p->unit, p->split, lo.as<double>(), hi.as<double>(), m.pmin, delta,
-                             npt, p->colptr.as<int32_t>(), p->rowidx.as<int32_t>(),
+                             npt, nazim, p->colptr.as<int32_t>(), p->rowidx.as<int32_t>(),
                              cdata64.as<double>(), pix.as<int32_t>(), s), "fill");
     // bin-major order: stable sort of the pixel-major entries by bin
     AZI_HIP(work.alloc(azi::sort_work_bytes(nnz), device), "sort work");
     AZI_HIP(skeys.alloc(n1 * 4, device), "sorted bins");
     AZI_HIP(perm.alloc(n1 * 4, device), "permutation");
-    AZI_HIP(azi::launch_sort(p->rowidx.as<int32_t>(), nnz, bit_length(npt - 1),
+    AZI_HIP(azi::launch_sort(p->rowidx.as<int32_t>(), nnz, bit_length(m.npt - 1),
                              skeys.as<int32_t>(), perm.as<int32_t>(), work.p, s), "sort");
-    AZI_HIP(p->rowptr.alloc((size_t)(npt + 1) * 4, device), "indptr");
-    AZI_HIP(azi::launch_bounds(skeys.as<int32_t>(), nnz, npt, p->rowptr.as<int32_t>(), s),
+    AZI_HIP(p->rowptr.alloc((size_t)(m.npt + 1) * 4, device), "indptr");
+    AZI_HIP(azi::launch_bounds(skeys.as<int32_t>(), nnz, m.npt, p->rowptr.as<int32_t>(), s),
             "indptr");
     AZI_HIP(p->indices.alloc((size_t)nnz_alloc * 4, device), "indices");
     AZI_HIP(p->data.alloc((size_t)nnz_alloc * es, device), "data");
@@ -961,7 +968,7 @@ int plan_build_device(azi_plan* p, int32_t npt, const double* range2, int device
         int rc = download(m.colptr, p->colptr.p, npix + 1, s);
         if (rc == AZI_OK) rc = download(m.rowidx, p->rowidx.p, nnz, s);
         if (rc == AZI_OK) rc = download(m.cdata, cdata64.p, nnz, s);
-        if (rc == AZI_OK) rc = download(m.indptr, p->rowptr.p, (int64_t)npt + 1, s);
+        if (rc == AZI_OK) rc = download(m.indptr, p->rowptr.p, (int64_t)m.npt + 1, s);
         if (rc == AZI_OK) rc = download(m.indices, p->indices.p, nnz, s);
         if (rc == AZI_OK)
             rc = download(m.data, p->dtype == AZI_F64 ? p->data.p : data64.p, nnz, s);
@@ -976,7 +983,14 @@ int plan_build_device(azi_plan* p, int32_t npt, const double* range2, int device
     p->order.release();
     p->used = npix;
     AZI_HIP(p->xwork.alloc((size_t)npix * es, device), "work image");
-    AZI_HIP(p->vwork.alloc((size_t)(npt + kAdjPad) * 8, device), "work vector");
+    AZI_HIP(p->vwork.alloc((size_t)(m.npt + kAdjPad) * 8, device), "work vector");
+    if (two_d) {
+        // short rows: the plain CSR with whole rows per tile, as for
+        // host-built two-dimensional plans
+        p->layout = AZI_LAYOUT_PIXEL;
+        p->tiling = kDefaultTiling2d;
+        return plan_upload_tiles(p);
+    }
     // the band layout's own bands of 4 bins (band 16 means four neighbouring
     // bands per workgroup only in the run layout)
     p->layout = AZI_LAYOUT_BAND;
@@ -1001,6 +1015,21 @@ int azi_plan_create_device(const azi_geom* geom, int32_t npt, int32_t unit, int3
         return fail(AZI_EDEVICE, "no such HIP device");
     }
     return plan_create(geom, npt, 0, unit, split, range2, dtype, accum, out, device,
+                       static_cast<hipStream_t>(stream));
+}
+
+int azi_plan_create2d_device(const azi_geom* geom, int32_t npt_rad, int32_t npt_azim,
+                             int32_t unit, int32_t split, const double* range2, int32_t dtype,
+                             int32_t accum, int32_t device, void* stream, azi_plan** out) {
+    if (device < 0) {
+        if (out) *out = nullptr;
+        return fail(AZI_EDEVICE, "no such HIP device");
+    }
+    if (npt_azim < 2) {
+        if (out) *out = nullptr;
+        return fail(AZI_EINVAL, "npt_azim must be >= 2");
+    }
+    return plan_create(geom, npt_rad, npt_azim, unit, split, range2, dtype, accum, out, device,
                        static_cast<hipStream_t>(stream));
 }
 

@@ -169,4 +169,203 @@ __host__ __device__ inline void full_pixel(int64_t i, int64_t j, const azi_geom&
     }
 }
 
+// ---------------------------------------------------------------------------
+// Two-dimensional integration (radius x azimuth): rows are (wedge k, radial
+// bin b) -> k * nrad + b, wedges of width dchi from -pi, periodic.
+// ---------------------------------------------------------------------------
+struct Grid2d {
+    double pmin, delta, dchi;
+    int32_t nrad, nazim;
+};
+
+__host__ __device__ inline int32_t wrap_wedge(int64_t k, int32_t n) {
+    return (int32_t)(((k % n) + n) % n);
+}
+
+// Azimuths chi = atan2(y, x) of the four corners of pixel (i, j), in the
+// order (j, i), (j+1, i), (j+1, i+1), (j, i+1), unwrapped to within pi of
+// the first corner; p0 (optional) receives the corners' output coordinate.
+__host__ __device__ inline void pixel_corners(int64_t i, int64_t j, const azi_geom& g,
+                                              int32_t unit, double* p0, double* p1) {
+    const int da[4] = {0, 1, 1, 0}, db[4] = {0, 0, 1, 1};
+    for (int k = 0; k < 4; ++k) {
+        const double x = ((double)(j + da[k]) - g.center_x_px) * g.pixel_x_m;
+        const double y = ((double)(i + db[k]) - g.center_y_px) * g.pixel_y_m;
+        if (p0) p0[k] = to_unit(::sqrt(x * x + y * y), unit, g.dist_m, g.wavelength_m);
+        p1[k] = ::atan2(y, x);
+    }
+    for (int k = 1; k < 4; ++k)
+        p1[k] += ::nearbyint((p1[0] - p1[k]) / (2.0 * M_PI)) * (2.0 * M_PI);
+}
+
+// Calls f(k) for every raw wedge index k of [k0, k1] in ascending order of
+// the wedge it wraps to (ties, possible with very few wedges, by ascending
+// k): the pixel's entries then come out in ascending row order.
+template <class F>
+__host__ __device__ inline void wedges_ascending(int64_t k0, int64_t k1, int32_t n, F&& f) {
+    if (k1 < k0) return;
+    const int64_t t0 = k0 >= 0 ? k0 / n : -((-k0 + n - 1) / n);  // floor(k / n)
+    const int64_t t1 = k1 >= 0 ? k1 / n : -((-k1 + n - 1) / n);
+    if (t0 == t1) {
+        for (int64_t k = k0; k <= k1; ++k) f(k);
+        return;
+    }
+    if (t1 == t0 + 1 && k1 - k0 + 1 < n) {  // one crossing of the periodic cut
+        for (int64_t k = t1 * n; k <= k1; ++k) f(k);
+        for (int64_t k = k0; k < t1 * n; ++k) f(k);
+        return;
+    }
+    for (int32_t w = 0; w < n; ++w)
+        for (int64_t t = t0; t <= t1; ++t) {
+            const int64_t k = w + t * n;
+            if (k >= k0 && k <= k1) f(k);
+        }
+}
+
+// Bounding box in two dimensions: the radial shares of the box (as in one
+// dimension) times the azimuthal shares of [chi_lo, chi_hi], the range of
+// the corner azimuths (along a straight edge that misses the beam the
+// azimuth is monotone): outer wedges get their overlap over the span, inner
+// ones 1 / span; a pixel holding the beam spreads evenly over all wedges.
+// emit(row, c) in ascending row order.
+template <class Emit>
+__host__ __device__ inline void bbox2d_entries(int64_t i, int64_t j, const azi_geom& g, double lo,
+                                               double hi, const Grid2d& G, Emit&& emit) {
+    const BoxTerms rt = bbox_terms(lo, hi, G.pmin, G.delta, G.nrad);
+    if (rt.b0 > rt.b1) return;
+    auto radial = [&](int32_t w, double ac) {
+        const int32_t row0 = w * G.nrad;
+        emit(row0 + rt.b0, rt.cl * ac);
+        if (rt.b1 == rt.b0) return;
+        for (int32_t b = rt.b0 + 1; b < rt.b1; ++b) emit(row0 + b, rt.ci * ac);
+        emit(row0 + rt.b1, rt.cr * ac);
+    };
+    if (lo == 0.0) {
+        for (int32_t k = 0; k < G.nazim; ++k) radial(k, 1.0 / G.nazim);
+        return;
+    }
+    double p1[4];
+    pixel_corners(i, j, g, AZI_UNIT_R_M, nullptr, p1);
+    const double clo = vmin(vmin(p1[0], p1[1]), vmin(p1[2], p1[3]));
+    const double chi = vmax(vmax(p1[0], p1[1]), vmax(p1[2], p1[3]));
+    const double gl = (clo + M_PI) / G.dchi;
+    const double gh = (chi + M_PI) / G.dchi;
+    const double width = gh - gl;
+    const int64_t k0 = (int64_t)::floor(gl);
+    int64_t k1 = (int64_t)::ceil(gh) - 1;
+    if (width == 0.0 || k1 < k0) k1 = k0;
+    wedges_ascending(k0, k1, G.nazim, [&](int64_t k) {
+        double c;
+        if (k0 == k1) c = 1.0;
+        else if (k == k0) c = ((double)(k0 + 1) - gl) / width;
+        else if (k == k1) c = (gh - (double)k1) / width;
+        else c = 1.0 / width;
+        if (c > 0.0) radial(wrap_wedge(k, G.nazim), c);
+    });
+}
+
+// Integral over [a, b] of clamp(y0 + (x - x0) * slope, t0, t1): the
+// interval is cut where the line meets t0 and t1, and the clamped line is
+// linear on every piece, so each piece is an exact trapezoid.
+__host__ __device__ inline double clamped_line(double x0, double y0, double slope, double a,
+                                               double b, double t0, double t1) {
+    double cut[4];
+    int n = 0;
+    cut[n++] = a;
+    if (slope != 0.0) {
+        double xa = x0 + (t0 - y0) / slope, xb = x0 + (t1 - y0) / slope;
+        if (xa > xb) {
+            const double tmp = xa;
+            xa = xb;
+            xb = tmp;
+        }
+        if (xa > a && xa < b) cut[n++] = xa;
+        if (xb > a && xb < b) cut[n++] = xb;
+    }
+    cut[n++] = b;
+    double s = 0.0;
+    for (int k = 0; k + 1 < n; ++k) {
+        const double u = cut[k], v = cut[k + 1];
+        const double yu = vmin(vmax(y0 + (u - x0) * slope, t0), t1);
+        const double yv = vmin(vmax(y0 + (v - x0) * slope, t0), t1);
+        s += (v - u) * (yu + yv) / 2.0;
+    }
+    return s;
+}
+
+// Area of the quadrilateral inside [e0, e1] x [t0, t1]: over every x of the
+// slab, the boundary's lower and upper crossings bound the section, and
+// clamp(upper) - clamp(lower) is the part of it inside [t0, t1]; summing the
+// clamped edge lines with the edge's direction as sign gives that total.
+__host__ __device__ inline double edge_integral_box(const Quad& q, double e0, double e1,
+                                                    double t0, double t1) {
+    double s = 0.0;
+    for (int k = 0; k < 4; ++k) {
+        const double ax = q.x[k], ay = q.y[k];
+        const double bx = q.x[(k + 1) & 3], by = q.y[(k + 1) & 3];
+        if (ax == bx) continue;
+        const double lo = vmax(vmin(ax, bx), e0);
+        const double hi = vmin(vmax(ax, bx), e1);
+        if (!(hi > lo)) continue;
+        const double part = clamped_line(ax, ay, (by - ay) / (bx - ax), lo, hi, t0, t1);
+        s += bx > ax ? part : -part;
+    }
+    return ::fabs(s);
+}
+
+// Full splitting in two dimensions: the quadrilateral of the corners in
+// (output unit, azimuth) clipped to each bin's rectangle, the wedge repeated
+// every 2 pi; a pixel holding the beam takes the bounding box.  emit(row, c)
+// in ascending row order.
+template <class Emit>
+__host__ __device__ inline void full2d_entries(int64_t i, int64_t j, const azi_geom& g,
+                                               int32_t unit, double lo, double hi,
+                                               const Grid2d& G, Emit&& emit) {
+    if (lo == 0.0) {
+        bbox2d_entries(i, j, g, lo, hi, G, emit);
+        return;
+    }
+    double p0[4], p1[4];
+    pixel_corners(i, j, g, unit, p0, p1);
+    const double mn = vmin(vmin(p0[0], p0[1]), vmin(p0[2], p0[3]));
+    const double mx = vmax(vmax(p0[0], p0[1]), vmax(p0[2], p0[3]));
+    const double cmn = vmin(vmin(p1[0], p1[1]), vmin(p1[2], p1[3]));
+    const double cmx = vmax(vmax(p1[0], p1[1]), vmax(p1[2], p1[3]));
+    Quad q;
+    for (int k = 0; k < 4; ++k) {
+        q.x[k] = p0[k] - p0[0];
+        q.y[k] = p1[k] - p1[0];
+    }
+    const double area = edge_integral(q, -HUGE_VAL, HUGE_VAL);
+    const double fl = (mn - G.pmin) / G.delta, fh = (mx - G.pmin) / G.delta;
+    if (area == 0.0 || fh == fl) return;
+    const int32_t b0 = vmax((int32_t)::floor(fl), 0);
+    const int32_t b1 = vmin((int32_t)::ceil(fh) - 1, G.nrad - 1);
+    const int64_t k0 = (int64_t)::floor((cmn + M_PI) / G.dchi);
+    const int64_t k1 = vmax((int64_t)::ceil((cmx + M_PI) / G.dchi) - 1, k0);
+    wedges_ascending(k0, k1, G.nazim, [&](int64_t k) {
+        const double t0 = (-M_PI + (double)k * G.dchi) - p1[0];
+        const double t1 = (-M_PI + (double)(k + 1) * G.dchi) - p1[0];
+        const int32_t row0 = wrap_wedge(k, G.nazim) * G.nrad;
+        for (int32_t b = b0; b <= b1; ++b) {
+            const double e0 = (G.pmin + b * G.delta) - p0[0];
+            const double e1 = (G.pmin + (b + 1) * G.delta) - p0[0];
+            const double c = edge_integral_box(q, e0, e1, t0, t1) / area;
+            if (c > 0.0) emit(row0 + b, c);
+        }
+    });
+}
+
+// No split in two dimensions: the bin of the pixel midpoint, fc its
+// fractional radial position.
+template <class Emit>
+__host__ __device__ inline void none2d_entry(int64_t i, int64_t j, const azi_geom& g, double fc,
+                                             const Grid2d& G, Emit&& emit) {
+    if (!(fc >= 0.0 && fc <= (double)G.nrad)) return;
+    const double xc = ((double)j + 0.5 - g.center_x_px) * g.pixel_x_m;
+    const double yc = ((double)i + 0.5 - g.center_y_px) * g.pixel_y_m;
+    const int64_t k = (int64_t)::floor((::atan2(yc, xc) + M_PI) / G.dchi);
+    emit(wrap_wedge(k, G.nazim) * G.nrad + vmin((int32_t)::floor(fc), G.nrad - 1), 1.0);
+}
+
 }  // namespace azi

@@ -17,166 +17,6 @@
 #include "pixel_math.h"
 
 namespace azi {
-namespace {
-
-// Azimuths chi = atan2(y, x) of the four corners of pixel (i, j), in the
-// order (j, i), (j+1, i), (j+1, i+1), (j, i+1), unwrapped to within pi of
-// the first corner; p0 (optional) receives the corners' output coordinate.
-inline void pixel_corners(int64_t i, int64_t j, const azi_geom& g, int32_t unit, double* p0,
-                          double* p1) {
-    const int da[4] = {0, 1, 1, 0}, db[4] = {0, 0, 1, 1};
-    for (int k = 0; k < 4; ++k) {
-        const double x = ((double)(j + da[k]) - g.center_x_px) * g.pixel_x_m;
-        const double y = ((double)(i + db[k]) - g.center_y_px) * g.pixel_y_m;
-        if (p0) p0[k] = to_unit(std::sqrt(x * x + y * y), unit, g.dist_m, g.wavelength_m);
-        p1[k] = std::atan2(y, x);
-    }
-    for (int k = 1; k < 4; ++k)
-        p1[k] += std::nearbyint((p1[0] - p1[k]) / (2.0 * M_PI)) * (2.0 * M_PI);
-}
-
-inline int32_t wrap(int64_t k, int32_t n) { return (int32_t)(((k % n) + n) % n); }
-
-// Azimuthal shares of a pixel whose azimuth spans [clo, chi] (corner
-// extremes: along a straight edge missing the beam the azimuth is
-// monotone): wedges of width dchi from -pi, periodic; outer wedges get
-// their overlap over the span, inner ones 1 / span.  A pixel holding the
-// beam (whole) spreads evenly over all wedges.
-template <class Emit>
-inline void azimuth_shares(bool whole, double clo, double chi, int32_t nazim, double dchi,
-                           Emit&& emit) {
-    if (whole) {
-        for (int32_t k = 0; k < nazim; ++k) emit(k, 1.0 / nazim);
-        return;
-    }
-    const double gl = (clo + M_PI) / dchi;
-    const double gh = (chi + M_PI) / dchi;
-    const double width = gh - gl;
-    const int64_t k0 = (int64_t)std::floor(gl);
-    int64_t k1 = (int64_t)std::ceil(gh) - 1;
-    if (width == 0.0 || k1 < k0) k1 = k0;
-    for (int64_t k = k0; k <= k1; ++k) {
-        double c;
-        if (k0 == k1) c = 1.0;
-        else if (k == k0) c = ((double)(k0 + 1) - gl) / width;
-        else if (k == k1) c = (gh - (double)k1) / width;
-        else c = 1.0 / width;
-        if (c > 0.0) emit(wrap(k, nazim), c);
-    }
-}
-
-// Integral over [a, b] of clamp(y0 + (x - x0) * slope, t0, t1): the
-// interval is cut where the line meets t0 and t1, and the clamped line is
-// linear on every piece, so each piece is an exact trapezoid.
-inline double clamped_line(double x0, double y0, double slope, double a, double b, double t0,
-                           double t1) {
-    double cut[4];
-    int n = 0;
-    cut[n++] = a;
-    if (slope != 0.0) {
-        double xa = x0 + (t0 - y0) / slope, xb = x0 + (t1 - y0) / slope;
-        if (xa > xb) std::swap(xa, xb);
-        if (xa > a && xa < b) cut[n++] = xa;
-        if (xb > a && xb < b) cut[n++] = xb;
-    }
-    cut[n++] = b;
-    double s = 0.0;
-    for (int k = 0; k + 1 < n; ++k) {
-        const double u = cut[k], v = cut[k + 1];
-        const double yu = std::min(std::max(y0 + (u - x0) * slope, t0), t1);
-        const double yv = std::min(std::max(y0 + (v - x0) * slope, t0), t1);
-        s += (v - u) * (yu + yv) / 2.0;
-    }
-    return s;
-}
-
-// Area of the quadrilateral inside [e0, e1] x [t0, t1]: over every x of the
-// slab, the boundary's lower and upper crossings bound the section, and
-// clamp(upper) - clamp(lower) is the part of it inside [t0, t1]; summing the
-// clamped edge lines with the edge's direction as sign gives that total.
-inline double edge_integral_box(const Quad& q, double e0, double e1, double t0, double t1) {
-    double s = 0.0;
-    for (int k = 0; k < 4; ++k) {
-        const double ax = q.x[k], ay = q.y[k];
-        const double bx = q.x[(k + 1) & 3], by = q.y[(k + 1) & 3];
-        if (ax == bx) continue;
-        const double lo = std::max(std::min(ax, bx), e0);
-        const double hi = std::min(std::max(ax, bx), e1);
-        if (!(hi > lo)) continue;
-        const double part = clamped_line(ax, ay, (by - ay) / (bx - ax), lo, hi, t0, t1);
-        s += bx > ax ? part : -part;
-    }
-    return std::fabs(s);
-}
-
-// One pixel of two-dimensional integration; emit(row, coefficient) with
-// row = azimuthal wedge * nrad + radial bin.
-struct Grid2d {
-    double pmin, delta, dchi;
-    int32_t nrad, nazim;
-};
-
-template <class Emit>
-inline void bbox2d_pixel(int64_t i, int64_t j, const azi_geom& g, double lo, double hi,
-                         const Grid2d& G, std::vector<std::pair<int32_t, double>>& rad,
-                         Emit&& emit) {
-    rad.clear();
-    bbox_pixel(lo, hi, G.pmin, G.delta, G.nrad,
-               [&](int32_t b, double c) { rad.emplace_back(b, c); });
-    if (rad.empty()) return;
-    const bool whole = lo == 0.0;
-    double clo = 0.0, chi = 0.0;
-    if (!whole) {
-        double p1[4];
-        pixel_corners(i, j, g, AZI_UNIT_R_M, nullptr, p1);
-        clo = std::min(std::min(p1[0], p1[1]), std::min(p1[2], p1[3]));
-        chi = std::max(std::max(p1[0], p1[1]), std::max(p1[2], p1[3]));
-    }
-    azimuth_shares(whole, clo, chi, G.nazim, G.dchi, [&](int32_t k, double ac) {
-        for (const auto& e : rad) emit(k * G.nrad + e.first, e.second * ac);
-    });
-}
-
-template <class Emit>
-inline void full2d_pixel(int64_t i, int64_t j, const azi_geom& g, int32_t unit, double lo,
-                         double hi, const Grid2d& G,
-                         std::vector<std::pair<int32_t, double>>& rad, Emit&& emit) {
-    if (lo == 0.0) {  // the beam lies on this pixel
-        bbox2d_pixel(i, j, g, lo, hi, G, rad, emit);
-        return;
-    }
-    double p0[4], p1[4];
-    pixel_corners(i, j, g, unit, p0, p1);
-    const double mn = std::min(std::min(p0[0], p0[1]), std::min(p0[2], p0[3]));
-    const double mx = std::max(std::max(p0[0], p0[1]), std::max(p0[2], p0[3]));
-    const double cmn = std::min(std::min(p1[0], p1[1]), std::min(p1[2], p1[3]));
-    const double cmx = std::max(std::max(p1[0], p1[1]), std::max(p1[2], p1[3]));
-    Quad q;
-    for (int k = 0; k < 4; ++k) {
-        q.x[k] = p0[k] - p0[0];
-        q.y[k] = p1[k] - p1[0];
-    }
-    const double area = edge_integral(q, -HUGE_VAL, HUGE_VAL);
-    const double fl = (mn - G.pmin) / G.delta, fh = (mx - G.pmin) / G.delta;
-    if (area == 0.0 || fh == fl) return;
-    const int32_t b0 = std::max((int32_t)std::floor(fl), 0);
-    const int32_t b1 = std::min((int32_t)std::ceil(fh) - 1, G.nrad - 1);
-    const int64_t k0 = (int64_t)std::floor((cmn + M_PI) / G.dchi);
-    const int64_t k1 = std::max((int64_t)std::ceil((cmx + M_PI) / G.dchi) - 1, k0);
-    for (int32_t b = b0; b <= b1; ++b) {
-        const double e0 = (G.pmin + b * G.delta) - p0[0];
-        const double e1 = (G.pmin + (b + 1) * G.delta) - p0[0];
-        for (int64_t k = k0; k <= k1; ++k) {
-            const double t0 = (-M_PI + (double)k * G.dchi) - p1[0];
-            const double t1 = (-M_PI + (double)(k + 1) * G.dchi) - p1[0];
-            const double c = edge_integral_box(q, e0, e1, t0, t1) / area;
-            if (c > 0.0) emit(wrap(k, G.nazim) * G.nrad + b, c);
-        }
-    }
-}
-
-}  // namespace
-
 int build_matrix(const azi_geom& g, int32_t npt, int32_t npt_azim, int32_t unit, int32_t split,
                  const double* range2, HostMatrix& m, std::string& err) {
     const int64_t h = g.h, w = g.w, npix = h * w;
@@ -262,32 +102,13 @@ int build_matrix(const azi_geom& g, int32_t npt, int32_t npt_azim, int32_t unit,
         m.cdata.push_back(c);
     };
     const Grid2d G{pmin, delta, two_d ? (2.0 * M_PI) / npt_azim : 0.0, nrad, m.npt_azim};
-    std::vector<std::pair<int32_t, double>> rad, ents;
-    auto collect = [&](int32_t row, double c) { ents.emplace_back(row, c); };
     for (int64_t p = 0; p < npix; ++p) {
         if (two_d) {
-            // a pixel's entries in ascending row order
-            ents.clear();
+            // a pixel's entries come out in ascending row order
             const int64_t i = p / w, j = p % w;
-            if (split == AZI_SPLIT_BBOX) {
-                bbox2d_pixel(i, j, g, lo[p], hi[p], G, rad, collect);
-            } else if (split == AZI_SPLIT_FULL) {
-                full2d_pixel(i, j, g, unit, lo[p], hi[p], G, rad, collect);
-            } else {
-                const double fc = (lo[p] - pmin) / delta;
-                if (fc >= 0.0 && fc <= (double)nrad) {
-                    const double xc = ((double)j + 0.5 - g.center_x_px) * g.pixel_x_m;
-                    const double yc = ((double)i + 0.5 - g.center_y_px) * g.pixel_y_m;
-                    const int64_t k = (int64_t)std::floor((std::atan2(yc, xc) + M_PI) / G.dchi);
-                    collect(wrap(k, npt_azim) * nrad + std::min((int32_t)std::floor(fc), nrad - 1),
-                            1.0);
-                }
-            }
-            std::sort(ents.begin(), ents.end(),
-                      [](const std::pair<int32_t, double>& a, const std::pair<int32_t, double>& b) {
-                          return a.first < b.first;
-                      });
-            for (const auto& e : ents) push(e.first, e.second);
+            if (split == AZI_SPLIT_BBOX) bbox2d_entries(i, j, g, lo[p], hi[p], G, push);
+            else if (split == AZI_SPLIT_FULL) full2d_entries(i, j, g, unit, lo[p], hi[p], G, push);
+            else none2d_entry(i, j, g, (lo[p] - pmin) / delta, G, push);
         } else if (split == AZI_SPLIT_BBOX) {
             bbox_pixel(lo[p], hi[p], pmin, delta, npt, push);
         } else if (split == AZI_SPLIT_FULL) {

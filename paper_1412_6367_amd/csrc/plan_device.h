@@ -1,5 +1,5 @@
 // Device plan builder: launch wrappers (host side).  The builder forms the
-// same one-dimensional matrix as the host builder -- per-pixel extents,
+// same one- or two-dimensional matrix as the host builder -- per-pixel extents,
 // per-pixel entries in pixel-major order, then the bin-major order by a
 // stable sort on the bin -- with every bin decision taken by the same IEEE
 // operations (pixel_math.h, both sides compiled without contraction).
@@ -20,14 +20,15 @@ hipError_t launch_extents(const azi_geom& g, int32_t unit, int32_t split, double
 // out2 = {min of bmin, max of bmax} over n blocks.
 hipError_t launch_minmax(const double* bmin, const double* bmax, int64_t n, double* out2,
                          hipStream_t s);
-// Entries per pixel.
+// Entries per pixel.  npt radial bins; nazim > 0 builds the
+// two-dimensional rows (wedge * npt + radial bin) of nazim wedges.
 hipError_t launch_count(const azi_geom& g, int32_t unit, int32_t split, const double* lo,
-                        const double* hi, double pmin, double delta, int32_t npt, int32_t* count,
-                        hipStream_t s);
+                        const double* hi, double pmin, double delta, int32_t npt, int32_t nazim,
+                        int32_t* count, hipStream_t s);
 // Pixel-major entries: rowidx (bin), cdata (coefficient), pix (pixel id) at
 // colptr[p] .. colptr[p + 1].
 hipError_t launch_fill(const azi_geom& g, int32_t unit, int32_t split, const double* lo,
-                       const double* hi, double pmin, double delta, int32_t npt,
+                       const double* hi, double pmin, double delta, int32_t npt, int32_t nazim,
                        const int32_t* colptr, int32_t* rowidx, double* cdata, int32_t* pix,
                        hipStream_t s);
 

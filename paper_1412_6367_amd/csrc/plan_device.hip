@@ -1,5 +1,5 @@
-// Device plan builder kernels (one-dimensional plans, Sections 3.3, 4.1,
-// 4.2 and 5.2.1): per-pixel extents and entries as the host builder forms
+// Device plan builder kernels (one- and two-dimensional plans, Sections
+// 3.3, 4.1, 4.2 and 5.2.1): per-pixel extents and entries as the host builder forms
 // them, a scan for the pixel-major offsets, and a stable least-significant-
 // digit radix sort that turns the pixel-major entry list into the bin-major
 // (CSR) order and into the band order of the gather kernels.  Integer sums
@@ -70,11 +70,21 @@ __global__ void k_minmax(const double* bmin, const double* bmax, int64_t n, doub
     }
 }
 
-// The entries of pixel p, in ascending bin order, handed to emit(bin, c).
+// The entries of pixel p, in ascending bin (row) order, handed to
+// emit(bin, c).  nazim > 0: two-dimensional rows (wedge * npt + radial bin),
+// npt being the radial bins.
 template <class Emit>
 __device__ inline void pixel_entries(const azi_geom& g, int32_t unit, int32_t split, int64_t p,
                                      const double* lo, const double* hi, double pmin,
-                                     double delta, int32_t npt, Emit&& emit) {
+                                     double delta, int32_t npt, int32_t nazim, Emit&& emit) {
+    if (nazim > 0) {
+        const Grid2d G{pmin, delta, (2.0 * M_PI) / nazim, npt, nazim};
+        const int64_t i = p / g.w, j = p % g.w;
+        if (split == AZI_SPLIT_BBOX) bbox2d_entries(i, j, g, lo[p], hi[p], G, emit);
+        else if (split == AZI_SPLIT_FULL) full2d_entries(i, j, g, unit, lo[p], hi[p], G, emit);
+        else none2d_entry(i, j, g, (lo[p] - pmin) / delta, G, emit);
+        return;
+    }
     if (split == AZI_SPLIT_BBOX) {
         bbox_pixel(lo[p], hi[p], pmin, delta, npt, emit);
     } else if (split == AZI_SPLIT_FULL) {
@@ -86,25 +96,26 @@ __device__ inline void pixel_entries(const azi_geom& g, int32_t unit, int32_t sp
 }
 
 __global__ void k_count(azi_geom g, int32_t unit, int32_t split, const double* lo,
-                        const double* hi, double pmin, double delta, int32_t npt,
+                        const double* hi, double pmin, double delta, int32_t npt, int32_t nazim,
                         int32_t* count) {
     const int64_t npix = (int64_t)g.h * g.w;
     const int64_t p = (int64_t)blockIdx.x * kB + threadIdx.x;
     if (p >= npix) return;
     int32_t c = 0;
-    pixel_entries(g, unit, split, p, lo, hi, pmin, delta, npt, [&](int32_t, double) { ++c; });
+    pixel_entries(g, unit, split, p, lo, hi, pmin, delta, npt, nazim,
+                  [&](int32_t, double) { ++c; });
     count[p] = c;
 }
 
 __global__ void k_fill(azi_geom g, int32_t unit, int32_t split, const double* lo,
-                       const double* hi, double pmin, double delta, int32_t npt,
+                       const double* hi, double pmin, double delta, int32_t npt, int32_t nazim,
                        const int32_t* colptr, int32_t* rowidx, double* cdata, int32_t* pix) {
     const int64_t npix = (int64_t)g.h * g.w;
     const int64_t p = (int64_t)blockIdx.x * kB + threadIdx.x;
     if (p >= npix) return;
     int64_t k = colptr[p];
     const int64_t k1 = colptr[p + 1];
-    pixel_entries(g, unit, split, p, lo, hi, pmin, delta, npt, [&](int32_t b, double c) {
+    pixel_entries(g, unit, split, p, lo, hi, pmin, delta, npt, nazim, [&](int32_t b, double c) {
         if (k < k1) {
             rowidx[k] = b;
             cdata[k] = c;
@@ -330,23 +341,23 @@ hipError_t launch_minmax(const double* bmin, const double* bmax, int64_t n, doub
 }
 
 hipError_t launch_count(const azi_geom& g, int32_t unit, int32_t split, const double* lo,
-                        const double* hi, double pmin, double delta, int32_t npt, int32_t* count,
-                        hipStream_t s) {
+                        const double* hi, double pmin, double delta, int32_t npt, int32_t nazim,
+                        int32_t* count, hipStream_t s) {
     const int64_t npix = (int64_t)g.h * g.w;
     if (!grid_fits(npix)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_count, dim3(blocks_for(npix)), dim3(kB), 0, s, g, unit, split, lo, hi,
-                       pmin, delta, npt, count);
+                       pmin, delta, npt, nazim, count);
     return hipGetLastError();
 }
 
 hipError_t launch_fill(const azi_geom& g, int32_t unit, int32_t split, const double* lo,
-                       const double* hi, double pmin, double delta, int32_t npt,
+                       const double* hi, double pmin, double delta, int32_t npt, int32_t nazim,
                        const int32_t* colptr, int32_t* rowidx, double* cdata, int32_t* pix,
                        hipStream_t s) {
     const int64_t npix = (int64_t)g.h * g.w;
     if (!grid_fits(npix)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_fill, dim3(blocks_for(npix)), dim3(kB), 0, s, g, unit, split, lo, hi,
-                       pmin, delta, npt, colptr, rowidx, cdata, pix);
+                       pmin, delta, npt, nazim, colptr, rowidx, cdata, pix);
     return hipGetLastError();
 }
 

@@ -123,3 +123,127 @@ def test_device_plan_c2_size(dev):
     say(f"host build {t1 - t0:.3f} s, device build {t2 - t1:.3f} s")
     for a, b in zip(hp.export_csr() + hp.export_csc(), dp.export_csr() + dp.export_csc()):
         assert np.array_equal(a, b)
+
+
+GEOMS2D = [
+    # h, w, center_y, center_x, npt_rad, npt_azim, unit, split, dtype
+    (100, 100, 50.0, 50.0, 40, 36, "r_m", "bbox", "f64"),
+    (64, 48, -5.0, 70.0, 30, 8, "r_m", "bbox", "f64"),       # beam off the detector
+    (37, 53, 10.25, 40.5, 25, 12, "r_m", "none", "f64"),
+    (120, 130, 60.2, 64.9, 50, 24, "r_m", "full", "f64"),
+    (90, 70, -10.0, 35.0, 40, 16, "q_nm", "full", "f64"),
+    (31, 29, 15.5, 14.5, 20, 2, "r_m", "bbox", "f32"),       # two wedges: raw wedges tie
+    (45, 45, 22.5, 22.5, 15, 3, "2th_deg", "bbox", "f64"),
+    (1, 17, 0.5, 8.5, 5, 4, "r_mm", "bbox", "f64"),
+]
+
+
+@pytest.mark.parametrize("g", GEOMS2D, ids=lambda g: f"{g[0]}x{g[1]}-{g[6]}-{g[7]}-{g[4]}x{g[5]}")
+def test_device_plan2d_matches_host_and_oracle(g, dev):
+    """Two-dimensional plans built on the device: the same rows and
+    coefficients as the host builder up to the device atan2's last bits (a
+    wedge-edge coefficient to rounding, a sliver entry of a few ulps that one
+    side keeps and the other does not), and integration like the oracle."""
+    h, w, cy, cx, nr, na, unit, split, dt = g
+    say("device build 2d", g)
+    az = azint()
+    dtype = torch.float64 if dt == "f64" else torch.float32
+    kw = dict(npt_azim=na, center=(cy, cx), unit=unit, split=split, dtype=dtype)
+    hp = az.Plan(h, w, nr, device=dev, **kw)
+    dp = az.Plan.on_device(h, w, nr, device=dev, **kw)
+    assert dp.shape() == hp.shape() == (nr, na)
+    assert dp.layout() == "pixel"
+    ih, idv = hp.info(), dp.info()
+    assert idv["npt"] == nr * na and idv["npix"] == h * w
+    if unit in ("r_m", "r_mm"):
+        assert idv["range"] == ih["range"]
+    dh, dd = hp.export_csr(), dp.export_csr()
+    A = dense(dh, (nr * na, h * w))
+    B = dense(dd, (nr * na, h * w))
+    tol = 1e-12 if unit in ("r_m", "r_mm") else 1e-9
+    assert np.abs(A - B).max() <= tol
+    # entries on one side only are slivers
+    only = (A != 0) ^ (B != 0)
+    assert np.abs(A[only]).max(initial=0.0) <= tol and np.abs(B[only]).max(initial=0.0) <= tol
+    # entries both keep agree to rounding, absolutely (a share cut close to
+    # a wedge edge is the difference of nearby values, so its relative error
+    # is larger); bit for bit where no corner's atan2 differs
+    both = (A != 0) & (B != 0)
+    say(f"entries bit-equal: {(A[both] == B[both]).mean():.4f}, one side only: {only.sum()}")
+    # per-pixel entries stay in ascending rows (the CSC export)
+    _, rows, colptr = dp.export_csc()
+    for p in range(h * w):
+        r = rows[colptr[p]:colptr[p + 1]]
+        assert np.all(np.diff(r) >= 0), p
+    # integration: like the oracle (the host-built plan is checked against
+    # it elsewhere), and like the host-built plan
+    m = az_oracle2d(h, w, cy, cx, nr, na, unit, split)
+    x = np.random.default_rng(h * w + na).uniform(-2.0, 1000.0, size=h * w)
+    xt = torch.from_numpy(x.astype(np.float64 if dt == "f64" else np.float32)).to(dev)
+    out = dp.integrate(xt, empty=-1.5)
+    torch.cuda.synchronize()
+    tolI = TOL64 if dt == "f64" else 1e-6
+    xo = x if dt == "f64" else x.astype(np.float32).astype(np.float64)
+    if unit in ("r_m", "r_mm") and split != "full":
+        check(out, m, xo, tolI, empty=-1.5, what=str(g))
+    else:
+        # full splitting clips the quadrilateral by the wedges in differences
+        # of corner azimuths (~1e-3 rad across a pixel) taken from atan2
+        # values of order 1, and 2theta / q pass through atan and sin: an ulp
+        # of the device functions against the C library's moves a coefficient
+        # by up to ~1e-12 relative and can add or drop a sliver entry (which
+        # can turn an empty bin into a non-empty one).  The matrix is held to
+        # the host builder's above; the integration is checked against the
+        # oracle's sums over the device-built matrix itself.
+        data, idx, ptr = dd
+        md = dict(npt=nr * na, pix=idx.astype(np.int64),
+                  bins=np.repeat(np.arange(nr * na), np.diff(ptr)),
+                  coef=data.astype(np.float64))
+        check(out, md, xo, tolI, empty=-1.5, what=str(g))
+
+
+def az_oracle2d(h, w, cy, cx, nr, na, unit, split):
+    import oracle
+    return oracle.build_matrix2d(h=h, w=w, pixel_y=1e-4, pixel_x=1e-4, center_y=cy, center_x=cx,
+                                 dist=0.1, wavelength=1e-10, npt_rad=nr, npt_azim=na, unit=unit,
+                                 split=split)
+
+
+def test_device_plan2d_c2_size(dev):
+    """The 10-Mpixel detector in 1000 x 360 bins: the device-built plan
+    integrates like the host-built one and both build times are printed.
+    Every coefficient of the two plans agrees to 1e-12 absolutely (the small
+    cases above), so a bin's U and W may differ by 1e-12 per entry of the bin
+    (times the largest pixel value for W): relatively more than the FP64
+    tolerance in bins near the beam, whose U is a few small shares."""
+    say("device build 2d c2")
+    az = azint()
+    inst = synth.instance(synth.C2["n"], synth.C2["seed"])
+    g = inst.geom
+    t0 = time.perf_counter()
+    hp = az.Plan(g.h, g.w, 1000, npt_azim=360, center=(g.center_y, g.center_x), device=dev)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dp = az.Plan.on_device(g.h, g.w, 1000, npt_azim=360, center=(g.center_y, g.center_x),
+                           device=dev)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    say(f"2-D host build + upload {t1 - t0:.3f} s, device build {t2 - t1:.3f} s, "
+        f"nnz host {hp.nnz} device {dp.nnz}")
+    assert abs(dp.nnz - hp.nnz) <= 1e-4 * hp.nnz
+    x = torch.from_numpy(inst.raw.reshape(-1).astype(np.float64)).to(dev)
+    Ih, Wh, Uh = (a.cpu().numpy() for a in hp.integrate(x))
+    Id, Wd, Ud = (a.cpu().numpy() for a in dp.integrate(x))
+    torch.cuda.synchronize()
+    nb = np.diff(hp.export_csr()[2]).astype(np.float64)
+    xmax = float(inst.raw.max())
+    nz = Uh > 0
+    assert np.array_equal(nz, Ud > 0)
+    assert np.all(np.abs(Ud - Uh) <= 1e-12 * nb)
+    assert np.all(np.abs(Wd - Wh) <= 1e-12 * nb * xmax)
+    # bins away from the beam (U of at least one whole pixel share) agree
+    # to the FP64 tolerance
+    big = Uh >= 1.0
+    assert big.sum() > 100_000
+    assert np.max(np.abs(Ud - Uh)[big] / Uh[big]) <= TOL64
+    say(f"largest relative U difference {np.max(np.abs(Ud - Uh)[nz] / Uh[nz]):.2e}")
