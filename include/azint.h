@@ -222,7 +222,7 @@ int azi_plan_export_csc(const azi_plan* plan, void* data, int32_t* bins, int32_t
  * new plan starts at tile_nnz 4096, block 256, variant 5, grid 0, band 16,
  * stage AZI_STAGE_FOLD; below 2^22 nonzeros at tile_nnz 2048 (plans built
  * on the device, which start in the band layout: band 4;
- * two-dimensional plans: 4096, 256, 2, 0, 1, AZI_STAGE_GATHER).
+ * two-dimensional plans: 4096, 256, 1, 0, 1, AZI_STAGE_GATHER).
  *   tile_nnz  most nonzeros one workgroup sums per tile (64..16384, a
  *             multiple of 64); rows longer than that are cut into pieces
  *             whose sums are added in order by a small fix-up kernel.

@@ -146,11 +146,10 @@ constexpr int64_t kSmallNnz = (int64_t)1 << 22;
 
 void size_default_tiling(azi_plan* p);
 // Two-dimensional plans (short rows, CSR layout): lane-strided loads of
-// whole rows, 8 deep, pixel ids through the caches and coefficients
-// non-temporal (71 us warm, 108 us cold for 1000 x 360 bins of a ~1e7-pixel
-// frame; 79 / 103 us with the whole matrix non-temporal, 70 / 124 us with
-// all of it cached).
-constexpr azi_tiling kDefaultTiling2d = {4096, 256, 2, 0, 1, AZI_STAGE_GATHER};
+// whole rows, 4 deep, all through the caches (70 us back to back, 82 us
+// after a 1 GiB read-only flush for 1000 x 360 bins of a ~1e7-pixel frame;
+// 70 / 86 us with the coefficients non-temporal and 8 deep).
+constexpr azi_tiling kDefaultTiling2d = {4096, 256, 1, 0, 1, AZI_STAGE_GATHER};
 
 // Converts double coefficients to the storage type into a padded buffer.
 std::vector<char> to_storage(const double* src, int64_t n, int64_t n_alloc, int32_t dtype) {
@@ -2265,7 +2264,7 @@ int azi_plan_autotune(azi_plan* p, const void* x, void* I, void* W, void* U, voi
         if (relayout || layout == p->layout) cands.push_back(Cand{layout, {tn, bl, var, 0, band, st}});
     };
     if (p->m.two_d) {
-        for (int32_t var : {2, 3, 5})
+        for (int32_t var : {1, 2, 3, 5})
             for (int32_t tn : {2048, 4096, 8192})
                 for (int32_t bl : {128, 256}) add(AZI_LAYOUT_PIXEL, tn, bl, var, 1);
         add(AZI_LAYOUT_RUN, 4096, 128, 5, 4);
