@@ -219,13 +219,23 @@ int azi_plan_export_csc(const azi_plan* plan, void* data, int32_t* bins, int32_t
  * Launch and tile schedule of the forward kernel (tuning only: results
  * change at most in the order of the floating-point additions, and, for
  * the stage, by the one rounding of the fused or folded correction).  A
- * new plan starts at tile_nnz 4096, block 256, variant 5, grid 0, band 16,
- * stage AZI_STAGE_FOLD; below 2^22 nonzeros at tile_nnz 2048 (plans built
- * on the device, which start in the band layout: band 4;
- * two-dimensional plans: 4096, 256, 1, 0, 1, AZI_STAGE_GATHER).
+ * new plan starts at tile_nnz 0, block 256, variant 5, grid 0, band 16,
+ * stage AZI_STAGE_FOLD (plans built on the device, which start in the band
+ * layout: band 4; two-dimensional plans: 4096, 256, 1, 0, 1,
+ * AZI_STAGE_GATHER); a new batch at the same tiling.
  *   tile_nnz  most nonzeros one workgroup sums per tile (64..16384, a
  *             multiple of 64); rows longer than that are cut into pieces
  *             whose sums are added in order by a small fix-up kernel.
+ *             0: sized by the library.  Run layout with band 16 or 32
+ *             (one-dimensional or 2-D plans): each group of bands' common
+ *             stretches are cut so that no band has more than a bound of
+ *             runs in one, the stretches of a group as even as their number
+ *             allows, with the smallest bound that keeps the workgroups
+ *             within k rounds of what the device holds at once (CUs x 8 for
+ *             band 16, x 4 for band 32), k the fewest rounds whose bound is
+ *             2048 runs or less: every resident workgroup takes about the
+ *             same work.  Other layouts, and every layout of a batch: 2048
+ *             below 2^22 nonzeros (of the instance, in a batch), else 4096.
  *   block     threads per workgroup: 64, 128, 256 or 512.
  *   variant   load scheme, 0..AZI_NUM_VARIANTS-1: 0 four consecutive
  *             nonzeros per lane, 2 loads in flight; 4 the same with 4 in
@@ -298,7 +308,9 @@ int azi_plan_tile_schedule(const azi_plan* plan, const azi_tiling* tiling, int32
                            int32_t* tiles, int32_t* nsplits, int32_t* splits);
 
 /* Host-side view of the run encoding (AZI_LAYOUT_RUN) of a one-dimensional
- * or 2-D plan's matrix with pieces of tile_nnz / 2 runs (no device needed;
+ * or 2-D plan's matrix with pieces of tile_nnz / 2 runs (tile_nnz 0: sized
+ * as the tiling's tile_nnz 0 sizes them on the plan's device, or on 256 CUs
+ * for a plan without one; no device needed;
  * for inspection and tests).  Host buffers, any of them NULL to skip:
  *   runs[nruns]      pixel | first row in the band << 27 | (count - 1) << 29
  *                    per run, -1 for the padding that starts every band on a
@@ -315,8 +327,8 @@ int azi_plan_tile_schedule(const azi_plan* plan, const azi_tiling* tiling, int32
  *   bin_slot[npt], bin_count[npt]  each bin's first partial slot and count
  *                    (slots first, first + 4, ...).
  * nruns / npieces (may be NULL) receive the counts.  AZI_EOVERFLOW for
- * images of 2^27 pixels or more, AZI_EINVAL for a tile_nnz outside
- * [64, 16384]. */
+ * images of 2^27 pixels or more, AZI_EINVAL for a tile_nnz other than 0
+ * outside [64, 16384]. */
 int azi_plan_run_schedule(const azi_plan* plan, int32_t tile_nnz, int64_t* nruns, int32_t* runs,
                           int32_t* gbase, double* coef, int32_t* npieces, int32_t* pieces,
                           int32_t* bin_slot, int32_t* bin_count);

@@ -54,7 +54,7 @@ class Tiling(ctypes.Structure):
 
 
 STAGES = {"gather": 0, "scatter": 1, "tile": 2, "fuse": 3, "fold": 4}
-DEFAULT_TILING = dict(tile_nnz=4096, block=256, variant=5, grid=0, band=16, stage=4)
+DEFAULT_TILING = dict(tile_nnz=0, block=256, variant=5, grid=0, band=16, stage=4)
 
 
 def _tiling(cur=None, **kw):

@@ -115,14 +115,46 @@ size_t elem_size_any(int32_t dtype) {
 }
 
 const char* kTilingRule =
-    "tiling: tile_nnz a multiple of 64 in [64, 16384], block one of 64/128/256/512, variant in "
-    "[0, AZI_NUM_VARIANTS), grid >= 0, band >= 0, stage one of AZI_STAGE_*";
+    "tiling: tile_nnz 0 or a multiple of 64 in [64, 16384], block one of 64/128/256/512, variant "
+    "in [0, AZI_NUM_VARIANTS), grid >= 0, band >= 0, stage one of AZI_STAGE_*";
 
 bool valid_tiling(const azi_tiling& t) {
-    return t.tile_nnz >= 64 && t.tile_nnz <= 16384 && t.tile_nnz % 64 == 0 &&
+    return (t.tile_nnz == 0 || (t.tile_nnz >= 64 && t.tile_nnz <= 16384 && t.tile_nnz % 64 == 0)) &&
            (t.block == 64 || t.block == 128 || t.block == 256 || t.block == 512) &&
            t.variant >= 0 && t.variant < azi::kNumVariants && t.grid >= 0 && t.band >= 0 &&
            t.stage >= AZI_STAGE_GATHER && t.stage <= AZI_STAGE_FOLD;
+}
+
+// Below ~4e6 nonzeros (a ~1e6-pixel frame) there are too few 4096-entry
+// pieces to fill 256 CUs: 2048 entries (18 us against 21 us at 1e6 pixels).
+constexpr int64_t kSmallNnz = (int64_t)1 << 22;
+
+// Nonzeros per piece of a tiling over `nnz` nonzeros: tile_nnz, or for a
+// tiling sized by the library (tile_nnz 0) 2048 below kSmallNnz and 4096
+// above wherever the pieces are not sized from the device.
+// (Batches size each instance's pieces by its own nonzeros, as its plan
+// would; the co-scheduled run bands of a batch take these fixed pieces too,
+// the rounds of a balanced tiling being those of one plan's launch.)
+int32_t piece_nnz(const azi_tiling& t, int64_t nnz) {
+    return t.tile_nnz > 0 ? t.tile_nnz : nnz < kSmallNnz ? 2048 : 4096;
+}
+
+// Workgroups of one round of a balanced tiling (tile_nnz 0) of a plan's
+// co-scheduled run bands: as many as the device keeps resident at once,
+// workgroups of `waves` wavefronts at 8 per SIMD (the run kernels'
+// occupancy).  The schedule is cut into the fewest such rounds that keep a
+// band's stretch within 2048 runs, each workgroup taking as nearly the same
+// work as the bands allow (the ~1e7-pixel frame: one round; 2048^2, 4096^2
+// and off-centre frames: 27-36 % faster than pieces of 2048 runs but for
+// 4096^2, two rounds, 10 %).  None for the other layouts (0).  Without a
+// device, MI355X's 256 CUs.
+int64_t balanced_tiles(const azi_tiling& t, int device, int32_t waves) {
+    if (t.tile_nnz != 0 || waves <= 1) return 0;
+    int ncu = 256;
+    if (device >= 0 && hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount,
+                                              device) != hipSuccess)
+        ncu = 256;
+    return (int64_t)ncu * 32 / waves;
 }
 
 // Stages whose raw-frame path corrects each pixel in the band gather.
@@ -131,20 +163,16 @@ bool gather_corrects(int32_t stage) {
 }
 
 // Fastest measured on the ~1e7-pixel, 3162-bin workload: run layout with
-// four neighbouring bands of 4 bins per workgroup, pieces of 2048 runs
-// (tile_nnz 4096), raw frames corrected in the gather with 1 / norm folded
-// into the coefficients and dark stored per run (float64: 90 us warm and
-// cold against 106 / 116 us with one band per workgroup and the (dark,
-// 1 / norm) pair gathered per pixel).
-constexpr azi_tiling kDefaultTiling = {4096, 256, 5, 0, 16, AZI_STAGE_FOLD};
-constexpr azi_tiling kDefaultTiling32 = {4096, 256, 5, 0, 16, AZI_STAGE_FOLD};
-// Below ~4e6 nonzeros (a ~1e6-pixel frame) there are too few 4096-entry
-// pieces to fill 256 CUs: 2048 entries (18 us against 21 us at 1e6 pixels).
-// The workgroup stays at 256 threads, the raw-frame band kernel's, so the
-// raw and corrected-image entry points sum in the same order.
-constexpr int64_t kSmallNnz = (int64_t)1 << 22;
-
-void size_default_tiling(azi_plan* p);
+// four neighbouring bands of 4 bins per workgroup, the pieces sized by the
+// library (balanced rounds of resident workgroups), raw frames corrected in
+// the gather with 1 / norm folded into the coefficients and dark stored per
+// run (float64: 85 / 88 us warm / flushed, against 86 / 89 us for pieces of
+// 2048 runs and 106 / 116 us with one band per workgroup and the (dark,
+// 1 / norm) pair gathered per pixel).  The workgroup stays at 256 threads,
+// the raw-frame band kernel's, so the raw and corrected-image entry points
+// sum in the same order.
+constexpr azi_tiling kDefaultTiling = {0, 256, 5, 0, 16, AZI_STAGE_FOLD};
+constexpr azi_tiling kDefaultTiling32 = {0, 256, 5, 0, 16, AZI_STAGE_FOLD};
 // Two-dimensional plans (short rows, CSR layout): lane-strided loads of
 // whole rows, 4 deep, all through the caches (70 us back to back, 82 us
 // after a 1 GiB read-only flush for 1000 x 360 bins of a ~1e7-pixel frame;
@@ -249,7 +277,8 @@ int plan_upload_tiles(azi_plan* p) {
     std::vector<azi::Tile> tiles;
     std::vector<azi::Split> splits;
     int32_t nparts = 0;
-    azi::build_tiles(p->m.indptr.data(), p->m.npt, 0, 0, 0, p->tiling.tile_nnz, p->tiling.band,
+    azi::build_tiles(p->m.indptr.data(), p->m.npt, 0, 0, 0, piece_nnz(p->tiling, p->m.nnz()),
+                     p->tiling.band,
                      tiles, splits, nparts);
     AZI_HIP(p->tiles.upload(tiles.data(), tiles.size() * sizeof(azi::Tile), p->device), "tiles");
     AZI_HIP(p->splits.upload(splits.data(), splits.size() * sizeof(azi::Split), p->device),
@@ -271,8 +300,9 @@ int batch_upload_tiles(azi_batch* b, const std::vector<const int32_t*>& indptrs,
     for (int32_t k = 0; k < b->n; ++k) {
         b->tile_off[k] = (int64_t)tiles.size();
         b->split_off[k] = (int64_t)splits.size();
+        const int64_t nnz_k = (int64_t)indptrs[k][npts[k]] - indptrs[k][0];
         azi::build_tiles(indptrs[k], npts[k], b->nz_off[k], b->bin_off[k], b->ip_off[k],
-                         b->tiling.tile_nnz, b->tiling.band, tiles, splits, nparts);
+                         piece_nnz(b->tiling, nnz_k), b->tiling.band, tiles, splits, nparts);
     }
     b->tile_off[b->n] = (int64_t)tiles.size();
     b->split_off[b->n] = (int64_t)splits.size();
@@ -370,8 +400,10 @@ int plan_upload_bands(azi_plan* p) {
     if (p->layout == AZI_LAYOUT_RUN) {
         try {
             azi::RunMatrix rm;
-            if (!azi::build_runs(p->m, std::max(64, p->tiling.tile_nnz / 2), 0, 0, rm, nullptr,
-                                 run_waves(p->tiling)))
+            if (!azi::build_runs(p->m, std::max(64, piece_nnz(p->tiling, p->m.nnz()) / 2), 0, 0, rm,
+                                 nullptr,
+                                 run_waves(p->tiling),
+                                 balanced_tiles(p->tiling, p->device, run_waves(p->tiling))))
                 return fail(AZI_EOVERFLOW,
                             "the run layout takes images below 2^27 pixels and 2^31 entries");
             azi::BandMatrix bm;
@@ -396,7 +428,7 @@ int plan_upload_bands(azi_plan* p) {
     try {
         azi::BandMatrix bm;
         p->band_rows = band_rows_of(p->tiling);
-        if (!azi::build_bands(p->m, p->band_rows, p->tiling.tile_nnz, 0, 0, bm))
+        if (!azi::build_bands(p->m, p->band_rows, piece_nnz(p->tiling, p->m.nnz()), 0, 0, bm))
             return fail(AZI_EOVERFLOW, "the band layout takes images below 2^27 pixels");
         int rc = upload_bands(bm, p->dtype, p->device, p->npieces_buf, p->npacked, p->ncoef,
                               p->bin_slot, p->bin_count, p->nparts_buf, p->max_count);
@@ -565,7 +597,7 @@ int plan_fold(azi_plan* p, hipStream_t s) {
             if (rc != AZI_OK) return rc;
         }
         azi::RunMatrix rm;
-        if (!azi::build_runs(p->m, std::max(64, p->tiling.tile_nnz / 2), 0, 0, rm,
+        if (!azi::build_runs(p->m, std::max(64, piece_nnz(p->tiling, p->m.nnz()) / 2), 0, 0, rm,
                              p->has_norm ? inv.data() : nullptr, run_waves(p->tiling)))
             return fail(AZI_EOVERFLOW,
                         "the run layout takes images below 2^27 pixels and 2^31 entries");
@@ -788,7 +820,6 @@ int plan_create(const azi_geom* geom, int32_t npt, int32_t npt_azim, int32_t uni
         return fail(AZI_ENOMEM, "out of host memory building the matrix");
     }
     if (rc != AZI_OK) return fail(rc, err);
-    size_default_tiling(p.get());
     // the run layout numbers pixels in 27 bits; larger images take the CSR
     p->layout = p->m.npix < ((int64_t)1 << azi::kBandShift) ? AZI_LAYOUT_RUN : AZI_LAYOUT_PIXEL;
     if (p->m.two_d) {
@@ -801,9 +832,6 @@ int plan_create(const azi_geom* geom, int32_t npt, int32_t npt_azim, int32_t uni
     return AZI_OK;
 }
 
-void size_default_tiling(azi_plan* p) {
-    if (!p->m.two_d && p->m.nnz() < kSmallNnz) p->tiling.tile_nnz = 2048;
-}
 
 int bit_length(int64_t v) {
     int b = 0;
@@ -855,7 +883,7 @@ int plan_device_bands(azi_plan* p, const int32_t* rowidx, const int32_t* pix, co
         for (int32_t b = 0; b < nbands; ++b) start[b] = p->m.indptr[(size_t)b * R];
         start[nbands] = nnz;
         azi::BandMatrix bm;
-        azi::band_pieces(start.data(), nbands, npt, R, p->tiling.tile_nnz, 0, 0, 0, bm);
+        azi::band_pieces(start.data(), nbands, npt, R, piece_nnz(p->tiling, nnz), 0, 0, 0, bm);
         AZI_HIP(p->npieces_buf.upload(bm.pieces.data(), bm.pieces.size() * sizeof(azi::BandPiece),
                                       dev), "band pieces");
         AZI_HIP(p->bin_slot.upload(bm.bin_slot.data(), bm.bin_slot.size() * 4, dev), "bin slots");
@@ -933,7 +961,6 @@ int plan_build_device(azi_plan* p, int32_t npt, int32_t npt_azim, const double* 
     if (nnz >= (int64_t)INT32_MAX - 2 * kPad)
         return fail(AZI_EOVERFLOW, "matrix has 2^31 nonzeros or more");
     cnt.release();
-    if (nnz < kSmallNnz) p->tiling.tile_nnz = 2048;
     const int64_t nnz_alloc = round_up(nnz, kPad) + kPad;
     const size_t es = elem_size(p->dtype);
     const size_t n1 = (size_t)std::max<int64_t>(nnz, 1);
@@ -1148,7 +1175,8 @@ int azi_plan_tile_schedule(const azi_plan* p, const azi_tiling* tl, int32_t* nti
     std::vector<azi::Tile> t;
     std::vector<azi::Split> sp;
     int32_t nparts = 0;
-    azi::build_tiles(p->m.indptr.data(), p->m.npt, 0, 0, 0, tl->tile_nnz, tl->band, t, sp, nparts);
+    azi::build_tiles(p->m.indptr.data(), p->m.npt, 0, 0, 0, piece_nnz(*tl, p->m.nnz()), tl->band,
+                     t, sp, nparts);
     if (ntiles) *ntiles = (int32_t)t.size();
     if (nsplits) *nsplits = (int32_t)sp.size();
     if (tiles) std::memcpy(tiles, t.data(), t.size() * sizeof(azi::Tile));
@@ -1160,11 +1188,14 @@ int azi_plan_run_schedule(const azi_plan* p, int32_t tile_nnz, int64_t* nruns, i
                           int32_t* gbase, double* coef, int32_t* npieces, int32_t* pieces,
                           int32_t* bin_slot, int32_t* bin_count) {
     if (!p) return fail(AZI_EINVAL, "plan is NULL");
-    if (tile_nnz < 64 || tile_nnz > 16384) return fail(AZI_EINVAL, "tile_nnz must be in [64, 16384]");
+    if (tile_nnz != 0 && (tile_nnz < 64 || tile_nnz > 16384))
+        return fail(AZI_EINVAL, "tile_nnz must be 0 or in [64, 16384]");
     try {
         azi::RunMatrix rm;
-        if (!azi::build_runs(p->m, std::max(64, tile_nnz / 2), 0, 0, rm, nullptr,
-                             run_waves(p->tiling)))
+        azi_tiling tl = p->tiling;
+        tl.tile_nnz = tile_nnz;
+        if (!azi::build_runs(p->m, std::max(64, piece_nnz(tl, p->m.nnz()) / 2), 0, 0, rm, nullptr,
+                             run_waves(tl), balanced_tiles(tl, p->device, run_waves(tl))))
             return fail(AZI_EOVERFLOW,
                         "the run layout takes images below 2^27 pixels and 2^31 entries");
         if (nruns) *nruns = (int64_t)rm.runs.size();
@@ -1846,8 +1877,9 @@ int batch_build_bands(azi_batch* b, const std::vector<const azi::HostMatrix*>& m
         b->piece_off.assign(b->n + 1, 0);
         for (int32_t k = 0; k < b->n; ++k) {
             b->piece_off[k] = (int64_t)rm.pieces.size();
-            if (!azi::build_runs(*ms[k], std::max(64, b->tiling.tile_nnz / 2), b->pix_off[k],
-                                 b->bin_off[k], rm, nullptr, run_waves(b->tiling)))
+            if (!azi::build_runs(*ms[k], std::max(64, piece_nnz(b->tiling, ms[k]->nnz()) / 2),
+                                 b->pix_off[k], b->bin_off[k], rm, nullptr,
+                                 run_waves(b->tiling)))
                 return fail(AZI_EOVERFLOW,
                             "the run layout takes images below 2^27 pixels and 2^31 runs and "
                             "entries per batch");
@@ -1872,7 +1904,8 @@ int batch_build_bands(azi_batch* b, const std::vector<const azi::HostMatrix*>& m
     b->piece_off.assign(b->n + 1, 0);
     for (int32_t k = 0; k < b->n; ++k) {
         b->piece_off[k] = (int64_t)bm.pieces.size();
-        if (!azi::build_bands(*ms[k], b->band_rows, b->tiling.tile_nnz, b->pix_off[k],
+        if (!azi::build_bands(*ms[k], b->band_rows, piece_nnz(b->tiling, ms[k]->nnz()),
+                              b->pix_off[k],
                               b->bin_off[k], bm))
             return fail(AZI_EOVERFLOW, "the band layout takes images below 2^27 pixels");
     }
@@ -2268,12 +2301,13 @@ int azi_plan_autotune(azi_plan* p, const void* x, void* I, void* W, void* U, voi
             for (int32_t tn : {2048, 4096, 8192})
                 for (int32_t bl : {128, 256}) add(AZI_LAYOUT_PIXEL, tn, bl, var, 1);
         add(AZI_LAYOUT_RUN, 4096, 128, 5, 4);
+        add(AZI_LAYOUT_RUN, 0, 256, 5, 16);
     } else {
         const bool runs_ok = p->m.npix < ((int64_t)1 << azi::kBandShift);
         if (runs_ok) {
             for (int32_t tn : {2048, 4096, 8192})
                 for (int32_t bl : {128, 256}) add(AZI_LAYOUT_RUN, tn, bl, 5, 4);
-            for (int32_t tn : {2048, 4096, 8192})
+            for (int32_t tn : {0, 2048, 4096, 8192})
                 for (int32_t band : {16, 32}) add(AZI_LAYOUT_RUN, tn, 256, 5, band);
             for (int32_t tn : {2048, 4096})
                 for (int32_t band : {4, 8}) add(AZI_LAYOUT_BAND, tn, 256, 5, band);

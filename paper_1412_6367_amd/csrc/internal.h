@@ -202,12 +202,20 @@ struct RunMatrix {
 // waves > 1: the pieces are instead cut for workgroups of `waves`
 // neighbouring bands over common stretches of image rows: entry
 // t * waves + w of rm.pieces is band w of workgroup t (z0 == z1 and slot0 ==
-// -1 past the last band).  The rows of a stretch end where the group's
-// longest band has a piece boundary (pieces of at most piece_runs runs);
-// every band's runs are cut on multiples of 64 at the first group of 64 runs
-// whose first pixel lies in the next stretch.
+// -1 past the last band).  Each band's runs are cut on multiples of 64: a
+// group of 64 runs belongs to the stretch that holds its first pixel.  The
+// stretches are cut in pixel order so that no band has more than a bound of
+// groups of 64 runs in one (the greedy cut, which gives the fewest
+// stretches), then made as even as their number allows (the smallest bound
+// giving no more).  The bound is piece_runs / 64 groups or, with
+// round_tiles > 0 (the workgroups a device keeps resident at once), the
+// smallest that keeps the instance's workgroups within k * round_tiles, for
+// the fewest rounds k that bring the bound to kRoundRuns runs or less: each
+// round's workgroups then take as nearly the same work as the bands allow.
+constexpr int64_t kRoundRuns = 2048;
 bool build_runs(const HostMatrix& m, int32_t piece_runs, int64_t pix_off, int64_t bin_off,
-                RunMatrix& rm, const double* scale = nullptr, int32_t waves = 1);
+                RunMatrix& rm, const double* scale = nullptr, int32_t waves = 1,
+                int64_t round_tiles = 0);
 
 // Matrix-free ("fused") schedule: the image cut into kFusedH x kFusedW
 // tiles; tile t feeds the bin window [wlo, wlo + nwin) and writes the partial

@@ -317,7 +317,7 @@ void band_pieces(const int64_t* start, int32_t nbands, int32_t npt, int32_t R, i
 }
 
 bool build_runs(const HostMatrix& m, int32_t piece_runs, int64_t pix_off, int64_t bin_off,
-                RunMatrix& rm, const double* scale, int32_t waves) {
+                RunMatrix& rm, const double* scale, int32_t waves, int64_t round_tiles) {
     constexpr int32_t R = kRunRows;
     if (m.npix >= ((int64_t)1 << kBandShift)) return false;
     const int32_t npt = m.npt;
@@ -381,20 +381,96 @@ bool build_runs(const HostMatrix& m, int32_t piece_runs, int64_t pix_off, int64_
     const int64_t chunk = std::max<int64_t>(64, piece_runs / 64 * 64);
     if (waves > 1) {
         constexpr int32_t kPixMask = (1 << kBandShift) - 1;
-        for (int32_t g0 = 0; g0 < nbands; g0 += waves) {
+        const int32_t ngroups = (nbands + waves - 1) / waves;
+        // Per group of bands, the groups of 64 runs of its bands as events
+        // (first pixel, band in the group), in pixel order.
+        struct Event {
+            int64_t pix;
+            int32_t w;
+        };
+        std::vector<int64_t> ev_off((size_t)ngroups + 1, 0);
+        for (int32_t gi = 0; gi < ngroups; ++gi) {
+            int64_t n = 0;
+            for (int32_t b = gi * waves; b < std::min(nbands, (gi + 1) * waves); ++b)
+                n += (cnt[b] + 63) / 64;
+            ev_off[gi + 1] = ev_off[gi] + n;
+        }
+        std::vector<Event> ev((size_t)ev_off[ngroups]);
+        for (int32_t gi = 0; gi < ngroups; ++gi) {
+            int64_t e = ev_off[gi];
+            for (int32_t b = gi * waves; b < std::min(nbands, (gi + 1) * waves); ++b)
+                for (int64_t j = 0; j < (cnt[b] + 63) / 64; ++j)
+                    ev[e++] = Event{rm.runs[start[b] + 64 * j] & kPixMask, b - gi * waves};
+            std::stable_sort(ev.begin() + ev_off[gi], ev.begin() + ev_off[gi + 1],
+                             [](const Event& a, const Event& b) { return a.pix < b.pix; });
+        }
+        // Greedy stretches of group gi in pixel order, none holding more
+        // than `bound` groups of 64 runs of one band (events of one pixel stay
+        // together); their count, and the first pixel of each stretch but
+        // the first in *cuts.
+        auto stretches = [&](int32_t gi, int64_t bound, std::vector<int64_t>* cuts) {
+            int64_t c[32] = {0};
+            int32_t k = 1;
+            for (int64_t i = ev_off[gi]; i < ev_off[gi + 1];) {
+                int64_t j = i;
+                int64_t add[32] = {0};
+                while (j < ev_off[gi + 1] && ev[j].pix == ev[i].pix) add[ev[j++].w]++;
+                bool over = false;
+                for (int32_t w = 0; w < waves; ++w) over |= add[w] > 0 && c[w] + add[w] > bound;
+                if (over) {
+                    ++k;
+                    if (cuts) cuts->push_back(ev[i].pix);
+                    for (int32_t w = 0; w < waves; ++w) c[w] = 0;
+                }
+                for (int32_t w = 0; w < waves; ++w) c[w] += add[w];
+                i = j;
+            }
+            return k;
+        };
+        int64_t maxg = 1;
+        for (int32_t b = 0; b < nbands; ++b) maxg = std::max(maxg, (cnt[b] + 63) / 64);
+        // the smallest bound that keeps the schedule within max_tiles workgroups
+        auto bound_for = [&](int64_t max_tiles) {
+            int64_t lo = 1, hi = maxg;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) / 2;
+                int64_t tiles = 0;
+                for (int32_t gi = 0; gi < ngroups && tiles <= max_tiles; ++gi)
+                    tiles += stretches(gi, mid, nullptr);
+                if (tiles <= max_tiles) hi = mid;
+                else lo = mid + 1;
+            }
+            return lo;
+        };
+        // the bound on a band's groups per stretch: from the piece size, or
+        // for rounds of round_tiles workgroups, the fewest rounds whose
+        // bound keeps a band's stretch within kRoundRuns runs
+        int64_t bound = std::min(maxg, chunk / 64);
+        if (round_tiles > 0) {
+            for (int64_t k = 1;; ++k) {
+                bound = bound_for(k * round_tiles);
+                if (bound * 64 <= kRoundRuns || bound == 1) break;
+            }
+        }
+        for (int32_t gi = 0; gi < ngroups; ++gi) {
+            const int32_t g0 = gi * waves;
             const int32_t gn = std::min(waves, nbands - g0);
-            int32_t bmax = g0;
-            for (int32_t b = g0; b < g0 + gn; ++b)
-                if (cnt[b] > cnt[bmax]) bmax = b;
-            const int64_t maxlen = cnt[bmax];
-            const int32_t K = maxlen > 0 ? (int32_t)((maxlen + chunk - 1) / chunk) : 1;
-            // first pixel of each stretch but the first, from the longest band
-            std::vector<int64_t> cut((size_t)K + 1, 0);
-            const int64_t gmax = (maxlen + 63) / 64;
-            for (int32_t k = 1; k < K; ++k)
-                cut[k] = rm.runs[start[bmax] + 64 * (gmax * k / K)] & kPixMask;
-            cut[K] = std::numeric_limits<int64_t>::max();
-            // per band: group boundaries of the stretches
+            // as many stretches as the bound needs, each group's as even as
+            // that count allows: the smallest bound giving no more
+            const int32_t K = stretches(gi, bound, nullptr);
+            int64_t lo = 1, hi = bound;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) / 2;
+                if (stretches(gi, mid, nullptr) <= K) hi = mid;
+                else lo = mid + 1;
+            }
+            std::vector<int64_t> cut;
+            cut.reserve((size_t)K + 1);
+            cut.push_back(0);
+            stretches(gi, lo, &cut);
+            cut.push_back(std::numeric_limits<int64_t>::max());
+            // per band: group boundaries of the stretches (a band's group
+            // belongs to the stretch holding its first pixel)
             std::vector<int64_t> zc((size_t)gn * (K + 1));
             for (int32_t w = 0; w < gn; ++w) {
                 const int32_t b = g0 + w;

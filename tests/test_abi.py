@@ -436,6 +436,75 @@ def test_run_encoding_holds_every_entry_once(g, tile):
                 assert s["bin_count"][bin0 + r] == len(slots)
 
 
+def _greedy_stretches(firsts, bound):
+    """Stretches of one group of bands cut in pixel order so that no band has
+    more than `bound` groups of 64 runs in one (groups starting at one pixel
+    stay together): firsts[w] holds the first pixel of each group of band w."""
+    ev = sorted((int(px), w) for w, arr in enumerate(firsts) for px in arr)
+    count = [0] * len(firsts)
+    k, i = 1, 0
+    while i < len(ev):
+        j = i
+        add = [0] * len(firsts)
+        while j < len(ev) and ev[j][0] == ev[i][0]:
+            add[ev[j][1]] += 1
+            j += 1
+        if any(a and count[w] + a > bound for w, a in enumerate(add)):
+            k += 1
+            count = [0] * len(firsts)
+        count = [c + a for c, a in zip(count, add)]
+        i = j
+    return k
+
+
+@pytest.mark.parametrize("g", [(300, 280, 150.2, 140.7, 260), (257, 263, 10.0, 250.0, 333),
+                               (600, 500, 310.5, 240.2, 500), (1000, 1000, 500.3, 499.7, 1000),
+                               (1400, 1300, 650.3, 720.7, 1200)],
+                         ids=lambda g: f"{g[0]}x{g[1]}-{g[4]}")
+@pytest.mark.parametrize("band", [16, 32])
+def test_balanced_run_schedule_bound_is_smallest(g, band):
+    """tile_nnz 0 on a plan without a device (256 CUs): one round of
+    256 * 32 / waves workgroups at most, and the bound on a band's groups of
+    64 runs per stretch is the smallest that fits it (recounted here from
+    the run words with a greedy cut written for this test); each group of
+    bands has exactly as many workgroups as that cut gives."""
+    h, w, cy, cx, npt = g
+    waves = band // 4
+    az = azint()
+    plan = az.Plan(h, w, npt, center=(cy, cx), tile_nnz=0, band=band)
+    s = plan.run_schedule(tile_nnz=0)
+    runs, pieces = s["runs"], s["pieces"]
+    nt = len(pieces) // waves
+    target = 256 * 32 // waves
+    assert nt <= target
+    lens = (pieces[:, 1] - pieces[:, 0]).astype(np.int64)
+    assert np.all(lens % 64 == 0)
+    bound = int(lens.max()) // 64
+    assert bound * 64 <= 2048 or bound == 1
+    mask = (1 << 27) - 1
+    nbands = (npt + 3) // 4
+    # first pixel of each group of 64 runs, per band, from the schedule's
+    # own band extents (a band's entries tile its runs)
+    firsts, tiles_of = {}, {}
+    for t in range(nt):
+        ents = pieces[t * waves:(t + 1) * waves]
+        gi = int(ents[0][2]) // 4 // waves
+        tiles_of[gi] = tiles_of.get(gi, 0) + 1
+        for e in ents:
+            if e[4] < 0:
+                continue
+            b = int(e[2]) // 4
+            for z in range(int(e[0]), int(e[1]), 64):
+                firsts.setdefault(b, []).append(int(runs[z]) & mask)
+    groups = range((nbands + waves - 1) // waves)
+    per = {gi: [firsts.get(b, []) for b in range(gi * waves, min(nbands, (gi + 1) * waves))]
+           for gi in groups}
+    for gi in groups:
+        assert tiles_of[gi] == _greedy_stretches(per[gi], bound), gi
+    if bound > 1:
+        assert sum(_greedy_stretches(per[gi], bound - 1) for gi in groups) > target
+
+
 def test_new_entry_points_reject_bad_arguments():
     """Argument errors of the run-schedule export, the plan autotuner and the
     correction-bytes query, without a GPU."""
@@ -443,7 +512,7 @@ def test_new_entry_points_reject_bad_arguments():
     L = az.lib()
     plan = az.Plan(12, 13, 6)
     n = ctypes.c_int64()
-    for tn in (0, 63, 16385):
+    for tn in (-64, 63, 16385):
         rc, msg = _err(L.azi_plan_run_schedule(plan.handle, tn, ctypes.byref(n), None, None,
                                                None, None, None, None, None))
         assert rc == -1 and "tile_nnz" in msg
@@ -504,7 +573,7 @@ def test_images_of_2_27_pixels_default_to_the_csr_layout():
                                (257, 263, 10.0, 250.0, 333)],
                          ids=lambda g: f"{g[0]}x{g[1]}-{g[4]}")
 @pytest.mark.parametrize("band", [16, 32])
-@pytest.mark.parametrize("tile", [128, 1024, 4096])
+@pytest.mark.parametrize("tile", [128, 1024, 4096, 0])
 def test_grouped_run_schedule_covers_every_run_once(g, band, tile):
     """Workgroups of 4 or 8 neighbouring bands: entry t * waves + w is band
     w of the workgroup's group; each band's entries tile its runs on

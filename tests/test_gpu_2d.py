@@ -67,7 +67,8 @@ def check_slivers(out, m, x, tol, empty, what):
 
 
 TILINGS = [dict(), dict(tile_nnz=256, block=64, variant=0, band=1),
-           dict(tile_nnz=4096, block=512, variant=6, grid=128, band=8)]
+           dict(tile_nnz=4096, block=512, variant=6, grid=128, band=8),
+           dict(tile_nnz=0, band=16)]
 
 
 @pytest.mark.parametrize("layout", ["band", "tile", "ring", "pixel", "run"])

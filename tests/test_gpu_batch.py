@@ -19,14 +19,18 @@ def say(*a):
 
 
 def make_batch(insts, dtype, dev, tile=None, layout="band"):
+    """Plans of one fixed tiling (pieces of 2048 nonzeros unless `tile` says
+    otherwise: a batch cuts each instance as its plan would, but for the
+    balanced rounds of tile_nnz 0, which are one plan's) and their batch."""
     az = azint()
     plans = []
+    tile = dict(tile or {})
+    tile.setdefault("tile_nnz", 2048)
     for inst in insts:
         g = inst.geom
         p = az.Plan(g.h, g.w, inst.npt, center=(g.center_y, g.center_x), dtype=dtype,
                     layout=layout)
-        if tile:
-            p.set_tiling(**tile)
+        p.set_tiling(**tile)
         plans.append(p)
     return plans, az.Batch(plans, device=dev)
 
@@ -462,7 +466,9 @@ def test_lane_and_wavefront_reductions_agree(dtype, accum, band, dev):
     form), over bins with 1 to 8 partials."""
     say("lane vs wavefront reduction", dtype, accum)
     az = azint()
-    geoms = [(300, 300, 20), (100, 100, 50), (64, 64, 40), (70, 50, 45)]
+    # band 16 cuts the 100 x 100 image's bands into 9 pieces: a smaller one there
+    geoms = [(300, 300, 20), (100, 100, 50) if band == 4 else (96, 96, 50), (64, 64, 40),
+             (70, 50, 45)]
     tile = 512
     plans = []
     for h, w, n in geoms:

@@ -85,7 +85,7 @@ def test_fold_follows_tiling_changes(band, dev):
     for p in (fold, fuse):
         p.set_corrections(t(inst.dark), t(inst.flat), t(inst.solid), t(inst.polar))
     for kw in (dict(tile_nnz=1024), dict(block=128), dict(grid=64), dict(tile_nnz=8192, grid=0),
-               dict(block=256, tile_nnz=4096)):
+               dict(block=256, tile_nnz=4096), dict(tile_nnz=0)):
         for p in (fold, fuse):
             p.set_tiling(**kw)
         a = fold.integrate_raw(t(inst.raw))

@@ -64,7 +64,7 @@ GEOMS = [
 TILINGS = [(2048, 256, 3, 0, 1, 2), (1024, 64, 3, 0, 16, 0), (2048, 256, 2, 0, 1, 1),
            (64, 64, 0, 0, 16, 2), (256, 128, 1, 0, 4, 0), (1024, 512, 3, 64, 16, 1),
            (16384, 256, 4, 0, 1, 2), (128, 64, 5, 8, 16, 0), (4096, 512, 6, 0, 2, 1),
-           (512, 256, 3, 2048, 1, 2)]
+           (512, 256, 3, 2048, 1, 2), (0, 256, 5, 0, 32, 4)]
 
 
 def tiling_kw(t):
@@ -399,7 +399,8 @@ def test_band_layout_shapes(R, piece, block, grid, dev):
           what="band")
 
 
-@pytest.mark.parametrize("piece,grid", [(4096, 0), (64, 0), (128, 8), (16384, 2048), (1024, 64)])
+@pytest.mark.parametrize("piece,grid", [(4096, 0), (64, 0), (128, 8), (16384, 2048), (1024, 64),
+                                        (0, 0), (0, 96)])
 @pytest.mark.parametrize("g", [(300, 280, 150.2, 139.7, 250, "r_m", "bbox"),
                                (1, 17, 0.5, 8.5, 5, "r_m", "bbox"),
                                (64, 48, -5.0, 70.0, 40, "r_m", "bbox"),
@@ -412,7 +413,8 @@ def test_run_layout_shapes(g, piece, grid, dev):
     """The run encoding of the band layout (a word per pixel run within a
     band, coefficients slot-major per 64 runs) against the oracle, for
     pieces from one group of 64 runs to 8192 runs and persistent grids, and
-    within FP64 rounding of the per-entry band encoding."""
+    within FP64 rounding of the per-entry band encoding; piece 0: the
+    balanced pieces the library sizes for the device."""
     h, w, cy, cx, npt, unit, split = g
     say("run shapes", g, piece, grid)
     az = azint()
