@@ -60,11 +60,14 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-TRAFFIC_SOURCES = ("kernels.hip", "accum.h")
+# the integration kernels and the schedule builder (the pieces a launch
+# walks decide which lines are fetched twice)
+TRAFFIC_SOURCES = ("kernels.hip", "accum.h", "plan_builder.cpp")
 
 
 def kernel_source_hash():
-    """sha256 over the sources of the integration kernels."""
+    """sha256 over the sources of the integration kernels and of the
+    schedule builder."""
     import hashlib
     h = hashlib.sha256()
     for name in TRAFFIC_SOURCES:
