@@ -140,21 +140,33 @@ int32_t piece_nnz(const azi_tiling& t, int64_t nnz) {
 }
 
 // Workgroups of one round of a balanced tiling (tile_nnz 0) of a plan's
-// co-scheduled run bands: as many as the device keeps resident at once,
-// workgroups of `waves` wavefronts at 8 per SIMD (the run kernels'
-// occupancy).  The schedule is cut into the fewest such rounds that keep a
+// co-scheduled run bands: as many as the device keeps resident at once
+// (CUs times the run kernel's resident workgroups per CU, from the
+// runtime: 8 of 4 wavefronts at its 64 VGPRs or fewer; a round sized for
+// more than fit spills a few workgroups into a second round, which costs
+// as much as the round itself).  The schedule is cut into the fewest such rounds that keep a
 // band's stretch within 2048 runs, each workgroup taking as nearly the same
 // work as the bands allow (the ~1e7-pixel frame: one round; 2048^2, 4096^2
 // and off-centre frames: 27-36 % faster than pieces of 2048 runs but for
 // 4096^2, two rounds, 10 %).  None for the other layouts (0).  Without a
-// device, MI355X's 256 CUs.
-int64_t balanced_tiles(const azi_tiling& t, int device, int32_t waves) {
+// device, MI355X's 256 CUs at 8 workgroups of 4 wavefronts.
+int64_t balanced_tiles(const azi_tiling& t, int device, int32_t waves, int32_t dtype,
+                       int32_t accum) {
     if (t.tile_nnz != 0 || waves <= 1) return 0;
     int ncu = 256;
-    if (device >= 0 && hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount,
-                                              device) != hipSuccess)
-        ncu = 256;
-    return (int64_t)ncu * 32 / waves;
+    int32_t per_cu = 32 / waves;
+    if (device >= 0) {
+        DeviceGuard g(device);
+        if (g.err == hipSuccess &&
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) ==
+                hipSuccess) {
+            const int32_t r = azi::runs_resident_per_cu(dtype, accum, waves);
+            if (r > 0) per_cu = r;
+        } else {
+            ncu = 256;
+        }
+    }
+    return (int64_t)ncu * per_cu;
 }
 
 // Stages whose raw-frame path corrects each pixel in the band gather.
@@ -403,7 +415,8 @@ int plan_upload_bands(azi_plan* p) {
             if (!azi::build_runs(p->m, std::max(64, piece_nnz(p->tiling, p->m.nnz()) / 2), 0, 0, rm,
                                  nullptr,
                                  run_waves(p->tiling),
-                                 balanced_tiles(p->tiling, p->device, run_waves(p->tiling))))
+                                 balanced_tiles(p->tiling, p->device, run_waves(p->tiling),
+                                                p->dtype, p->accum)))
                 return fail(AZI_EOVERFLOW,
                             "the run layout takes images below 2^27 pixels and 2^31 entries");
             azi::BandMatrix bm;
@@ -1195,7 +1208,8 @@ int azi_plan_run_schedule(const azi_plan* p, int32_t tile_nnz, int64_t* nruns, i
         azi_tiling tl = p->tiling;
         tl.tile_nnz = tile_nnz;
         if (!azi::build_runs(p->m, std::max(64, piece_nnz(tl, p->m.nnz()) / 2), 0, 0, rm, nullptr,
-                             run_waves(tl), balanced_tiles(tl, p->device, run_waves(tl))))
+                             run_waves(tl),
+                             balanced_tiles(tl, p->device, run_waves(tl), p->dtype, p->accum)))
             return fail(AZI_EOVERFLOW,
                         "the run layout takes images below 2^27 pixels and 2^31 entries");
         if (nruns) *nruns = (int64_t)rm.runs.size();

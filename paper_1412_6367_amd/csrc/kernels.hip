@@ -1075,6 +1075,16 @@ hipError_t runs_kernel(const BandLaunch& a, const T* x, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <class T, class Acc, int WAVES>
+int32_t runs_resident() {
+    int n = 0;
+    const void* f = reinterpret_cast<const void*>(
+        &k_runs_grouped<T, Acc, kRunGroups<T>, WAVES, int32_t, true, RunDark<float>>);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, WAVES * kWave, 0) != hipSuccess)
+        return 0;
+    return n;
+}
+
 template <class T, class Acc, class RawT, class CorrT>
 hipError_t runs_launch_raw(const BandLaunch& a, int, hipStream_t s) {
     return runs_kernel<T, Acc, RawT, true, CorrT>(a, nullptr, s);
@@ -1317,6 +1327,19 @@ hipError_t launch_corr_pair(const void* dark, const void* norm, void* pair, int3
                            static_cast<const float*>(dark), static_cast<const float*>(norm),
                            static_cast<float2*>(pair), n);
     return hipGetLastError();
+}
+
+int32_t runs_resident_per_cu(int32_t dtype, int32_t accum, int32_t waves) {
+    const bool k32 = dtype == AZI_F32 && accum == AZI_ACC_KAHAN32;
+    if (waves == 4)
+        return dtype == AZI_F64 ? runs_resident<double, AccF64, 4>()
+               : k32            ? runs_resident<float, AccK32, 4>()
+                                : runs_resident<float, AccF64, 4>();
+    if (waves == 8)
+        return dtype == AZI_F64 ? runs_resident<double, AccF64, 8>()
+               : k32            ? runs_resident<float, AccK32, 8>()
+                                : runs_resident<float, AccF64, 8>();
+    return 0;
 }
 
 hipError_t launch_band(const BandLaunch& a, hipStream_t s) {
