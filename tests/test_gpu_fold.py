@@ -167,3 +167,49 @@ def test_fold_band_layout_is_fuse(dev):
         torch.cuda.synchronize()
     for a, b in zip(*res):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("band", [16, 32])
+def test_balanced_schedule_fills_one_round_on_the_device(band, dev):
+    """tile_nnz 0 on an uploaded plan: the run schedule takes at most as many
+    workgroups as the device keeps resident (CUs x 8 of four wavefronts,
+    x 4 of eight), the bound on a band's groups of 64 runs per stretch is the
+    smallest that fits (one group less overflows the round: recounted with
+    the greedy cut written for the CPU test), and the folded step on it
+    matches the oracle."""
+    from tests.test_abi import _greedy_stretches
+    say("balanced on device", band)
+    az = azint()
+    h, w, cy, cx, npt = 1400, 1300, 650.3, 720.7, 1200
+    waves = band // 4
+    plan = az.Plan(h, w, npt, center=(cy, cx), tile_nnz=0, band=band, device=dev)
+    ncu = torch.cuda.get_device_properties(dev).multi_processor_count
+    target = ncu * 32 // waves
+    s = plan.run_schedule(tile_nnz=0)
+    runs, pieces = s["runs"], s["pieces"]
+    nt = len(pieces) // waves
+    assert nt <= target
+    lens = (pieces[:, 1] - pieces[:, 0]).astype(np.int64)
+    bound = int(lens.max()) // 64
+    mask = (1 << 27) - 1
+    nbands = (npt + 3) // 4
+    firsts = {}
+    for t in range(nt):
+        for e in pieces[t * waves:(t + 1) * waves]:
+            if e[4] >= 0:
+                b = int(e[2]) // 4
+                for z in range(int(e[0]), int(e[1]), 64):
+                    firsts.setdefault(b, []).append(int(runs[z]) & mask)
+    groups = range((nbands + waves - 1) // waves)
+    per = [[firsts.get(b, []) for b in range(gi * waves, min(nbands, (gi + 1) * waves))]
+           for gi in groups]
+    assert sum(_greedy_stretches(p, bound) for p in per) == nt
+    if bound > 1:
+        assert sum(_greedy_stretches(p, bound - 1) for p in per) > target
+    # and the step on it
+    inst = synth.instance_hw(h, w, 14, npt=npt, corrections=True)
+    t = lambda a: _tensor(a, dev)
+    plan.set_corrections(t(inst.dark), t(inst.flat), t(inst.solid), t(inst.polar))
+    m = oracle_matrix(h, w, cy, cx, npt)
+    x = oracle.correct(inst.raw, inst.dark, inst.flat, inst.solid, inst.polar)
+    check(plan.integrate_raw(t(inst.raw)), m, x, TOL64, what=f"balanced band {band}")
