@@ -18,6 +18,7 @@ constexpr int kWave = 64;
 // ---------------------------------------------------------------------------
 
 struct AccF64 {
+    using Slot = AccF64;  // what a partial-sum slot holds
     double w, u;
     __device__ void zero() { w = 0.0; u = 0.0; }
     template <class T>
@@ -34,11 +35,38 @@ struct AccF64 {
     }
     __device__ double W() const { return w; }
     __device__ double U() const { return u; }
+    __device__ Slot slot() const { return *this; }
+};
+
+// W alone, for kernels whose U is taken from elsewhere (the folded
+// coefficients carry 1 / norm, so their sums are not U): the same w
+// operations as AccF64, and a partial-sum slot of AccF64's layout with u 0.
+struct AccWF64 {
+    using Slot = AccF64;
+    double w;
+    __device__ void zero() { w = 0.0; }
+    template <class T>
+    __device__ void add(T c, T x) { w = __fma_rn((double)c, (double)x, w); }
+    __device__ void merge(const AccWF64& o) { w += o.w; }
+    __device__ AccWF64 shfl_xor(int m) const {
+        AccWF64 r;
+        r.w = __shfl_xor(w, m, kWave);
+        return r;
+    }
+    __device__ double W() const { return w; }
+    __device__ double U() const { return 0.0; }
+    __device__ Slot slot() const {
+        Slot s;
+        s.w = w;
+        s.u = 0.0;
+        return s;
+    }
 };
 
 // Kahan (1965) compensated float sums; merge keeps the rounding error of the
 // addition of the two leading parts (TwoSum) in the compensation term.
 struct AccK32 {
+    using Slot = AccK32;
     float ws, wc, us, uc;  // running sum and compensation (to be added)
     __device__ void zero() { ws = wc = us = uc = 0.0f; }
     __device__ static void kadd(float& s, float& c, float v) {
@@ -78,7 +106,44 @@ struct AccK32 {
     }
     __device__ float W() const { return __fsub_rn(ws, wc); }
     __device__ float U() const { return __fsub_rn(us, uc); }
+    __device__ Slot slot() const { return *this; }
 };
+
+// The W half of AccK32 (see AccWF64).
+struct AccWK32 {
+    using Slot = AccK32;
+    float ws, wc;
+    __device__ void zero() { ws = wc = 0.0f; }
+    template <class T>
+    __device__ void add(T c, T x) { AccK32::kadd(ws, wc, __fmul_rn((float)c, (float)x)); }
+    __device__ void merge(const AccWK32& o) {
+        float s, e;
+        AccK32::two_sum(ws, o.ws, s, e);
+        wc = __fsub_rn(__fadd_rn(wc, o.wc), e);
+        ws = s;
+    }
+    __device__ AccWK32 shfl_xor(int m) const {
+        AccWK32 r;
+        r.ws = __shfl_xor(ws, m, kWave);
+        r.wc = __shfl_xor(wc, m, kWave);
+        return r;
+    }
+    __device__ float W() const { return __fsub_rn(ws, wc); }
+    __device__ float U() const { return 0.0f; }
+    __device__ Slot slot() const {
+        Slot s;
+        s.ws = ws;
+        s.wc = wc;
+        s.us = 0.0f;
+        s.uc = 0.0f;
+        return s;
+    }
+};
+
+// The W-only accumulator of an accumulator.
+template <class Acc> struct WOnly;
+template <> struct WOnly<AccF64> { using type = AccWF64; };
+template <> struct WOnly<AccK32> { using type = AccWK32; };
 
 static_assert(sizeof(AccF64) == 16 && sizeof(AccK32) == 16, "partial slot is 16 bytes");
 

@@ -128,8 +128,8 @@ hipError_t launch_band(const BandLaunch& a, hipStream_t s);
 // Workgroups of the co-scheduled run kernel (`waves` bands; the storage type
 // and accumulator of `dtype` / `accum`) that one CU of the current device
 // keeps resident, from the runtime's occupancy calculator for the kernel's
-// raw-frame, folded-correction form (its other forms take the same
-// registers within a few); 0 if the runtime cannot tell.
+// raw-frame, folded-correction form (W accumulated alone; its other forms
+// are held to the same 8 wavefronts per SIMD); 0 if the runtime cannot tell.
 int32_t runs_resident_per_cu(int32_t dtype, int32_t accum, int32_t waves);
 
 // pair[i] = (dark[i], 1 / norm[i]) in the storage type (0 and 1 where the

@@ -537,7 +537,7 @@ template <class T, class Acc, int U, int WAVES, class RawT = T, bool kCorr = fal
 __global__ __launch_bounds__(WAVES * kWave) void k_runs_grouped(
     const BandPiece* __restrict__ pieces, int32_t ntiles, const int32_t* __restrict__ runs,
     const int32_t* __restrict__ gbase, const T* __restrict__ coef, const T* __restrict__ x,
-    Acc* __restrict__ parts, const RawT* __restrict__ raw = nullptr,
+    typename Acc::Slot* __restrict__ parts, const RawT* __restrict__ raw = nullptr,
     const CorrT* __restrict__ corr = nullptr) {
     constexpr int R = kRunRows;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -556,7 +556,7 @@ __global__ __launch_bounds__(WAVES * kWave) void k_runs_grouped(
         for (int r = 0; r < R; ++r) group_reduce(a[r], kWave);
         if (lane == 0 && pc.slot0 >= 0) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) parts[pc.slot0 + r] = a[r];
+            for (int r = 0; r < R; ++r) parts[pc.slot0 + r] = a[r].slot();
         }
     }
 }
@@ -1034,34 +1034,52 @@ hipError_t band_block(const BandLaunch& a, hipStream_t s) {
 }
 
 // Groups in flight per wavefront (measured at 1e7 pixels: 2 for float64,
-// 4 for float32, whose registers are half the size).
-template <class T> constexpr int kRunGroups = sizeof(T) == 8 ? 2 : 4;
+// 4 for float32, whose registers are half the size; 3 for float64 when the
+// accumulator holds W alone, which frees the registers of a third group
+// within the 64 VGPRs of 8 wavefronts per SIMD).
+template <class T, class Acc>
+constexpr int kRunGroups = sizeof(T) == 8 ? (std::is_same<Acc, AccWF64>::value ? 3 : 2) : 4;
+
+// The co-scheduled kernel of `a.waves` bands per workgroup, accumulating in
+// Acc (partial-sum slots of Acc::Slot).
+template <class T, class Acc, class RawT, bool kCorr, class CorrT>
+hipError_t grouped_launch(const BandLaunch& a, const T* x, hipStream_t s) {
+    constexpr int G = kRunGroups<T, Acc>;
+    const T* coef = static_cast<const T*>(a.coef);
+    auto* parts = static_cast<typename Acc::Slot*>(a.parts);
+    const RawT* raw = static_cast<const RawT*>(a.raw);
+    const CorrT* corr = static_cast<const CorrT*>(a.corr);
+    const int32_t ntiles = a.npieces / a.waves;
+    const int grid = a.grid > 0 ? a.grid : ntiles;
+    if (ntiles <= 0) return hipSuccess;
+    if (a.waves == 4)
+        hipLaunchKernelGGL((k_runs_grouped<T, Acc, G, 4, RawT, kCorr, CorrT>), dim3(grid),
+                           dim3(4 * kWave), 0, s, a.pieces, ntiles, a.packed, a.gbase, coef, x,
+                           parts, raw, corr);
+    else if (a.waves == 8)
+        hipLaunchKernelGGL((k_runs_grouped<T, Acc, G, 8, RawT, kCorr, CorrT>), dim3(grid),
+                           dim3(8 * kWave), 0, s, a.pieces, ntiles, a.packed, a.gbase, coef, x,
+                           parts, raw, corr);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
 
 // Launches the run-layout kernel of the launch's form: one band per
 // workgroup of a.block threads (a.waves == 1), or a.waves co-scheduled
-// bands per workgroup.
+// bands per workgroup.  A raw-frame launch that takes U from the plan
+// (ufix_in: the folded coefficients) accumulates W alone.
 template <class T, class Acc, class RawT, bool kCorr, class CorrT>
 hipError_t runs_kernel(const BandLaunch& a, const T* x, hipStream_t s) {
-    constexpr int G = kRunGroups<T>;
+    constexpr int G = kRunGroups<T, Acc>;
     const T* coef = static_cast<const T*>(a.coef);
     Acc* parts = static_cast<Acc*>(a.parts);
     const RawT* raw = static_cast<const RawT*>(a.raw);
     const CorrT* corr = static_cast<const CorrT*>(a.corr);
     if (a.waves > 1) {
-        const int32_t ntiles = a.npieces / a.waves;
-        const int grid = a.grid > 0 ? a.grid : ntiles;
-        if (ntiles <= 0) return hipSuccess;
-        if (a.waves == 4)
-            hipLaunchKernelGGL((k_runs_grouped<T, Acc, G, 4, RawT, kCorr, CorrT>), dim3(grid),
-                               dim3(4 * kWave), 0, s, a.pieces, ntiles, a.packed, a.gbase, coef,
-                               x, parts, raw, corr);
-        else if (a.waves == 8)
-            hipLaunchKernelGGL((k_runs_grouped<T, Acc, G, 8, RawT, kCorr, CorrT>), dim3(grid),
-                               dim3(8 * kWave), 0, s, a.pieces, ntiles, a.packed, a.gbase, coef,
-                               x, parts, raw, corr);
-        else
-            return hipErrorInvalidValue;
-        return hipGetLastError();
+        if (kCorr && a.ufix_in)
+            return grouped_launch<T, typename WOnly<Acc>::type, RawT, kCorr, CorrT>(a, x, s);
+        return grouped_launch<T, Acc, RawT, kCorr, CorrT>(a, x, s);
     }
     const int grid = a.grid > 0 ? a.grid : a.npieces;
     if (a.block == 128)
@@ -1075,11 +1093,12 @@ hipError_t runs_kernel(const BandLaunch& a, const T* x, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <class T, class Acc, int WAVES>
+template <class T, class Acc0, int WAVES>
 int32_t runs_resident() {
+    using Acc = typename WOnly<Acc0>::type;  // the folded raw-frame form
     int n = 0;
     const void* f = reinterpret_cast<const void*>(
-        &k_runs_grouped<T, Acc, kRunGroups<T>, WAVES, int32_t, true, RunDark<float>>);
+        &k_runs_grouped<T, Acc, kRunGroups<T, Acc>, WAVES, int32_t, true, RunDark<float>>);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, WAVES * kWave, 0) != hipSuccess)
         return 0;
     return n;
