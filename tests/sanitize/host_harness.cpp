@@ -9,6 +9,7 @@
 //   h w center_y center_x npt npt_azim unit split range_min range_max
 // (npt_azim 0 for a one-dimensional matrix; range_min > range_max for the
 // default range).
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <string>
@@ -107,6 +108,23 @@ int main() {
                 expect(halves, "scaled coefficients", line);
             }
         }
+        // balanced rounds of 64 and 2048 workgroups: every run in one
+        // entry, no band's stretch above 2048 runs unless one group of 64
+        // already overflows the rounds
+        for (int64_t round : {64, 2048})
+            for (int32_t waves : {4, 8}) {
+                azi::RunMatrix rb;
+                if (!azi::build_runs(m, 4096, 0, 0, rb, nullptr, waves, round)) continue;
+                expect(rb.pieces.size() % (size_t)waves == 0, "balanced entries", line);
+                int64_t covered = 0, longest = 0;
+                for (const azi::BandPiece& pc : rb.pieces)
+                    if (pc.slot0 >= 0) {
+                        covered += pc.z1 - pc.z0;
+                        longest = std::max<int64_t>(longest, pc.z1 - pc.z0);
+                    }
+                expect(covered == (int64_t)rb.runs.size(), "balanced cover", line);
+                expect(longest <= azi::kRoundRuns || longest == 64, "balanced bound", line);
+            }
         if (!m.two_d) {
             std::vector<azi::FusedTile> ft;
             std::vector<int32_t> slots, bin_ptr;
