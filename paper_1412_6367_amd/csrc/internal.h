@@ -195,8 +195,8 @@ struct RunMatrix {
 // Appends the run encoding of one instance (CSC `m`; its pixels start at
 // pix_off, its bins at bin_off of the batch) to `rm`, with pieces of at most
 // piece_runs runs (rounded down to a multiple of 64).  Returns false if the
-// image has 2^27 pixels or more or the runs or coefficients would not fit
-// int32 positions.
+// image has 2^27 pixels or more, the runs or coefficients would not fit
+// int32 positions, or waves exceeds 32.
 // With `scale` (npix values), every coefficient of pixel p is multiplied by
 // scale[p] (rounded once) as it is stored.
 // waves > 1: the pieces are instead cut for workgroups of `waves`

@@ -379,6 +379,7 @@ bool build_runs(const HostMatrix& m, int32_t piece_runs, int64_t pix_off, int64_
         rm.bin_count.resize(bin_off + npt, 0);
     }
     const int64_t chunk = std::max<int64_t>(64, piece_runs / 64 * 64);
+    if (waves > 32) return false;  // the stretch counters below hold 32 bands
     if (waves > 1) {
         constexpr int32_t kPixMask = (1 << kBandShift) - 1;
         const int32_t ngroups = (nbands + waves - 1) / waves;
