@@ -130,8 +130,10 @@ def raw_bytes(nnz, npix, npt, es, cb):
     """Algorithmic bytes of one raw-frame integration with the correction
     in the gather: the matrix, the raw int32 frame, dark and 1/norm (cb
     bytes per pixel: a pair of the storage type, or 12 for float64 with
-    dark values that are floats), row pointers, three outputs."""
-    return nnz * (es + 4) + npix * (4 + cb) + (npt + 1) * 4 + 3 * npt * es
+    dark values that are floats; at least 4, a float dark map, when the
+    plan stores its integer dark counts in 2 bytes: the yardstick does not
+    shrink with the encoding), row pointers, three outputs."""
+    return nnz * (es + 4) + npix * (4 + max(cb, 4)) + (npt + 1) * 4 + 3 * npt * es
 
 
 def encoding_bytes(plan, np, npix, npt, es, cb):

@@ -273,8 +273,11 @@ int azi_plan_export_csc(const azi_plan* plan, void* data, int32_t* bins, int32_t
  *             into the coefficients when the corrections are set (a second
  *             copy of the coefficients, each multiplied by its pixel's
  *             1 / norm and rounded once) and each run of the run encoding
- *             keeps its pixel's dark value beside its word, so the raw
- *             count is the only gathered value: the kernel forms
+ *             keeps its pixel's dark value beside its word (in 16 bits when
+ *             every dark value is an integer in [0, 65535], as a float when
+ *             every one is a float, else in the storage type: exact
+ *             conversions, the same bits), so the raw count is the only
+ *             gathered value: the kernel forms
  *             A_bp * (raw - dark) with A_bp carrying 1 / norm, the same sum
  *             in another order, one rounding per product away from the
  *             quotient of azi_correct.  U, which does not depend on the
@@ -417,7 +420,8 @@ int azi_plan_set_corrections(azi_plan* plan, const void* dark, const void* flat,
 /* Bytes per pixel of the per-pixel correction the band gather reads (16 or
  * 8 for pairs of float64 / float32, 12 for the records above; with
  * AZI_STAGE_FOLD the dark value alone, stored per run rather than per
- * pixel: 4 as a float, else the storage size), or 0 when the raw-frame
+ * pixel: 2 for integer counts of 16 bits, 4 as a float, else the storage
+ * size), or 0 when the raw-frame
  * path keeps no such array (no corrections or no dark with
  * AZI_STAGE_FOLD, or another layout or stage).  0 for a NULL plan. */
 int32_t azi_plan_correction_bytes(const azi_plan* plan);

@@ -620,23 +620,34 @@ int plan_fold(azi_plan* p, hipStream_t s) {
             AZI_HIP(p->fcoef.upload(c.data(), c.size(), p->device), "folded coefficients");
         }
         if (p->has_dark) {
-            // float when every dark value is one (always for float32 plans)
-            bool as_float = true;
-            for (double d : dark)
-                if ((double)(float)d != d) {
-                    as_float = false;
-                    break;
-                }
+            // uint16 when every dark value is an integer count that fits
+            // (its conversion to the storage type is exact: the same bits
+            // from half the bytes), else float when every value is one
+            // (always for float32 plans), else the storage type
+            bool as_u16 = true, as_float = true;
+            for (double d : dark) {
+                as_u16 = as_u16 && d >= 0.0 && d <= 65535.0 && d == std::floor(d);
+                as_float = as_float && (double)(float)d == d;
+            }
             constexpr int32_t kPixMask = (1 << azi::kBandShift) - 1;
             const size_t nr = rm.runs.size() + kPad;
-            std::vector<double> rd(nr, 0.0);
-            for (size_t z = 0; z < rm.runs.size(); ++z)
-                if (rm.runs[z] >= 0) rd[z] = dark[(size_t)(rm.runs[z] & kPixMask)];
-            std::vector<char> c = to_storage(rd.data(), (int64_t)nr, (int64_t)nr,
-                                             as_float ? AZI_F32 : p->dtype);
-            AZI_HIP(p->corr.upload(c.data(), c.size(), p->device), "run dark values");
-            p->corr_kind = as_float && p->dtype == AZI_F64 ? azi::kCorrRunDarkF32
-                                                           : azi::kCorrRunDark;
+            if (as_u16) {
+                std::vector<uint16_t> rd(nr, 0);
+                for (size_t z = 0; z < rm.runs.size(); ++z)
+                    if (rm.runs[z] >= 0)
+                        rd[z] = (uint16_t)dark[(size_t)(rm.runs[z] & kPixMask)];
+                AZI_HIP(p->corr.upload(rd.data(), rd.size() * 2, p->device), "run dark values");
+                p->corr_kind = azi::kCorrRunDarkU16;
+            } else {
+                std::vector<double> rd(nr, 0.0);
+                for (size_t z = 0; z < rm.runs.size(); ++z)
+                    if (rm.runs[z] >= 0) rd[z] = dark[(size_t)(rm.runs[z] & kPixMask)];
+                std::vector<char> c = to_storage(rd.data(), (int64_t)nr, (int64_t)nr,
+                                                 as_float ? AZI_F32 : p->dtype);
+                AZI_HIP(p->corr.upload(c.data(), c.size(), p->device), "run dark values");
+                p->corr_kind = as_float && p->dtype == AZI_F64 ? azi::kCorrRunDarkF32
+                                                               : azi::kCorrRunDark;
+            }
         } else {
             p->corr_kind = azi::kCorrRunDark;
         }
@@ -1362,6 +1373,7 @@ int azi_plan_upload(azi_plan* p, int32_t device) {
 int32_t azi_plan_correction_bytes(const azi_plan* p) {
     if (!p || !p->corr.p) return 0;
     if (p->corr_kind == azi::kCorrRecord12) return (int32_t)sizeof(azi::Corr12);
+    if (p->corr_kind == azi::kCorrRunDarkU16) return 2;
     if (p->corr_kind == azi::kCorrRunDarkF32) return 4;
     if (p->corr_kind == azi::kCorrRunDark) return (int32_t)elem_size(p->dtype);
     return (int32_t)(2 * elem_size(p->dtype));

@@ -65,10 +65,12 @@ hipError_t launch_correct(const void* raw, int32_t raw_dtype, const int32_t* ord
 // the normalisation folded into the coefficients (AZI_STAGE_FOLD, run
 // layout) dark alone is subtracted, stored once per run beside the run
 // words and read with them (run z's value is the dark of its pixel), which
-// leaves the raw count as the only gather: as float for float64 plans whose
-// dark values are all floats (kCorrRunDarkF32), else in the storage type
-// (kCorrRunDark).
-constexpr int32_t kCorrPair = 0, kCorrRecord12 = 1, kCorrRunDarkF32 = 2, kCorrRunDark = 3;
+// leaves the raw count as the only gather: as uint16 when every dark value
+// is an integer in [0, 65535] (kCorrRunDarkU16), as float for float64 plans
+// whose dark values are all floats (kCorrRunDarkF32), else in the storage
+// type (kCorrRunDark); the conversions are exact, so all give the same bits.
+constexpr int32_t kCorrPair = 0, kCorrRecord12 = 1, kCorrRunDarkF32 = 2, kCorrRunDark = 3,
+                  kCorrRunDarkU16 = 4;
 // Element type of a run-indexed dark array.
 template <class V>
 struct RunDark {

@@ -285,6 +285,9 @@ __device__ inline double corr_apply(double v, const Corr12& c) {
 __device__ inline double corr_apply(double v, float d) { return v - (double)d; }
 __device__ inline double corr_apply(double v, double d) { return v - d; }
 __device__ inline float corr_apply(float v, float d) { return v - d; }
+// An integer dark count of 16 bits: exact in float and double alike.
+__device__ inline double corr_apply(double v, uint16_t d) { return v - (double)d; }
+__device__ inline float corr_apply(float v, uint16_t d) { return v - (float)d; }
 template <class T, class V>
 __device__ inline T corr_apply(T v, RunDark<V> d) { return corr_apply(v, d.v); }
 template <class C> struct IsRunDark { static constexpr bool value = false; };
@@ -1077,9 +1080,16 @@ hipError_t runs_kernel(const BandLaunch& a, const T* x, hipStream_t s) {
     const RawT* raw = static_cast<const RawT*>(a.raw);
     const CorrT* corr = static_cast<const CorrT*>(a.corr);
     if (a.waves > 1) {
-        if (kCorr && a.ufix_in)
+        if constexpr (kCorr && IsRunDark<CorrT>::value) {
+            // a dark value per run exists only with the folded coefficients,
+            // whose U is the plan's
+            if (!a.ufix_in) return hipErrorInvalidValue;
             return grouped_launch<T, typename WOnly<Acc>::type, RawT, kCorr, CorrT>(a, x, s);
-        return grouped_launch<T, Acc, RawT, kCorr, CorrT>(a, x, s);
+        } else {
+            if (kCorr && a.ufix_in)
+                return grouped_launch<T, typename WOnly<Acc>::type, RawT, kCorr, CorrT>(a, x, s);
+            return grouped_launch<T, Acc, RawT, kCorr, CorrT>(a, x, s);
+        }
     }
     const int grid = a.grid > 0 ? a.grid : a.npieces;
     if (a.block == 128)
@@ -1119,6 +1129,8 @@ hipError_t runs_raw_corr(const BandLaunch& a, int grid, hipStream_t s) {
     }
     if (a.corr && a.corr_kind == kCorrRunDark)
         return runs_launch_raw<T, Acc, RawT, RunDark<T>>(a, grid, s);
+    if (a.corr && a.corr_kind == kCorrRunDarkU16)
+        return runs_launch_raw<T, Acc, RawT, RunDark<uint16_t>>(a, grid, s);
     if (a.corr_kind != kCorrPair && a.corr) return hipErrorInvalidValue;
     return runs_launch_raw<T, Acc, RawT, typename Pair2<T>::type>(a, grid, s);
 }

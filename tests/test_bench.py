@@ -34,6 +34,10 @@ def test_byte_counts_of_the_c2_frame():
     assert abs(bench.raw_bytes(nnz, npix, npt, 8, 16) / 1e6 - 540.0) < 0.1
     assert bench.raw_bytes(nnz, npix, npt, 8, 16) - bench.raw_bytes(nnz, npix, npt, 8, 12) \
         == 4 * npix
+    # folded: a float dark per pixel (420 MB); integer dark counts kept in 2
+    # bytes do not shrink the yardstick
+    assert abs(bench.raw_bytes(nnz, npix, npt, 8, 4) / 1e6 - 420.0) < 0.1
+    assert bench.raw_bytes(nnz, npix, npt, 8, 2) == bench.raw_bytes(nnz, npix, npt, 8, 4)
     # adjoint of a 1-D plan: coefficients, column pointers and one first-bin
     # word per pixel instead of per-entry bin ids
     assert bench.bwd_bytes(nnz, npix, npt, 8) == nnz * 8 + (npix + 1) * 4 + npix * 4 + \

@@ -110,17 +110,19 @@ def test_fold_stage_switch_and_recorrect(dev):
     for stage in ("fold", "fuse", "fold"):
         plan.set_tiling(stage=stage)
         check(plan.integrate_raw(t(inst.raw)), m, x, TOL64, what=stage)
-    assert plan.correction_bytes() == 4         # integer dark: a float per run
+    assert plan.correction_bytes() == 2         # integer dark counts: 16 bits per run
     flat2 = inst.flat[::-1].copy()
     plan.set_corrections(None, t(flat2), None, t(inst.polar))
     x2 = oracle.correct(inst.raw, None, flat2, None, inst.polar)
     check(plan.integrate_raw(t(inst.raw)), m, x2, TOL64, what="new corrections")
-    # a float64 dark that is not a float keeps its double form
-    dark = inst.dark.reshape(-1).astype(np.float64) + 0.1
-    plan.set_corrections(t(dark), t(inst.flat), t(inst.solid), t(inst.polar))
-    assert plan.correction_bytes() == 8
-    x3 = oracle.correct(inst.raw, dark, inst.flat, inst.solid, inst.polar)
-    check(plan.integrate_raw(t(inst.raw)), m, x3, TOL64, what="double dark")
+    # a float64 dark that is not a float keeps its double form; fractional
+    # floats and integers beyond 16 bits take a float per run
+    for add, nbytes in ((0.1, 8), (0.25, 4), (70000.0, 4), (0.0, 2)):
+        dark = inst.dark.reshape(-1).astype(np.float64) + add
+        plan.set_corrections(t(dark), t(inst.flat), t(inst.solid), t(inst.polar))
+        assert plan.correction_bytes() == nbytes, add
+        x3 = oracle.correct(inst.raw, dark, inst.flat, inst.solid, inst.polar)
+        check(plan.integrate_raw(t(inst.raw)), m, x3, TOL64, what=f"dark + {add}")
 
 
 def test_fold_graph_and_noalloc(dev):
