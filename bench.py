@@ -50,7 +50,11 @@ def kernel_of(line):
              f"{t['band'] // 4} neighbouring bands of 4 bins per workgroup")
     else:
         k = KERNEL_OF_LAYOUT[line["layout"]]
-    if t["stage"] == 4:
+    if t["stage"] == 5 and line.get("accum") == "f64":
+        return k + ", 1/norm folded into the coefficients and the dark term summed once per " \
+                   "correction set: the raw count is the only gathered value, no dark value " \
+                   "is read per frame"
+    if t["stage"] in (4, 5):
         return k + ", 1/norm folded into the coefficients and dark stored per run: the raw " \
                    "count is the only gathered value"
     return k + ", reading the raw frame and correcting in the gather"
@@ -131,8 +135,9 @@ def raw_bytes(nnz, npix, npt, es, cb):
     in the gather: the matrix, the raw int32 frame, dark and 1/norm (cb
     bytes per pixel: a pair of the storage type, or 12 for float64 with
     dark values that are floats; at least 4, a float dark map, when the
-    plan stores its integer dark counts in 2 bytes: the yardstick does not
-    shrink with the encoding), row pointers, three outputs."""
+    plan stores its integer dark counts in 2 bytes or sums the dark term
+    once per correction set and reads none per frame: the yardstick does
+    not shrink with the encoding), row pointers, three outputs."""
     return nnz * (es + 4) + npix * (4 + max(cb, 4)) + (npt + 1) * 4 + 3 * npt * es
 
 
@@ -141,7 +146,8 @@ def encoding_bytes(plan, np, npix, npt, es, cb):
     pixel run within a band of 4 bins instead of an index per entry; the
     step's roofline keeps the CSR figure of raw_bytes as its yardstick).
     With 1/norm folded into the coefficients the dark value (cb bytes) is
-    stored per run beside the run word instead of gathered per pixel."""
+    stored per run beside the run word instead of gathered per pixel (cb 0
+    when the dark term is summed once per correction set)."""
     if plan.layout() != "run":
         return raw_bytes(plan.nnz, npix, npt, es, cb)
     _, bins, colptr = plan.export_csc()
@@ -149,7 +155,7 @@ def encoding_bytes(plan, np, npix, npt, es, cb):
     first = bins[colptr[:-1][full]] // 4
     last = bins[colptr[1:][full] - 1] // 4
     runs = int((last - first + 1).sum())
-    if plan.tiling()["stage"] == 4:
+    if plan.tiling()["stage"] in (4, 5):
         return runs * (4 + cb) + plan.nnz * es + npix * 4 + 3 * npt * es
     return runs * 4 + plan.nnz * es + npix * (4 + cb) + 3 * npt * es
 

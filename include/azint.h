@@ -220,7 +220,7 @@ int azi_plan_export_csc(const azi_plan* plan, void* data, int32_t* bins, int32_t
  * change at most in the order of the floating-point additions, and, for
  * the stage, by the one rounding of the fused or folded correction).  A
  * new plan starts at tile_nnz 0, block 256, variant 5, grid 0, band 16,
- * stage AZI_STAGE_FOLD (plans built on the device, which start in the band
+ * stage AZI_STAGE_FOLD_SUM (plans built on the device, which start in the band
  * layout: band 4; two-dimensional plans: 4096, 256, 1, 0, 1,
  * AZI_STAGE_GATHER); a new batch at the same tiling.
  *   tile_nnz  most nonzeros one workgroup sums per tile (64..16384, a
@@ -283,6 +283,19 @@ int azi_plan_export_csc(const azi_plan* plan, void* data, int32_t* bins, int32_t
  *             quotient of azi_correct.  U, which does not depend on the
  *             image, is summed once from the unfolded coefficients at that
  *             point and written with every frame.
+ *             AZI_STAGE_FOLD_SUM (run layout; the band layout takes it as
+ *             AZI_STAGE_FUSE): as AZI_STAGE_FOLD, but, for plans that
+ *             accumulate in float64, the dark term of W does not depend on
+ *             the frame either: D_b = sum_p A_bp * dark_p (A_bp carrying
+ *             1 / norm) is summed once per correction set, in the
+ *             per-frame order, and the frame's W is sum_p A_bp * raw_p - D_b,
+ *             so no dark value is read per frame.  The subtraction moves the
+ *             rounding error's scale from sum_p A_bp |raw_p - dark_p| to
+ *             sum_p A_bp (|raw_p| + |dark_p|), which in float64 stays far
+ *             below the 1e-12 tolerance unless the dark current outweighs
+ *             the signal by several hundred times in a whole bin.  Plans
+ *             with Kahan float sums keep the dark value per run (as
+ *             AZI_STAGE_FOLD).
  */
 #define AZI_NUM_VARIANTS 7
 #define AZI_STAGE_GATHER 0
@@ -290,6 +303,7 @@ int azi_plan_export_csc(const azi_plan* plan, void* data, int32_t* bins, int32_t
 #define AZI_STAGE_TILE 2
 #define AZI_STAGE_FUSE 3
 #define AZI_STAGE_FOLD 4
+#define AZI_STAGE_FOLD_SUM 5
 typedef struct azi_tiling {
     int32_t tile_nnz, block, variant, grid, band, stage;
 } azi_tiling;
@@ -423,7 +437,8 @@ int azi_plan_set_corrections(azi_plan* plan, const void* dark, const void* flat,
  * pixel: 2 for integer counts of 16 bits, 4 as a float, else the storage
  * size), or 0 when the raw-frame
  * path keeps no such array (no corrections or no dark with
- * AZI_STAGE_FOLD, or another layout or stage).  0 for a NULL plan. */
+ * AZI_STAGE_FOLD, AZI_STAGE_FOLD_SUM with float64 sums, or another layout
+ * or stage).  0 for a NULL plan. */
 int32_t azi_plan_correction_bytes(const azi_plan* plan);
 
 /*
@@ -462,7 +477,7 @@ int azi_integrate1d_raw(const azi_plan* plan, const void* raw, int32_t raw_dtype
  * buffer.  Every device the library runs on holds one such array until the
  * process ends; its address is looked up on the first call on each device.
  * The call allocates nothing and does not synchronise.
- *   Layouts: run and band (stage AZI_STAGE_FUSE or _FOLD), tile and
+ *   Layouts: run and band (stage AZI_STAGE_FUSE, _FOLD or _FOLD_SUM), tile and
  *   fused; the pixel and ring layouts (which also need the plan's work
  *   image) give AZI_EINVAL.
  *   Limit: a plan whose partial sums exceed the array (16 bytes per slot:

@@ -53,8 +53,8 @@ class Tiling(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
-STAGES = {"gather": 0, "scatter": 1, "tile": 2, "fuse": 3, "fold": 4}
-DEFAULT_TILING = dict(tile_nnz=0, block=256, variant=5, grid=0, band=16, stage=4)
+STAGES = {"gather": 0, "scatter": 1, "tile": 2, "fuse": 3, "fold": 4, "fold_sum": 5}
+DEFAULT_TILING = dict(tile_nnz=0, block=256, variant=5, grid=0, band=16, stage=5)
 
 
 def _tiling(cur=None, **kw):

@@ -163,14 +163,21 @@ __device__ inline void write_row(int32_t r, const Acc& a, T* __restrict__ I, T* 
 }
 
 // write_row with U taken from outside the partial sums (ufix_in, the plan's
-// U in double), or only U stored (ufix_out): see BandLaunch.
+// U in double) and a fixed term subtracted from W (wsub_in), or only U or W
+// stored (ufix_out, wfix_out): see BandLaunch.
 template <class T, class Acc>
 __device__ inline void write_row_u(int32_t r, const Acc& a, T* __restrict__ I,
                                    T* __restrict__ W, T* __restrict__ U, double empty,
                                    const double* __restrict__ ufix_in,
-                                   double* __restrict__ ufix_out) {
+                                   double* __restrict__ ufix_out,
+                                   const double* __restrict__ wsub_in,
+                                   double* __restrict__ wfix_out) {
     if (ufix_out) {
         ufix_out[r] = (double)a.U();
+        return;
+    }
+    if (wfix_out) {
+        wfix_out[r] = (double)a.W();
         return;
     }
     if (!ufix_in) {
@@ -179,7 +186,8 @@ __device__ inline void write_row_u(int32_t r, const Acc& a, T* __restrict__ I,
     }
     using V = decltype(a.U());
     const V u = (V)ufix_in[r];
-    const auto w = a.W();
+    V w = (V)a.W();
+    if (wsub_in) w -= (V)wsub_in[r];
     if (W) W[r] = (T)w;
     if (U) U[r] = (T)u;
     I[r] = (u != 0) ? (T)(w / u) : (T)empty;

@@ -122,7 +122,7 @@ bool valid_tiling(const azi_tiling& t) {
     return (t.tile_nnz == 0 || (t.tile_nnz >= 64 && t.tile_nnz <= 16384 && t.tile_nnz % 64 == 0)) &&
            (t.block == 64 || t.block == 128 || t.block == 256 || t.block == 512) &&
            t.variant >= 0 && t.variant < azi::kNumVariants && t.grid >= 0 && t.band >= 0 &&
-           t.stage >= AZI_STAGE_GATHER && t.stage <= AZI_STAGE_FOLD;
+           t.stage >= AZI_STAGE_GATHER && t.stage <= AZI_STAGE_FOLD_SUM;
 }
 
 // Below ~4e6 nonzeros (a ~1e6-pixel frame) there are too few 4096-entry
@@ -171,20 +171,24 @@ int64_t balanced_tiles(const azi_tiling& t, int device, int32_t waves, int32_t d
 
 // Stages whose raw-frame path corrects each pixel in the band gather.
 bool gather_corrects(int32_t stage) {
-    return stage == AZI_STAGE_FUSE || stage == AZI_STAGE_FOLD;
+    return stage == AZI_STAGE_FUSE || stage == AZI_STAGE_FOLD || stage == AZI_STAGE_FOLD_SUM;
 }
+
+// Stages that fold 1 / norm into the coefficients (run layout).
+bool folds(int32_t stage) { return stage == AZI_STAGE_FOLD || stage == AZI_STAGE_FOLD_SUM; }
 
 // Fastest measured on the ~1e7-pixel, 3162-bin workload: run layout with
 // four neighbouring bands of 4 bins per workgroup, the pieces sized by the
 // library (balanced rounds of resident workgroups), raw frames corrected in
-// the gather with 1 / norm folded into the coefficients and dark stored per
-// run (float64: 85 / 88 us warm / flushed, against 86 / 89 us for pieces of
-// 2048 runs and 106 / 116 us with one band per workgroup and the (dark,
-// 1 / norm) pair gathered per pixel).  The workgroup stays at 256 threads,
+// the gather with 1 / norm folded into the coefficients and the dark term
+// summed once per correction set (float64: 85 / 88 us warm / flushed with a
+// dark value stored per run, against 86 / 89 us for pieces of 2048 runs and
+// 106 / 116 us with one band per workgroup and the (dark, 1 / norm) pair
+// gathered per pixel).  The workgroup stays at 256 threads,
 // the raw-frame band kernel's, so the raw and corrected-image entry points
 // sum in the same order.
-constexpr azi_tiling kDefaultTiling = {0, 256, 5, 0, 16, AZI_STAGE_FOLD};
-constexpr azi_tiling kDefaultTiling32 = {0, 256, 5, 0, 16, AZI_STAGE_FOLD};
+constexpr azi_tiling kDefaultTiling = {0, 256, 5, 0, 16, AZI_STAGE_FOLD_SUM};
+constexpr azi_tiling kDefaultTiling32 = {0, 256, 5, 0, 16, AZI_STAGE_FOLD_SUM};
 // Two-dimensional plans (short rows, CSR layout): lane-strided loads of
 // whole rows, 4 deep, all through the caches (70 us back to back, 82 us
 // after a 1 GiB read-only flush for 1000 x 360 bins of a ~1e7-pixel frame;
@@ -242,9 +246,9 @@ struct azi_plan {
     DevBuf rowptr, indices, data, colptr, rowidx, cdata, tiles, splits, parts, dark, norm, xwork,
         vwork, order, dark_r, norm_r, pos, stiles, lidx, dest, btiles, brows, blp, bcoef, bin_ptr,
         bparts, npieces_buf, npacked, ncoef, bin_slot, bin_count, nparts_buf, ftiles, fslots,
-        fbin_ptr, fparts, corr, cfirst, rgbase, fcoef, ufix;
+        fbin_ptr, fparts, corr, cfirst, rgbase, fcoef, ufix, wdark;
     int32_t nstiles = 0, nbtiles = 0, npieces = 0, band_rows = 8, nftiles = 0;
-    bool folded = false;  // run layout, AZI_STAGE_FOLD, corrections set
+    bool folded = false;  // run layout, AZI_STAGE_FOLD(_SUM), corrections set
     int32_t max_count = INT32_MAX;  // largest number of band partials of a bin
     int32_t corr_kind = azi::kCorrPair;
     int32_t ntiles = 0, nsplits = 0, nparts = 0;
@@ -483,7 +487,8 @@ azi::BandLaunch plan_band_args(const azi_plan* p, const void* x, void* I, void* 
 
 // Raw-frame band launch: cast and correction in the gather; with the
 // normalisation folded (AZI_STAGE_FOLD) the folded coefficients, dark alone
-// and the plan's U.
+// and the plan's U; with the dark term summed too (AZI_STAGE_FOLD_SUM,
+// float64 sums) the raw count alone, the plan's D subtracted from W.
 azi::BandLaunch plan_band_raw_args(const azi_plan* p, const void* raw, int32_t raw_dtype,
                                    void* I, void* W, void* U, double empty) {
     azi::BandLaunch a = plan_band_args(p, nullptr, I, W, U, empty);
@@ -494,6 +499,10 @@ azi::BandLaunch plan_band_raw_args(const azi_plan* p, const void* raw, int32_t r
     if (p->folded) {
         if (p->fcoef.p) a.coef = p->fcoef.p;
         a.ufix_in = p->ufix.as<double>();
+        if (p->wdark.p) {  // the dark term is the plan's: the raw count alone
+            a.corr = nullptr;
+            a.wsub_in = p->wdark.as<double>();
+        }
     }
     return a;
 }
@@ -582,7 +591,9 @@ int plan_upload_fused(azi_plan* p) {
 // rounded once to the storage type), each run's dark value stored beside
 // the run words, and the U of every bin summed once from the unfolded
 // coefficients in the per-frame order (the kernels over any image, the
-// reduction keeping U only).
+// reduction keeping U only).  AZI_STAGE_FOLD_SUM with float64 sums stores
+// no dark value per run: D = (folded A) dark is summed once in the same
+// order (the dark array as the image, the reduction keeping W only).
 template <class S>
 int download_as_double(const DevBuf& src, int64_t n, std::vector<double>& out, hipStream_t s) {
     std::vector<S> tmp((size_t)n);
@@ -595,6 +606,7 @@ int download_as_double(const DevBuf& src, int64_t n, std::vector<double>& out, h
 
 int plan_fold(azi_plan* p, hipStream_t s) {
     const int64_t npix = p->m.npix;
+    const bool sum_dark = p->tiling.stage == AZI_STAGE_FOLD_SUM && p->accum == AZI_ACC_F64;
     try {
         std::vector<double> inv, dark;
         int rc = AZI_OK;
@@ -604,7 +616,7 @@ int plan_fold(azi_plan* p, hipStream_t s) {
             if (rc != AZI_OK) return rc;
             for (double& v : inv) v = 1.0 / v;
         }
-        if (p->has_dark) {
+        if (p->has_dark && !sum_dark) {
             rc = p->dtype == AZI_F64 ? download_as_double<double>(p->dark, npix, dark, s)
                                      : download_as_double<float>(p->dark, npix, dark, s);
             if (rc != AZI_OK) return rc;
@@ -619,7 +631,9 @@ int plan_fold(azi_plan* p, hipStream_t s) {
                                              (int64_t)rm.coef.size() + kPad, p->dtype);
             AZI_HIP(p->fcoef.upload(c.data(), c.size(), p->device), "folded coefficients");
         }
-        if (p->has_dark) {
+        if (p->has_dark && sum_dark) {
+            p->corr_kind = azi::kCorrRunDark;  // no per-run array: D below
+        } else if (p->has_dark) {
             // uint16 when every dark value is an integer count that fits
             // (its conversion to the storage type is exact: the same bits
             // from half the bytes), else float when every value is one
@@ -658,6 +672,15 @@ int plan_fold(azi_plan* p, hipStream_t s) {
     azi::BandLaunch a = plan_band_args(p, p->xwork.p, nullptr, nullptr, nullptr, 0.0);
     a.ufix_out = p->ufix.as<double>();
     AZI_HIP(azi::launch_band(a, s), "fixed U");
+    if (p->has_dark && sum_dark) {
+        // D = (folded A) dark over the per-frame pieces, the dark array as
+        // the image
+        AZI_HIP(p->wdark.alloc((size_t)p->m.npt * 8, p->device), "fixed dark term");
+        azi::BandLaunch d = plan_band_args(p, p->dark.p, nullptr, nullptr, nullptr, 0.0);
+        if (p->fcoef.p) d.coef = p->fcoef.p;
+        d.wfix_out = p->wdark.as<double>();
+        AZI_HIP(azi::launch_band(d, s), "fixed dark term");
+    }
     AZI_HIP(hipStreamSynchronize(s), "folded corrections");
     return AZI_OK;
 }
@@ -666,17 +689,19 @@ int plan_corr_pair(azi_plan* p, hipStream_t s) {
     p->corr.release();
     p->fcoef.release();
     p->ufix.release();
+    p->wdark.release();
     p->folded = false;
     p->corr_kind = azi::kCorrPair;
     if (!is_band(p->layout) || !gather_corrects(p->tiling.stage) ||
         !(p->has_dark || p->has_norm))
         return AZI_OK;
-    if (p->layout == AZI_LAYOUT_RUN && p->tiling.stage == AZI_STAGE_FOLD) {
+    if (p->layout == AZI_LAYOUT_RUN && folds(p->tiling.stage)) {
         const int rc = plan_fold(p, s);
         if (rc != AZI_OK) {
             p->corr.release();
             p->fcoef.release();
             p->ufix.release();
+            p->wdark.release();
             p->corr_kind = azi::kCorrPair;
             return rc;
         }
@@ -1382,7 +1407,7 @@ int32_t azi_plan_correction_bytes(const azi_plan* p) {
 int64_t azi_plan_device_bytes(const azi_plan* p) {
     if (!p) return 0;
     const DevBuf* bufs[] = {&p->ftiles, &p->fslots, &p->fbin_ptr, &p->fparts, &p->corr, &p->cfirst,
-                            &p->fcoef, &p->ufix,
+                            &p->fcoef, &p->ufix, &p->wdark,
                             &p->rowptr, &p->indices, &p->data, &p->colptr, &p->rowidx,
                             &p->cdata, &p->tiles, &p->splits, &p->parts, &p->dark,
                             &p->norm, &p->xwork, &p->vwork, &p->order, &p->dark_r,
@@ -1626,7 +1651,7 @@ int azi_integrate1d_raw_noalloc(const azi_plan* p, const void* raw, int32_t raw_
     else
         return fail(AZI_EINVAL,
                     "the allocation-free call takes the run and band layouts (stage "
-                    "AZI_STAGE_FUSE or AZI_STAGE_FOLD), the tile layout and the fused layout");
+                    "AZI_STAGE_FUSE, _FOLD or _FOLD_SUM), the tile layout and the fused layout");
     if (need > kScratchBytes)
         return fail(AZI_EINVAL, "plan needs " + std::to_string(need) +
                                     " bytes of partial sums, more than the " +

@@ -123,6 +123,12 @@ struct BandLaunch {
     // whose sums are then not U).
     double* ufix_out = nullptr;
     const double* ufix_in = nullptr;
+    // The frame-independent dark term of W (AZI_STAGE_FOLD_SUM).  wfix_out:
+    // the reduction writes each bin's W (as the accumulator holds it, in
+    // double) there and nothing else; wsub_in (with ufix_in): the reduction
+    // subtracts it from each bin's W before forming I.
+    double* wfix_out = nullptr;
+    const double* wsub_in = nullptr;
 };
 
 hipError_t launch_band(const BandLaunch& a, hipStream_t s);

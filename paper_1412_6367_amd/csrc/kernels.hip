@@ -571,7 +571,8 @@ __global__ void k_band_reduce(const int32_t* __restrict__ bin_slot,
                               const int32_t* __restrict__ bin_count, int32_t R, int64_t b0,
                               int64_t b1, const Acc* __restrict__ parts, T* __restrict__ I,
                               T* __restrict__ W, T* __restrict__ U, double empty,
-                              const double* __restrict__ ufix_in, double* __restrict__ ufix_out) {
+                              const double* __restrict__ ufix_in, double* __restrict__ ufix_out,
+                              const double* __restrict__ wsub_in, double* __restrict__ wfix_out) {
     const int64_t b = b0 + (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (b >= b1) return;
     const int lane = threadIdx.x & (kWave - 1);
@@ -580,7 +581,8 @@ __global__ void k_band_reduce(const int32_t* __restrict__ bin_slot,
     const int32_t first = bin_slot[b], cnt = bin_count[b];
     for (int32_t k = lane; k < cnt; k += kWave) a.merge(parts[first + (int64_t)k * R]);
     group_reduce(a, kWave);
-    if (lane == 0) write_row_u((int32_t)b, a, I, W, U, empty, ufix_in, ufix_out);
+    if (lane == 0)
+        write_row_u((int32_t)b, a, I, W, U, empty, ufix_in, ufix_out, wsub_in, wfix_out);
 }
 
 // One lane per bin, for matrices whose bins have at most kLaneParts
@@ -597,7 +599,9 @@ __global__ void k_band_reduce_lane(const int32_t* __restrict__ bin_slot,
                                    int64_t b1, const Acc* __restrict__ parts, T* __restrict__ I,
                                    T* __restrict__ W, T* __restrict__ U, double empty,
                                    const double* __restrict__ ufix_in,
-                                   double* __restrict__ ufix_out) {
+                                   double* __restrict__ ufix_out,
+                                   const double* __restrict__ wsub_in,
+                                   double* __restrict__ wfix_out) {
     const int64_t b = b0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= b1) return;
     const int32_t first = bin_slot[b], cnt = bin_count[b];
@@ -612,7 +616,7 @@ __global__ void k_band_reduce_lane(const int32_t* __restrict__ bin_slot,
 #pragma unroll
         for (int k = 0; k < m; ++k) v[k].merge(v[k + m]);
     }
-    write_row_u((int32_t)b, v[0], I, W, U, empty, ufix_in, ufix_out);
+    write_row_u((int32_t)b, v[0], I, W, U, empty, ufix_in, ufix_out, wsub_in, wfix_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -1174,7 +1178,7 @@ hipError_t band_impl(const BandLaunch& a, hipStream_t s) {
                            dim3(256), 0, s, a.bin_slot, a.bin_count, a.R, a.b0, a.b1,
                            static_cast<const Acc*>(a.parts), static_cast<T*>(a.I),
                            static_cast<T*>(a.W), static_cast<T*>(a.U), a.empty, a.ufix_in,
-                           a.ufix_out);
+                           a.ufix_out, a.wsub_in, a.wfix_out);
         return hipGetLastError();
     }
     if (nb > 0) {
@@ -1182,7 +1186,7 @@ hipError_t band_impl(const BandLaunch& a, hipStream_t s) {
                            s, a.bin_slot, a.bin_count, a.R, a.b0, a.b1,
                            static_cast<const Acc*>(a.parts), static_cast<T*>(a.I),
                            static_cast<T*>(a.W), static_cast<T*>(a.U), a.empty, a.ufix_in,
-                           a.ufix_out);
+                           a.ufix_out, a.wsub_in, a.wfix_out);
         return hipGetLastError();
     }
     return hipSuccess;

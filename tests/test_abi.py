@@ -197,7 +197,7 @@ def test_argument_errors():
     assert _err(L.azi_plan_set_tiling(plan.handle, T(1024, 128, 7, 0, 0, 0)))[0] == -1
     assert _err(L.azi_plan_set_tiling(plan.handle, T(1024, 128, -1, 0, 0, 0)))[0] == -1
     assert _err(L.azi_plan_set_tiling(plan.handle, T(1024, 128, 1, -8, 0, 0)))[0] == -1
-    assert _err(L.azi_plan_set_tiling(plan.handle, T(1024, 128, 1, 0, 0, 5)))[0] == -1
+    assert _err(L.azi_plan_set_tiling(plan.handle, T(1024, 128, 1, 0, 0, 6)))[0] == -1
     assert _err(L.azi_plan_set_tiling(plan.handle, None))[0] == -1
     assert L.azi_plan_set_tiling(plan.handle, T(1024, 128, 6, 512, 4, 1)) == 0
     assert plan.tiling() == dict(tile_nnz=1024, block=128, variant=6, grid=512, band=4, stage=1)

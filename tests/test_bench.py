@@ -38,6 +38,7 @@ def test_byte_counts_of_the_c2_frame():
     # bytes do not shrink the yardstick
     assert abs(bench.raw_bytes(nnz, npix, npt, 8, 4) / 1e6 - 420.0) < 0.1
     assert bench.raw_bytes(nnz, npix, npt, 8, 2) == bench.raw_bytes(nnz, npix, npt, 8, 4)
+    assert bench.raw_bytes(nnz, npix, npt, 8, 0) == bench.raw_bytes(nnz, npix, npt, 8, 4)
     # adjoint of a 1-D plan: coefficients, column pointers and one first-bin
     # word per pixel instead of per-entry bin ids
     assert bench.bwd_bytes(nnz, npix, npt, 8) == nnz * 8 + (npix + 1) * 4 + npix * 4 + \
@@ -57,6 +58,10 @@ def test_encoding_bytes_count_the_runs():
     plan.set_tiling(stage="fold")
     got = bench.encoding_bytes(plan, np, plan.npix, plan.npt, 8, 4)
     assert got == runs * (4 + 4) + plan.nnz * 8 + plan.npix * 4 + 3 * plan.npt * 8
+    # the dark term summed once per correction set: nothing stored per run
+    plan.set_tiling(stage="fold_sum")
+    got = bench.encoding_bytes(plan, np, plan.npix, plan.npt, 8, 0)
+    assert got == runs * 4 + plan.nnz * 8 + plan.npix * 4 + 3 * plan.npt * 8
     plan.set_layout("band")
     assert bench.encoding_bytes(plan, np, plan.npix, plan.npt, 8, 12) == \
         bench.raw_bytes(plan.nnz, plan.npix, plan.npt, 8, 12)

@@ -1,8 +1,9 @@
 """The raw-frame path with 1/norm folded into the coefficients
-(AZI_STAGE_FOLD, run layout) against the FP64 oracle, and against the
-unfolded path (AZI_STAGE_FUSE) on the same plan: W and I within the stated
-tolerance, U bit for bit (it is summed once from the unfolded coefficients
-in the per-frame order)."""
+(AZI_STAGE_FOLD, run layout; AZI_STAGE_FOLD_SUM also sums the dark term
+once) against the FP64 oracle, and against the unfolded path
+(AZI_STAGE_FUSE) on the same plan: W and I within the stated tolerance, U
+bit for bit (it is summed once from the unfolded coefficients in the
+per-frame order)."""
 import sys
 
 import numpy as np
@@ -54,19 +55,21 @@ def test_fold_matches_oracle(dtype, accum, combo, raw_dtype, band, dev):
     raw_np = inst.raw.reshape(-1).astype(raw_dtype)
     raw = _tensor(raw_np, dev)
     outs = {}
-    for stage in ("fold", "fuse"):
+    for stage in ("fold_sum", "fold", "fuse"):
         plan = _setup(az, dev, inst, dtype, accum, stage, band=band)
         plan.set_corrections(*(None if a is None else _tensor(a, dev, npd) for a in arrs))
         outs[stage] = plan.integrate_raw(raw, empty=-3.0)
         torch.cuda.synchronize()
     # U does not depend on the image: the folded path's U is the unfolded one's
     assert torch.equal(outs["fold"][2], outs["fuse"][2])
+    assert torch.equal(outs["fold_sum"][2], outs["fuse"][2])
     m = oracle_matrix(g.h, g.w, g.center_y, g.center_x, inst.npt)
     # the oracle corrects the same storage-type corrections as the plan holds
     x = oracle.correct(raw_np, *(None if a is None else a.astype(npd).astype(np.float64)
                                  for a in arrs))
     tol = TOL64 if dtype == torch.float64 else TOL32_F64
     check(outs["fold"], m, x, tol, empty=-3.0, what=f"fold {combo}")
+    check(outs["fold_sum"], m, x, tol, empty=-3.0, what=f"fold_sum {combo}")
 
 
 @pytest.mark.parametrize("band", [4, 16, 32])
@@ -81,18 +84,21 @@ def test_fold_follows_tiling_changes(band, dev):
     m = oracle_matrix(g.h, g.w, g.center_y, g.center_x, inst.npt)
     x = oracle.correct(inst.raw, inst.dark, inst.flat, inst.solid, inst.polar)
     fold = _setup(az, dev, inst, torch.float64, "f64", "fold", band=band)
+    fsum = _setup(az, dev, inst, torch.float64, "f64", "fold_sum", band=band)
     fuse = _setup(az, dev, inst, torch.float64, "f64", "fuse", band=band)
-    for p in (fold, fuse):
+    for p in (fold, fsum, fuse):
         p.set_corrections(t(inst.dark), t(inst.flat), t(inst.solid), t(inst.polar))
     for kw in (dict(tile_nnz=1024), dict(block=128), dict(grid=64), dict(tile_nnz=8192, grid=0),
                dict(block=256, tile_nnz=4096), dict(tile_nnz=0)):
-        for p in (fold, fuse):
+        for p in (fold, fsum, fuse):
             p.set_tiling(**kw)
         a = fold.integrate_raw(t(inst.raw))
+        c = fsum.integrate_raw(t(inst.raw))
         b = fuse.integrate_raw(t(inst.raw))
         torch.cuda.synchronize()
-        assert torch.equal(a[2], b[2]), kw
+        assert torch.equal(a[2], b[2]) and torch.equal(c[2], b[2]), kw
         check(a, m, x, TOL64, what=str(kw))
+        check(c, m, x, TOL64, what=f"fold_sum {kw}")
 
 
 def test_fold_stage_switch_and_recorrect(dev):
@@ -107,10 +113,13 @@ def test_fold_stage_switch_and_recorrect(dev):
     plan = _setup(az, dev, inst, torch.float64, "f64", "fuse")
     plan.set_corrections(t(inst.dark), t(inst.flat), t(inst.solid), t(inst.polar))
     x = oracle.correct(inst.raw, inst.dark, inst.flat, inst.solid, inst.polar)
-    for stage in ("fold", "fuse", "fold"):
+    for stage in ("fold", "fold_sum", "fuse", "fold_sum", "fold"):
         plan.set_tiling(stage=stage)
         check(plan.integrate_raw(t(inst.raw)), m, x, TOL64, what=stage)
     assert plan.correction_bytes() == 2         # integer dark counts: 16 bits per run
+    plan.set_tiling(stage="fold_sum")
+    assert plan.correction_bytes() == 0         # the dark term summed once: nothing per run
+    plan.set_tiling(stage="fold")
     flat2 = inst.flat[::-1].copy()
     plan.set_corrections(None, t(flat2), None, t(inst.polar))
     x2 = oracle.correct(inst.raw, None, flat2, None, inst.polar)
@@ -125,15 +134,16 @@ def test_fold_stage_switch_and_recorrect(dev):
         check(plan.integrate_raw(t(inst.raw)), m, x3, TOL64, what=f"dark + {add}")
 
 
-def test_fold_graph_and_noalloc(dev):
+@pytest.mark.parametrize("stage", ["fold", "fold_sum"])
+def test_fold_graph_and_noalloc(stage, dev):
     """The folded step captured in a graph and through the allocation-free
     entry point gives the eager call's bits, replay after replay."""
-    say("fold graph")
+    say("fold graph", stage)
     az = azint()
     inst = synth.instance_hw(300, 280, 12, npt=250, corrections=True)
     g = inst.geom
     t = lambda a: _tensor(a, dev)
-    plan = _setup(az, dev, inst, torch.float64, "f64", "fold")
+    plan = _setup(az, dev, inst, torch.float64, "f64", stage)
     plan.set_corrections(t(inst.dark), t(inst.flat), t(inst.solid), t(inst.polar))
     raw = t(inst.raw)
     ref = [o.clone() for o in plan.integrate_raw(raw)]
@@ -155,17 +165,69 @@ def test_fold_graph_and_noalloc(dev):
 
 
 def test_fold_band_layout_is_fuse(dev):
-    """The band layout takes AZI_STAGE_FOLD as AZI_STAGE_FUSE."""
+    """The band layout takes AZI_STAGE_FOLD and _FOLD_SUM as AZI_STAGE_FUSE."""
     az = azint()
     inst = synth.instance_hw(120, 110, 13, npt=90, corrections=True)
     g = inst.geom
     t = lambda a: _tensor(a, dev)
     res = []
-    for stage in ("fold", "fuse"):
+    for stage in ("fold", "fold_sum", "fuse"):
         p = az.Plan(g.h, g.w, inst.npt, center=(g.center_y, g.center_x), layout="band",
                     stage=stage, device=dev)
         p.set_corrections(t(inst.dark), t(inst.flat), t(inst.solid), t(inst.polar))
         res.append(p.integrate_raw(t(inst.raw)))
+        torch.cuda.synchronize()
+    for r in res[:2]:
+        for a, b in zip(r, res[2]):
+            assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_fold_sum_on_a_dark_dominated_frame(dtype, dev):
+    """Summing the dark term once subtracts two large sums when the dark
+    current outweighs the signal: a frame whose dark counts are ~200 times
+    its signal stays within the float64 tolerance of the oracle (normalised,
+    as everywhere, by sum_p A_bp |x_p| of the corrected image), and the
+    dark-per-run form on the same plan agrees with it."""
+    say("fold_sum dark-dominated", dtype)
+    az = azint()
+    inst = synth.instance_hw(260, 250, 15, npt=180, corrections=True)
+    g = inst.geom
+    rng = np.random.default_rng(15)
+    dark = rng.integers(4000, 6000, size=(g.h, g.w)).astype(np.float64)
+    raw = (dark + rng.integers(0, 100, size=(g.h, g.w))).astype(np.int32)
+    npd = np.float64 if dtype == torch.float64 else np.float32
+    t = lambda a: _tensor(a, dev, npd)
+    m = oracle_matrix(g.h, g.w, g.center_y, g.center_x, inst.npt)
+    plan = _setup(az, dev, inst, dtype, "f64", "fold_sum")
+    plan.set_corrections(t(dark), t(inst.flat), t(inst.solid), t(inst.polar))
+    assert plan.correction_bytes() == 0
+    rawt = _tensor(raw, dev)
+    a = [o.clone() for o in plan.integrate_raw(rawt)]
+    plan.set_tiling(stage="fold")
+    b = plan.integrate_raw(rawt)
+    torch.cuda.synchronize()
+    x = oracle.correct(raw, *(v.astype(npd).astype(np.float64)
+                              for v in (dark, inst.flat, inst.solid, inst.polar)))
+    tol = TOL64 if dtype == torch.float64 else TOL32_F64
+    e = check(a, m, x, tol, what="fold_sum, dark 200x the signal")
+    say("normalised errors", e)
+    check(b, m, x, tol, what="fold, dark 200x the signal")
+    assert torch.equal(a[2], b[2])
+
+
+def test_fold_sum_with_kahan_sums_keeps_dark_per_run(dev):
+    """Plans with Kahan float sums take AZI_STAGE_FOLD_SUM as AZI_STAGE_FOLD:
+    the same bits, the dark value stored per run."""
+    az = azint()
+    inst = synth.instance_hw(140, 150, 16, npt=100, corrections=True)
+    t = lambda a: _tensor(a, dev, np.float32)
+    res = []
+    for stage in ("fold_sum", "fold"):
+        p = _setup(az, dev, inst, torch.float32, "kahan32", stage)
+        p.set_corrections(t(inst.dark), t(inst.flat), t(inst.solid), t(inst.polar))
+        assert p.correction_bytes() == 2
+        res.append(p.integrate_raw(_tensor(inst.raw, dev)))
         torch.cuda.synchronize()
     for a, b in zip(*res):
         assert torch.equal(a, b)
