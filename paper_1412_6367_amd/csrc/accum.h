@@ -162,15 +162,34 @@ __device__ inline void write_row(int32_t r, const Acc& a, T* __restrict__ I, T* 
     I[r] = (u != 0) ? (T)(w / u) : (T)empty;
 }
 
-// write_row with U taken from outside the partial sums (ufix_in, the plan's
-// U in double) and a fixed term subtracted from W (wsub_in), or only U or W
-// stored (ufix_out, wfix_out): see BandLaunch.
+// The plan's fixed per-bin terms of a reduction (see BandLaunch), loaded
+// before the partial sums so that their latency overlaps them.
+struct RowFixed {
+    bool has_u = false, has_w = false;
+    double u = 0.0, w = 0.0;
+};
+
+__device__ inline RowFixed load_row_fixed(int64_t r, const double* __restrict__ ufix_in,
+                                          const double* __restrict__ wsub_in) {
+    RowFixed f;
+    if (ufix_in) {
+        f.has_u = true;
+        f.u = ufix_in[r];
+        if (wsub_in) {
+            f.has_w = true;
+            f.w = wsub_in[r];
+        }
+    }
+    return f;
+}
+
+// write_row with U taken from outside the partial sums (the plan's U in
+// double) and a fixed term subtracted from W, or only U or W stored
+// (ufix_out, wfix_out): see BandLaunch.
 template <class T, class Acc>
 __device__ inline void write_row_u(int32_t r, const Acc& a, T* __restrict__ I,
                                    T* __restrict__ W, T* __restrict__ U, double empty,
-                                   const double* __restrict__ ufix_in,
-                                   double* __restrict__ ufix_out,
-                                   const double* __restrict__ wsub_in,
+                                   const RowFixed& f, double* __restrict__ ufix_out,
                                    double* __restrict__ wfix_out) {
     if (ufix_out) {
         ufix_out[r] = (double)a.U();
@@ -180,14 +199,14 @@ __device__ inline void write_row_u(int32_t r, const Acc& a, T* __restrict__ I,
         wfix_out[r] = (double)a.W();
         return;
     }
-    if (!ufix_in) {
+    if (!f.has_u) {
         write_row(r, a, I, W, U, empty);
         return;
     }
     using V = decltype(a.U());
-    const V u = (V)ufix_in[r];
+    const V u = (V)f.u;
     V w = (V)a.W();
-    if (wsub_in) w -= (V)wsub_in[r];
+    if (f.has_w) w -= (V)f.w;
     if (W) W[r] = (T)w;
     if (U) U[r] = (T)u;
     I[r] = (u != 0) ? (T)(w / u) : (T)empty;

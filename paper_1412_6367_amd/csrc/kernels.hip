@@ -579,10 +579,10 @@ __global__ void k_band_reduce(const int32_t* __restrict__ bin_slot,
     Acc a;
     a.zero();
     const int32_t first = bin_slot[b], cnt = bin_count[b];
+    const RowFixed f = load_row_fixed(b, ufix_in, wsub_in);
     for (int32_t k = lane; k < cnt; k += kWave) a.merge(parts[first + (int64_t)k * R]);
     group_reduce(a, kWave);
-    if (lane == 0)
-        write_row_u((int32_t)b, a, I, W, U, empty, ufix_in, ufix_out, wsub_in, wfix_out);
+    if (lane == 0) write_row_u((int32_t)b, a, I, W, U, empty, f, ufix_out, wfix_out);
 }
 
 // One lane per bin, for matrices whose bins have at most kLaneParts
@@ -605,6 +605,7 @@ __global__ void k_band_reduce_lane(const int32_t* __restrict__ bin_slot,
     const int64_t b = b0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= b1) return;
     const int32_t first = bin_slot[b], cnt = bin_count[b];
+    const RowFixed f = load_row_fixed(b, ufix_in, wsub_in);
     Acc v[kLaneParts];
 #pragma unroll
     for (int k = 0; k < kLaneParts; ++k) {
@@ -616,7 +617,7 @@ __global__ void k_band_reduce_lane(const int32_t* __restrict__ bin_slot,
 #pragma unroll
         for (int k = 0; k < m; ++k) v[k].merge(v[k + m]);
     }
-    write_row_u((int32_t)b, v[0], I, W, U, empty, ufix_in, ufix_out, wsub_in, wfix_out);
+    write_row_u((int32_t)b, v[0], I, W, U, empty, f, ufix_out, wfix_out);
 }
 
 // ---------------------------------------------------------------------------
