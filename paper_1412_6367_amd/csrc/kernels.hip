@@ -1042,11 +1042,13 @@ hipError_t band_block(const BandLaunch& a, hipStream_t s) {
 }
 
 // Groups in flight per wavefront (measured at 1e7 pixels: 2 for float64,
-// 4 for float32, whose registers are half the size; 3 for float64 when the
-// accumulator holds W alone, which frees the registers of a third group
-// within the 64 VGPRs of 8 wavefronts per SIMD).
+// 4 for float32, whose registers are half the size; one more when the
+// accumulator holds W alone, which frees the registers of another group
+// within the 64 VGPRs of 8 wavefronts per SIMD: float64 60, float32 62 at
+// most over the raw types and dark forms).
 template <class T, class Acc>
-constexpr int kRunGroups = sizeof(T) == 8 ? (std::is_same<Acc, AccWF64>::value ? 3 : 2) : 4;
+constexpr int kRunGroups = std::is_same<Acc, AccWF64>::value ? (sizeof(T) == 8 ? 3 : 5)
+                                                            : (sizeof(T) == 8 ? 2 : 4);
 
 // The co-scheduled kernel of `a.waves` bands per workgroup, accumulating in
 // Acc (partial-sum slots of Acc::Slot).
