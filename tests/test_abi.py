@@ -188,6 +188,9 @@ def test_argument_errors():
     assert L.azi_plan_destroy(None) == 0
     # per-frame calls on a plan that is not on a device
     plan = az.Plan(10, 10, 10)
+    # a new plan starts in the stage that sums the dark term once
+    assert plan.tiling() == dict(az.DEFAULT_TILING) and plan.tiling()["stage"] == 5
+    assert az.STAGES["fold_sum"] == 5 and az.STAGES["fold"] == 4
     rc, msg = _err(L.azi_integrate1d(plan.handle, ctypes.c_void_p(16), ctypes.c_void_p(16),
                                      None, None, 0.0, None))
     assert rc == -5 and "azi_plan_upload" in msg
