@@ -687,7 +687,9 @@ def main():
                         "[0, 2^20), dark/flat/solid/polar corrections, bounding-box split, "
                         "3162 radial bins, float64 storage and accumulation; step = cast + "
                         "correction + sparse gather integration (I, W, U), the correction "
-                        "applied in the integration kernel's gather",
+                        "applied inside the integration (1/norm folded into the "
+                        "coefficients and the dark term summed once per correction set, "
+                        "per the plan's stage)",
             "npix": line64["npix"], "npt": line64["npt"], "nnz": line64["nnz"],
         },
         # headline: the step with L2 and MALL flushed before every launch (the
