@@ -132,6 +132,15 @@ def test_fold_stage_switch_and_recorrect(dev):
         assert plan.correction_bytes() == nbytes, add
         x3 = oracle.correct(inst.raw, dark, inst.flat, inst.solid, inst.polar)
         check(plan.integrate_raw(t(inst.raw)), m, x3, TOL64, what=f"dark + {add}")
+    # new corrections on a plan in the fold-sum stage: its dark term is
+    # summed again from the new dark map (and dropped with it)
+    plan.set_tiling(stage="fold_sum")
+    for dark in (inst.dark * 3.0 + 7.0, None):
+        plan.set_corrections(None if dark is None else t(dark), t(inst.flat), None,
+                             t(inst.polar))
+        assert plan.correction_bytes() == 0
+        x4 = oracle.correct(inst.raw, dark, inst.flat, None, inst.polar)
+        check(plan.integrate_raw(t(inst.raw)), m, x4, TOL64, what=f"fold_sum, dark {dark is None}")
 
 
 @pytest.mark.parametrize("stage", ["fold", "fold_sum"])
