@@ -291,9 +291,10 @@ int azi_plan_export_csc(const azi_plan* plan, void* data, int32_t* bins, int32_t
  *             per-frame order, and the frame's W is sum_p A_bp * raw_p - D_b,
  *             so no dark value is read per frame.  The subtraction moves the
  *             rounding error's scale from sum_p A_bp |raw_p - dark_p| to
- *             sum_p A_bp (|raw_p| + |dark_p|), which in float64 stays far
- *             below the 1e-12 tolerance unless the dark current outweighs
- *             the signal by several hundred times in a whole bin.  Plans
+ *             sum_p A_bp (|raw_p| + |dark_p|): the error grows with the ratio
+ *             of dark current to signal in a bin, and in float64 stays
+ *             within 1e-12 of sum_p A_bp |x_p| up to ratios of some
+ *             thousands (3e-14 at 200).  Plans
  *             with Kahan float sums keep the dark value per run (as
  *             AZI_STAGE_FOLD).
  */
