@@ -292,9 +292,10 @@ int azi_plan_export_csc(const azi_plan* plan, void* data, int32_t* bins, int32_t
  *             so no dark value is read per frame.  The subtraction moves the
  *             rounding error's scale from sum_p A_bp |raw_p - dark_p| to
  *             sum_p A_bp (|raw_p| + |dark_p|): the error grows with the ratio
- *             of dark current to signal in a bin, and in float64 stays
- *             within 1e-12 of sum_p A_bp |x_p| up to ratios of some
- *             thousands (3e-14 at 200).  Plans
+ *             of dark current to signal in a bin, about linearly: in
+ *             float64, 3e-14 of sum_p A_bp |x_p| measured at a ratio of
+ *             200, so the 1e-12 tolerance is reached near some thousands.
+ *             Plans
  *             with Kahan float sums keep the dark value per run (as
  *             AZI_STAGE_FOLD).
  */
