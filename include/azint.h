@@ -293,8 +293,9 @@ int azi_plan_export_csc(const azi_plan* plan, void* data, int32_t* bins, int32_t
  *             rounding error's scale from sum_p A_bp |raw_p - dark_p| to
  *             sum_p A_bp (|raw_p| + |dark_p|): the error grows with the ratio
  *             of dark current to signal in a bin, about linearly: in
- *             float64, 3e-14 of sum_p A_bp |x_p| measured at a ratio of
- *             200, so the 1e-12 tolerance is reached near some thousands.
+ *             float64, 3.1e-14 of sum_p A_bp |x_p| measured at a ratio of
+ *             100 and 3.2e-13 at 1000, so the 1e-12 tolerance is reached
+ *             near 3000.
  *             Plans
  *             with Kahan float sums keep the dark value per run (as
  *             AZI_STAGE_FOLD).

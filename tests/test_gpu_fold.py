@@ -191,19 +191,21 @@ def test_fold_band_layout_is_fuse(dev):
             assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("dark_lo", [4000, 40000], ids=["dark100x", "dark1000x"])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
-def test_fold_sum_on_a_dark_dominated_frame(dtype, dev):
+def test_fold_sum_on_a_dark_dominated_frame(dtype, dark_lo, dev):
     """Summing the dark term once subtracts two large sums when the dark
-    current outweighs the signal: a frame whose dark counts are ~200 times
-    its signal stays within the float64 tolerance of the oracle (normalised,
-    as everywhere, by sum_p A_bp |x_p| of the corrected image), and the
-    dark-per-run form on the same plan agrees with it."""
-    say("fold_sum dark-dominated", dtype)
+    current outweighs the signal: frames whose dark counts are on average
+    ~100 and ~1000 times their signal (signal uniform in [0, 100)) stay
+    within the float64 tolerance of the oracle
+    (normalised, as everywhere, by sum_p A_bp |x_p| of the corrected image),
+    and the dark-per-run form on the same plan agrees with it."""
+    say("fold_sum dark-dominated", dtype, dark_lo)
     az = azint()
     inst = synth.instance_hw(260, 250, 15, npt=180, corrections=True)
     g = inst.geom
     rng = np.random.default_rng(15)
-    dark = rng.integers(4000, 6000, size=(g.h, g.w)).astype(np.float64)
+    dark = rng.integers(dark_lo, dark_lo * 3 // 2, size=(g.h, g.w)).astype(np.float64)
     raw = (dark + rng.integers(0, 100, size=(g.h, g.w))).astype(np.int32)
     npd = np.float64 if dtype == torch.float64 else np.float32
     t = lambda a: _tensor(a, dev, npd)
@@ -219,9 +221,9 @@ def test_fold_sum_on_a_dark_dominated_frame(dtype, dev):
     x = oracle.correct(raw, *(v.astype(npd).astype(np.float64)
                               for v in (dark, inst.flat, inst.solid, inst.polar)))
     tol = TOL64 if dtype == torch.float64 else TOL32_F64
-    e = check(a, m, x, tol, what="fold_sum, dark 200x the signal")
-    say("normalised errors", e)
-    check(b, m, x, tol, what="fold, dark 200x the signal")
+    e = check(a, m, x, tol, what=f"fold_sum, dark from {dark_lo}")
+    say("normalised errors", dark_lo, e)
+    check(b, m, x, tol, what=f"fold, dark from {dark_lo}")
     assert torch.equal(a[2], b[2])
 
 
